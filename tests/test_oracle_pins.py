@@ -1,0 +1,536 @@
+"""Pins of the CPU oracle to facts fixed by the paper and by mathematics.
+
+None of these re-derives a value with the oracle's own formula: each compares
+against a closed form, a printed table, a brute-force search, an invariance, or
+a textbook routine computed a different way.
+"""
+import itertools
+import math
+import os
+import statistics
+
+import numpy as np
+import pytest
+
+import oracle
+import synthdata
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- constants
+
+@pytest.mark.parametrize("q", [0.5, 0.75, 0.9, 0.975, 0.99])
+def test_chi2_quantile_p2_closed_form(q):
+    # chi2_2 is exponential with mean 2: quantile -2 ln(1-q).
+    assert oracle.chi2_quantile(q, 2) == pytest.approx(-2.0 * math.log(1.0 - q), rel=1e-12)
+
+
+@pytest.mark.parametrize("alpha", [0.5, 0.55, 0.75, 0.9])
+def test_consistency_factor_p2_closed_form(alpha):
+    # F_{chi2_4}(x) = 1 - e^{-x/2}(1 + x/2), x = -2 ln(1-alpha).
+    ref = alpha / (1.0 - (1.0 - alpha) * (1.0 - math.log(1.0 - alpha)))
+    assert oracle.consistency_factor(alpha, 2) == pytest.approx(ref, rel=1e-10)
+
+
+@pytest.mark.parametrize("alpha", [0.5, 0.5001, 0.75, 0.975])
+def test_consistency_factor_p1_closed_form(alpha):
+    # x = chi2_{1,alpha} = (Phi^-1((1+alpha)/2))^2 ; F_{chi2_3}(x) = erf(sqrt(x/2)) - sqrt(2x/pi) e^{-x/2}
+    z = statistics.NormalDist().inv_cdf((1.0 + alpha) / 2.0)
+    x = z * z
+    F3 = math.erf(math.sqrt(x / 2.0)) - math.sqrt(2.0 * x / math.pi) * math.exp(-x / 2.0)
+    assert oracle.consistency_factor(alpha, 1) == pytest.approx(alpha / F3, rel=1e-9)
+
+
+def test_block_count_rule_table4_panelC():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "table4_panelC_blocks.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 10
+    cells = 0
+    for r in rows:
+        n = int(r[0])
+        vals = list(map(int, r[1:]))
+        for wi, omega in enumerate((2**12, 2**13, 2**14)):
+            for pi, p in enumerate((4, 8, 16)):
+                assert oracle.n_blocks(n, p, omega) == vals[3 * wi + pi], (n, p, omega)
+                cells += 1
+    assert cells == 90
+
+
+def test_subset_size_rule():
+    assert oracle.subset_size(10_000, 10, 0.75) == 7500
+    assert oracle.subset_size(15_625, 20, 0.75) == 11_718
+    assert oracle.subset_size(9_765, 40, 0.75) == 7_323
+    # clamped to (m+p+1)/2 from below and m-1 from above
+    assert oracle.subset_size(100, 10, 0.3) == 55
+    assert oracle.subset_size(100, 10, 1.0) == 99
+
+
+# ---------------------------------------------------------------- univariate MCD
+
+def _brute_unimcd(x):
+    v = np.sort(x)
+    n = len(v)
+    hh = n // 2 + 1
+    best, js = None, None
+    for j in range(n - hh + 1):
+        w = v[j:j + hh]
+        var = float(np.var(w, ddof=1))       # two-pass, independent of prefix sums
+        if best is None or var < best - 1e-12 * max(best, 1e-300):
+            best, js = var, j
+    return js, float(np.mean(v[js:js + hh])), best
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_unimcd_matches_brute_force_window(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(7, 180))
+    x = rng.standard_normal(n)
+    x[: n // 5] += rng.uniform(3, 10)          # a contaminated tail
+    js, mean, var = _brute_unimcd(x)
+    u = oracle.unimcd(x)
+    assert u.start == js
+    assert u.mu_raw == pytest.approx(mean, rel=1e-12, abs=1e-12)
+    hh = n // 2 + 1
+    c = oracle.consistency_factor(hh / n, 1)
+    assert u.var_raw == pytest.approx(var * c, rel=1e-10)
+    # reweighting by brute force
+    keep = [xi for xi in x if (xi - u.mu_raw) ** 2 <= oracle.chi2_quantile(0.975, 1) * u.var_raw]
+    assert u.n_kept == len(keep)
+    assert u.mu == pytest.approx(statistics.fmean(keep), rel=1e-12, abs=1e-12)
+    assert u.var == pytest.approx(statistics.variance(keep) * oracle.consistency_factor(0.975, 1),
+                                  rel=1e-10)
+
+
+def test_unimcd_location_scale_equivariance():
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(501)
+    u = oracle.unimcd(x)
+    v = oracle.unimcd(3.0 * x - 2.0)
+    assert v.start == u.start
+    assert v.mu == pytest.approx(3.0 * u.mu - 2.0, rel=1e-12)
+    assert v.var == pytest.approx(9.0 * u.var, rel=1e-12)
+
+
+def test_unimcd_gaussian_consistency():
+    # With the consistency factors, raw and reweighted variances estimate 1 on N(0,1).
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(1_000_000)
+    u = oracle.unimcd(x)
+    assert abs(u.mu) < 0.01
+    assert u.var_raw == pytest.approx(1.0, abs=0.02)
+    assert u.var == pytest.approx(1.0, abs=0.01)
+
+
+def test_unimcd_resists_contamination():
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(20_000)
+    x[:8_000] = 50.0 + rng.standard_normal(8_000)   # 40% far away
+    u = oracle.unimcd(x)
+    # the far group never enters the reweighted set; the location is unaffected
+    assert u.n_kept <= 12_000 and abs(u.mu) < 0.05 and 0.8 < u.var < 1.5
+
+
+# ---------------------------------------------------------------- wrapping
+
+def test_wrapping_golden_points():
+    for line in open(os.path.join(GOLDEN, "wrapping_points.txt")):
+        if not line.strip() or line.startswith("#"):
+            continue
+        z, g, tol = map(float, line.split())
+        assert float(oracle.wrap(np.array([z]))[0]) == pytest.approx(g, abs=max(tol, 1e-15))
+
+
+def test_wrapping_odd_and_bounded():
+    z = np.linspace(-6, 6, 2001)
+    g = oracle.wrap(z)
+    assert np.allclose(g, -oracle.wrap(-z), atol=0)
+    assert np.all(np.abs(g) <= 1.5 + 2e-4)
+    # continuity at b: 1.541 tanh(0.862 * 2.5) = 1.500147 (printed constants are rounded)
+    assert 1.541 * math.tanh(0.862 * 2.5) == pytest.approx(1.500147, abs=1e-6)
+
+
+def test_wrapping_keeps_about_85_percent():
+    # P(|N(0,1)| <= 1.5) = 0.8664 (Sec. 3.2: "about 85% of the values are left unchanged")
+    rng = np.random.default_rng(5)
+    z = rng.standard_normal(400_000)
+    frac = float(np.mean(oracle.wrap(z) == z))
+    assert frac == pytest.approx(math.erf(1.5 / math.sqrt(2)), abs=0.003)
+
+
+# ---------------------------------------------------------------- GSSCM
+
+def test_gsscm_reduces_to_second_moment_when_cutoffs_infinite():
+    rng = np.random.default_rng(2)
+    Z = rng.standard_normal((500, 4))
+    S = oracle.init_gsscm(Z, A=1e300, B=2e300)
+    ref = sum(np.outer(z, z) for z in Z) / 500.0
+    assert np.allclose(S, ref, rtol=1e-12, atol=1e-14)
+
+
+def test_gsscm_weight_function():
+    r = np.array([0.0, 1.0, 2.0, 2.5, 3.0, 3.5])
+    w = oracle.xi_lr(r, 2.0, 3.0)
+    assert list(w) == [1.0, 1.0, 1.0, 0.5, 0.0, 0.0]
+
+
+def test_gsscm_cutoffs_median():
+    r = np.array([1.0, 2.0, 4.0, 8.0, 3.0])
+    A, B = oracle.gsscm_cutoffs(r)
+    assert A == 3.0
+    s = sorted(x ** (2 / 3) for x in r)
+    med = s[2]
+    mad = sorted(abs(x - med) for x in s)[2]
+    assert B == pytest.approx((med + mad) ** 1.5, rel=1e-14)
+    assert B >= A
+
+
+def test_wrap_cov_is_classical_cov_of_wrapped():
+    rng = np.random.default_rng(4)
+    Z = rng.standard_normal((300, 3)) * 2
+    W = np.array([[float(oracle.wrap(np.array([v]))[0]) for v in row] for row in Z])
+    mu = W.mean(axis=0)
+    ref = sum(np.outer(w - mu, w - mu) for w in W) / 299.0
+    assert np.allclose(oracle.init_wrap_cov(Z), ref, rtol=1e-12, atol=1e-14)
+
+
+# ---------------------------------------------------------------- refinement
+
+def test_refinement_consistent_on_clean_gaussian():
+    ds = synthdata.small_gaussian(200_000, 4, seed=1, rho=0.6)
+    X = ds.X
+    loc = np.array([oracle.unimcd(X[:, j]).mu for j in range(4)])
+    sc = np.sqrt([oracle.unimcd(X[:, j]).var for j in range(4)])
+    Z = (X - loc) / sc
+    R = ds.cov          # unit diagonal: the standardised covariance is R
+    for S0 in (oracle.init_wrap_cov(Z), oracle.init_gsscm(Z)):
+        st = oracle.refine(S0, Z)
+        assert st.ok
+        assert np.max(np.abs(st.sigma - R)) < 0.03
+        assert np.max(np.abs(st.mu)) < 0.02
+
+
+def test_refinement_signed_permutation_equivariance():
+    rng = np.random.default_rng(8)
+    Z = rng.standard_normal((3000, 4)) @ np.array(
+        [[1, .3, 0, 0], [0, 1, .2, 0], [0, 0, 1, .5], [0, 0, 0, 1.]])
+    P = np.eye(4)[[2, 0, 3, 1]] * np.array([1, -1, 1, -1])[:, None]
+    a = oracle.refine(oracle.init_gsscm(Z), Z)
+    b = oracle.refine(oracle.init_gsscm(Z @ P.T), Z @ P.T)
+    assert np.allclose(b.sigma, P @ a.sigma @ P.T, rtol=1e-9, atol=1e-12)
+    assert np.allclose(b.mu, P @ a.mu, rtol=1e-9, atol=1e-12)
+
+
+def test_refinement_drops_ill_conditioned():
+    Z = np.random.default_rng(1).standard_normal((200, 3))
+    S = np.diag([1.0, 1.0, 1e-4])
+    assert not oracle.refine(S, Z).ok
+
+
+# ---------------------------------------------------------------- distances & C-steps
+
+def test_mahalanobis_matches_textbook_inverse():
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((50, 5))
+    A = rng.standard_normal((5, 5))
+    S = A @ A.T + 5 * np.eye(5)
+    mu = rng.standard_normal(5)
+    d2 = oracle.mahalanobis2(X, mu, np.linalg.cholesky(S))
+    Si = np.linalg.inv(S)
+    ref = np.array([(x - mu) @ Si @ (x - mu) for x in X])
+    assert np.allclose(d2, ref, rtol=1e-11)
+    L = np.linalg.cholesky(S)
+    assert 2 * np.sum(np.log(np.diag(L))) == pytest.approx(np.linalg.slogdet(S)[1], rel=1e-12)
+
+
+def test_select_ties_by_index():
+    d2 = np.array([3.0, 1.0, 1.0, 2.0, 1.0, 0.5])
+    assert list(oracle.select_h(d2, 2)) == [1, 5]
+    assert list(oracle.select_h(d2, 3)) == [1, 2, 5]
+    assert list(oracle.select_h(d2, 4)) == [1, 2, 4, 5]
+
+
+def _contaminated(n, p, seed, eps=0.2):
+    return synthdata.small_gaussian(n, p, seed=seed, rho=0.7, eps=eps, kind="shift", gamma=6).X
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_cstep_monotone_and_fixed_point(seed):
+    X = _contaminated(800, 4, seed)
+    h = 600
+    rng = np.random.default_rng(seed)
+    H0 = np.sort(rng.choice(800, h, replace=False))
+    mu0, S0 = oracle.subset_stats(X, H0)
+    r = oracle.csteps(X, h, mu0, S0)
+    assert r.status == oracle.ST_CONVERGED
+    # Proposition 1 of FastMCD: det non-increasing between subset covariances
+    assert all(b <= a + 1e-12 for a, b in zip(r.logdets, r.logdets[1:]))
+    # fixed point: one more C-step reproduces H
+    d2 = oracle.mahalanobis2(X, r.mu, np.linalg.cholesky(r.sigma))
+    assert np.array_equal(oracle.select_h(d2, h), r.H)
+    mu, S = oracle.subset_stats(X, r.H)
+    assert np.allclose(mu, r.mu) and np.allclose(S, r.sigma)
+
+
+def test_cstep_affine_equivariance():
+    X = _contaminated(600, 3, 5)
+    h = 400
+    H0 = np.arange(0, 600, 3)[:h] if 600 // 3 >= h else np.arange(h)
+    mu0, S0 = oracle.subset_stats(X, H0)
+    A = np.array([[2.0, 0.5, 0.0], [-1.0, 1.0, 0.3], [0.2, 0.0, 3.0]])
+    b = np.array([10.0, -5.0, 1.0])
+    r1 = oracle.csteps(X, h, mu0, S0)
+    r2 = oracle.csteps(X @ A.T + b, h, A @ mu0 + b, A @ S0 @ A.T)
+    assert np.array_equal(r1.H, r2.H)
+    assert r2.logdet == pytest.approx(r1.logdet + 2 * np.log(abs(np.linalg.det(A))), abs=1e-9)
+
+
+def test_update_form_equals_full_recompute():
+    X = _contaminated(500, 5, 2)
+    rng = np.random.default_rng(0)
+    H_old = np.sort(rng.choice(500, 300, replace=False))
+    H_new = np.sort(np.concatenate([H_old[30:], np.setdiff1d(np.arange(500), H_old)[:30]]))
+    mu_o, S_o = oracle.subset_stats(X, H_old)
+    mu_u, Lam_u = oracle.update_stats(X, H_old, H_new, mu_o, 299 * S_o)
+    mu_f, S_f = oracle.subset_stats(X, H_new)
+    assert np.allclose(mu_u, mu_f, rtol=1e-12, atol=1e-13)
+    assert np.allclose(Lam_u / 299, S_f, rtol=1e-11, atol=1e-13)
+
+
+def test_determinant_update_identity():
+    # det(Lambda + d u v^T) = (1 + d v^T Lambda^-1 u) det(Lambda)  (Sec. 3.5)
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((6, 6))
+    Lam = A @ A.T + np.eye(6)
+    u, v = rng.standard_normal(6), rng.standard_normal(6)
+    for d in (1, -1):
+        lhs = np.linalg.det(Lam + d * np.outer(u, v))
+        assert lhs == pytest.approx((1 + d * v @ np.linalg.solve(Lam, u)) * np.linalg.det(Lam), rel=1e-10)
+
+
+def test_kappa_threshold_stops_cstep():
+    X = _contaminated(400, 3, 1)
+    mu0 = X.mean(0)
+    S0 = np.diag([1.0, 1.0, 1e-5])        # condition 1e5 > 1000
+    r = oracle.csteps(X, 300, mu0, S0)
+    assert r.status == oracle.ST_DROP_FIRST
+
+
+# ---------------------------------------------------------------- exact MCD on tiny n
+
+@pytest.mark.parametrize("seed,p", [(0, 1), (1, 2), (2, 2)])
+def test_exact_mcd_enumeration(seed, p):
+    rng = np.random.default_rng(seed)
+    n, h = 12, 8 if p == 2 else 7
+    X = rng.standard_normal((n, p))
+    X[:3] += 6.0
+    best, bestH = math.inf, None
+    for H in itertools.combinations(range(n), h):
+        H = np.array(H)
+        _, S = oracle.subset_stats(X, H)
+        ld = float(np.linalg.slogdet(np.atleast_2d(S))[1])
+        if ld < best:
+            best, bestH = ld, H
+    # the global optimum is a C-step fixed point
+    mu, S = oracle.subset_stats(X, bestH)
+    r = oracle.csteps(X, h, mu, np.atleast_2d(S))
+    # (step 1 reproduces H from the start, step 2 confirms it)
+    assert np.array_equal(r.H, bestH) and r.iters == 2
+    # any C-step fixed point has log-det >= the optimum
+    H0 = np.arange(h)
+    mu0, S0 = oracle.subset_stats(X, H0)
+    r2 = oracle.csteps(X, h, mu0, np.atleast_2d(S0))
+    assert r2.logdet >= best - 1e-12
+
+
+# ---------------------------------------------------------------- aggregation
+
+def test_kl_nonnegative_zero_iff_equal():
+    rng = np.random.default_rng(6)
+    for _ in range(20):
+        A = rng.standard_normal((4, 4)); A = A @ A.T + 0.5 * np.eye(4)
+        B = rng.standard_normal((4, 4)); B = B @ B.T + 0.5 * np.eye(4)
+        a, b = rng.standard_normal(4), rng.standard_normal(4)
+        assert oracle.kl_deviation(a, A, b, B) > 0
+        assert oracle.kl_deviation(a, A, a, A) == pytest.approx(0.0, abs=1e-12)
+
+
+def test_kl_rank_key_orders_like_kl():
+    rng = np.random.default_rng(7)
+    Amed = np.eye(3) * 1.5
+    amed = np.zeros(3)
+    fits = []
+    for _ in range(12):
+        B = rng.standard_normal((3, 3)); B = B @ B.T + 0.3 * np.eye(3)
+        fits.append((rng.standard_normal(3), B))
+    kl = [oracle.kl_deviation(amed, Amed, b, B) for b, B in fits]
+    kp = [oracle.kl_rank_key(amed, Amed, b, B) for b, B in fits]
+    assert list(np.argsort(kl)) == list(np.argsort(kp))
+    c = -3 - np.linalg.slogdet(Amed)[1]
+    assert np.allclose(np.array(kp) + c, kl)
+
+
+def test_pooling_equals_direct_covariance_of_union():
+    rng = np.random.default_rng(1)
+    m, p = 40, 3
+    blocks = [rng.standard_normal((m, p)) + rng.standard_normal(p) for _ in range(5)]
+    mus = [b.mean(0) for b in blocks]
+    sig = [np.cov(b, rowvar=False) for b in blocks]
+    mu, S = oracle.pool_printed(mus, sig, m)
+    U = np.concatenate(blocks)
+    assert np.allclose(mu, U.mean(0), rtol=1e-12)
+    assert np.allclose(S, np.cov(U, rowvar=False), rtol=1e-11)
+    # unequal counts (step 9)
+    sizes = [5, 17, 1, 30]
+    bl = [rng.standard_normal((k, p)) for k in sizes]
+    lams = [(b - b.mean(0)).T @ (b - b.mean(0)) for b in bl]
+    mu2, Lam2, n2 = oracle.pool_counts([b.mean(0) for b in bl], lams, sizes)
+    U = np.concatenate(bl)
+    assert n2 == sum(sizes)
+    assert np.allclose(mu2, U.mean(0)) and np.allclose(Lam2 / (n2 - 1), np.cov(U, rowvar=False))
+
+
+def test_aggregate_single_block_is_identity():
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((3, 3)); A = A @ A.T + np.eye(3)
+    mu = rng.standard_normal(3)
+    m_, S_, keep, _ = oracle.aggregate([mu], [A], 100)
+    assert np.allclose(m_, mu) and np.allclose(S_, A) and list(keep) == [0]
+
+
+def test_aggregate_discards_far_blocks():
+    rng = np.random.default_rng(3)
+    good = [(0.01 * rng.standard_normal(2), np.eye(2) * (1 + 0.01 * rng.random())) for _ in range(5)]
+    bad = [(np.array([20.0, 20.0]), np.eye(2) * 50) for _ in range(3)]
+    fits = good + bad
+    _, _, keep, _ = oracle.aggregate([f[0] for f in fits], [f[1] for f in fits], 100)
+    assert len(keep) == 4 and all(k < 5 for k in keep)
+
+
+# ---------------------------------------------------------------- full fit
+
+def test_fit_single_chunk_flags_all_planted_outliers():
+    ds = synthdata.workload_single_chunk_f64(n=2000, p=5)
+    f = oracle.fit(ds.X)
+    out = np.zeros(len(ds.X), bool)
+    out[ds.outlier_rows] = True
+    assert f.outlier[out].all()
+    assert 0.005 < f.outlier[~out].mean() < 0.06
+    assert f.hsubset.shape == (1, 1500)
+    assert not np.isin(ds.outlier_rows, f.hsubset[0]).any()
+
+
+def test_fit_monomial_equivariance():
+    ds = synthdata.small_gaussian(3000, 4, seed=3, rho=0.5, eps=0.15, kind="cluster", gamma=7)
+    X = ds.X
+    perm = [2, 0, 3, 1]
+    s = np.array([2.0, 0.5, 3.0, 1.5])
+    b = np.array([1.0, -4.0, 0.0, 7.0])
+    Y = X[:, perm] * s + b
+    f1 = oracle.fit(X, n_chunks=2)
+    f2 = oracle.fit(Y, n_chunks=2)
+    assert np.array_equal(f1.hsubset, f2.hsubset)
+    assert np.array_equal(f1.outlier, f2.outlier)
+    assert np.allclose(f2.mu, f1.mu[perm] * s + b, rtol=1e-9, atol=1e-9)
+    assert np.allclose(f2.sigma, f1.sigma[np.ix_(perm, perm)] * np.outer(s, s), rtol=1e-9, atol=1e-12)
+    assert np.allclose(f1.dist, f2.dist, rtol=1e-9)
+
+
+def test_fit_multi_chunk_union_pooling_option():
+    ds = synthdata.small_gaussian(8000, 3, seed=4, rho=0.3, eps=0.1, kind="point", gamma=6)
+    a = oracle.fit(ds.X, n_chunks=4, pool="printed")
+    b = oracle.fit(ds.X, n_chunks=4, pool="union")
+    assert np.array_equal(a.hsubset, b.hsubset)
+    # both keep the point outliers out of the reweighted fit
+    out = np.zeros(len(ds.X), bool)
+    out[ds.outlier_rows] = True
+    assert a.outlier[out].all() and b.outlier[out].all()
+
+
+def test_fit_remainder_rows_scored():
+    ds = synthdata.small_gaussian(4003, 3, seed=5)
+    f = oracle.fit(ds.X, n_chunks=4)
+    assert f.m == 1000 and len(f.dist) == 4003
+    d2 = oracle.mahalanobis2((ds.X[-3:] - f.loc) / f.scale, f.diag["mu_rew_z"],
+                             np.linalg.cholesky(f.diag["sigma_rew_z"]))
+    assert np.allclose(f.dist[-3:] ** 2, d2)
+
+
+def test_refinement_location_translation_equivariance():
+    # mu_k(Z + b) = mu_k(Z) + b for a fixed initial scatter (Sec. 3.3 step 4)
+    rng = np.random.default_rng(12)
+    C = np.array([[1.0, 0.6, 0.1], [0.6, 2.0, -0.4], [0.1, -0.4, 0.7]])
+    Z = rng.standard_normal((4000, 3)) @ np.linalg.cholesky(C).T
+    S0 = oracle.init_gsscm(Z)
+    b = np.array([0.8, -1.5, 0.4])
+    a = oracle.refine(S0, Z)
+    c = oracle.refine(S0, Z + b)
+    assert np.allclose(c.mu, a.mu + b, rtol=0, atol=1e-9)
+    assert np.allclose(c.sigma, a.sigma, rtol=1e-9)
+
+
+def test_refinement_small_case_brute_force():
+    # Whole refinement on a tiny block with a brute-force univariate MCD.
+    rng = np.random.default_rng(13)
+    Z = rng.standard_normal((41, 2)) @ np.array([[1.0, 0.0], [0.7, 0.5]])
+    S0 = oracle.init_wrap_cov(Z)
+
+    def brute(x):
+        js, mean, var = _brute_unimcd(x)
+        n = len(x)
+        var_raw = var * oracle.consistency_factor((n // 2 + 1) / n, 1)
+        keep = [v for v in x if (v - mean) ** 2 <= oracle.chi2_quantile(0.975, 1) * var_raw]
+        return statistics.fmean(keep), statistics.variance(keep) * oracle.consistency_factor(0.975, 1)
+
+    lam, V = np.linalg.eigh(S0)
+    V = V[:, ::-1]
+    T = Z @ V
+    sig2 = np.array([brute(T[:, j])[1] for j in range(2)])
+    Sig = V @ np.diag(sig2) @ V.T
+    Zt = Z @ (V @ np.diag(sig2 ** -0.5) @ V.T)
+    mut = np.array([brute(Zt[:, j])[0] for j in range(2)])
+    mu = V @ np.diag(sig2 ** 0.5) @ V.T @ mut
+    st = oracle.refine(S0, Z)
+    assert np.allclose(st.sigma, Sig, rtol=1e-10) and np.allclose(st.mu, mu, rtol=1e-9, atol=1e-12)
+
+
+def test_aggregate_keeps_ceil_half_of_odd_count():
+    rng = np.random.default_rng(14)
+    fits = [(0.01 * rng.standard_normal(2), np.eye(2) * (1 + 0.01 * rng.random())) for _ in range(7)]
+    _, _, keep, _ = oracle.aggregate([f[0] for f in fits], [f[1] for f in fits], 50)
+    assert len(keep) == 4
+
+
+def test_fit_reweighting_set_by_textbook_distances():
+    ds = synthdata.small_gaussian(3000, 2, seed=6, rho=0.4, eps=0.1, kind="shift", gamma=5)
+    f = oracle.fit(ds.X)
+    Z = (ds.X - f.loc) / f.scale
+    Si = np.linalg.inv(f.diag["sigma_raw_z"])
+    D = Z - f.diag["mu_raw_z"]
+    d2 = np.einsum("ij,jk,ik->i", D, Si, D)
+    W = d2 <= -2.0 * math.log(0.025)          # chi2_{2,0.975} closed form
+    assert f.n_w == int(W.sum())
+    assert np.allclose(f.diag["mu_rew_z"], Z[W].mean(axis=0), rtol=1e-10)
+    Dw = Z[W] - Z[W].mean(axis=0)
+    assert np.allclose(f.diag["sigma_rew_z"], Dw.T @ Dw / (W.sum() - 1), rtol=1e-10)
+    # flags: final squared distance above the same cutoff
+    Si2 = np.linalg.inv(f.diag["sigma_rew_z"])
+    D2 = Z - f.diag["mu_rew_z"]
+    fl = np.einsum("ij,jk,ik->i", D2, Si2, D2) > -2.0 * math.log(0.025)
+    assert np.array_equal(fl.astype(np.uint8), f.outlier)
+
+
+def test_condition_check_in_standardised_units():
+    # The condition monitor of Sec. 3.4 acts on standardised data; raw units pass
+    # their column scales so that rescaling a column does not trip it.
+    X = _contaminated(500, 2, 3, eps=0.0)
+    s = np.array([1.0, 300.0])
+    H0 = np.arange(400)
+    mu0, S0 = oracle.subset_stats(X, H0)
+    Xs = X * s
+    r_scaled = oracle.csteps(Xs, 400, mu0 * s, S0 * np.outer(s, s), kappa_scale=s)
+    r_plain = oracle.csteps(X, 400, mu0, S0)
+    assert r_scaled.status == r_plain.status == oracle.ST_CONVERGED
+    assert np.array_equal(r_scaled.H, r_plain.H)
+    r_raw = oracle.csteps(Xs, 400, mu0 * s, S0 * np.outer(s, s))
+    assert r_raw.status == oracle.ST_DROP_FIRST
