@@ -1,0 +1,189 @@
+/*
+ * librtdetmcd -- RT-DetMCD (arXiv 1910.05615) on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Plain pointers and sizes only.  Unless stated otherwise every data
+ * pointer is a DEVICE pointer on the handle's device, owned by the caller, and
+ * every call is asynchronous on the handle's stream.  Matrices are row-major.
+ * Status codes are returned synchronously for argument errors; data-dependent
+ * outcomes are reported in device-side status arrays.  No C++ exception
+ * crosses this boundary.  One handle must not be used from two host threads at
+ * once.
+ *
+ * Method references:
+ *   Sec. 2.1   raw MCD (eq. mcdraw), statistical distance (eq. statdist),
+ *              C-step (eq. cstep1 .. cstep4b), reweighting and flagging
+ *   Sec. 3.1   univariate reweighted MCD standardisation
+ *   Sec. 3.2   wrapping (eq. wrapping) and GSSCM (eq. LR) initial estimators
+ *   Sec. 3.3   refinement of the initial estimators
+ *   Sec. 3.4   Cholesky distances and condition monitor (eq. choleskymonitor)
+ *   Sec. 3.5   update-based C-step (eq. propcstep1, muUpdate, propcstep2)
+ *   Sec. 4     blocks, entrywise median, KL deviation (eq. KL), pooling
+ *              (eq. covpool1, covpool2), distributed reweighting, flags
+ *   Sec. 5     block-count rule (eq. partitionsize)
+ */
+#ifndef RTDETMCD_H
+#define RTDETMCD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ codes */
+typedef int32_t rtdetmcd_status;
+#define RTDETMCD_OK            0
+#define RTDETMCD_EINVAL       -1   /* bad argument (sizes, h out of (p, m), null) */
+#define RTDETMCD_ENOMEM       -2   /* device allocation of the workspace failed */
+#define RTDETMCD_EDEVICE      -3   /* HIP runtime error (message in last_error) */
+#define RTDETMCD_ESINGULAR    -4   /* no block produced a valid fit */
+#define RTDETMCD_EUNSUPPORTED -6   /* p > RTDETMCD_MAX_P or unknown dtype */
+
+#define RTDETMCD_MAX_P 64
+
+/* data types of X */
+#define RTDETMCD_F32 0
+#define RTDETMCD_F64 1
+
+/* Per-start / per-block status values written to device arrays.  A block's
+ * status is that of its chosen start; RTDETMCD_BLOCK_INVALID marks a block
+ * whose two starts were both dropped (excluded from aggregation, Sec. 4 step 4). */
+#define RTDETMCD_ST_CONVERGED   0  /* h-subset repeated (Sec. 2.2 step 4) */
+#define RTDETMCD_ST_NOTCONV     1  /* max_csteps reached; fit still usable */
+#define RTDETMCD_ST_ILLCOND     2  /* next C-step refused by the condition monitor (Sec. 3.4) */
+#define RTDETMCD_ST_DROP_REFINE 3  /* start dropped in refinement (Sec. 3.3 step 2) */
+#define RTDETMCD_ST_DROP_FIRST  4  /* start refused before its first C-step */
+#define RTDETMCD_ST_SINGULAR    5  /* a subset covariance was not positive definite */
+#define RTDETMCD_BLOCK_INVALID  3
+
+/* option values */
+#define RTDETMCD_STD_UNIMCD 0   /* univariate reweighted MCD (Sec. 3.1) */
+#define RTDETMCD_STD_MEDMAD 1   /* median and 1.4826 MAD */
+#define RTDETMCD_CSTEP_FULL   0 /* recompute the subset mean / covariance (eq. cstep4a, cstep4b) */
+#define RTDETMCD_CSTEP_UPDATE 1 /* update from the swapped rows only (Sec. 3.5) */
+#define RTDETMCD_CSTEP_AUTO   2 /* update, with a full recompute when many rows swap */
+#define RTDETMCD_POOL_PRINTED 0 /* Sec. 4 step 7 formulas with block counts m */
+#define RTDETMCD_POOL_UNION   1 /* covariance of the union of the kept h-subsets */
+#define RTDETMCD_LAUNCH_BATCHED 0 /* every block and start in the same launches */
+#define RTDETMCD_LAUNCH_PLAIN   1 /* one block, one start at a time, host-driven */
+
+typedef struct rtdetmcd_opts {
+  int32_t struct_size;      /* sizeof(rtdetmcd_opts) */
+  double  alpha;            /* h = floor(alpha m) when h_sub == 0 (default 0.75) */
+  int32_t standardize;      /* RTDETMCD_STD_* (default UNIMCD) */
+  int32_t cstep_mode;       /* RTDETMCD_CSTEP_* (default AUTO) */
+  int32_t max_csteps;       /* default 100 */
+  double  kappa_max;        /* condition bound, default 1000 (Sec. 3.3, 3.4) */
+  double  cutoff_q;         /* chi-square quantile of the cutoff, default 0.975 */
+  int32_t pool_mode;        /* RTDETMCD_POOL_* (default PRINTED) */
+  int32_t rew_consistency;  /* 1: multiply the reweighted scatter by c(cutoff_q) (default 0) */
+  int32_t omega;            /* block-count rule bound (default 4096) */
+  int32_t launch;           /* RTDETMCD_LAUNCH_* (default BATCHED) */
+  int32_t graph;            /* 1: replay the C-step rounds from a captured hipGraph */
+  int32_t rounds_per_sync;  /* C-steps enqueued between host checks of convergence (default 4) */
+} rtdetmcd_opts;
+
+/* Output buffers of a fit.  Every field is a caller-allocated device buffer or
+ * NULL ("do not produce").  Sizes use q, m, h from rtdetmcd_plan.  Location and
+ * scatter are in the units of X. */
+typedef struct rtdetmcd_out {
+  double*  mu;            /* [p]   reweighted location (Sec. 4 step 9) */
+  double*  sigma;         /* [p*p] reweighted scatter */
+  double*  mu_raw;        /* [p]   aggregated raw location (Sec. 4 step 7) */
+  double*  sigma_raw;     /* [p*p] aggregated raw scatter */
+  double*  logdet;        /* [2]   log det of sigma_raw, sigma */
+  double*  dist;          /* [n]   final robust distances (Sec. 4 step 10) */
+  uint8_t* outlier;       /* [n]   1 iff squared distance > chi2_{p,cutoff_q} */
+  int32_t* hsubset;       /* [q*h] chosen h-subset of each block, ascending row indices of X */
+  int32_t* block_status;  /* [q]   RTDETMCD_ST_* of the chosen start, or BLOCK_INVALID */
+  int32_t* block_start;   /* [q]   0 = wrapping start, 1 = GSSCM start, -1 none */
+  int32_t* block_iters;   /* [q]   C-steps taken by the chosen start */
+  double*  loc;           /* [p]   standardisation location (Sec. 3.1) */
+  double*  scale;         /* [p]   standardisation scale */
+  int64_t* n_w;           /* [1]   rows kept by the reweighting */
+} rtdetmcd_out;
+
+typedef struct rtdetmcd_ctx* rtdetmcd_handle;
+
+/* Create a handle on `device` that enqueues on `hip_stream` (a hipStream_t;
+ * NULL = the null stream).  The handle owns a device workspace that grows on
+ * demand and is freed by rtdetmcd_destroy. */
+rtdetmcd_status rtdetmcd_create(rtdetmcd_handle* out, int32_t device, void* hip_stream);
+rtdetmcd_status rtdetmcd_destroy(rtdetmcd_handle h);
+rtdetmcd_status rtdetmcd_set_stream(rtdetmcd_handle h, void* hip_stream);
+/* Message of the last error on this handle (valid until the next call). */
+const char* rtdetmcd_last_error(rtdetmcd_handle h);
+/* Paper defaults (Sec. 2.1, 3.3, 3.4, 5). */
+void rtdetmcd_default_opts(rtdetmcd_opts* o);
+
+/* Block count q, block length m = floor(n/q) and subset size h of a fit
+ * (host-only).  n_chunks == 0 applies q = max(floor(n/(p omega)), 1)
+ * (eq. partitionsize); h_sub == 0 applies h = floor(alpha m) clamped into
+ * [(m+p+1)/2, m-1] (Sec. 2.1).  EINVAL unless p < h < m and n > 2p. */
+rtdetmcd_status rtdetmcd_plan(int64_t n, int32_t p, int64_t h_sub, int32_t n_chunks,
+                              const rtdetmcd_opts* o, int32_t* q, int64_t* m, int64_t* h);
+
+/* Full RT-DetMCD fit of X (n x p, row stride ld elements, dtype F32 or F64)
+ * (Sec. 4 steps 1-10; q = 1 is the serial version).  Blocks are the
+ * contiguous row ranges [l m, (l+1) m); the n - q m remainder rows are not
+ * fitted but are scored and flagged.  Synchronises the stream once at the end
+ * to read the validity of the blocks; returns ESINGULAR if none is valid. */
+rtdetmcd_status rtdetmcd_fit(rtdetmcd_handle h, const void* X, int32_t dtype, int64_t n,
+                             int32_t p, int64_t ld, int64_t h_sub, int32_t n_chunks,
+                             const rtdetmcd_opts* o, const rtdetmcd_out* out);
+
+/* Many independent datasets fitted in the same launches.  `sets` is a HOST
+ * array of n_datasets descriptors; each descriptor's X and out are device
+ * buffers as for rtdetmcd_fit.  status[i] (host) receives each dataset's code. */
+typedef struct rtdetmcd_dataset {
+  const void* X; int32_t dtype; int64_t n; int32_t p; int64_t ld;
+  int64_t h_sub; int32_t n_chunks; rtdetmcd_out out;
+} rtdetmcd_dataset;
+rtdetmcd_status rtdetmcd_fit_batched(rtdetmcd_handle h, int32_t n_datasets,
+                                     const rtdetmcd_dataset* sets, const rtdetmcd_opts* o,
+                                     rtdetmcd_status* status);
+
+/* ---- host-only distribution helpers (no device work) --------------------- */
+
+/* Quantile and CDF of the chi-square distribution with df degrees of freedom
+ * (regularised incomplete gamma by its power series / continued fraction;
+ * quantile by bisection), and the consistency factor
+ * c(alpha) = alpha / F_{chi2_{p+2}}(chi2_{p,alpha}) of the raw MCD scatter
+ * (Sec. 2.1, eq. mcdraw; the factor the paper cites without printing). */
+double rtdetmcd_chi2_quantile(double q, int32_t df);
+double rtdetmcd_chi2_cdf(double x, int32_t df);
+double rtdetmcd_consistency(double alpha, int32_t p);
+
+/* ---- low-level steps (parity tests and composition) ---------------------- */
+
+/* Squared statistical distances d2[i] = ||L^{-1}(x_i - mu)||^2 of the n rows
+ * of X, with L the lower Cholesky factor of Sigma (eq. statdist via Sec. 3.4).
+ * mu [p] and L [p*p, lower triangle read] are device float64. */
+rtdetmcd_status rtdetmcd_distances(rtdetmcd_handle h, const void* X, int32_t dtype, int64_t n,
+                                   int32_t p, int64_t ld, const double* mu, const double* L,
+                                   double* d2);
+
+/* Indices of the h_sub smallest d2 values, ties broken by the smaller index
+ * (C-step steps 2-3 of Sec. 2.1).  idx [h_sub] receives them ascending; mask
+ * [m] (nullable) receives 1 for selected rows and 0 otherwise.  Exact: the
+ * comparison is on the float64 bit patterns. */
+rtdetmcd_status rtdetmcd_select(rtdetmcd_handle h, const double* d2, int64_t m, int64_t h_sub,
+                                int32_t* idx, uint8_t* mask);
+
+/* C-steps on one block X (m x p) from the start (mu0, sigma0) until the
+ * h-subset repeats (Sec. 2.1, 3.4, 3.5).  kappa_scale [p] (nullable) gives the
+ * column scales by which sigma is divided before the condition check, so that
+ * the check acts in standardised units.  Outputs (device): mu [p], sigma [p*p]
+ * (subset covariance, divisor h-1), hsubset [h_sub] ascending, status [1],
+ * iters [1], logdet [1]. */
+rtdetmcd_status rtdetmcd_cstep(rtdetmcd_handle h, const void* X, int32_t dtype, int64_t m,
+                               int32_t p, int64_t ld, int64_t h_sub, const double* mu0,
+                               const double* sigma0, const double* kappa_scale,
+                               const rtdetmcd_opts* o, double* mu, double* sigma,
+                               int32_t* hsubset, int32_t* status, int32_t* iters,
+                               double* logdet);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTDETMCD_H */

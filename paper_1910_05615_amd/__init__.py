@@ -1,0 +1,7 @@
+"""librtdetmcd: RT-DetMCD (arXiv 1910.05615) with hand-written HIP kernels for MI355X.
+
+The compute path is the in-tree shared library ``librtdetmcd.so`` (C ABI in
+``include/rtdetmcd.h``); this package only marshals arguments to it.
+"""
+from .api import (RTDetMCDError, chi2_cdf, chi2_quantile, consistency, cstep,  # noqa: F401
+                  distances, make_opts, plan, select)

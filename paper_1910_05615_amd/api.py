@@ -1,0 +1,174 @@
+"""Python binding of librtdetmcd: argument marshalling only.
+
+Tensors live on the GPU; every step runs in the library's HIP kernels on the
+current torch stream.  The library must be built (``python -m
+paper_1910_05615_amd.build``); nothing here falls back to a CPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import _lib
+
+_handles = {}
+
+STD = {"unimcd": 0, "medmad": 1}
+CSTEP = {"full": 0, "update": 1, "auto": 2}
+POOL = {"printed": 0, "union": 1}
+LAUNCH = {"batched": 0, "plain": 1}
+
+
+class RTDetMCDError(RuntimeError):
+    pass
+
+
+def _handle(device: torch.device):
+    lib = _lib.load()
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    h = _handles.get(idx)
+    if h is None:
+        hv = C.c_void_p()
+        st = lib.rtdetmcd_create(C.byref(hv), idx, None)
+        if st != 0:
+            raise RTDetMCDError(f"rtdetmcd_create failed ({_lib.STATUS_NAMES.get(st, st)})")
+        h = hv.value
+        _handles[idx] = h
+    stream = torch.cuda.current_stream(device).cuda_stream
+    lib.rtdetmcd_set_stream(h, C.c_void_p(stream))
+    return lib, h
+
+
+def _check(lib, h, st, what):
+    if st != 0:
+        msg = lib.rtdetmcd_last_error(h)
+        raise RTDetMCDError(f"{what}: {_lib.STATUS_NAMES.get(st, st)}: "
+                            f"{msg.decode() if msg else ''}")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dtype_code(X: torch.Tensor) -> int:
+    if X.dtype == torch.float32:
+        return 0
+    if X.dtype == torch.float64:
+        return 1
+    raise TypeError("X must be float32 or float64")
+
+
+def _check_X(X: torch.Tensor):
+    if not X.is_cuda:
+        raise ValueError("X must be a CUDA (HIP) tensor")
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be 2-D with unit column stride")
+
+
+def make_opts(alpha: float = 0.75, standardize: str = "unimcd", cstep_mode: str = "auto",
+              max_csteps: int = 100, kappa_max: float = 1000.0, cutoff_q: float = 0.975,
+              pool: str = "printed", rew_consistency: bool = False, omega: int = 4096,
+              launch: str = "batched", graph: bool = False, rounds_per_sync: int = 4) -> _lib.Opts:
+    lib = _lib.load()
+    o = _lib.Opts()
+    lib.rtdetmcd_default_opts(C.byref(o))
+    o.alpha = alpha
+    o.standardize = STD[standardize]
+    o.cstep_mode = CSTEP[cstep_mode]
+    o.max_csteps = max_csteps
+    o.kappa_max = kappa_max
+    o.cutoff_q = cutoff_q
+    o.pool_mode = POOL[pool]
+    o.rew_consistency = int(rew_consistency)
+    o.omega = omega
+    o.launch = LAUNCH[launch]
+    o.graph = int(graph)
+    o.rounds_per_sync = rounds_per_sync
+    return o
+
+
+def plan(n: int, p: int, h_sub: int = 0, n_chunks: int = 0, **opts):
+    lib = _lib.load()
+    o = make_opts(**opts)
+    q, m, h = C.c_int32(), C.c_int64(), C.c_int64()
+    st = lib.rtdetmcd_plan(n, p, h_sub, n_chunks, C.byref(o), C.byref(q), C.byref(m), C.byref(h))
+    if st != 0:
+        raise RTDetMCDError(f"rtdetmcd_plan: {_lib.STATUS_NAMES.get(st, st)}")
+    return q.value, m.value, h.value
+
+
+def chi2_quantile(q: float, df: int) -> float:
+    return _lib.load().rtdetmcd_chi2_quantile(q, df)
+
+
+def chi2_cdf(x: float, df: int) -> float:
+    return _lib.load().rtdetmcd_chi2_cdf(x, df)
+
+
+def consistency(alpha: float, p: int) -> float:
+    return _lib.load().rtdetmcd_consistency(alpha, p)
+
+
+# ----------------------------------------------------------------- low-level steps
+
+def distances(X: torch.Tensor, mu: torch.Tensor, L: torch.Tensor) -> torch.Tensor:
+    """Squared distances ||L^{-1}(x_i - mu)||^2 of the rows of X (float64 output)."""
+    _check_X(X)
+    n, p = X.shape
+    lib, h = _handle(X.device)
+    mu = mu.to(device=X.device, dtype=torch.float64).contiguous()
+    L = L.to(device=X.device, dtype=torch.float64).contiguous()
+    d2 = torch.empty(n, dtype=torch.float64, device=X.device)
+    st = lib.rtdetmcd_distances(h, _ptr(X), _dtype_code(X), n, p, X.stride(0), _ptr(mu),
+                                _ptr(L), _ptr(d2))
+    _check(lib, h, st, "rtdetmcd_distances")
+    return d2
+
+
+def select(d2: torch.Tensor, h_sub: int):
+    """(ascending indices of the h_sub smallest d2, 0/1 mask); ties by index."""
+    d2 = d2.to(torch.float64).contiguous()
+    m = d2.numel()
+    lib, h = _handle(d2.device)
+    idx = torch.empty(h_sub, dtype=torch.int32, device=d2.device)
+    mask = torch.empty(m, dtype=torch.uint8, device=d2.device)
+    st = lib.rtdetmcd_select(h, _ptr(d2), m, h_sub, _ptr(idx), _ptr(mask))
+    _check(lib, h, st, "rtdetmcd_select")
+    return idx, mask
+
+
+@dataclasses.dataclass
+class CStepResult:
+    mu: torch.Tensor
+    sigma: torch.Tensor
+    hsubset: torch.Tensor
+    status: int
+    iters: int
+    logdet: float
+
+
+def cstep(X: torch.Tensor, h_sub: int, mu0: torch.Tensor, sigma0: torch.Tensor,
+          kappa_scale: Optional[torch.Tensor] = None, **opts) -> CStepResult:
+    """C-steps on one block from (mu0, sigma0) until the h-subset repeats."""
+    _check_X(X)
+    m, p = X.shape
+    lib, h = _handle(X.device)
+    o = make_opts(**opts)
+    dev = X.device
+    mu0 = mu0.to(device=dev, dtype=torch.float64).contiguous()
+    sigma0 = sigma0.to(device=dev, dtype=torch.float64).contiguous()
+    ks = None if kappa_scale is None else kappa_scale.to(device=dev, dtype=torch.float64).contiguous()
+    mu = torch.empty(p, dtype=torch.float64, device=dev)
+    sig = torch.empty(p, p, dtype=torch.float64, device=dev)
+    hs = torch.empty(h_sub, dtype=torch.int32, device=dev)
+    stt = torch.empty(1, dtype=torch.int32, device=dev)
+    its = torch.empty(1, dtype=torch.int32, device=dev)
+    ld = torch.empty(1, dtype=torch.float64, device=dev)
+    st = lib.rtdetmcd_cstep(h, _ptr(X), _dtype_code(X), m, p, X.stride(0), h_sub, _ptr(mu0),
+                            _ptr(sigma0), _ptr(ks), C.byref(o), _ptr(mu), _ptr(sig), _ptr(hs),
+                            _ptr(stt), _ptr(its), _ptr(ld))
+    _check(lib, h, st, "rtdetmcd_cstep")
+    return CStepResult(mu, sig, hs, int(stt.item()), int(its.item()), float(ld.item()))

@@ -1,0 +1,433 @@
+// C entry points of librtdetmcd: handle management, options, low-level steps
+// and the C-step loop driver.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "driver.h"
+
+namespace rtd {
+
+rtdetmcd_status ensure_ws(rtdetmcd_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->ws_size) return RTDETMCD_OK;
+  RTD_HIP(hipSetDevice(ctx->device));
+  if (ctx->ws) {
+    RTD_HIP(hipStreamSynchronize(ctx->stream));
+    RTD_HIP(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_size = 0;
+  }
+  const size_t want = bytes + bytes / 4 + (1u << 20);
+  if (hipMalloc(&ctx->ws, want) != hipSuccess) {
+    ctx->ws = nullptr;
+    ctx->err = "workspace allocation of " + std::to_string(want) + " bytes failed";
+    (void)hipGetLastError();
+    return RTDETMCD_ENOMEM;
+  }
+  ctx->ws_size = want;
+  return RTDETMCD_OK;
+}
+
+rtdetmcd_status Uploader::flush(rtdetmcd_ctx* ctx) {
+  if (ents.empty()) return RTDETMCD_OK;
+  if (ctx->pin_pending) {
+    RTD_HIP(hipEventSynchronize(ctx->pin_ev));
+    ctx->pin_pending = false;
+  }
+  if (buf.size() > ctx->pin_size) {
+    if (ctx->pin) RTD_HIP(hipHostFree(ctx->pin));
+    ctx->pin = nullptr;
+    const size_t want = buf.size() + (1u << 16);
+    RTD_HIP(hipHostMalloc(&ctx->pin, want, hipHostMallocDefault));
+    ctx->pin_size = want;
+  }
+  std::memcpy(ctx->pin, buf.data(), buf.size());
+  for (const E& e : ents)
+    if (e.bytes)
+      RTD_HIP(hipMemcpyAsync(e.dst, static_cast<char*>(ctx->pin) + e.off, e.bytes,
+                             hipMemcpyHostToDevice, ctx->stream));
+  RTD_HIP(hipEventRecord(ctx->pin_ev, ctx->stream));
+  ctx->pin_pending = true;
+  ents.clear();
+  buf.clear();
+  return RTDETMCD_OK;
+}
+
+void layout_items(Layout& L, const ItemSet& S, size_t off[20]) {
+  const size_t I = S.items.size();
+  off[0] = L.add(I * sizeof(ItemDesc));
+  off[1] = L.add(S.dtiles.size() * sizeof(Tile));
+  off[2] = L.add(S.stiles.size() * sizeof(Tile));
+  off[3] = L.add(I * 4);             // status
+  off[4] = L.add(I * 4);             // iter
+  off[5] = L.add(I * 4);             // kswap
+  off[6] = L.add(I * 4);             // full
+  off[7] = L.add(I * 8);             // logdet
+  off[8] = L.add(I * PMAX * 8);      // mux
+  off[9] = L.add(I * MSTRIDE * 8);   // lamx
+  off[10] = L.add(I * PMAX * 8);     // muz
+  off[11] = L.add(I * MSTRIDE * 8);  // sigz
+  off[12] = L.add(I * MSTRIDE * 8);  // linv
+  off[13] = L.add(I * TRI * 8);      // mtri
+  off[14] = L.add((size_t)S.rows * 8);   // d2
+  off[15] = L.add((size_t)S.rows);       // mask
+  off[16] = L.add((size_t)S.rows * 4);   // swap
+  off[17] = L.add(S.stiles.size() * PSTRIDE * 8);  // partials
+  off[18] = L.add(64);                   // nactive
+}
+
+void bind_items(char* base, const ItemSet& S, const size_t off[20], ItemDev& D) {
+  D.items = reinterpret_cast<ItemDesc*>(base + off[0]);
+  D.dtiles = reinterpret_cast<Tile*>(base + off[1]);
+  D.stiles = reinterpret_cast<Tile*>(base + off[2]);
+  ItemArrays& A = D.A;
+  A.status = reinterpret_cast<int32_t*>(base + off[3]);
+  A.iter = reinterpret_cast<int32_t*>(base + off[4]);
+  A.kswap = reinterpret_cast<int32_t*>(base + off[5]);
+  A.full = reinterpret_cast<int32_t*>(base + off[6]);
+  A.logdet = reinterpret_cast<double*>(base + off[7]);
+  A.mux = reinterpret_cast<double*>(base + off[8]);
+  A.lamx = reinterpret_cast<double*>(base + off[9]);
+  A.muz = reinterpret_cast<double*>(base + off[10]);
+  A.sigz = reinterpret_cast<double*>(base + off[11]);
+  A.linv = reinterpret_cast<double*>(base + off[12]);
+  A.mtri = reinterpret_cast<double*>(base + off[13]);
+  A.d2 = reinterpret_cast<double*>(base + off[14]);
+  A.mask = reinterpret_cast<uint8_t*>(base + off[15]);
+  A.swap = reinterpret_cast<int32_t*>(base + off[16]);
+  A.part = reinterpret_cast<double*>(base + off[17]);
+  A.nactive = reinterpret_cast<int32_t*>(base + off[18]);
+  (void)S;
+}
+
+rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int bucket,
+                           int dtype, int first, int n, const rtdetmcd_opts& o,
+                           int32_t* pin_flag) {
+  hipStream_t st = ctx->stream;
+  const int maxs = o.max_csteps;
+  if (o.launch == RTDETMCD_LAUNCH_BATCHED) {
+    // tiles of the items [first, first+n) are contiguous in both tables
+    const int dt0 = S.dt_first[first];
+    const int dtn = S.dt_first[first + n - 1] + S.dt_count[first + n - 1] - dt0;
+    const int st0 = S.items[first].tile0;
+    const int stn = S.items[first + n - 1].tile0 + S.items[first + n - 1].ntiles - st0;
+    RTD_HIP(launch_finalize(D.items, D.A, first, n, 1, maxs, o.kappa_max, SSCP_TILE, st));
+    const int R = std::max(1, o.rounds_per_sync);
+    for (int t = 1; t <= maxs; ++t) {
+      RTD_HIP(launch_fill_i32(D.A.nactive, 0, 1, st));
+      RTD_HIP(launch_dist(bucket, dtype, D.items, D.dtiles + dt0, dtn, DIST_TILE, D.A.mtri,
+                          D.A.mux, D.A.status, D.A.d2, st));
+      RTD_HIP(launch_select(D.items, D.A, first, n, o.cstep_mode, st));
+      RTD_HIP(launch_sscp(bucket, dtype, SSCP_CSTEP, D.items, D.A, D.stiles + st0, stn,
+                          SSCP_TILE, nullptr, 0, nullptr, st));
+      RTD_HIP(launch_finalize(D.items, D.A, first, n, 0, maxs, o.kappa_max, SSCP_TILE, st));
+      if (t % R == 0 || t == maxs) {
+        RTD_HIP(hipMemcpyAsync(pin_flag, D.A.nactive, 4, hipMemcpyDeviceToHost, st));
+        RTD_HIP(hipStreamSynchronize(st));
+        if (*pin_flag == 0) break;
+      }
+    }
+    return RTDETMCD_OK;
+  }
+  // plain: one item at a time, host-driven, one host check per step
+  for (int i = first; i < first + n; ++i) {
+    const ItemDesc& d = S.items[i];
+    RTD_HIP(launch_finalize(D.items, D.A, i, 1, 1, maxs, o.kappa_max, SSCP_TILE, st));
+    RTD_HIP(hipMemcpyAsync(pin_flag, D.A.status + i, 4, hipMemcpyDeviceToHost, st));
+    RTD_HIP(hipStreamSynchronize(st));
+    if (*pin_flag != ACTIVE) continue;
+    for (int t = 1; t <= maxs; ++t) {
+      RTD_HIP(launch_dist(bucket, dtype, D.items, D.dtiles + S.dt_first[i], S.dt_count[i],
+                          DIST_TILE, D.A.mtri, D.A.mux, D.A.status, D.A.d2, st));
+      RTD_HIP(launch_select(D.items, D.A, i, 1, o.cstep_mode, st));
+      RTD_HIP(launch_sscp(bucket, dtype, SSCP_CSTEP, D.items, D.A, D.stiles + d.tile0,
+                          d.ntiles, SSCP_TILE, nullptr, 0, nullptr, st));
+      RTD_HIP(launch_finalize(D.items, D.A, i, 1, 0, maxs, o.kappa_max, SSCP_TILE, st));
+      RTD_HIP(hipMemcpyAsync(pin_flag, D.A.status + i, 4, hipMemcpyDeviceToHost, st));
+      RTD_HIP(hipStreamSynchronize(st));
+      if (*pin_flag != ACTIVE) break;
+    }
+  }
+  return RTDETMCD_OK;
+}
+
+rtdetmcd_status check_opts(rtdetmcd_ctx* ctx, const rtdetmcd_opts* in, rtdetmcd_opts& o) {
+  rtdetmcd_default_opts(&o);
+  if (in) {
+    if (in->struct_size != (int32_t)sizeof(rtdetmcd_opts)) {
+      ctx->err = "rtdetmcd_opts.struct_size mismatch";
+      return RTDETMCD_EINVAL;
+    }
+    o = *in;
+  }
+  if (!(o.alpha > 0.5 && o.alpha <= 1.0) || o.max_csteps < 1 || !(o.kappa_max > 1.0) ||
+      !(o.cutoff_q > 0.0 && o.cutoff_q < 1.0) || o.omega < 1 || o.standardize < 0 ||
+      o.standardize > 1 || o.cstep_mode < 0 || o.cstep_mode > 2 || o.pool_mode < 0 ||
+      o.pool_mode > 1 || o.launch < 0 || o.launch > 1) {
+    ctx->err = "invalid option value";
+    return RTDETMCD_EINVAL;
+  }
+  return RTDETMCD_OK;
+}
+
+namespace {
+
+__global__ void k_cstep_init(const double* __restrict__ mu0, const double* __restrict__ s0,
+                             const double* __restrict__ sc, int p, double* __restrict__ muz,
+                             double* __restrict__ sigz, double* __restrict__ loc,
+                             double* __restrict__ scale) {
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    const double si = sc ? sc[i] : 1.0, sj = sc ? sc[j] : 1.0;
+    sigz[i * PMAX + j] = s0[i * p + j] / (si * sj);
+  }
+  for (int j = threadIdx.x; j < p; j += blockDim.x) {
+    const double s = sc ? sc[j] : 1.0;
+    muz[j] = mu0[j] / s;
+    loc[j] = 0.0;
+    scale[j] = s;
+  }
+}
+
+__global__ void k_cstep_out(const double* __restrict__ mux, const double* __restrict__ lamx,
+                            const double* __restrict__ scale, const int32_t* __restrict__ status,
+                            const int32_t* __restrict__ iter, const double* __restrict__ logdet,
+                            int p, double h, double* mu, double* sigma, int32_t* st,
+                            int32_t* its, double* ld) {
+  const int s = *status;
+  const bool ok = (s == ST_CONVERGED || s == ST_NOTCONV || s == ST_ILLCOND);
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    if (sigma) sigma[e] = ok ? lamx[i * PMAX + j] / (h - 1.0) : NAN;
+  }
+  for (int j = threadIdx.x; j < p; j += blockDim.x)
+    if (mu) mu[j] = ok ? mux[j] : NAN;
+  if (threadIdx.x == 0) {
+    if (st) *st = s;
+    if (its) *its = *iter;
+    if (ld) {
+      double a = *logdet;
+      for (int j = 0; j < p; ++j) a += 2.0 * log(scale[j]);
+      *ld = ok ? a : NAN;
+    }
+  }
+}
+
+__global__ void k_copy_pad(const double* __restrict__ src, int p, double* __restrict__ dst) {
+  for (int j = threadIdx.x; j < PMAX; j += blockDim.x) dst[j] = j < p ? src[j] : 0.0;
+}
+
+}  // namespace
+}  // namespace rtd
+
+using namespace rtd;
+
+extern "C" {
+
+void rtdetmcd_default_opts(rtdetmcd_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = (int32_t)sizeof(rtdetmcd_opts);
+  o->alpha = 0.75;
+  o->standardize = RTDETMCD_STD_UNIMCD;
+  o->cstep_mode = RTDETMCD_CSTEP_AUTO;
+  o->max_csteps = 100;
+  o->kappa_max = 1000.0;
+  o->cutoff_q = 0.975;
+  o->pool_mode = RTDETMCD_POOL_PRINTED;
+  o->rew_consistency = 0;
+  o->omega = 4096;
+  o->launch = RTDETMCD_LAUNCH_BATCHED;
+  o->graph = 0;
+  o->rounds_per_sync = 4;
+}
+
+rtdetmcd_status rtdetmcd_create(rtdetmcd_handle* out, int32_t device, void* hip_stream) {
+  if (!out) return RTDETMCD_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return RTDETMCD_EDEVICE;
+  rtdetmcd_ctx* c = new rtdetmcd_ctx();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipSetDevice(device) != hipSuccess ||
+      hipEventCreateWithFlags(&c->pin_ev, hipEventDisableTiming) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->flag), 256, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return RTDETMCD_EDEVICE;
+  }
+  *out = c;
+  return RTDETMCD_OK;
+}
+
+rtdetmcd_status rtdetmcd_destroy(rtdetmcd_handle ctx) {
+  if (!ctx) return RTDETMCD_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->pin) (void)hipHostFree(ctx->pin);
+  if (ctx->pin_ev) (void)hipEventDestroy(ctx->pin_ev);
+  if (ctx->flag) (void)hipHostFree(ctx->flag);
+  delete ctx;
+  return RTDETMCD_OK;
+}
+
+rtdetmcd_status rtdetmcd_set_stream(rtdetmcd_handle ctx, void* hip_stream) {
+  if (!ctx) return RTDETMCD_EINVAL;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return RTDETMCD_OK;
+}
+
+const char* rtdetmcd_last_error(rtdetmcd_handle ctx) { return ctx ? ctx->err.c_str() : "null handle"; }
+
+double rtdetmcd_chi2_quantile(double q, int32_t df) { return rtd::chi2_quantile(q, df); }
+double rtdetmcd_chi2_cdf(double x, int32_t df) { return rtd::chi2_cdf(x, df); }
+double rtdetmcd_consistency(double alpha, int32_t p) { return rtd::consistency(alpha, p); }
+
+rtdetmcd_status rtdetmcd_plan(int64_t n, int32_t p, int64_t h_sub, int32_t n_chunks,
+                              const rtdetmcd_opts* o_in, int32_t* q, int64_t* m, int64_t* h) {
+  rtdetmcd_opts o;
+  rtdetmcd_default_opts(&o);
+  if (o_in) o = *o_in;
+  if (p < 1 || n <= 2 * (int64_t)p || n_chunks < 0 || h_sub < 0) return RTDETMCD_EINVAL;
+  if (p > RTDETMCD_MAX_P) return RTDETMCD_EUNSUPPORTED;
+  int64_t qq = n_chunks > 0 ? n_chunks : std::max<int64_t>(n / ((int64_t)p * o.omega), 1);
+  if (qq > n) return RTDETMCD_EINVAL;
+  const int64_t mm = n / qq;
+  int64_t hh = h_sub;
+  if (hh == 0) {
+    hh = (int64_t)std::floor(o.alpha * (double)mm);
+    hh = std::max<int64_t>(hh, (mm + p + 1) / 2);
+    hh = std::min<int64_t>(hh, mm - 1);
+  }
+  if (!(hh > p && hh < mm)) return RTDETMCD_EINVAL;
+  if (mm > INT32_MAX) return RTDETMCD_EUNSUPPORTED;
+  if (q) *q = (int32_t)qq;
+  if (m) *m = mm;
+  if (h) *h = hh;
+  return RTDETMCD_OK;
+}
+
+rtdetmcd_status rtdetmcd_distances(rtdetmcd_handle ctx, const void* X, int32_t dtype, int64_t n,
+                                   int32_t p, int64_t ld, const double* mu, const double* L,
+                                   double* d2) {
+  if (!ctx) return RTDETMCD_EINVAL;
+  if (!X || !mu || !L || !d2 || n < 0 || p < 1 || ld < p || (dtype != 0 && dtype != 1)) {
+    ctx->err = "rtdetmcd_distances: bad argument";
+    return RTDETMCD_EINVAL;
+  }
+  if (p > RTDETMCD_MAX_P) return RTDETMCD_EUNSUPPORTED;
+  if (n == 0) return RTDETMCD_OK;
+  RTD_HIP(hipSetDevice(ctx->device));
+  ItemSet S;
+  ItemDesc d{};
+  d.X = X; d.ld = ld; d.row0 = 0; d.m = n; d.h = 0; d.p = p; d.dtype = dtype; d.start = -1;
+  S.add(d);
+  Layout L0;
+  size_t off[20];
+  layout_items(L0, S, off);
+  // only items, tiles, mux and mtri are used
+  RTD_TRY(ensure_ws(ctx, L0.off));
+  ItemDev D;
+  bind_items(static_cast<char*>(ctx->ws), S, off, D);
+  Uploader up;
+  up.add(D.items, S.items.data(), S.items.size());
+  up.add(D.dtiles, S.dtiles.data(), S.dtiles.size());
+  RTD_TRY(up.flush(ctx));
+  hipLaunchKernelGGL(k_copy_pad, dim3(1), dim3(64), 0, ctx->stream, mu, p, D.A.mux);
+  RTD_HIP(hipGetLastError());
+  RTD_HIP(launch_chol_factor(L, p, D.A.mtri, ctx->stream));
+  // the distance kernel writes d2 + roff with roff = 0
+  RTD_HIP(launch_dist(bucket_of(p), dtype, D.items, D.dtiles, (int)S.dtiles.size(), DIST_TILE,
+                      D.A.mtri, D.A.mux, nullptr, d2, ctx->stream));
+  return RTDETMCD_OK;
+}
+
+rtdetmcd_status rtdetmcd_select(rtdetmcd_handle ctx, const double* d2, int64_t m, int64_t h_sub,
+                                int32_t* idx, uint8_t* mask) {
+  if (!ctx) return RTDETMCD_EINVAL;
+  if (!d2 || !idx || m < 1 || h_sub < 1 || h_sub > m || m > INT32_MAX) {
+    ctx->err = "rtdetmcd_select: bad argument";
+    return RTDETMCD_EINVAL;
+  }
+  RTD_HIP(hipSetDevice(ctx->device));
+  ItemSet S;
+  ItemDesc d{};
+  d.m = m; d.h = h_sub; d.p = 1; d.start = -1;
+  S.add(d);
+  Layout L0;
+  size_t off[20];
+  layout_items(L0, S, off);
+  RTD_TRY(ensure_ws(ctx, L0.off));
+  ItemDev D;
+  bind_items(static_cast<char*>(ctx->ws), S, off, D);
+  Uploader up;
+  up.add(D.items, S.items.data(), 1);
+  RTD_TRY(up.flush(ctx));
+  hipStream_t st = ctx->stream;
+  ItemArrays A = D.A;
+  A.d2 = const_cast<double*>(d2);
+  RTD_HIP(launch_fill_i32(A.status, ACTIVE, 1, st));
+  RTD_HIP(launch_fill_i32(A.iter, 0, 1, st));
+  RTD_HIP(launch_fill_u8(A.mask, 0, m, st));
+  RTD_HIP(launch_select(D.items, A, 0, 1, RTDETMCD_CSTEP_FULL, st));
+  RTD_HIP(launch_extract_subset(D.items, A, 0, 1, idx, h_sub, 0, st));
+  if (mask) RTD_HIP(hipMemcpyAsync(mask, A.mask, (size_t)m, hipMemcpyDeviceToDevice, st));
+  return RTDETMCD_OK;
+}
+
+rtdetmcd_status rtdetmcd_cstep(rtdetmcd_handle ctx, const void* X, int32_t dtype, int64_t m,
+                               int32_t p, int64_t ld, int64_t h_sub, const double* mu0,
+                               const double* sigma0, const double* kappa_scale,
+                               const rtdetmcd_opts* o_in, double* mu, double* sigma,
+                               int32_t* hsubset, int32_t* status, int32_t* iters,
+                               double* logdet) {
+  if (!ctx) return RTDETMCD_EINVAL;
+  rtdetmcd_opts o;
+  RTD_TRY(check_opts(ctx, o_in, o));
+  if (!X || !mu0 || !sigma0 || p < 1 || ld < p || !(h_sub > p && h_sub < m) ||
+      m > INT32_MAX || (dtype != 0 && dtype != 1)) {
+    ctx->err = "rtdetmcd_cstep: bad argument (need p < h < m)";
+    return RTDETMCD_EINVAL;
+  }
+  if (p > RTDETMCD_MAX_P) return RTDETMCD_EUNSUPPORTED;
+  RTD_HIP(hipSetDevice(ctx->device));
+  ItemSet S;
+  ItemDesc d{};
+  d.X = X; d.ld = ld; d.row0 = 0; d.m = m; d.h = h_sub; d.p = p; d.dtype = dtype; d.start = -1;
+  S.add(d);
+  Layout L0;
+  size_t off[20];
+  layout_items(L0, S, off);
+  const size_t o_loc = L0.add(PMAX * 8), o_scale = L0.add(PMAX * 8), o_flag = L0.add(64);
+  RTD_TRY(ensure_ws(ctx, L0.off));
+  char* base = static_cast<char*>(ctx->ws);
+  ItemDev D;
+  bind_items(base, S, off, D);
+  double* loc = reinterpret_cast<double*>(base + o_loc);
+  double* scale = reinterpret_cast<double*>(base + o_scale);
+  (void)o_flag;
+  S.items[0].loc = loc;
+  S.items[0].scale = scale;
+  Uploader up;
+  up.add(D.items, S.items.data(), 1);
+  up.add(D.dtiles, S.dtiles.data(), S.dtiles.size());
+  up.add(D.stiles, S.stiles.data(), S.stiles.size());
+  RTD_TRY(up.flush(ctx));
+  hipStream_t st = ctx->stream;
+  hipLaunchKernelGGL(k_cstep_init, dim3(1), dim3(256), 0, st, mu0, sigma0, kappa_scale, p,
+                     D.A.muz, D.A.sigz, loc, scale);
+  RTD_HIP(hipGetLastError());
+  RTD_HIP(launch_fill_i32(D.A.status, ACTIVE, 1, st));
+  RTD_HIP(launch_fill_i32(D.A.iter, 0, 1, st));
+  RTD_HIP(launch_fill_u8(D.A.mask, 0, m, st));
+  RTD_TRY(run_csteps(ctx, S, D, bucket_of(p), dtype, 0, 1, o, ctx->flag));
+  hipLaunchKernelGGL(k_cstep_out, dim3(1), dim3(256), 0, st, D.A.mux, D.A.lamx, scale,
+                     D.A.status, D.A.iter, D.A.logdet, p, (double)h_sub, mu, sigma, status,
+                     iters, logdet);
+  RTD_HIP(hipGetLastError());
+  if (hsubset) RTD_HIP(launch_extract_subset(D.items, D.A, 0, 1, hsubset, h_sub, 0, st));
+  return RTDETMCD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+// Internal declarations shared by the librtdetmcd HIP sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace rtd {
+
+constexpr int PMAX = 64;                 // largest supported p
+constexpr int MSTRIDE = PMAX * PMAX;     // per-item stride of p x p matrices
+constexpr int TRI = PMAX * (PMAX + 1) / 2;  // packed lower triangle
+constexpr int ACTIVE = -1;               // item still iterating
+
+// Status values (same numbering as the public header).
+constexpr int ST_CONVERGED = 0, ST_NOTCONV = 1, ST_ILLCOND = 2, ST_DROP_REFINE = 3,
+              ST_DROP_FIRST = 4, ST_SINGULAR = 5;
+
+// One C-step work item: a (dataset, block, start) triple, or a plain row set
+// (reweighting, final scoring, low-level calls) with start = -1.
+struct ItemDesc {
+  const void* X;     // dataset base (device), row-major
+  int64_t ld;        // row stride in elements
+  int64_t row0;      // first dataset row of the block
+  int64_t m;         // rows of the block
+  int64_t h;         // subset size
+  int64_t roff;      // offset of this item's rows in the per-row work arrays
+  const double* loc;    // [p] standardisation location of the dataset
+  const double* scale;  // [p] standardisation scale of the dataset
+  int32_t p;
+  int32_t dtype;     // 0 = f32, 1 = f64
+  int32_t ds;        // dataset index
+  int32_t blk;       // block index within the dataset
+  int32_t start;     // 0 = wrapping start, 1 = GSSCM start, -1 = none
+  int32_t tile0;     // first tile of this item in the SSCP tile table
+  int32_t ntiles;    // number of SSCP tiles of this item
+  int32_t pad;
+};
+
+// Per-item state (device arrays, item-major).
+struct ItemArrays {
+  int32_t* status;   // [I] ACTIVE or a terminal status
+  int32_t* iter;     // [I] C-steps evaluated
+  int32_t* kswap;    // [I] rows that entered the subset in the last step
+  int32_t* full;     // [I] 1: next statistics are recomputed in full
+  double* logdet;    // [I] log det of the current scatter (standardised units)
+  double* mux;       // [I*PMAX] current mean, data units
+  double* lamx;      // [I*MSTRIDE] sscp about mux, data units
+  double* muz;       // [I*PMAX] current mean, standardised units
+  double* sigz;      // [I*MSTRIDE] current covariance, standardised units
+  double* linv;      // [I*MSTRIDE] inverse Cholesky factor of sigz
+  double* mtri;      // [I*TRI] packed L^{-1} D^{-1}: distances in data units
+  double* d2;        // [rows] squared distances
+  uint8_t* mask;     // [rows] current subset
+  int32_t* swap;     // [rows] entering rows from 0, leaving rows from m/2
+  double* part;      // [tiles * PSTRIDE] SSCP tile partials
+  int32_t* nactive;  // [1] items still active after the last finalize
+};
+
+constexpr int PSTRIDE = 1 + PMAX + TRI;  // count, sum, packed sscp
+
+// Row-source modes of the SSCP kernel.
+enum SscpMode : int {
+  SSCP_CSTEP = 0,    // subset rows (full) or swapped rows (update), about mux
+  SSCP_D2CUT = 1,    // rows with d2 <= cut, about the given pivot (reweighting)
+  SSCP_WRAP = 2,     // all rows, wrapped standardised values, about 0
+  SSCP_GSSCM = 3,    // all rows, standardised values weighted by xi^2(||z||)
+};
+
+struct Tile {
+  int32_t item;
+  int32_t t;         // tile index within the item
+};
+
+inline int bucket_of(int p) {
+  if (p <= 4) return 4;
+  if (p <= 5) return 5;
+  if (p <= 8) return 8;
+  if (p <= 10) return 10;
+  if (p <= 16) return 16;
+  if (p <= 20) return 20;
+  if (p <= 24) return 24;
+  if (p <= 32) return 32;
+  if (p <= 40) return 40;
+  if (p <= 48) return 48;
+  return 64;
+}
+
+// Launch helpers implemented in the .hip files (all enqueue on `s`).
+hipError_t launch_dist(int bucket, int dtype, const ItemDesc* items, const Tile* tiles, int ntiles,
+                       int tile_rows, const double* mtri, const double* mux, const int32_t* status,
+                       double* d2, hipStream_t s);
+hipError_t launch_select(const ItemDesc* items, ItemArrays A, int first_item, int nitems,
+                         int cstep_mode, hipStream_t s);
+hipError_t launch_sscp(int bucket, int dtype, int mode, const ItemDesc* items, ItemArrays A,
+                       const Tile* tiles, int ntiles, int tile_rows, const double* pivot,
+                       int pivot_stride, const double* cut, hipStream_t s);
+hipError_t launch_finalize(const ItemDesc* items, ItemArrays A, int first_item, int nitems,
+                           int from_start, int max_csteps, double kappa_max, int tile_rows,
+                           hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
+hipError_t launch_chol_factor(const double* sigma, int p, double* mtri, hipStream_t s);
+hipError_t launch_extract_subset(const ItemDesc* items, ItemArrays A, int first_item, int nitems,
+                                 int32_t* out, int64_t out_stride, int global_rows,
+                                 hipStream_t s);
+hipError_t launch_select_plain(const double* d2, int64_t m, int64_t h, int32_t* idx,
+                               uint8_t* mask, hipStream_t s);
+
+}  // namespace rtd

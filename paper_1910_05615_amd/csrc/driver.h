@@ -1,0 +1,101 @@
+// Host driver pieces shared by the C entry points: workspace layout, uploads
+// through pinned staging, item tables and the C-step loop.
+#pragma once
+
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rtdetmcd.h"
+#include "host_util.h"
+
+namespace rtd {
+
+constexpr int DIST_TILE = 2048;   // rows per block of the distance kernel
+constexpr int SSCP_TILE = 4096;   // candidate rows per block of the sscp kernel
+
+#define RTD_HIP(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);                \
+      return RTDETMCD_EDEVICE;                                                     \
+    }                                                                              \
+  } while (0)
+
+#define RTD_TRY(expr)                     \
+  do {                                    \
+    rtdetmcd_status s_ = (expr);          \
+    if (s_ != RTDETMCD_OK) return s_;     \
+  } while (0)
+
+struct Layout {
+  size_t off = 0;
+  size_t add(size_t bytes) {
+    const size_t o = (off + 255) & ~(size_t)255;
+    off = o + (bytes ? bytes : 1);
+    return o;
+  }
+};
+
+rtdetmcd_status ensure_ws(rtdetmcd_ctx* ctx, size_t bytes);
+
+// Collects host->device copies and issues them from pinned staging.
+struct Uploader {
+  struct E { void* dst; size_t off; size_t bytes; };
+  std::vector<E> ents;
+  std::vector<char> buf;
+  template <typename T>
+  void add(void* dst, const T* src, size_t n) {
+    const size_t bytes = n * sizeof(T);
+    const size_t off = (buf.size() + 15) & ~(size_t)15;
+    buf.resize(off + bytes);
+    if (bytes) std::memcpy(buf.data() + off, src, bytes);
+    ents.push_back({dst, off, bytes});
+  }
+  rtdetmcd_status flush(rtdetmcd_ctx* ctx);
+};
+
+// Items of one C-step run plus their tile tables (host copies kept for
+// per-item launches).
+struct ItemSet {
+  std::vector<ItemDesc> items;
+  std::vector<Tile> dtiles, stiles;
+  std::vector<int> dt_first, dt_count;   // per item, into dtiles
+  int64_t rows = 0;                      // sum of m
+  void add(const ItemDesc& d) {
+    ItemDesc e = d;
+    e.roff = rows;
+    e.tile0 = (int)stiles.size();
+    const int ns = (int)((e.m + SSCP_TILE - 1) / SSCP_TILE);
+    e.ntiles = ns < 1 ? 1 : ns;
+    for (int t = 0; t < e.ntiles; ++t) stiles.push_back({(int)items.size(), t});
+    dt_first.push_back((int)dtiles.size());
+    const int nd = (int)((e.m + DIST_TILE - 1) / DIST_TILE);
+    for (int t = 0; t < nd; ++t) dtiles.push_back({(int)items.size(), t});
+    dt_count.push_back(nd);
+    rows += e.m;
+    items.push_back(e);
+  }
+};
+
+// Device copies of an ItemSet and its state arrays inside the workspace.
+struct ItemDev {
+  ItemDesc* items = nullptr;
+  Tile* dtiles = nullptr;
+  Tile* stiles = nullptr;
+  ItemArrays A{};
+};
+
+void layout_items(Layout& L, const ItemSet& S, size_t off[20]);
+void bind_items(char* base, const ItemSet& S, const size_t off[20], ItemDev& D);
+
+// Enqueue the C-step loop for items [first, first+n) of a bucket/dtype class.
+// Batched: all items in each launch, host checks convergence every
+// rounds_per_sync steps.  Plain: one item at a time, host check every step.
+rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int bucket, int dtype,
+                           int first, int n, const rtdetmcd_opts& o, int32_t* pin_flag);
+
+rtdetmcd_status check_opts(rtdetmcd_ctx* ctx, const rtdetmcd_opts* in, rtdetmcd_opts& o);
+
+}  // namespace rtd

@@ -1,0 +1,85 @@
+// Host-side helpers of librtdetmcd: chi-square distribution, consistency
+// factor, the block-count and subset-size rules, and the handle/workspace.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace rtd {
+
+// Regularised lower incomplete gamma P(a, x): power series for x < a + 1,
+// otherwise 1 - Q with Q from the Legendre continued fraction evaluated by the
+// modified Lentz method (the classical series / continued-fraction pair).
+inline double gamma_p(double a, double x) {
+  if (x <= 0.0) return 0.0;
+  const double lg = std::lgamma(a);
+  if (x < a + 1.0) {
+    double ap = a, sum = 1.0 / a, del = sum;
+    for (int n = 0; n < 10000; ++n) {
+      ap += 1.0;
+      del *= x / ap;
+      sum += del;
+      if (std::fabs(del) < std::fabs(sum) * 1e-17) break;
+    }
+    return sum * std::exp(-x + a * std::log(x) - lg);
+  }
+  const double tiny = 1e-300;
+  double b = x + 1.0 - a, c = 1.0 / tiny, d = 1.0 / b, hh = d;
+  for (int i = 1; i < 10000; ++i) {
+    const double an = -i * (i - a);
+    b += 2.0;
+    d = an * d + b;
+    if (std::fabs(d) < tiny) d = tiny;
+    c = b + an / c;
+    if (std::fabs(c) < tiny) c = tiny;
+    d = 1.0 / d;
+    const double del = d * c;
+    hh *= del;
+    if (std::fabs(del - 1.0) < 1e-17) break;
+  }
+  return 1.0 - std::exp(-x + a * std::log(x) - lg) * hh;
+}
+
+inline double chi2_cdf(double x, double df) { return gamma_p(0.5 * df, 0.5 * x); }
+
+// Quantile by bracketing and bisection to the last bit.
+inline double chi2_quantile(double q, double df) {
+  if (q <= 0.0) return 0.0;
+  double lo = 0.0, hi = df + 10.0;
+  while (chi2_cdf(hi, df) < q) hi *= 2.0;
+  for (int i = 0; i < 2000; ++i) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (chi2_cdf(mid, df) < q) lo = mid;
+    else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Gaussian consistency factor of the raw MCD scatter at coverage alpha
+// (Sec. 2.1): alpha / F_{chi2_{p+2}}(chi2_{p,alpha}).
+inline double consistency(double alpha, int p) {
+  if (alpha >= 1.0) return 1.0;
+  return alpha / chi2_cdf(chi2_quantile(alpha, p), p + 2);
+}
+
+}  // namespace rtd
+
+struct rtdetmcd_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  void* ws = nullptr;          // device workspace (grow only)
+  size_t ws_size = 0;
+  void* pin = nullptr;         // pinned host staging (grow only)
+  size_t pin_size = 0;
+  hipEvent_t pin_ev = nullptr; // last upload out of the staging buffer
+  bool pin_pending = false;
+  int32_t* flag = nullptr;     // pinned readback word
+};

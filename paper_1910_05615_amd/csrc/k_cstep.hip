@@ -1,0 +1,421 @@
+// Per-item kernels of the C-step loop: exact h-subset selection, and the
+// float64 statistics / Cholesky / condition-monitor step.
+#include "common.h"
+
+namespace rtd {
+
+namespace {
+
+// d2 >= 0, so the IEEE bit pattern orders like the value.  NaN sorts last.
+__device__ inline uint64_t key_of(double v) {
+  if (!(v == v)) return ~0ull;
+  if (v <= 0.0) return 0ull;     // also maps -0.0 to +0.0
+  return (uint64_t)__double_as_longlong(v);
+}
+
+// Block-wide exclusive scan of one int per thread (blockDim = NT, NT/64 waves).
+template <int NT>
+__device__ inline int block_excl_scan(int v, int* wtot, int& total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int x = v;
+  // inclusive wave scan
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wtot[wv] = x;
+  __syncthreads();
+  int off = 0;
+  total = 0;
+#pragma unroll
+  for (int k = 0; k < NT / 64; ++k) {
+    const int t = wtot[k];
+    if (k < wv) off += t;
+    total += t;
+  }
+  __syncthreads();
+  return off + x - v;
+}
+
+// ---------------------------------------------------------------------------
+// h-subset selection (Sec. 2.1 C-step steps 2-3) by radix select on the
+// float64 bit patterns, digits 12/13/13/13/13 bits from the top, then one pass
+// in row order that resolves ties by index and records the swapped rows for
+// the update-based step (Sec. 3.5).
+// ---------------------------------------------------------------------------
+constexpr int SEL_NT = 1024;
+
+__global__ __launch_bounds__(SEL_NT) void k_select(const ItemDesc* __restrict__ items,
+                                                   ItemArrays A, int first_item,
+                                                   int cstep_mode) {
+  __shared__ unsigned hist[8192];
+  __shared__ int wtot[3][SEL_NT / 64];
+  __shared__ int s_bin, s_cnt;
+  __shared__ long long s_below;
+  const int it = first_item + blockIdx.x;
+  if (A.status[it] != ACTIVE) return;
+  const ItemDesc D = items[it];
+  const int64_t m = D.m, h = D.h;
+  const double* __restrict__ d2 = A.d2 + D.roff;
+  uint8_t* __restrict__ mask = A.mask + D.roff;
+  int32_t* __restrict__ swp = A.swap + D.roff;
+  const int tid = threadIdx.x;
+
+  const int shifts[5] = {52, 39, 26, 13, 0};
+  const int bitsv[5] = {12, 13, 13, 13, 13};
+  uint64_t prefix = 0, pmask = 0;
+  int64_t rank = h;   // 1-based rank of the threshold key among candidates
+  bool take_all = false;
+#pragma unroll
+  for (int ps = 0; ps < 5; ++ps) {
+    const int shift = shifts[ps], bits = bitsv[ps];
+    const int nbins = 1 << bits;
+    for (int b = tid; b < nbins; b += SEL_NT) hist[b] = 0u;
+    __syncthreads();
+    for (int64_t i = tid; i < m; i += SEL_NT) {
+      const uint64_t k = key_of(d2[i]);
+      if ((k & pmask) == prefix) atomicAdd(&hist[(k >> shift) & (uint64_t)(nbins - 1)], 1u);
+    }
+    __syncthreads();
+    // locate the bin that holds the rank-th candidate
+    const int per = nbins / SEL_NT;   // 4 or 8 bins per thread
+    int loc = 0;
+    for (int b = 0; b < per; ++b) loc += (int)hist[tid * per + b];
+    int tot;
+    const int before = block_excl_scan<SEL_NT>(loc, wtot[0], tot);
+    if ((int64_t)before < rank && rank <= (int64_t)(before + loc)) {
+      int64_t run = before;
+      for (int b = 0; b < per; ++b) {
+        const int c = (int)hist[tid * per + b];
+        if (rank <= run + c) { s_bin = tid * per + b; s_cnt = c; s_below = run; break; }
+        run += c;
+      }
+    }
+    __syncthreads();
+    prefix |= (uint64_t)s_bin << shift;
+    pmask |= (uint64_t)(nbins - 1) << shift;
+    rank -= s_below;
+    const int cnt = s_cnt;
+    __syncthreads();
+    if ((int64_t)cnt == rank) { take_all = true; break; }
+  }
+
+  // final pass in row order
+  const int it0 = A.iter[it];
+  const bool first = (it0 == 0);
+  int64_t tie_seen = 0, nin = 0, nout = 0;
+  const int64_t half = m / 2;
+  for (int64_t base = 0; base < m; base += SEL_NT) {
+    const int64_t i = base + tid;
+    const bool valid = i < m;
+    const uint64_t k = valid ? key_of(d2[i]) : ~0ull;
+    bool sel;
+    int eq = 0;
+    if (take_all) {
+      sel = valid && ((k & pmask) <= prefix);
+    } else {
+      eq = (valid && k == prefix) ? 1 : 0;
+      sel = valid && k < prefix;
+    }
+    int tot_eq;
+    const int eq_before = block_excl_scan<SEL_NT>(eq, wtot[0], tot_eq);
+    if (!take_all && eq && (tie_seen + eq_before) < rank) sel = true;
+    tie_seen += tot_eq;
+    const int old = valid ? (int)mask[i] : 0;
+    const int ent = (sel && !old) ? 1 : 0;
+    const int lft = (valid && !sel && old) ? 1 : 0;
+    int tot_in, tot_out;
+    const int pin = block_excl_scan<SEL_NT>(ent, wtot[1], tot_in);
+    const int pout = block_excl_scan<SEL_NT>(lft, wtot[2], tot_out);
+    if (!first) {
+      if (ent) swp[nin + pin] = (int32_t)i;
+      if (lft) swp[half + nout + pout] = (int32_t)i;
+    }
+    if (valid) mask[i] = sel ? 1 : 0;
+    nin += tot_in;
+    nout += tot_out;
+  }
+  if (tid == 0) {
+    const int itn = it0 + 1;
+    A.iter[it] = itn;
+    A.kswap[it] = first ? 0 : (int32_t)nin;
+    int full;
+    if (first || cstep_mode == 0) full = 1;
+    else if (cstep_mode == 1) full = 0;
+    else full = (8 * nin > h) ? 1 : 0;
+    A.full[it] = full;
+    if (!first && nin == 0) A.status[it] = ST_CONVERGED;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Statistics and Cholesky step of one item (Sec. 2.1 eq. cstep4a/cstep4b,
+// Sec. 3.4, Sec. 3.5), all in float64:
+//   * from the sscp tile partials, mean and sscp about the new mean, either
+//     recomputed (full) or updated from the swapped rows:
+//       mu_new = c + s/h,  Lambda_new = Lambda_old + S - s s^T / h
+//     with c = mu_old the pivot of the partial sums (Lambda_old = 0 when full);
+//   * Sigma = D^{-1} Lambda D^{-1} / (h-1) in standardised units, its Cholesky
+//     factor, log det, inverse factor and exact 1-norm condition number;
+//   * M = L^{-1} D^{-1} packed for the distance kernel.
+// from_start: (muz, sigz) already hold the start; nothing is reduced.
+// ---------------------------------------------------------------------------
+constexpr int FIN_NT = 256;
+
+__global__ __launch_bounds__(FIN_NT) void k_finalize(const ItemDesc* __restrict__ items,
+                                                     ItemArrays A, int first_item, int from_start,
+                                                     int max_csteps, double kappa_max,
+                                                     int tile_rows) {
+  __shared__ double Sg[PMAX * PMAX];   // Sigma (standardised), then L in the lower triangle
+  __shared__ double Li[PMAX * PMAX];   // L^{-1}
+  __shared__ double sv[PMAX + 1];
+  __shared__ double cs[2][PMAX];
+  __shared__ int fail;
+  const int it = first_item + blockIdx.x;
+  if (A.status[it] != ACTIVE) return;
+  const ItemDesc D = items[it];
+  const int p = D.p;
+  const int tid = threadIdx.x;
+  const double h = (double)D.h;
+  double* __restrict__ mux = A.mux + (size_t)it * PMAX;
+  double* __restrict__ lam = A.lamx + (size_t)it * MSTRIDE;
+  double* __restrict__ muz = A.muz + (size_t)it * PMAX;
+  double* __restrict__ sigz = A.sigz + (size_t)it * MSTRIDE;
+
+  if (!from_start) {
+    const int full = A.full[it];
+    const int64_t nsrc = full ? D.m : 2 * (int64_t)A.kswap[it];
+    int ntv = (int)((nsrc + tile_rows - 1) / tile_rows);
+    if (ntv < 1) ntv = 1;
+    // count and sum vector
+    for (int e = tid; e <= p; e += FIN_NT) {
+      const int idx = (e == 0) ? 0 : e;
+      double s = 0.0;
+      for (int t = 0; t < ntv; ++t) s += A.part[(size_t)(D.tile0 + t) * PSTRIDE + idx];
+      sv[e] = s;
+    }
+    __syncthreads();
+    // mean update (sv[1..p] is the pivot-centred sum)
+    for (int j = tid; j < p; j += FIN_NT) cs[0][j] = sv[1 + j] / h;   // mu_new - c
+    __syncthreads();
+    for (int e = tid; e < p * p; e += FIN_NT) {
+      const int i = e / p, j = e % p;
+      const int a = i >= j ? i : j, b = i >= j ? j : i;
+      double s = 0.0;
+      for (int t = 0; t < ntv; ++t)
+        s += A.part[(size_t)(D.tile0 + t) * PSTRIDE + 1 + PMAX + a * (a + 1) / 2 + b];
+      const double old = full ? 0.0 : lam[i * PMAX + j];
+      const double v = old + s - h * cs[0][i] * cs[0][j];
+      lam[i * PMAX + j] = v;
+      Sg[i * PMAX + j] = v / (D.scale[i] * D.scale[j]) / (h - 1.0);
+    }
+    __syncthreads();
+    for (int j = tid; j < p; j += FIN_NT) {
+      const double mnew = mux[j] + cs[0][j];
+      mux[j] = mnew;
+      muz[j] = (mnew - D.loc[j]) / D.scale[j];
+    }
+  } else {
+    for (int e = tid; e < p * p; e += FIN_NT) {
+      const int i = e / p, j = e % p;
+      Sg[i * PMAX + j] = 0.5 * (sigz[i * PMAX + j] + sigz[j * PMAX + i]);
+    }
+    for (int j = tid; j < p; j += FIN_NT) mux[j] = D.loc[j] + D.scale[j] * muz[j];
+  }
+  __syncthreads();
+  for (int e = tid; e < p * p; e += FIN_NT) {
+    const int i = e / p, j = e % p;
+    sigz[i * PMAX + j] = Sg[i * PMAX + j];
+  }
+  // column 1-norms of Sigma
+  for (int j = tid; j < p; j += FIN_NT) {
+    double s = 0.0;
+    for (int i = 0; i < p; ++i) s += fabs(Sg[i * PMAX + j]);
+    cs[0][j] = s;
+  }
+  if (tid == 0) fail = 0;
+  __syncthreads();
+  // Cholesky (right-looking, in place in the lower triangle)
+  for (int k = 0; k < p; ++k) {
+    if (tid == 0) {
+      const double d = Sg[k * PMAX + k];
+      if (!(d > 0.0) || !(d < 1e300)) fail = 1;
+      else Sg[k * PMAX + k] = sqrt(d);
+    }
+    __syncthreads();
+    if (fail) break;
+    const double lkk = Sg[k * PMAX + k];
+    for (int i = k + 1 + tid; i < p; i += FIN_NT) Sg[i * PMAX + k] /= lkk;
+    __syncthreads();
+    const int n = p - k - 1;
+    for (int e = tid; e < n * n; e += FIN_NT) {
+      const int i = k + 1 + e / n, j = k + 1 + e % n;
+      if (j <= i) Sg[i * PMAX + j] -= Sg[i * PMAX + k] * Sg[j * PMAX + k];
+    }
+    __syncthreads();
+  }
+  if (fail) {
+    if (tid == 0) A.status[it] = from_start ? ST_DROP_FIRST : ST_SINGULAR;
+    return;
+  }
+  // inverse factor, one column per thread
+  for (int j = tid; j < p; j += FIN_NT) {
+    for (int i = 0; i < j; ++i) Li[i * PMAX + j] = 0.0;
+    Li[j * PMAX + j] = 1.0 / Sg[j * PMAX + j];
+    for (int i = j + 1; i < p; ++i) {
+      double s = 0.0;
+      for (int k = j; k < i; ++k) s = fma(Sg[i * PMAX + k], Li[k * PMAX + j], s);
+      Li[i * PMAX + j] = -s / Sg[i * PMAX + i];
+    }
+  }
+  __syncthreads();
+  // column 1-norms of Sigma^{-1} = L^{-T} L^{-1}
+  for (int j = tid; j < p; j += FIN_NT) {
+    double s = 0.0;
+    for (int i = 0; i < p; ++i) {
+      const int k0 = i > j ? i : j;
+      double v = 0.0;
+      for (int k = k0; k < p; ++k) v = fma(Li[k * PMAX + i], Li[k * PMAX + j], v);
+      s += fabs(v);
+    }
+    cs[1][j] = s;
+  }
+  __syncthreads();
+  double* __restrict__ linv = A.linv + (size_t)it * MSTRIDE;
+  double* __restrict__ mt = A.mtri + (size_t)it * TRI;
+  for (int e = tid; e < TRI; e += FIN_NT) {
+    int i = 0, k = e;
+    while (k > i) { k -= i + 1; ++i; }
+    const int j = k;
+    mt[e] = (i < p && j < p) ? Li[i * PMAX + j] / D.scale[j] : 0.0;
+  }
+  for (int e = tid; e < p * p; e += FIN_NT) {
+    const int i = e / p, j = e % p;
+    linv[i * PMAX + j] = Li[i * PMAX + j];
+  }
+  if (tid == 0) {
+    double ld = 0.0, n1 = 0.0, n2 = 0.0;
+    for (int j = 0; j < p; ++j) {
+      ld += log(Sg[j * PMAX + j]);
+      n1 = fmax(n1, cs[0][j]);
+      n2 = fmax(n2, cs[1][j]);
+    }
+    A.logdet[it] = 2.0 * ld;
+    const double kap = n1 * n2;
+    int st = ACTIVE;
+    if (from_start) {
+      if (!(kap < kappa_max)) st = ST_DROP_FIRST;
+    } else if (A.iter[it] >= max_csteps) {
+      st = ST_NOTCONV;
+    } else if (!(kap < kappa_max)) {
+      st = ST_ILLCOND;
+    }
+    A.status[it] = st;
+    if (st == ACTIVE && A.nactive) atomicAdd(A.nactive, 1);
+  }
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_u8(uint8_t* p, uint8_t v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Packed inverse of a given lower Cholesky factor (for the low-level distance call).
+__global__ void k_chol_factor(const double* __restrict__ L, int p, double* __restrict__ mt) {
+  __shared__ double Li[PMAX * PMAX];
+  const int tid = threadIdx.x;
+  for (int j = tid; j < p; j += blockDim.x) {
+    for (int i = 0; i < j; ++i) Li[i * PMAX + j] = 0.0;
+    Li[j * PMAX + j] = 1.0 / L[j * p + j];
+    for (int i = j + 1; i < p; ++i) {
+      double s = 0.0;
+      for (int k = j; k < i; ++k) s = fma(L[i * p + k], Li[k * PMAX + j], s);
+      Li[i * PMAX + j] = -s / L[i * p + i];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < TRI; e += blockDim.x) {
+    int i = 0, k = e;
+    while (k > i) { k -= i + 1; ++i; }
+    mt[e] = (i < p && k < p) ? Li[i * PMAX + k] : 0.0;
+  }
+}
+
+// Ascending row indices of each item's subset (offset by row0 when global_rows).
+__global__ __launch_bounds__(1024) void k_extract_subset(const ItemDesc* __restrict__ items,
+                                                         ItemArrays A, int first_item,
+                                                         int32_t* __restrict__ out,
+                                                         int64_t out_stride, int global_rows) {
+  __shared__ int wtot[16];
+  const int it = first_item + blockIdx.x;
+  const ItemDesc D = items[it];
+  const uint8_t* __restrict__ mask = A.mask + D.roff;
+  int32_t* __restrict__ o = out + (size_t)blockIdx.x * out_stride;
+  int64_t n = 0;
+  for (int64_t base = 0; base < D.m; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const int f = (i < D.m && mask[i]) ? 1 : 0;
+    int tot;
+    const int pos = block_excl_scan<1024>(f, wtot, tot);
+    if (f && n + pos < D.h) o[n + pos] = (int32_t)(global_rows ? D.row0 + i : i);
+    n += tot;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_select(const ItemDesc* items, ItemArrays A, int first_item, int nitems,
+                         int cstep_mode, hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_select, dim3(nitems), dim3(SEL_NT), 0, s, items, A, first_item,
+                     cstep_mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const ItemDesc* items, ItemArrays A, int first_item, int nitems,
+                           int from_start, int max_csteps, double kappa_max, int tile_rows,
+                           hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize, dim3(nitems), dim3(FIN_NT), 0, s, items, A, first_item,
+                     from_start, max_csteps, kappa_max, tile_rows);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t nb = (n + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)nb), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t nb = (n + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)nb), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_chol_factor(const double* L, int p, double* mtri, hipStream_t s) {
+  hipLaunchKernelGGL(k_chol_factor, dim3(1), dim3(64), 0, s, L, p, mtri);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract_subset(const ItemDesc* items, ItemArrays A, int first_item, int nitems,
+                                 int32_t* out, int64_t out_stride, int global_rows,
+                                 hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_extract_subset, dim3(nitems), dim3(1024), 0, s, items, A, first_item,
+                     out, out_stride, global_rows);
+  return hipGetLastError();
+}
+
+}  // namespace rtd

@@ -1,0 +1,350 @@
+// Row-streaming kernels: statistical distances and weighted sscp partial sums.
+//
+// Both read the rows of X exactly once per launch and compute in float64;
+// float32 inputs are widened exactly.  Each kernel is instantiated per
+// p-bucket P (p <= P, the padding contributes exact zeros).
+#include "common.h"
+
+namespace rtd {
+
+namespace {
+
+template <typename T>
+__device__ inline double ld_elem(const T* __restrict__ p, int64_t i) {
+  return static_cast<double>(p[i]);
+}
+
+// Wrapping transform g of Sec. 3.2 (eq. wrapping) with the paper's defaults.
+__device__ inline double wrap_g(double z) {
+  const double b = 1.5, c = 4.0, q1 = 1.541, q2 = 0.862;
+  const double a = fabs(z);
+  if (a <= b) return z;
+  if (a <= c) return copysign(q1 * tanh(q2 * (c - a)), z);
+  return 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Distances (Sec. 3.4): d2 = ||M (x - mu)||^2 with M = L^{-1} D^{-1} packed
+// lower-triangular, so that the standardisation is folded into M and mu.
+// One thread per row; M and mu are uniform per block and are read through the
+// scalar cache.
+// ---------------------------------------------------------------------------
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_dist(const ItemDesc* __restrict__ items,
+                                              const Tile* __restrict__ tiles, int tile_rows,
+                                              const double* __restrict__ mtri,
+                                              const double* __restrict__ mux,
+                                              const int32_t* __restrict__ status,
+                                              double* __restrict__ d2) {
+  const Tile tl = tiles[blockIdx.x];
+  const int it = tl.item;
+  if (status != nullptr && status[it] != ACTIVE) return;
+  const ItemDesc D = items[it];
+  const int p = D.p;
+  const double* __restrict__ M = mtri + (size_t)it * TRI;
+  const double* __restrict__ mu = mux + (size_t)it * PMAX;
+  const T* __restrict__ X = static_cast<const T*>(D.X) + D.row0 * D.ld;
+  const int64_t r0 = (int64_t)tl.t * tile_rows;
+  const int64_t r1 = min(r0 + (int64_t)tile_rows, D.m);
+  double* __restrict__ out = d2 + D.roff;
+  double muv[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) muv[j] = mu[j];
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+    const T* __restrict__ xr = X + r * D.ld;
+    double z[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) z[j] = (j < p) ? ld_elem(xr, j) - muv[j] : 0.0;
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      double y = 0.0;
+#pragma unroll
+      for (int j = 0; j <= i; ++j) y = fma(M[i * (i + 1) / 2 + j], z[j], y);
+      acc = fma(y, y, acc);
+    }
+    out[r] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weighted sscp partial sums over one tile of candidate rows:
+//   count = sum w,  s = sum w v,  S = sum w v v^T (lower triangle)
+// where v is the row value of the mode (see SscpMode) and w its weight.
+// Selected rows are compacted into LDS in batches and the lower triangle is
+// accumulated in 4x4 register blocks; every reduction has a fixed order, so
+// results do not depend on scheduling.
+// ---------------------------------------------------------------------------
+template <int P>
+struct SscpShape {
+  static constexpr int NB = (P + 3) / 4;              // 4-wide column blocks
+  static constexpr int NBLK = NB * (NB + 1) / 2;      // lower blocks
+  static constexpr int NRL = 256 / NBLK;              // row lanes
+  static constexpr int BR = P <= 24 ? 256 : (P <= 40 ? 128 : 64);   // rows per batch
+  static constexpr int PP = NB * 4 + 1;               // padded LDS row pitch (doubles)
+  static constexpr int XS = BR * PP;
+  static constexpr int RED = NRL * NBLK * 16;
+  static constexpr int LDSD = XS > RED ? XS : RED;
+  static constexpr int NRR = 256 / P;                 // row lanes of the sum vector
+};
+
+template <typename T, int P, int MODE>
+__global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items, ItemArrays A,
+                                              const Tile* __restrict__ tiles, int tile_rows,
+                                              const double* __restrict__ pivot, int pivot_stride,
+                                              const double* __restrict__ cut) {
+  using S = SscpShape<P>;
+  __shared__ double lds[S::LDSD];
+  __shared__ double wsh[S::BR];
+  __shared__ int64_t rsh[S::BR];
+  __shared__ int wcount[4];
+  __shared__ double sred[256];
+
+  const Tile tl = tiles[blockIdx.x];
+  const int it = tl.item;
+  const ItemDesc D = items[it];
+  const int p = D.p;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+
+  bool list_mode = false;
+  int64_t nsrc = D.m;
+  int kin = 0;
+  if (MODE == SSCP_CSTEP) {
+    if (A.status[it] != ACTIVE) return;
+    if (!A.full[it]) {
+      list_mode = true;
+      kin = A.kswap[it];
+      nsrc = 2 * (int64_t)kin;
+    }
+  }
+  const int64_t s0 = (int64_t)tl.t * tile_rows;
+  if (s0 >= nsrc && !(s0 == 0)) return;   // tile beyond the update list: no partial
+  const int64_t s1 = min(s0 + (int64_t)tile_rows, nsrc);
+
+  double c[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    double v = 0.0;
+    if (j < p) {
+      if (MODE == SSCP_CSTEP) v = A.mux[(size_t)it * PMAX + j];
+      else if (MODE == SSCP_D2CUT) v = pivot[(size_t)D.ds * pivot_stride + j];
+    }
+    c[j] = v;
+  }
+  double gA = 0.0, gB = 0.0, dcut = 0.0;
+  if (MODE == SSCP_GSSCM) { gA = cut[2 * it]; gB = cut[2 * it + 1]; }
+  if (MODE == SSCP_D2CUT) dcut = cut[D.ds];
+
+  const T* __restrict__ X = static_cast<const T*>(D.X) + D.row0 * D.ld;
+
+  // block accumulators
+  const int blk = tid % S::NBLK;
+  const int rl = tid / S::NBLK;
+  int bi = 0, bj = 0;
+  {
+    int k = blk;
+    while (k > bi) { k -= bi + 1; ++bi; }
+    bj = k;
+  }
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  const int sj = tid % P, srr = tid / P;
+  double sacc = 0.0, wacc = 0.0;
+
+  for (int64_t base = s0; base < s1; base += S::BR) {
+    // 1. evaluate candidates and compact the selected rows (order preserving)
+    int64_t row = -1;
+    double w = 0.0;
+    const int64_t cand = base + tid;
+    if (tid < S::BR && cand < s1) {
+      if (MODE == SSCP_CSTEP) {
+        if (list_mode) {
+          const int64_t half = D.m / 2;
+          if (cand < kin) { row = A.swap[D.roff + cand]; w = 1.0; }
+          else { row = A.swap[D.roff + half + (cand - kin)]; w = -1.0; }
+        } else if (A.mask[D.roff + cand]) {
+          row = cand; w = 1.0;
+        }
+      } else if (MODE == SSCP_D2CUT) {
+        if (A.d2[D.roff + cand] <= dcut) { row = cand; w = 1.0; }
+      } else if (MODE == SSCP_WRAP) {
+        row = cand; w = 1.0;
+      } else {  // GSSCM: weight xi^2(||z||) of eq. (LR)
+        const T* xr = X + cand * D.ld;
+        double r2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+          if (j < p) {
+            const double z = (ld_elem(xr, j) - D.loc[j]) / D.scale[j];
+            r2 = fma(z, z, r2);
+          }
+        const double r = sqrt(r2);
+        double xi;
+        if (gB <= gA) xi = (r <= gA) ? 1.0 : 0.0;
+        else xi = (r <= gA) ? 1.0 : ((r <= gB) ? (gB - r) / (gB - gA) : 0.0);
+        row = cand; w = xi * xi;
+      }
+    }
+    const bool sel = row >= 0 && w != 0.0;
+    const uint64_t bal = __ballot(sel);
+    const int pos_w = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wcount[wv] = __popcll(bal);
+    __syncthreads();
+    int off = 0, nb = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (k < wv) off += wcount[k];
+      nb += wcount[k];
+    }
+    if (sel) { rsh[off + pos_w] = row; wsh[off + pos_w] = w; }
+    __syncthreads();
+    // 2. load the selected rows, transformed, into LDS
+    for (int e = tid; e < nb * P; e += 256) {
+      const int r = e / P, j = e - r * P;
+      double v = 0.0;
+      if (j < p) {
+        const double x = ld_elem(X + rsh[r] * D.ld, j);
+        if (MODE == SSCP_WRAP) v = wrap_g((x - D.loc[j]) / D.scale[j]);
+        else if (MODE == SSCP_GSSCM) v = (x - D.loc[j]) / D.scale[j];
+        else v = x - c[j];
+      }
+      lds[r * S::PP + j] = v;
+    }
+    for (int e = tid; e < nb * (S::PP - P); e += 256) {
+      const int r = e / (S::PP - P), j = P + e % (S::PP - P);
+      lds[r * S::PP + j] = 0.0;
+    }
+    __syncthreads();
+    // 3. accumulate the lower-triangular 4x4 blocks
+    if (rl < S::NRL) {
+      for (int r = rl; r < nb; r += S::NRL) {
+        const double* xr = lds + r * S::PP;
+        const double wr = wsh[r];
+        double a[4], b[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { a[k] = wr * xr[4 * bi + k]; b[k] = xr[4 * bj + k]; }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+      }
+    }
+    if (srr < S::NRR) {
+      for (int r = srr; r < nb; r += S::NRR) {
+        sacc = fma(wsh[r], lds[r * S::PP + sj], sacc);
+        if (sj == 0) wacc += wsh[r];
+      }
+    }
+    __syncthreads();
+  }
+
+  // 4. fixed-order reductions and the tile partial
+  double* __restrict__ part = A.part + (size_t)(D.tile0 + tl.t) * PSTRIDE;
+  if (rl < S::NRL) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) lds[(rl * S::NBLK + blk) * 16 + u * 4 + v] = acc[u][v];
+  }
+  sred[tid] = (srr < S::NRR) ? sacc : 0.0;
+  __syncthreads();
+  for (int o = tid; o < S::NBLK * 16; o += 256) {
+    const int b = o / 16, e = o % 16;
+    double s = 0.0;
+    for (int k = 0; k < S::NRL; ++k) s += lds[(k * S::NBLK + b) * 16 + e];
+    int bi2 = 0, k2 = b;
+    while (k2 > bi2) { k2 -= bi2 + 1; ++bi2; }
+    const int i = 4 * bi2 + e / 4, j = 4 * k2 + e % 4;
+    if (i < p && j <= i) part[1 + PMAX + i * (i + 1) / 2 + j] = s;
+  }
+  if (tid < P && tid < p) {
+    double s = 0.0;
+    for (int k = 0; k < S::NRR; ++k) s += sred[k * P + tid];
+    part[1 + tid] = s;
+  }
+  __syncthreads();
+  sred[tid] = (sj == 0 && srr < S::NRR) ? wacc : 0.0;
+  __syncthreads();
+  if (tid == 0) {
+    double s = 0.0;
+    for (int k = 0; k < S::NRR; ++k) s += sred[k * P];
+    part[0] = s;
+  }
+}
+
+template <typename T, int P>
+hipError_t dist_t(const ItemDesc* items, const Tile* tiles, int ntiles, int tile_rows,
+                  const double* mtri, const double* mux, const int32_t* status, double* d2,
+                  hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_dist<T, P>), dim3(ntiles), dim3(256), 0, s, items, tiles, tile_rows,
+                     mtri, mux, status, d2);
+  return hipGetLastError();
+}
+
+template <typename T, int P>
+hipError_t sscp_t(int mode, const ItemDesc* items, ItemArrays A, const Tile* tiles, int ntiles,
+                  int tile_rows, const double* pivot, int pivot_stride, const double* cut,
+                  hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  switch (mode) {
+    case SSCP_CSTEP:
+      hipLaunchKernelGGL((k_sscp<T, P, SSCP_CSTEP>), dim3(ntiles), dim3(256), 0, s, items, A,
+                         tiles, tile_rows, pivot, pivot_stride, cut);
+      break;
+    case SSCP_D2CUT:
+      hipLaunchKernelGGL((k_sscp<T, P, SSCP_D2CUT>), dim3(ntiles), dim3(256), 0, s, items, A,
+                         tiles, tile_rows, pivot, pivot_stride, cut);
+      break;
+    case SSCP_WRAP:
+      hipLaunchKernelGGL((k_sscp<T, P, SSCP_WRAP>), dim3(ntiles), dim3(256), 0, s, items, A,
+                         tiles, tile_rows, pivot, pivot_stride, cut);
+      break;
+    default:
+      hipLaunchKernelGGL((k_sscp<T, P, SSCP_GSSCM>), dim3(ntiles), dim3(256), 0, s, items, A,
+                         tiles, tile_rows, pivot, pivot_stride, cut);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define RTD_BUCKETS(X) X(4) X(5) X(8) X(10) X(16) X(20) X(24) X(32) X(40) X(48) X(64)
+
+hipError_t launch_dist(int bucket, int dtype, const ItemDesc* items, const Tile* tiles, int ntiles,
+                       int tile_rows, const double* mtri, const double* mux, const int32_t* status,
+                       double* d2, hipStream_t s) {
+#define CASE(PB)                                                                              \
+  case PB:                                                                                    \
+    return dtype == 0 ? dist_t<float, PB>(items, tiles, ntiles, tile_rows, mtri, mux, status, \
+                                          d2, s)                                              \
+                      : dist_t<double, PB>(items, tiles, ntiles, tile_rows, mtri, mux, status, \
+                                           d2, s);
+  switch (bucket) {
+    RTD_BUCKETS(CASE)
+    default: return hipErrorInvalidValue;
+  }
+#undef CASE
+}
+
+hipError_t launch_sscp(int bucket, int dtype, int mode, const ItemDesc* items, ItemArrays A,
+                       const Tile* tiles, int ntiles, int tile_rows, const double* pivot,
+                       int pivot_stride, const double* cut, hipStream_t s) {
+#define CASE(PB)                                                                         \
+  case PB:                                                                               \
+    return dtype == 0 ? sscp_t<float, PB>(mode, items, A, tiles, ntiles, tile_rows, pivot, \
+                                          pivot_stride, cut, s)                          \
+                      : sscp_t<double, PB>(mode, items, A, tiles, ntiles, tile_rows, pivot, \
+                                           pivot_stride, cut, s);
+  switch (bucket) {
+    RTD_BUCKETS(CASE)
+    default: return hipErrorInvalidValue;
+  }
+#undef CASE
+}
+
+}  // namespace rtd

@@ -1,0 +1,452 @@
+// Segmented stable LSD radix sort of order-preserving float keys, and the
+// order-statistic estimators computed on the sorted segments:
+//   * univariate reweighted MCD (Sec. 3.1), used for the standardisation and
+//     inside the refinement (Sec. 3.3 steps 3-4);
+//   * median and MAD (DetMCD's standardisation, Sec. 2.2 step 1);
+//   * the GSSCM cutoffs A, B of the linearly redescending weight (eq. LR).
+#include "common.h"
+#include "sortseg.h"
+
+namespace rtd {
+
+namespace {
+
+constexpr int RS_NT = 256;           // threads per tile
+constexpr int RS_ITEMS = 16;         // keys per thread
+constexpr int RS_TILE = RS_NT * RS_ITEMS;
+constexpr int RS_WAVES = RS_NT / 64;
+
+template <typename K>
+__device__ inline int digit_of(K k, int shift) { return (int)((k >> shift) & (K)0xFF); }
+
+// Per-tile digit counts of the pass at `shift`.
+template <typename K>
+__global__ __launch_bounds__(RS_NT) void k_rs_count(const K* __restrict__ keys,
+                                                    const SegTile* __restrict__ tiles,
+                                                    const int64_t* __restrict__ seg_off,
+                                                    const int64_t* __restrict__ seg_len,
+                                                    int shift, int32_t* __restrict__ counts) {
+  __shared__ int hist[256];
+  const SegTile t = tiles[blockIdx.x];
+  const int64_t base = seg_off[t.seg] + (int64_t)t.tile * RS_TILE;
+  const int64_t end = seg_off[t.seg] + seg_len[t.seg];
+  hist[threadIdx.x] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < RS_ITEMS; ++i) {
+    const int64_t k = base + i * RS_NT + threadIdx.x;
+    if (k < end) atomicAdd(&hist[digit_of(keys[k], shift)], 1);
+  }
+  __syncthreads();
+  counts[(size_t)blockIdx.x * 256 + threadIdx.x] = hist[threadIdx.x];
+}
+
+// Per segment: offsets[tile][d] = base(d) + counts of digit d in earlier tiles.
+__global__ __launch_bounds__(256) void k_rs_scan(const int32_t* __restrict__ counts,
+                                                 const int32_t* __restrict__ seg_tile0,
+                                                 int32_t* __restrict__ offs) {
+  __shared__ int tot[256];
+  const int s = blockIdx.x;
+  const int t0 = seg_tile0[s], t1 = seg_tile0[s + 1];
+  const int d = threadIdx.x;
+  int run = 0;
+  for (int t = t0; t < t1; ++t) {
+    const int c = counts[(size_t)t * 256 + d];
+    offs[(size_t)t * 256 + d] = run;
+    run += c;
+  }
+  tot[d] = run;
+  __syncthreads();
+  if (d == 0) {
+    int acc = 0;
+    for (int k = 0; k < 256; ++k) {
+      const int v = tot[k];
+      tot[k] = acc;
+      acc += v;
+    }
+  }
+  __syncthreads();
+  const int b = tot[d];
+  for (int t = t0; t < t1; ++t) offs[(size_t)t * 256 + d] += b;
+}
+
+// Stable scatter of one tile.  Wave w owns keys [w*1024, (w+1)*1024) of the
+// tile, visited 64 at a time in index order; equal digits are ranked with
+// eight ballots, so the tile order is preserved.
+template <typename K>
+__global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K* __restrict__ kin,
+                                                      K* __restrict__ kout,
+                                                      const SegTile* __restrict__ tiles,
+                                                      const int64_t* __restrict__ seg_off,
+                                                      const int64_t* __restrict__ seg_len,
+                                                      int shift,
+                                                      const int32_t* __restrict__ offs) {
+  __shared__ int wc[RS_WAVES][256];
+  const SegTile t = tiles[blockIdx.x];
+  const int64_t so = seg_off[t.seg];
+  const int64_t base = so + (int64_t)t.tile * RS_TILE;
+  const int64_t end = so + seg_len[t.seg];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int d = threadIdx.x; d < RS_WAVES * 256; d += RS_NT) (&wc[0][0])[d] = 0;
+  __syncthreads();
+  K kv[RS_ITEMS];
+  int dg[RS_ITEMS], rk[RS_ITEMS];
+  const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int i = 0; i < RS_ITEMS; ++i) {
+    const int64_t k = base + (int64_t)w * (RS_ITEMS * 64) + i * 64 + lane;
+    const bool valid = k < end;
+    kv[i] = valid ? kin[k] : (K)0;
+    const int d = digit_of(kv[i], shift);
+    dg[i] = d;
+    uint64_t match = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t bb = __ballot((d >> b) & 1);
+      match &= ((d >> b) & 1) ? bb : ~bb;
+    }
+    const int before = __popcll(match & below);
+    const int cur = wc[w][d];
+    rk[i] = cur + before;
+    if (valid && before == 0) wc[w][d] = cur + __popcll(match);
+  }
+  __syncthreads();
+  // exclusive scan over waves, per digit
+  {
+    const int d = threadIdx.x;
+    int acc = 0;
+#pragma unroll
+    for (int k = 0; k < RS_WAVES; ++k) {
+      const int v = wc[k][d];
+      wc[k][d] = acc;
+      acc += v;
+    }
+  }
+  __syncthreads();
+  const int32_t* __restrict__ o = offs + (size_t)blockIdx.x * 256;
+#pragma unroll
+  for (int i = 0; i < RS_ITEMS; ++i) {
+    const int64_t k = base + (int64_t)w * (RS_ITEMS * 64) + i * 64 + lane;
+    if (k < end) kout[so + o[dg[i]] + wc[w][dg[i]] + rk[i]] = kv[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Estimators on sorted segments.  One block per segment.
+// ---------------------------------------------------------------------------
+constexpr int SS_NT = 1024;
+
+template <typename K>
+__device__ inline double val_of(K k);
+template <>
+__device__ inline double val_of<uint32_t>(uint32_t k) {
+  const uint32_t b = (k & 0x80000000u) ? (k ^ 0x80000000u) : ~k;
+  return (double)__uint_as_float(b);
+}
+template <>
+__device__ inline double val_of<uint64_t>(uint64_t k) {
+  const uint64_t b = (k & 0x8000000000000000ull) ? (k ^ 0x8000000000000000ull) : ~k;
+  return __longlong_as_double((long long)b);
+}
+
+__device__ inline double block_sum_ordered(double v, double* red) {
+  // fixed-order reduction: per-thread values summed in thread order
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = SS_NT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Exclusive prefix (in thread order) of one double per thread.
+__device__ inline double block_excl_prefix(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    // each of 64 lanes scans a run of SS_NT/64 entries, then a wave scan
+    constexpr int R = SS_NT / 64;
+    double s = 0.0;
+    for (int k = 0; k < R; ++k) s += red[threadIdx.x * R + k];
+    double x = s;
+    for (int o = 1; o < 64; o <<= 1) {
+      const double y = __shfl_up(x, o, 64);
+      if ((int)threadIdx.x >= o) x += y;
+    }
+    double run = x - s;
+    for (int k = 0; k < R; ++k) {
+      const double t = red[threadIdx.x * R + k];
+      red[threadIdx.x * R + k] = run;
+      run += t;
+    }
+  }
+  __syncthreads();
+  const double r = red[threadIdx.x];
+  __syncthreads();
+  return r;
+}
+
+// k-th smallest (0-based) of |v_i - c| for a sorted segment v, by bisection on
+// the count of values within the band [c - t, c + t]; the answer is one of
+// the deviations, found exactly by searching over the two monotone runs.
+template <typename K>
+__device__ double kth_abs_dev(const K* __restrict__ v, int64_t L, double c, int64_t k) {
+  // split point: first index with v >= c
+  int64_t lo = 0, hi = L;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) / 2;
+    if (val_of<K>(v[mid]) < c) lo = mid + 1;
+    else hi = mid;
+  }
+  const int64_t s = lo;            // left run: c - v[s-1], c - v[s-2], ... (increasing)
+  const int64_t nl = s, nr = L - s;  // right run: v[s] - c, v[s+1] - c, ... (increasing)
+  // k-th smallest of two sorted sequences A (len nl) and B (len nr)
+  int64_t a_lo = k + 1 > nr ? k + 1 - nr : 0;
+  int64_t a_hi = k + 1 < nl ? k + 1 : nl;
+  // choose i elements from A, k+1-i from B
+  while (a_lo < a_hi) {
+    const int64_t i = (a_lo + a_hi) / 2;
+    const int64_t j = k + 1 - i;
+    const double Ai = (i < nl) ? c - val_of<K>(v[s - 1 - i]) : INFINITY;   // A[i]
+    const double Bj1 = (j > 0) ? val_of<K>(v[s + j - 1]) - c : -INFINITY; // B[j-1]
+    if (Ai < Bj1) a_lo = i + 1;
+    else a_hi = i;
+  }
+  const int64_t i = a_lo, j = k + 1 - i;
+  const double Ai1 = (i > 0) ? c - val_of<K>(v[s - i]) : -INFINITY;       // A[i-1]
+  const double Bj1 = (j > 0) ? val_of<K>(v[s + j - 1]) - c : -INFINITY;   // B[j-1]
+  return Ai1 > Bj1 ? Ai1 : Bj1;
+}
+
+template <typename K>
+__device__ inline double median_sorted(const K* __restrict__ v, int64_t L) {
+  const double a = val_of<K>(v[(L - 1) / 2]), b = val_of<K>(v[L / 2]);
+  return 0.5 * (a + b);
+}
+
+template <typename K>
+__global__ __launch_bounds__(SS_NT) void k_segstats(const K* __restrict__ keys,
+                                                    const int64_t* __restrict__ seg_off,
+                                                    const int64_t* __restrict__ seg_len,
+                                                    const double* __restrict__ seg_craw,
+                                                    double q1, double crew, int mode,
+                                                    SegStat* __restrict__ out) {
+  __shared__ double red[SS_NT];
+  __shared__ double s_best[SS_NT];
+  __shared__ int64_t s_bj[SS_NT];
+  const int sg = blockIdx.x;
+  const K* __restrict__ v = keys + seg_off[sg];
+  const int64_t L = seg_len[sg];
+  const int tid = threadIdx.x;
+  SegStat r{};
+  if (L <= 0) {
+    if (tid == 0) out[sg] = r;
+    return;
+  }
+  if (mode == SEGSTAT_MEDMAD) {
+    if (tid == 0) {
+      const double med = median_sorted(v, L);
+      const double a = kth_abs_dev(v, L, med, (L - 1) / 2);
+      const double b = kth_abs_dev(v, L, med, L / 2);
+      r.mu = r.mu_raw = med;
+      const double mad = 1.4826 * 0.5 * (a + b);
+      r.var = r.var_raw = mad * mad;
+      r.n_kept = L;
+      out[sg] = r;
+    }
+    return;
+  }
+  if (mode == SEGSTAT_GSSCM) {
+    // norms r sorted; s = r^(2/3) is sorted as well
+    if (tid == 0) {
+      const double A = median_sorted(v, L);
+      const double sa = pow(val_of<K>(v[(L - 1) / 2]), 2.0 / 3.0);
+      const double sb = pow(val_of<K>(v[L / 2]), 2.0 / 3.0);
+      const double ms = 0.5 * (sa + sb);
+      // median of |s_i - ms| by bisection over the two monotone runs of s
+      int64_t lo = 0, hi = L;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (pow(val_of<K>(v[mid]), 2.0 / 3.0) < ms) lo = mid + 1;
+        else hi = mid;
+      }
+      const int64_t s0 = lo, nl = s0, nr = L - s0;
+      double dev[2];
+      for (int q = 0; q < 2; ++q) {
+        const int64_t k = q == 0 ? (L - 1) / 2 : L / 2;
+        int64_t a_lo = k + 1 > nr ? k + 1 - nr : 0;
+        int64_t a_hi = k + 1 < nl ? k + 1 : nl;
+        while (a_lo < a_hi) {
+          const int64_t i = (a_lo + a_hi) / 2, j = k + 1 - i;
+          const double Ai = (i < nl) ? ms - pow(val_of<K>(v[s0 - 1 - i]), 2.0 / 3.0) : INFINITY;
+          const double Bj1 = (j > 0) ? pow(val_of<K>(v[s0 + j - 1]), 2.0 / 3.0) - ms : -INFINITY;
+          if (Ai < Bj1) a_lo = i + 1;
+          else a_hi = i;
+        }
+        const int64_t i = a_lo, j = k + 1 - i;
+        const double Ai1 = (i > 0) ? ms - pow(val_of<K>(v[s0 - i]), 2.0 / 3.0) : -INFINITY;
+        const double Bj1 = (j > 0) ? pow(val_of<K>(v[s0 + j - 1]), 2.0 / 3.0) - ms : -INFINITY;
+        dev[q] = Ai1 > Bj1 ? Ai1 : Bj1;
+      }
+      const double mad = 0.5 * (dev[0] + dev[1]);
+      r.mu = A;
+      r.var = pow(ms + mad, 1.5);
+      out[sg] = r;
+    }
+    return;
+  }
+  // ---- univariate reweighted MCD
+  const int64_t hh = L / 2 + 1;
+  const double c = val_of<K>(v[L / 2]);
+  const int64_t a0 = (L * tid) / SS_NT, a1 = (L * (tid + 1)) / SS_NT;
+  double l1 = 0.0, l2 = 0.0;
+  for (int64_t k = a0; k < a1; ++k) {
+    const double d = val_of<K>(v[k]) - c;
+    l1 += d;
+    l2 = fma(d, d, l2);
+  }
+  const double P1a = block_excl_prefix(l1, red);
+  const double P2a = block_excl_prefix(l2, red);
+  // prefix at a0 + hh: owner thread's prefix plus the part of its range
+  double P1b = 0.0, P2b = 0.0;
+  const int64_t nw = L - hh + 1;             // number of windows
+  const int64_t j0 = a0, j1 = a1 < nw ? a1 : nw;
+  // share the thread prefixes
+  __shared__ double pf1[SS_NT + 1], pf2[SS_NT + 1];
+  pf1[tid] = P1a;
+  pf2[tid] = P2a;
+  __syncthreads();
+  if (j0 < j1) {
+    const int64_t pos = j0 + hh;             // <= L
+    int ow = (int)((pos * SS_NT) / L);       // candidate owner
+    if (ow > SS_NT - 1) ow = SS_NT - 1;
+    while (ow > 0 && (L * ow) / SS_NT > pos) --ow;
+    while (ow < SS_NT - 1 && (L * (ow + 1)) / SS_NT <= pos) ++ow;
+    const int64_t ob = (L * ow) / SS_NT;
+    P1b = pf1[ow];
+    P2b = pf2[ow];
+    for (int64_t k = ob; k < pos; ++k) {
+      const double d = val_of<K>(v[k]) - c;
+      P1b += d;
+      P2b = fma(d, d, P2b);
+    }
+  }
+  double best = INFINITY;
+  int64_t bj = -1;
+  {
+    double q1l = P1a, q2l = P2a, q1h = P1b, q2h = P2b;
+    const double hd = (double)hh;
+    for (int64_t j = j0; j < j1; ++j) {
+      const double s1 = q1h - q1l, s2 = q2h - q2l;
+      const double wv = (s2 - s1 * s1 / hd) / (hd - 1.0);
+      if (wv < best) { best = wv; bj = j; }
+      const double dl = val_of<K>(v[j]) - c;
+      q1l += dl;
+      q2l = fma(dl, dl, q2l);
+      if (j + hh < L) {
+        const double dh = val_of<K>(v[j + hh]) - c;
+        q1h += dh;
+        q2h = fma(dh, dh, q2h);
+      }
+    }
+  }
+  s_best[tid] = best;
+  s_bj[tid] = bj;
+  __syncthreads();
+  for (int o = SS_NT / 2; o > 0; o >>= 1) {
+    if (tid < o) {
+      const double b2 = s_best[tid + o];
+      const int64_t j2 = s_bj[tid + o];
+      if (j2 >= 0 && (s_bj[tid] < 0 || b2 < s_best[tid] || (b2 == s_best[tid] && j2 < s_bj[tid]))) {
+        s_best[tid] = b2;
+        s_bj[tid] = j2;
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t js = s_bj[0];
+  const double wmin = s_best[0];
+  __syncthreads();
+  // window sums at the optimum, recomputed directly in thread order
+  double w1 = 0.0;
+  {
+    const int64_t b0 = js + (hh * tid) / SS_NT, b1 = js + (hh * (tid + 1)) / SS_NT;
+    for (int64_t k = b0; k < b1; ++k) w1 += val_of<K>(v[k]) - c;
+  }
+  const double S1w = block_sum_ordered(w1, red);
+  const double mu_raw = c + S1w / (double)hh;
+  const double var_raw = wmin * seg_craw[sg];
+  // reweighting: keep (v - mu_raw)^2 <= q1 var_raw
+  const double lim = q1 * var_raw;
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+  for (int64_t k = a0; k < a1; ++k) {
+    const double x = val_of<K>(v[k]);
+    const double e = x - mu_raw;
+    if (e * e <= lim) {
+      const double d = x - c;
+      c0 += 1.0;
+      c1 += d;
+      c2 = fma(d, d, c2);
+    }
+  }
+  const double N = block_sum_ordered(c0, red);
+  const double S1 = block_sum_ordered(c1, red);
+  const double S2 = block_sum_ordered(c2, red);
+  if (tid == 0) {
+    r.mu_raw = mu_raw;
+    r.var_raw = var_raw;
+    r.start = js;
+    r.n_kept = (int64_t)N;
+    r.mu = N > 0 ? c + S1 / N : NAN;
+    r.var = N > 1 ? (S2 - S1 * S1 / N) / (N - 1.0) * crew : 0.0;
+    out[sg] = r;
+  }
+}
+
+}  // namespace
+
+template <typename K>
+hipError_t sort_segments_t(SortPlan& P, hipStream_t s) {
+  K* a = static_cast<K*>(P.keys);
+  K* b = static_cast<K*>(P.tmp);
+  const int passes = (int)sizeof(K);
+  for (int ps = 0; ps < passes; ++ps) {
+    const int shift = 8 * ps;
+    hipLaunchKernelGGL((k_rs_count<K>), dim3(P.ntiles), dim3(RS_NT), 0, s, a, P.tiles,
+                       P.seg_off, P.seg_len, shift, P.counts);
+    hipLaunchKernelGGL(k_rs_scan, dim3(P.nseg), dim3(256), 0, s, P.counts, P.seg_tile0, P.offs);
+    hipLaunchKernelGGL((k_rs_scatter<K>), dim3(P.ntiles), dim3(RS_NT), 0, s, a, b, P.tiles,
+                       P.seg_off, P.seg_len, shift, P.offs);
+    K* t = a;
+    a = b;
+    b = t;
+  }
+  // an even number of passes leaves the result in P.keys
+  return hipGetLastError();
+}
+
+hipError_t sort_segments(SortPlan& P, hipStream_t s) {
+  if (P.ntiles <= 0) return hipSuccess;
+  return P.key_bytes == 4 ? sort_segments_t<uint32_t>(P, s) : sort_segments_t<uint64_t>(P, s);
+}
+
+hipError_t launch_segstats(const SortPlan& P, const double* seg_craw, double q1, double crew,
+                           int mode, SegStat* out, hipStream_t s) {
+  if (P.nseg <= 0) return hipSuccess;
+  if (P.key_bytes == 4)
+    hipLaunchKernelGGL((k_segstats<uint32_t>), dim3(P.nseg), dim3(SS_NT), 0, s,
+                       static_cast<const uint32_t*>(P.keys), P.seg_off, P.seg_len, seg_craw, q1,
+                       crew, mode, out);
+  else
+    hipLaunchKernelGGL((k_segstats<uint64_t>), dim3(P.nseg), dim3(SS_NT), 0, s,
+                       static_cast<const uint64_t*>(P.keys), P.seg_off, P.seg_len, seg_craw, q1,
+                       crew, mode, out);
+  return hipGetLastError();
+}
+
+int sort_tile_keys() { return RS_TILE; }
+
+}  // namespace rtd
