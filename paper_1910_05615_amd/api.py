@@ -172,3 +172,88 @@ def cstep(X: torch.Tensor, h_sub: int, mu0: torch.Tensor, sigma0: torch.Tensor,
                             _ptr(stt), _ptr(its), _ptr(ld))
     _check(lib, h, st, "rtdetmcd_cstep")
     return CStepResult(mu, sig, hs, int(stt.item()), int(its.item()), float(ld.item()))
+
+
+# ----------------------------------------------------------------- full fit
+
+@dataclasses.dataclass
+class Fit:
+    mu: torch.Tensor
+    sigma: torch.Tensor
+    mu_raw: torch.Tensor
+    sigma_raw: torch.Tensor
+    logdet: torch.Tensor          # [log det sigma_raw, log det sigma]
+    dist: torch.Tensor
+    outlier: torch.Tensor
+    hsubset: torch.Tensor         # q x h
+    block_status: torch.Tensor
+    block_start: torch.Tensor
+    block_iters: torch.Tensor
+    loc: torch.Tensor
+    scale: torch.Tensor
+    n_w: torch.Tensor
+    q: int
+    m: int
+    h: int
+
+
+def _alloc_fit(X: torch.Tensor, q: int, m: int, h: int):
+    n, p = X.shape
+    dev = X.device
+    f64 = dict(dtype=torch.float64, device=dev)
+    i32 = dict(dtype=torch.int32, device=dev)
+    F = Fit(mu=torch.empty(p, **f64), sigma=torch.empty(p, p, **f64),
+            mu_raw=torch.empty(p, **f64), sigma_raw=torch.empty(p, p, **f64),
+            logdet=torch.empty(2, **f64), dist=torch.empty(n, **f64),
+            outlier=torch.empty(n, dtype=torch.uint8, device=dev),
+            hsubset=torch.empty(q, h, **i32), block_status=torch.empty(q, **i32),
+            block_start=torch.empty(q, **i32), block_iters=torch.empty(q, **i32),
+            loc=torch.empty(p, **f64), scale=torch.empty(p, **f64),
+            n_w=torch.empty(1, dtype=torch.int64, device=dev), q=q, m=m, h=h)
+    out = _lib.Out(mu=F.mu.data_ptr(), sigma=F.sigma.data_ptr(), mu_raw=F.mu_raw.data_ptr(),
+                   sigma_raw=F.sigma_raw.data_ptr(), logdet=F.logdet.data_ptr(),
+                   dist=F.dist.data_ptr(), outlier=F.outlier.data_ptr(),
+                   hsubset=F.hsubset.data_ptr(), block_status=F.block_status.data_ptr(),
+                   block_start=F.block_start.data_ptr(), block_iters=F.block_iters.data_ptr(),
+                   loc=F.loc.data_ptr(), scale=F.scale.data_ptr(), n_w=F.n_w.data_ptr())
+    return F, out
+
+
+def fit(X: torch.Tensor, h_sub: int = 0, n_chunks: int = 0, **opts) -> Fit:
+    """RT-DetMCD fit of X (n x p) on the GPU; all outputs stay on the device."""
+    _check_X(X)
+    n, p = X.shape
+    q, m, h = plan(n, p, h_sub, n_chunks, **opts)
+    lib, hd = _handle(X.device)
+    o = make_opts(**opts)
+    F, out = _alloc_fit(X, q, m, h)
+    st = lib.rtdetmcd_fit(hd, _ptr(X), _dtype_code(X), n, p, X.stride(0), h_sub, n_chunks,
+                          C.byref(o), C.byref(out))
+    _check(lib, hd, st, "rtdetmcd_fit")
+    return F
+
+
+def fit_batched(Xs: Sequence[torch.Tensor], h_subs: Optional[Sequence[int]] = None,
+                n_chunks: Optional[Sequence[int]] = None, **opts):
+    """Fit many independent datasets in the same launches.
+
+    Returns (list of Fit, list of per-dataset status codes)."""
+    lib, hd = _handle(Xs[0].device)
+    o = make_opts(**opts)
+    k = len(Xs)
+    h_subs = list(h_subs) if h_subs is not None else [0] * k
+    n_chunks = list(n_chunks) if n_chunks is not None else [0] * k
+    arr = (_lib.DatasetDesc * k)()
+    fits = []
+    for i, X in enumerate(Xs):
+        _check_X(X)
+        n, p = X.shape
+        q, m, h = plan(n, p, h_subs[i], n_chunks[i], **opts)
+        F, out = _alloc_fit(X, q, m, h)
+        fits.append(F)
+        arr[i] = _lib.DatasetDesc(X=X.data_ptr(), dtype=_dtype_code(X), n=n, p=p, ld=X.stride(0),
+                                  h_sub=h_subs[i], n_chunks=n_chunks[i], out=out)
+    status = (C.c_int32 * k)()
+    st = lib.rtdetmcd_fit_batched(hd, k, arr, C.byref(o), status)
+    _check(lib, hd, st, "rtdetmcd_fit_batched")
+    return fits, [int(s) for s in status]

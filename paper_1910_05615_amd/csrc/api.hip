@@ -293,6 +293,7 @@ rtdetmcd_status rtdetmcd_plan(int64_t n, int32_t p, int64_t h_sub, int32_t n_chu
   if (p > RTDETMCD_MAX_P) return RTDETMCD_EUNSUPPORTED;
   int64_t qq = n_chunks > 0 ? n_chunks : std::max<int64_t>(n / ((int64_t)p * o.omega), 1);
   if (qq > n) return RTDETMCD_EINVAL;
+  if (qq > 8192) return RTDETMCD_EUNSUPPORTED;   // aggregation keeps at most 4096 blocks
   const int64_t mm = n / qq;
   int64_t hh = h_sub;
   if (hh == 0) {

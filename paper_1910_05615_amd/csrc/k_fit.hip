@@ -1,0 +1,814 @@
+// Kernels of the full RT-DetMCD fit around the C-step loop: standardisation
+// keys, projections for the initial estimators and the refinement, the small
+// per-block float64 steps, robust aggregation and reweighting.
+#include "../../include/rtdetmcd.h"
+#include "fitk.h"
+
+namespace rtd {
+
+namespace {
+
+__device__ inline uint32_t fkey32(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline uint64_t fkey64(double f) {
+  const uint64_t u = (uint64_t)__double_as_longlong(f);
+  return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+}
+
+template <typename T>
+__device__ inline double ldx(const T* __restrict__ p, int64_t i) { return (double)p[i]; }
+
+// ------------------------------------------------------------ standardisation
+
+template <typename T, typename K>
+__global__ void k_colkeys(const T* __restrict__ X, int64_t n, int64_t ld, int p,
+                          K* __restrict__ keys) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const T* xr = X + i * ld;
+    for (int j = 0; j < p; ++j) {
+      if constexpr (sizeof(K) == 4) keys[(size_t)j * n + i] = fkey32((float)xr[j]);
+      else keys[(size_t)j * n + i] = fkey64((double)xr[j]);
+    }
+  }
+}
+
+__global__ void k_std_finish(const SegStat* __restrict__ st32, const SegStat* __restrict__ st64,
+                             const int32_t* __restrict__ seg0, const int32_t* __restrict__ in64,
+                             int D, DsInfo* __restrict__ ds, FitArrays F) {
+  const int d = blockIdx.x;
+  if (d >= D) return;
+  const int p = ds[d].p;
+  const SegStat* __restrict__ st = in64[d] ? st64 : st32;
+  for (int j = threadIdx.x; j < PMAX; j += blockDim.x) {
+    double loc = 0.0, sc = 1.0;
+    if (j < p) {
+      const SegStat s = st[seg0[d] + j];
+      loc = s.mu;
+      sc = sqrt(s.var);
+      if (!(sc > 0.0) || !(sc < 1e300) || !(fabs(loc) < 1e300)) {
+        ds[d].err = RTDETMCD_ESINGULAR;
+        loc = 0.0;
+        sc = 1.0;
+      }
+    }
+    F.loc[(size_t)d * PMAX + j] = loc;
+    F.scale[(size_t)d * PMAX + j] = sc;
+  }
+}
+
+// ------------------------------------------------------------ projections
+// MODE 0: v_j = sum_k W_jk z_k for j < p, one key segment per j (refinement:
+//         W = V^T gives the scores T = Z V, W = Sigma^{-1/2} the sphered data).
+// MODE 1: v = ||z|| (GSSCM norms), one segment.
+// z = (x - loc) / scale, the standardised row (Sec. 3.1, Sec. 4 eq. standardization).
+template <typename T, int P, int MODE>
+__global__ __launch_bounds__(256) void k_project(const ItemDesc* __restrict__ items,
+                                                 const Tile* __restrict__ tiles, int tile_rows,
+                                                 const int32_t* __restrict__ status,
+                                                 const double* __restrict__ W,
+                                                 const int64_t* __restrict__ kbase,
+                                                 uint64_t* __restrict__ keys) {
+  const Tile tl = tiles[blockIdx.x];
+  const int it = tl.item;
+  if (status != nullptr && status[it] != ACTIVE) return;
+  const ItemDesc D = items[it];
+  const int p = D.p;
+  const T* __restrict__ X = static_cast<const T*>(D.X) + D.row0 * D.ld;
+  const double* __restrict__ Wi = W + (size_t)it * MSTRIDE;
+  uint64_t* __restrict__ ko = keys + kbase[it];
+  double loc[P], isc[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    loc[k] = k < p ? D.loc[k] : 0.0;
+    isc[k] = k < p ? D.scale[k] : 1.0;
+  }
+  const int64_t r0 = (int64_t)tl.t * tile_rows;
+  const int64_t r1 = min(r0 + (int64_t)tile_rows, D.m);
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+    const T* __restrict__ xr = X + r * D.ld;
+    double z[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) z[k] = (k < p) ? (ldx(xr, k) - loc[k]) / isc[k] : 0.0;
+    if (MODE == 1) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < P; ++k) s = fma(z[k], z[k], s);
+      ko[r] = fkey64(sqrt(s));
+    } else {
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        if (j < p) {
+          double v = 0.0;
+#pragma unroll
+          for (int k = 0; k < P; ++k) v = fma(Wi[j * PMAX + k], z[k], v);
+          ko[(size_t)j * D.m + r] = fkey64(v);
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ partial sums
+
+__global__ __launch_bounds__(256) void k_reduce_partials(const ItemDesc* __restrict__ items,
+                                                         const double* __restrict__ part,
+                                                         int first, double* __restrict__ cnt,
+                                                         double* __restrict__ sum,
+                                                         double* __restrict__ S) {
+  const int it = first + blockIdx.x;
+  const ItemDesc D = items[it];
+  const int p = D.p;
+  for (int e = threadIdx.x; e < 1 + p + p * p; e += blockDim.x) {
+    int idx;
+    if (e == 0) idx = 0;
+    else if (e <= p) idx = e;
+    else {
+      const int q = e - 1 - p, i = q / p, j = q % p;
+      const int a = i >= j ? i : j, b = i >= j ? j : i;
+      idx = 1 + PMAX + a * (a + 1) / 2 + b;
+    }
+    double s = 0.0;
+    for (int t = 0; t < D.ntiles; ++t) s += part[(size_t)(D.tile0 + t) * PSTRIDE + idx];
+    if (e == 0) cnt[it] = s;
+    else if (e <= p) sum[(size_t)it * PMAX + e - 1] = s;
+    else {
+      const int q = e - 1 - p;
+      S[(size_t)it * MSTRIDE + (q / p) * PMAX + q % p] = s;
+    }
+  }
+}
+
+// mode 0: S1 = classical covariance of the wrapped rows (Sec. 3.2)
+// mode 1: S2 = (1/m) sum xi^2 z z^T (eq. LR)
+// mode 2: copy the GSSCM cutoffs (A, B) of each block
+__global__ void k_init_cov(int mode, const ItemDesc* __restrict__ bitems, int first, FitArrays F,
+                           ItemArrays C, const DsInfo* __restrict__ ds, double* __restrict__ cut,
+                           const SegStat* __restrict__ gst) {
+  const int b = first + blockIdx.x;
+  const ItemDesc B = bitems[b];
+  const DsInfo d = ds[B.ds];
+  const int p = B.p;
+  if (mode == 2) {
+    if (threadIdx.x == 0) {
+      cut[2 * b] = gst[b].mu;
+      cut[2 * b + 1] = gst[b].var;
+    }
+    return;
+  }
+  const int ci = d.item0 + 2 * (b - d.blk0) + mode;
+  const double m = (double)B.m;
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    const double Sij = F.rS[(size_t)b * MSTRIDE + i * PMAX + j];
+    double v;
+    if (mode == 0) {
+      const double si = F.rsum[(size_t)b * PMAX + i], sj = F.rsum[(size_t)b * PMAX + j];
+      v = (Sij - si * sj / m) / (m - 1.0);
+    } else {
+      v = Sij / m;
+    }
+    C.sigz[(size_t)ci * MSTRIDE + i * PMAX + j] = v;
+  }
+}
+
+// ------------------------------------------------------------ refinement (Sec. 3.3)
+
+// Cyclic Jacobi eigen-decomposition of the initial scatter of each item, one
+// wave per matrix; eigenvalues in decreasing order (step 1) and the condition
+// check lambda_1 / lambda_p <= kappa_max (step 2).
+__global__ __launch_bounds__(64) void k_eig(const ItemDesc* __restrict__ items, ItemArrays A,
+                                            FitArrays F, int first, double kappa_max) {
+  __shared__ double a[PMAX * PMAX];
+  __shared__ double v[PMAX * PMAX];
+  __shared__ double red[64];
+  __shared__ int ord[PMAX];
+  const int it = first + blockIdx.x;
+  if (A.status[it] != ACTIVE) return;
+  const int p = items[it].p;
+  const int k = threadIdx.x;
+  const double* S = A.sigz + (size_t)it * MSTRIDE;
+  for (int e = k; e < p * p; e += 64) {
+    const int i = e / p, j = e % p;
+    a[i * PMAX + j] = 0.5 * (S[i * PMAX + j] + S[j * PMAX + i]);
+    v[i * PMAX + j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    if (k < p)
+      for (int j = 0; j < p; ++j) {
+        const double x = a[k * PMAX + j];
+        if (j != k) off += x * x;
+        else dia += x * x;
+      }
+    red[k] = off;
+    __syncthreads();
+    double offt = 0.0;
+    for (int q = 0; q < 64; ++q) offt += red[q];
+    __syncthreads();
+    red[k] = dia;
+    __syncthreads();
+    double diat = 0.0;
+    for (int q = 0; q < 64; ++q) diat += red[q];
+    __syncthreads();
+    if (!(offt > 1e-30 * diat)) break;
+    for (int i = 0; i < p - 1; ++i) {
+      for (int j = i + 1; j < p; ++j) {
+        const double apq = a[i * PMAX + j];
+        if (apq == 0.0) continue;
+        const double app = a[i * PMAX + i], aqq = a[j * PMAX + j];
+        const double tau = (aqq - app) / (2.0 * apq);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+        if (k < p) {
+          const double aki = a[k * PMAX + i], akj = a[k * PMAX + j];
+          a[k * PMAX + i] = c * aki - s * akj;
+          a[k * PMAX + j] = s * aki + c * akj;
+        }
+        __syncthreads();
+        if (k < p) {
+          const double aik = a[i * PMAX + k], ajk = a[j * PMAX + k];
+          a[i * PMAX + k] = c * aik - s * ajk;
+          a[j * PMAX + k] = s * aik + c * ajk;
+          const double vki = v[k * PMAX + i], vkj = v[k * PMAX + j];
+          v[k * PMAX + i] = c * vki - s * vkj;
+          v[k * PMAX + j] = s * vki + c * vkj;
+        }
+        __syncthreads();
+        if (k == 0) {
+          a[i * PMAX + j] = 0.0;
+          a[j * PMAX + i] = 0.0;
+        }
+        __syncthreads();
+      }
+    }
+  }
+  // order by decreasing eigenvalue (stable in the index)
+  if (k < p) {
+    const double lk = a[k * PMAX + k];
+    int r = 0;
+    for (int q = 0; q < p; ++q) {
+      const double lq = a[q * PMAX + q];
+      if (lq > lk || (lq == lk && q < k)) ++r;
+    }
+    ord[r] = k;
+  }
+  __syncthreads();
+  double* V = F.vbuf + (size_t)it * MSTRIDE;
+  double* W = F.wbuf + (size_t)it * MSTRIDE;
+  for (int e = k; e < p * p; e += 64) {
+    const int i = e / p, c = e % p;
+    const double x = v[i * PMAX + ord[c]];
+    V[i * PMAX + c] = x;         // column c = eigenvector of the c-th largest eigenvalue
+    W[c * PMAX + i] = x;         // W = V^T: scores t_c = sum_i V_ic z_i
+  }
+  if (k == 0) {
+    const double l1 = a[ord[0] * PMAX + ord[0]], lp = a[ord[p - 1] * PMAX + ord[p - 1]];
+    if (!(lp > 0.0) || !(l1 / lp <= kappa_max)) A.status[it] = ST_DROP_REFINE;
+  }
+}
+
+// stage 1 (Sec. 3.3 step 3): D~ = diag(sigma_uni^2(T_j)), Sigma_k = V D~ V^T and
+//          the sphering matrix Sigma_k^{-1/2} = V D~^{-1/2} V^T;
+// stage 2 (step 4): mu_k = Sigma_k^{1/2} (mu_uni(Z~_1), ..., mu_uni(Z~_p)).
+__global__ void k_refine(int stage, const ItemDesc* __restrict__ items, ItemArrays A, FitArrays F,
+                         int first, const SegStat* __restrict__ st,
+                         const int32_t* __restrict__ seg0) {
+  __shared__ double sg[PMAX];
+  __shared__ double mt[PMAX];
+  __shared__ int bad;
+  const int it = first + blockIdx.x;
+  if (A.status[it] != ACTIVE) return;
+  const int p = items[it].p;
+  const double* V = F.vbuf + (size_t)it * MSTRIDE;
+  const int s0 = seg0[it];
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  if (stage == 1) {
+    for (int j = threadIdx.x; j < p; j += blockDim.x) {
+      const double s2 = st[s0 + j].var;
+      if (!(s2 > 0.0) || !(s2 < 1e300)) bad = 1;
+      sg[j] = s2;
+      F.s2buf[(size_t)it * PMAX + j] = s2;
+    }
+    __syncthreads();
+    if (bad) {
+      if (threadIdx.x == 0) A.status[it] = ST_DROP_REFINE;
+      return;
+    }
+    double* S = A.sigz + (size_t)it * MSTRIDE;
+    double* W = F.wbuf + (size_t)it * MSTRIDE;
+    for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+      const int i = e / p, j = e % p;
+      double s = 0.0, w = 0.0;
+      for (int c = 0; c < p; ++c) {
+        const double vv = V[i * PMAX + c] * V[j * PMAX + c];
+        s = fma(vv, sg[c], s);
+        w = fma(vv, 1.0 / sqrt(sg[c]), w);
+      }
+      S[i * PMAX + j] = s;
+      W[i * PMAX + j] = w;
+    }
+  } else {
+    for (int j = threadIdx.x; j < p; j += blockDim.x) {
+      sg[j] = sqrt(F.s2buf[(size_t)it * PMAX + j]);
+      mt[j] = st[s0 + j].mu;
+    }
+    __syncthreads();
+    double* mu = A.muz + (size_t)it * PMAX;
+    for (int i = threadIdx.x; i < p; i += blockDim.x) {
+      double s = 0.0;
+      for (int j = 0; j < p; ++j) {
+        double r = 0.0;     // (Sigma_k^{1/2})_ij
+        for (int c = 0; c < p; ++c) r = fma(V[i * PMAX + c] * V[j * PMAX + c], sg[c], r);
+        s = fma(r, mt[j], s);
+      }
+      mu[i] = s;
+    }
+  }
+}
+
+// ------------------------------------------------------------ start choice (Sec. 4 step 4)
+// The start with the smaller determinant; equal subsets or equal log-dets go
+// to the first start.  The block fit is scaled by c(alpha) (eq. mcdraw).
+__global__ __launch_bounds__(256) void k_choose(const ItemDesc* __restrict__ bitems,
+                                                const ItemDesc* __restrict__ citems, ItemArrays A,
+                                                FitArrays F, const DsInfo* __restrict__ ds,
+                                                int first) {
+  __shared__ int diff;
+  const int b = first + blockIdx.x;
+  const ItemDesc B = bitems[b];
+  const DsInfo d = ds[B.ds];
+  const int p = B.p;
+  const int i0 = d.item0 + 2 * (b - d.blk0), i1 = i0 + 1;
+  auto okst = [](int s) { return s == ST_CONVERGED || s == ST_NOTCONV || s == ST_ILLCOND; };
+  const bool v0 = okst(A.status[i0]), v1 = okst(A.status[i1]);
+  if (threadIdx.x == 0) diff = 0;
+  __syncthreads();
+  if (v0 && v1) {
+    const uint8_t* m0 = A.mask + citems[i0].roff;
+    const uint8_t* m1 = A.mask + citems[i1].roff;
+    int dl = 0;
+    for (int64_t r = threadIdx.x; r < B.m; r += blockDim.x) dl |= (m0[r] != m1[r]);
+    if (dl) diff = 1;
+  }
+  __syncthreads();
+  int ch = -1;
+  if (v0 && v1) ch = (!diff || !(A.logdet[i1] < A.logdet[i0])) ? i0 : i1;
+  else if (v0) ch = i0;
+  else if (v1) ch = i1;
+  const double lc = log(d.calpha);
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    F.bsig[(size_t)b * MSTRIDE + i * PMAX + j] =
+        ch >= 0 ? d.calpha * A.sigz[(size_t)ch * MSTRIDE + i * PMAX + j] : 0.0;
+  }
+  for (int j = threadIdx.x; j < p; j += blockDim.x)
+    F.bmu[(size_t)b * PMAX + j] = ch >= 0 ? A.muz[(size_t)ch * PMAX + j] : 0.0;
+  if (threadIdx.x == 0) {
+    F.bitem[b] = ch;
+    F.bds[b] = B.ds;
+    F.bstat[b] = ch >= 0 ? A.status[ch] : RTDETMCD_BLOCK_INVALID;
+    F.bstart[b] = ch >= 0 ? ch - i0 : -1;
+    F.biters[b] = ch >= 0 ? A.iter[ch] : 0;
+    F.bld[b] = ch >= 0 ? A.logdet[ch] + p * lc : NAN;
+  }
+}
+
+// ------------------------------------------------------------ aggregation (Sec. 4 steps 5-7)
+
+// Entrywise median over the valid blocks of a dataset; an even count takes the
+// mean of the two middle values.  One block per (dataset, entry); entry e < p
+// is mu_e, otherwise a lower-triangle entry of Sigma.
+__global__ __launch_bounds__(256) void k_median(const DsInfo* __restrict__ ds, FitArrays F,
+                                                const int2* __restrict__ ent) {
+  __shared__ double lo_v, hi_v;
+  __shared__ int nvs;
+  const int2 de = ent[blockIdx.x];
+  const DsInfo d = ds[de.x];
+  const int p = d.p;
+  int i = -1, j = -1;
+  if (de.y >= p) {
+    int k = de.y - p, r = 0;
+    while (k > r) { k -= r + 1; ++r; }
+    i = r;
+    j = k;
+  }
+  auto val = [&](int b) -> double {
+    return i < 0 ? F.bmu[(size_t)b * PMAX + de.y] : F.bsig[(size_t)b * MSTRIDE + i * PMAX + j];
+  };
+  if (threadIdx.x == 0) {
+    int c = 0;
+    for (int b = d.blk0; b < d.blk0 + d.q; ++b) c += F.bitem[b] >= 0;
+    nvs = c;
+  }
+  __syncthreads();
+  const int nv = nvs;
+  if (nv == 0) return;
+  const int k1 = (nv - 1) / 2, k2 = nv / 2;
+  for (int b = d.blk0 + threadIdx.x; b < d.blk0 + d.q; b += blockDim.x) {
+    if (F.bitem[b] < 0) continue;
+    const double x = val(b);
+    int less = 0, eq = 0;
+    for (int c = d.blk0; c < d.blk0 + d.q; ++c) {
+      if (F.bitem[c] < 0) continue;
+      const double y = val(c);
+      less += y < x;
+      eq += y == x;
+    }
+    if (less <= k1 && k1 < less + eq) lo_v = x;   // all writers store the same value
+    if (less <= k2 && k2 < less + eq) hi_v = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double med = 0.5 * (lo_v + hi_v);
+    double* M = F.med + (size_t)de.x * (PMAX + MSTRIDE);
+    if (i < 0) M[de.y] = med;
+    else {
+      M[PMAX + i * PMAX + j] = med;
+      M[PMAX + j * PMAX + i] = med;
+    }
+  }
+}
+
+// KL'_l = tr(S_med S_l^{-1}) + log det S_l + (mu_med - mu_l)' S_l^{-1} (mu_med - mu_l)
+// for the raw block fit S_l = c(alpha) Sigma_l; eq. (KL) without its
+// l-independent terms, so that a non-positive-definite S_med is allowed.
+__global__ __launch_bounds__(256) void k_kl(const DsInfo* __restrict__ ds, ItemArrays A,
+                                            FitArrays F, int first) {
+  __shared__ double Si[PMAX * PMAX];
+  __shared__ double dv[PMAX];
+  __shared__ double red[256];
+  const int b = first + blockIdx.x;
+  const int ch = F.bitem[b];
+  if (ch < 0) {
+    if (threadIdx.x == 0) F.bkl[b] = INFINITY;
+    return;
+  }
+  const DsInfo d = ds[F.bds[b]];
+  const int p = d.p;
+  const double* Li = A.linv + (size_t)ch * MSTRIDE;
+  const double* M = F.med + (size_t)F.bds[b] * (PMAX + MSTRIDE);
+  const double ic = 1.0 / d.calpha;
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    const int k0 = i > j ? i : j;
+    double s = 0.0;
+    for (int k = k0; k < p; ++k) s = fma(Li[k * PMAX + i], Li[k * PMAX + j], s);
+    Si[i * PMAX + j] = s * ic;
+  }
+  for (int j = threadIdx.x; j < p; j += blockDim.x) dv[j] = M[j] - F.bmu[(size_t)b * PMAX + j];
+  __syncthreads();
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    acc = fma(M[PMAX + i * PMAX + j] + dv[i] * dv[j], Si[i * PMAX + j], acc);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < 256; ++k) s += red[k];
+    F.bkl[b] = s + F.bld[b];
+  }
+}
+
+// Keep the ceil(q/2) valid blocks of smallest KL' (ties to the lower block)
+// and pool them in that order with the single-pass update of Sec. 4 step 7
+// (block counts m, Lambda_l = (m-1) S_l).  The result is the start of the
+// first global item (reweighting).
+__global__ __launch_bounds__(256) void k_pool(DsInfo* __restrict__ ds, ItemArrays G, FitArrays F,
+                                              int first_ds) {
+  __shared__ int order[4096];   // ceil(q/2) <= 4096 (q <= 8192 is enforced by the planner)
+  __shared__ double mu[PMAX];
+  __shared__ double dmu[PMAX];
+  __shared__ int nvs;
+  const int dd = first_ds + blockIdx.x;
+  DsInfo d = ds[dd];
+  const int p = d.p, q = d.q;
+  if (d.err) return;
+  if (threadIdx.x == 0) {
+    int c = 0;
+    for (int b = d.blk0; b < d.blk0 + q; ++b) c += F.bitem[b] >= 0;
+    nvs = c;
+  }
+  __syncthreads();
+  const int nv = nvs;
+  if (nv == 0) {
+    if (threadIdx.x == 0) ds[dd].err = RTDETMCD_ESINGULAR;
+    return;
+  }
+  const int keep = (nv + 1) / 2;
+  for (int b = d.blk0 + threadIdx.x; b < d.blk0 + q; b += blockDim.x) {
+    if (F.bitem[b] < 0) continue;
+    const double x = F.bkl[b];
+    int r = 0;
+    for (int c = d.blk0; c < d.blk0 + q; ++c) {
+      if (F.bitem[c] < 0) continue;
+      const double y = F.bkl[c];
+      r += (y < x) || (y == x && c < b);
+    }
+    if (r < keep && r < 4096) order[r] = b;
+  }
+  __syncthreads();
+  const double m = (double)d.m;
+  const int g0 = d.glob0;
+  double* Lam = G.sigz + (size_t)g0 * MSTRIDE;   // accumulates Lambda_pooled
+  const int b0 = order[0];
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    Lam[i * PMAX + j] = (m - 1.0) * F.bsig[(size_t)b0 * MSTRIDE + i * PMAX + j];
+  }
+  for (int j = threadIdx.x; j < p; j += blockDim.x) mu[j] = F.bmu[(size_t)b0 * PMAX + j];
+  double np = m;
+  __syncthreads();
+  for (int r = 1; r < keep && r < 4096; ++r) {
+    const int b = order[r];
+    for (int j = threadIdx.x; j < p; j += blockDim.x) dmu[j] = F.bmu[(size_t)b * PMAX + j] - mu[j];
+    __syncthreads();
+    const double f = np * m / (np + m);
+    for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+      const int i = e / p, j = e % p;
+      Lam[i * PMAX + j] += (m - 1.0) * F.bsig[(size_t)b * MSTRIDE + i * PMAX + j] +
+                           dmu[i] * dmu[j] * f;
+    }
+    for (int j = threadIdx.x; j < p; j += blockDim.x)
+      mu[j] = (np * mu[j] + m * F.bmu[(size_t)b * PMAX + j]) / (np + m);
+    np += m;
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    const double v = 0.5 * (Lam[i * PMAX + j] + Lam[j * PMAX + i]) / (np - 1.0);
+    F.sigraw[(size_t)dd * MSTRIDE + i * PMAX + j] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    Lam[i * PMAX + j] = F.sigraw[(size_t)dd * MSTRIDE + i * PMAX + j];
+  }
+  for (int j = threadIdx.x; j < p; j += blockDim.x) {
+    F.muraw[(size_t)dd * PMAX + j] = mu[j];
+    G.muz[(size_t)g0 * PMAX + j] = mu[j];
+  }
+}
+
+// Reweighted location and scatter from the sscp partials of the rows with
+// RD^2 <= chi2_{p,q} (Sec. 2.1, Sec. 4 steps 8-9): the classical mean and
+// covariance (divisor n_w - 1) of those rows, optionally times c(q).  The
+// result is the start of the second global item (final distances).
+__global__ __launch_bounds__(256) void k_rew(DsInfo* __restrict__ ds,
+                                             const ItemDesc* __restrict__ gitems, ItemArrays G,
+                                             FitArrays F, int first_ds) {
+  __shared__ double sv[PMAX + 1];
+  const int dd = first_ds + blockIdx.x;
+  const DsInfo d = ds[dd];
+  if (d.err) return;
+  const int p = d.p;
+  const int g0 = d.glob0, g1 = d.glob1;
+  const ItemDesc D = gitems[g0];
+  for (int e = threadIdx.x; e <= p; e += blockDim.x) {
+    double s = 0.0;
+    for (int t = 0; t < D.ntiles; ++t) s += G.part[(size_t)(D.tile0 + t) * PSTRIDE + e];
+    sv[e] = s;
+  }
+  __syncthreads();
+  const double nw = sv[0];
+  if (!(nw > (double)p)) {
+    if (threadIdx.x == 0) ds[dd].err = RTDETMCD_ESINGULAR;
+    return;
+  }
+  const double* c = G.mux + (size_t)g0 * PMAX;
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    const int a = i >= j ? i : j, bb = i >= j ? j : i;
+    double s = 0.0;
+    for (int t = 0; t < D.ntiles; ++t)
+      s += G.part[(size_t)(D.tile0 + t) * PSTRIDE + 1 + PMAX + a * (a + 1) / 2 + bb];
+    const double lam = s - sv[1 + i] * sv[1 + j] / nw;
+    const double sx = lam / (nw - 1.0) * d.crew;
+    G.sigz[(size_t)g1 * MSTRIDE + i * PMAX + j] =
+        sx / (D.scale[i] * D.scale[j]);
+  }
+  for (int j = threadIdx.x; j < p; j += blockDim.x) {
+    const double mx = c[j] + sv[1 + j] / nw;
+    G.muz[(size_t)g1 * PMAX + j] = (mx - D.loc[j]) / D.scale[j];
+  }
+  if (threadIdx.x == 0) F.nw[dd] = (int64_t)nw;
+}
+
+// Subset indices of each block's chosen start, ascending dataset rows.
+__global__ __launch_bounds__(1024) void k_hsub(const ItemDesc* __restrict__ citems, ItemArrays A,
+                                               FitArrays F, const DsInfo* __restrict__ ds,
+                                               const rtdetmcd_out* __restrict__ outs, int first) {
+  __shared__ int wtot[16];
+  const int b = first + blockIdx.x;
+  const int dd = F.bds[b];
+  const DsInfo d = ds[dd];
+  int32_t* o = outs[dd].hsubset;
+  if (!o) return;
+  o += (size_t)(b - d.blk0) * d.h;
+  const int ch = F.bitem[b];
+  if (ch < 0) {
+    for (int64_t k = threadIdx.x; k < d.h; k += blockDim.x) o[k] = -1;
+    return;
+  }
+  const ItemDesc C = citems[ch];
+  const uint8_t* mk = A.mask + C.roff;
+  int64_t n = 0;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int64_t base = 0; base < C.m; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const int f = (i < C.m && mk[i]) ? 1 : 0;
+    const uint64_t bal = __ballot(f);
+    const int pos = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wtot[wv] = __popcll(bal);
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int k = 0; k < 16; ++k) {
+      if (k < wv) off += wtot[k];
+      tot += wtot[k];
+    }
+    if (f && n + off + pos < d.h) o[n + off + pos] = (int32_t)(C.row0 + i);
+    n += tot;
+    __syncthreads();
+  }
+}
+
+// Outputs in the units of X (affine equivariance: mu_X = loc + scale mu_Z,
+// Sigma_X = D Sigma_Z D, distances unchanged).
+__global__ __launch_bounds__(256) void k_outputs(const DsInfo* __restrict__ ds, ItemArrays G,
+                                                 FitArrays F, const rtdetmcd_out* __restrict__ outs,
+                                                 int first_ds) {
+  const int dd = first_ds + blockIdx.x;
+  const DsInfo d = ds[dd];
+  const rtdetmcd_out o = outs[dd];
+  const int p = d.p;
+  const double* loc = F.loc + (size_t)dd * PMAX;
+  const double* sc = F.scale + (size_t)dd * PMAX;
+  const int g0 = d.glob0, g1 = d.glob1;
+  const bool ok = d.err == 0;
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    if (o.sigma) o.sigma[e] = ok ? sc[i] * sc[j] * G.sigz[(size_t)g1 * MSTRIDE + i * PMAX + j] : NAN;
+    if (o.sigma_raw)
+      o.sigma_raw[e] = ok ? sc[i] * sc[j] * F.sigraw[(size_t)dd * MSTRIDE + i * PMAX + j] : NAN;
+  }
+  for (int j = threadIdx.x; j < p; j += blockDim.x) {
+    if (o.mu) o.mu[j] = ok ? loc[j] + sc[j] * G.muz[(size_t)g1 * PMAX + j] : NAN;
+    if (o.mu_raw) o.mu_raw[j] = ok ? loc[j] + sc[j] * F.muraw[(size_t)dd * PMAX + j] : NAN;
+    if (o.loc) o.loc[j] = loc[j];
+    if (o.scale) o.scale[j] = sc[j];
+  }
+  for (int b = threadIdx.x; b < d.q; b += blockDim.x) {
+    if (o.block_status) o.block_status[b] = F.bstat[d.blk0 + b];
+    if (o.block_start) o.block_start[b] = F.bstart[d.blk0 + b];
+    if (o.block_iters) o.block_iters[b] = F.biters[d.blk0 + b];
+  }
+  if (threadIdx.x == 0) {
+    double ls = 0.0;
+    for (int j = 0; j < p; ++j) ls += 2.0 * log(sc[j]);
+    if (o.logdet) {
+      o.logdet[0] = ok ? G.logdet[g0] + ls : NAN;
+      o.logdet[1] = ok ? G.logdet[g1] + ls : NAN;
+    }
+    if (o.n_w) *o.n_w = ok ? F.nw[dd] : 0;
+  }
+}
+
+template <typename T, int P, int MODE>
+hipError_t project_t(const ItemDesc* items, const Tile* tiles, int ntiles, int tile_rows,
+                     const int32_t* status, const double* W, const int64_t* kbase, uint64_t* keys,
+                     hipStream_t s) {
+  hipLaunchKernelGGL((k_project<T, P, MODE>), dim3(ntiles), dim3(256), 0, s, items, tiles,
+                     tile_rows, status, W, kbase, keys);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_colkeys(int dtype, const void* X, int64_t n, int64_t ld, int p, void* keys,
+                          hipStream_t s) {
+  int64_t nb = (n + 255) / 256;
+  if (nb > 8192) nb = 8192;
+  if (nb < 1) return hipSuccess;
+  if (dtype == 0)
+    hipLaunchKernelGGL((k_colkeys<float, uint32_t>), dim3((unsigned)nb), dim3(256), 0, s,
+                       static_cast<const float*>(X), n, ld, p, static_cast<uint32_t*>(keys));
+  else
+    hipLaunchKernelGGL((k_colkeys<double, uint64_t>), dim3((unsigned)nb), dim3(256), 0, s,
+                       static_cast<const double*>(X), n, ld, p, static_cast<uint64_t*>(keys));
+  return hipGetLastError();
+}
+
+hipError_t launch_std_finish(const SegStat* st32, const SegStat* st64, const int32_t* seg0,
+                             const int32_t* in64, int D, DsInfo* ds, FitArrays F, hipStream_t s) {
+  hipLaunchKernelGGL(k_std_finish, dim3(D), dim3(64), 0, s, st32, st64, seg0, in64, D, ds, F);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(int bucket, int dtype, int mode, const ItemDesc* items,
+                          const Tile* tiles, int ntiles, int tile_rows, const int32_t* status,
+                          const double* W, const int64_t* kbase, uint64_t* keys, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+#define CASE(PB)                                                                               \
+  case PB:                                                                                     \
+    if (dtype == 0)                                                                            \
+      return mode == 0 ? project_t<float, PB, 0>(items, tiles, ntiles, tile_rows, status, W,   \
+                                                 kbase, keys, s)                               \
+                       : project_t<float, PB, 1>(items, tiles, ntiles, tile_rows, status, W,   \
+                                                 kbase, keys, s);                              \
+    return mode == 0 ? project_t<double, PB, 0>(items, tiles, ntiles, tile_rows, status, W,    \
+                                                kbase, keys, s)                                \
+                     : project_t<double, PB, 1>(items, tiles, ntiles, tile_rows, status, W,    \
+                                                kbase, keys, s);
+  switch (bucket) {
+    CASE(4) CASE(5) CASE(8) CASE(10) CASE(16) CASE(20) CASE(24) CASE(32) CASE(40) CASE(48)
+    CASE(64)
+    default: return hipErrorInvalidValue;
+  }
+#undef CASE
+}
+
+hipError_t launch_reduce_partials(const ItemDesc* items, const double* part, int first, int n,
+                                  double* cnt, double* sum, double* S, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_partials, dim3(n), dim3(256), 0, s, items, part, first, cnt, sum, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_cov(int mode, const ItemDesc* bitems, int first, int n, FitArrays F,
+                           ItemArrays C, const DsInfo* ds, double* cut, const SegStat* gst,
+                           hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init_cov, dim3(n), dim3(256), 0, s, mode, bitems, first, F, C, ds, cut, gst);
+  return hipGetLastError();
+}
+
+hipError_t launch_eig(const ItemDesc* items, ItemArrays A, FitArrays F, int first, int n,
+                      double kappa_max, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_eig, dim3(n), dim3(64), 0, s, items, A, F, first, kappa_max);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine(int stage, const ItemDesc* items, ItemArrays A, FitArrays F, int first,
+                         int n, const SegStat* st, const int32_t* seg0, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_refine, dim3(n), dim3(256), 0, s, stage, items, A, F, first, st, seg0);
+  return hipGetLastError();
+}
+
+hipError_t launch_choose(const ItemDesc* bitems, const ItemDesc* citems, ItemArrays A,
+                         FitArrays F, const DsInfo* ds, int first, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_choose, dim3(n), dim3(256), 0, s, bitems, citems, A, F, ds, first);
+  return hipGetLastError();
+}
+
+hipError_t launch_median(const DsInfo* ds, FitArrays F, const int2* ent, int nent,
+                         hipStream_t s) {
+  if (nent <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_median, dim3(nent), dim3(256), 0, s, ds, F, ent);
+  return hipGetLastError();
+}
+
+hipError_t launch_kl(const DsInfo* ds, ItemArrays A, FitArrays F, int first_blk, int nblk,
+                     hipStream_t s) {
+  if (nblk <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_kl, dim3(nblk), dim3(256), 0, s, ds, A, F, first_blk);
+  return hipGetLastError();
+}
+
+hipError_t launch_pool(DsInfo* ds, ItemArrays G, FitArrays F, int first_ds, int nds, int,
+                       hipStream_t s) {
+  if (nds <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pool, dim3(nds), dim3(256), 0, s, ds, G, F, first_ds);
+  return hipGetLastError();
+}
+
+hipError_t launch_rew(DsInfo* ds, const ItemDesc* gitems, ItemArrays G, FitArrays F, int first_ds,
+                      int nds, hipStream_t s) {
+  if (nds <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rew, dim3(nds), dim3(256), 0, s, ds, gitems, G, F, first_ds);
+  return hipGetLastError();
+}
+
+hipError_t launch_hsub(const ItemDesc* citems, ItemArrays A, FitArrays F, const DsInfo* ds,
+                       const rtdetmcd_out* outs, int first, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hsub, dim3(n), dim3(1024), 0, s, citems, A, F, ds, outs, first);
+  return hipGetLastError();
+}
+
+hipError_t launch_outputs(const DsInfo* ds, ItemArrays G, FitArrays F, const rtdetmcd_out* outs,
+                          int first_ds, int nds, hipStream_t s) {
+  if (nds <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_outputs, dim3(nds), dim3(256), 0, s, ds, G, F, outs, first_ds);
+  return hipGetLastError();
+}
+
+}  // namespace rtd

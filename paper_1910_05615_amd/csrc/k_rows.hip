@@ -4,6 +4,7 @@
 // float32 inputs are widened exactly.  Each kernel is instantiated per
 // p-bucket P (p <= P, the padding contributes exact zeros).
 #include "common.h"
+#include "fitk.h"
 
 namespace rtd {
 
@@ -127,8 +128,7 @@ __global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items
   for (int j = 0; j < P; ++j) {
     double v = 0.0;
     if (j < p) {
-      if (MODE == SSCP_CSTEP) v = A.mux[(size_t)it * PMAX + j];
-      else if (MODE == SSCP_D2CUT) v = pivot[(size_t)D.ds * pivot_stride + j];
+      if (MODE == SSCP_CSTEP || MODE == SSCP_D2CUT) v = A.mux[(size_t)it * PMAX + j];
     }
     c[j] = v;
   }
@@ -276,6 +276,62 @@ __global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items
   }
 }
 
+// Final robust distances and flags (Sec. 4 step 10): RD = sqrt(d2) and
+// outlier = d2 > chi2_{p,q}; the decision is taken on the float64 d2.
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_final_dist(const ItemDesc* __restrict__ items,
+                                                    const Tile* __restrict__ tiles, int tile_rows,
+                                                    const double* __restrict__ mtri,
+                                                    const double* __restrict__ mux,
+                                                    const DsInfo* __restrict__ ds,
+                                                    const rtdetmcd_out* __restrict__ outs) {
+  const Tile tl = tiles[blockIdx.x];
+  const int it = tl.item;
+  const ItemDesc D = items[it];
+  const DsInfo dd = ds[D.ds];
+  if (dd.err) return;
+  const int p = D.p;
+  const double cut = dd.chi2p;
+  const double* __restrict__ M = mtri + (size_t)it * TRI;
+  const double* __restrict__ mu = mux + (size_t)it * PMAX;
+  const T* __restrict__ X = static_cast<const T*>(D.X) + D.row0 * D.ld;
+  const int64_t r0 = (int64_t)tl.t * tile_rows;
+  const int64_t r1 = min(r0 + (int64_t)tile_rows, D.m);
+  double* __restrict__ od = outs[D.ds].dist;
+  uint8_t* __restrict__ of = outs[D.ds].outlier;
+  if (od) od += D.row0;
+  if (of) of += D.row0;
+  double muv[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) muv[j] = mu[j];
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+    const T* __restrict__ xr = X + r * D.ld;
+    double z[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) z[j] = (j < p) ? ld_elem(xr, j) - muv[j] : 0.0;
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      double y = 0.0;
+#pragma unroll
+      for (int j = 0; j <= i; ++j) y = fma(M[i * (i + 1) / 2 + j], z[j], y);
+      acc = fma(y, y, acc);
+    }
+    if (od) od[r] = sqrt(acc);
+    if (of) of[r] = acc > cut ? 1 : 0;
+  }
+}
+
+template <typename T, int P>
+hipError_t final_t(const ItemDesc* items, const Tile* tiles, int ntiles, int tile_rows,
+                   const double* mtri, const double* mux, const DsInfo* ds,
+                   const rtdetmcd_out* outs, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_final_dist<T, P>), dim3(ntiles), dim3(256), 0, s, items, tiles, tile_rows,
+                     mtri, mux, ds, outs);
+  return hipGetLastError();
+}
+
 template <typename T, int P>
 hipError_t dist_t(const ItemDesc* items, const Tile* tiles, int ntiles, int tile_rows,
                   const double* mtri, const double* mux, const int32_t* status, double* d2,
@@ -324,6 +380,22 @@ hipError_t launch_dist(int bucket, int dtype, const ItemDesc* items, const Tile*
                                           d2, s)                                              \
                       : dist_t<double, PB>(items, tiles, ntiles, tile_rows, mtri, mux, status, \
                                            d2, s);
+  switch (bucket) {
+    RTD_BUCKETS(CASE)
+    default: return hipErrorInvalidValue;
+  }
+#undef CASE
+}
+
+hipError_t launch_final_dist(int bucket, int dtype, const ItemDesc* items, const Tile* tiles,
+                             int ntiles, int tile_rows, const double* mtri, const double* mux,
+                             const DsInfo* ds, const rtdetmcd_out* outs, hipStream_t s) {
+#define CASE(PB)                                                                              \
+  case PB:                                                                                    \
+    return dtype == 0 ? final_t<float, PB>(items, tiles, ntiles, tile_rows, mtri, mux, ds,    \
+                                           outs, s)                                           \
+                      : final_t<double, PB>(items, tiles, ntiles, tile_rows, mtri, mux, ds,   \
+                                            outs, s);
   switch (bucket) {
     RTD_BUCKETS(CASE)
     default: return hipErrorInvalidValue;

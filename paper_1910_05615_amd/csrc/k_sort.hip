@@ -44,10 +44,10 @@ __global__ __launch_bounds__(RS_NT) void k_rs_count(const K* __restrict__ keys,
 // Per segment: offsets[tile][d] = base(d) + counts of digit d in earlier tiles.
 __global__ __launch_bounds__(256) void k_rs_scan(const int32_t* __restrict__ counts,
                                                  const int32_t* __restrict__ seg_tile0,
-                                                 int32_t* __restrict__ offs) {
+                                                 int tile_first, int32_t* __restrict__ offs) {
   __shared__ int tot[256];
   const int s = blockIdx.x;
-  const int t0 = seg_tile0[s], t1 = seg_tile0[s + 1];
+  const int t0 = seg_tile0[s] - tile_first, t1 = seg_tile0[s + 1] - tile_first;
   const int d = threadIdx.x;
   int run = 0;
   for (int t = t0; t < t1; ++t) {
@@ -417,7 +417,8 @@ hipError_t sort_segments_t(SortPlan& P, hipStream_t s) {
     const int shift = 8 * ps;
     hipLaunchKernelGGL((k_rs_count<K>), dim3(P.ntiles), dim3(RS_NT), 0, s, a, P.tiles,
                        P.seg_off, P.seg_len, shift, P.counts);
-    hipLaunchKernelGGL(k_rs_scan, dim3(P.nseg), dim3(256), 0, s, P.counts, P.seg_tile0, P.offs);
+    hipLaunchKernelGGL(k_rs_scan, dim3(P.nseg), dim3(256), 0, s, P.counts, P.seg_tile0,
+                       P.tile_first, P.offs);
     hipLaunchKernelGGL((k_rs_scatter<K>), dim3(P.ntiles), dim3(RS_NT), 0, s, a, b, P.tiles,
                        P.seg_off, P.seg_len, shift, P.offs);
     K* t = a;
@@ -438,11 +439,11 @@ hipError_t launch_segstats(const SortPlan& P, const double* seg_craw, double q1,
   if (P.nseg <= 0) return hipSuccess;
   if (P.key_bytes == 4)
     hipLaunchKernelGGL((k_segstats<uint32_t>), dim3(P.nseg), dim3(SS_NT), 0, s,
-                       static_cast<const uint32_t*>(P.keys), P.seg_off, P.seg_len, seg_craw, q1,
+                       static_cast<const uint32_t*>(P.keys), P.seg_off + P.seg_first, P.seg_len + P.seg_first, seg_craw, q1,
                        crew, mode, out);
   else
     hipLaunchKernelGGL((k_segstats<uint64_t>), dim3(P.nseg), dim3(SS_NT), 0, s,
-                       static_cast<const uint64_t*>(P.keys), P.seg_off, P.seg_len, seg_craw, q1,
+                       static_cast<const uint64_t*>(P.keys), P.seg_off + P.seg_first, P.seg_len + P.seg_first, seg_craw, q1,
                        crew, mode, out);
   return hipGetLastError();
 }

@@ -23,6 +23,25 @@ struct SortPlan {
   const int32_t* seg_tile0 = nullptr;   // [nseg + 1] first tile of each segment
   int32_t* counts = nullptr;    // [ntiles * 256]
   int32_t* offs = nullptr;      // [ntiles * 256]
+  int tile_first = 0;           // absolute index of tiles[0] (seg_tile0 holds absolute indices)
+  int seg_first = 0;            // absolute index of the first segment of the plan
+  // The plan restricted to segments [a, b): pointers offset, tile counts
+  // given by the host copy of the absolute seg_tile0 table.
+  SortPlan sub(int a, int b, const int32_t* host_seg_tile0) const {
+    SortPlan r = *this;
+    const int ta = host_seg_tile0[a], tb = host_seg_tile0[b];
+    r.nseg = b - a;
+    r.ntiles = tb - ta;
+    r.tiles = tiles + ta;
+    // tiles carry absolute segment ids, so seg_off / seg_len stay absolute;
+    // kernels that index segments by block use seg_first
+    r.seg_first = seg_first + a;
+    r.seg_tile0 = seg_tile0 + a;
+    r.counts = counts + (size_t)ta * 256;
+    r.offs = offs + (size_t)ta * 256;
+    r.tile_first = ta;
+    return r;
+  }
 };
 
 struct SegStat {

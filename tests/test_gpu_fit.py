@@ -1,0 +1,129 @@
+"""End-to-end GPU parity of rtdetmcd_fit / rtdetmcd_fit_batched against the
+float64 CPU oracle.  h-subsets, flags, block status/start/iteration counts and
+n_w must match exactly; location/scatter within the stated relative bounds."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synthdata
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# Tolerances (float64 arithmetic on both sides; far inside the 1e-5 relative
+# Frobenius / 1e-6 log-det bar of the method's float32 targets).
+TOL_SIG = 1e-8
+TOL_MU = 1e-8
+TOL_LD = 1e-8
+
+
+def _P():
+    import paper_1910_05615_amd as P
+    return P
+
+
+def _dev():
+    return torch.device("cuda:0")
+
+
+def _relF(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _mahal(mu, ref_mu, ref_sig):
+    d = mu - ref_mu
+    return math.sqrt(max(float(d @ np.linalg.solve(ref_sig, d)), 0.0))
+
+
+def check_fit(F, ref, label=""):
+    g = lambda t: t.cpu().numpy()
+    assert (F.q, F.m, F.h) == (ref.q, ref.m, ref.h), label
+    assert np.array_equal(g(F.block_status), ref.chunk_status), label
+    assert np.array_equal(g(F.block_start), ref.chunk_start), label
+    assert np.array_equal(g(F.block_iters), ref.chunk_iters), label
+    assert np.array_equal(g(F.hsubset), ref.hsubset.astype(np.int32)), label
+    assert int(g(F.n_w)[0]) == ref.n_w, label
+    assert np.array_equal(g(F.outlier), ref.outlier), label
+    np.testing.assert_allclose(g(F.loc), ref.loc, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(g(F.scale), ref.scale, rtol=1e-12)
+    assert _relF(g(F.sigma_raw), ref.sigma_raw) < TOL_SIG, label
+    assert _relF(g(F.sigma), ref.sigma) < TOL_SIG, label
+    assert _mahal(g(F.mu_raw), ref.mu_raw, ref.sigma_raw) < TOL_MU, label
+    assert _mahal(g(F.mu), ref.mu, ref.sigma) < TOL_MU, label
+    ld = g(F.logdet)
+    assert abs(ld[0] - ref.logdet_raw) < TOL_LD and abs(ld[1] - ref.logdet_rew) < TOL_LD, label
+    np.testing.assert_allclose(g(F.dist), ref.dist, rtol=1e-9, atol=1e-12)
+
+
+def _run(X, **kw):
+    return _P().fit(torch.from_numpy(X).to(_dev()), **kw)
+
+
+def test_fit_single_block_f64():
+    ds = synthdata.workload_single_chunk_f64()           # n=10000, p=10, float64
+    ref = oracle.fit(ds.X)
+    check_fit(_run(ds.X), ref, "single block f64")
+
+
+@pytest.mark.parametrize("cstep_mode", ["full", "update", "auto"])
+def test_fit_chunked_p20_small(cstep_mode):
+    ds = synthdata.workload_chunked_p20(n=100_003)
+    ref = oracle.fit(ds.X, n_chunks=8)
+    check_fit(_run(ds.X, n_chunks=8, cstep_mode=cstep_mode), ref, cstep_mode)
+
+
+def test_fit_plain_equals_batched_bitwise():
+    ds = synthdata.workload_chunked_p20(n=60_000)
+    a = _run(ds.X, n_chunks=4, launch="batched")
+    b = _run(ds.X, n_chunks=4, launch="plain")
+    for name in ("mu", "sigma", "mu_raw", "sigma_raw", "logdet", "dist", "outlier", "hsubset",
+                 "block_status", "block_start", "block_iters", "loc", "scale", "n_w"):
+        assert torch.equal(getattr(a, name), getattr(b, name)), name
+
+
+@pytest.mark.parametrize("p", [5, 40])
+def test_fit_f32_varied_p(p):
+    ds = synthdata.small_gaussian(20_000 + 7, p, seed=p, dtype=np.float32, rho=0.5, eps=0.1,
+                                  kind="shift", gamma=8)
+    ref = oracle.fit(ds.X)
+    check_fit(_run(ds.X), ref, f"p={p}")
+
+
+def test_fit_point_contamination_many_blocks():
+    ds = synthdata.small_gaussian(48_011, 4, seed=11, dtype=np.float32, rho=0.75, eps=0.2,
+                                  kind="point", gamma=6)
+    ref = oracle.fit(ds.X, n_chunks=6)
+    check_fit(_run(ds.X, n_chunks=6), ref, "point")
+
+
+def test_fit_medmad_standardisation():
+    ds = synthdata.workload_single_chunk_f64(n=5000, p=6)
+    ref = oracle.fit(ds.X, standardize="medmad")
+    check_fit(_run(ds.X, standardize="medmad"), ref, "medmad")
+
+
+def test_fit_batched_uneven_datasets():
+    P = _P()
+    sets = synthdata.workload_batched_uneven(n_datasets=6, n_lo=2000, n_hi=40_000)
+    Xs = [torch.from_numpy(s.X).to(_dev()) for s in sets]
+    fits, status = P.fit_batched(Xs)
+    assert status == [0] * len(sets)
+    for s, F in zip(sets, fits):
+        check_fit(F, oracle.fit(s.X), s.name)
+
+
+def test_fit_constant_column_is_an_error():
+    P = _P()
+    X = np.random.default_rng(0).standard_normal((3000, 3))
+    X[:, 1] = 2.5
+    with pytest.raises(P.RTDetMCDError):
+        P.fit(torch.from_numpy(X).to(_dev()))
+
+
+def test_fit_chunked_p20_full_size():
+    ds = synthdata.workload_chunked_p20()                # n=1,000,000, p=20, 64 blocks
+    ref = oracle.fit(ds.X, n_chunks=64)
+    check_fit(_run(ds.X, n_chunks=64), ref, "full size p20")
