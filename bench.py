@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""Benchmark of librtdetmcd on one MI355X.
+
+Workload: RT-DetMCD fit of one dataset, n = 1,000,000 rows, p = 20, float32
+input, AR(0.75) inliers with 10% cluster outliers, 64 contiguous blocks of
+15,625 rows, h = 11,718 per block (seeded synthetic data).  One "step" is one
+complete fit (standardisation, starts, refinement, C-steps, aggregation,
+reweighting, final distances and flags) with X resident in HBM.
+
+Prints one JSON line: rows/s fitted with the batched launch (value), the plain
+per-block launch for comparison, a live-timed roofline of the distance kernel,
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, GB/s
+FP64_VALU_TFLOPS = 78.6          # MI355X vector fp64 peak
+
+N, P, BLOCKS = 1_000_000, 20, 64
+
+
+def _events_time(fn, reps, torch):
+    """Average duration of fn() (launches on the current stream) by HIP events."""
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e-3
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--cpu-sample-blocks", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: runs on more than one GPU are not part of this "
+              "build (the fit shards by blocks; see DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1910_05615_amd as R
+    import synthdata
+
+    dev = torch.device("cuda:0")
+    ds = synthdata.workload_chunked_p20(n=N, p=P)
+    X = torch.from_numpy(ds.X).to(dev)
+    q, m, h = R.plan(N, P, 0, BLOCKS)
+
+    # ---------------------------------------------------------------- batched fit
+    for _ in range(args.warmup):
+        R.fit(X, n_chunks=BLOCKS)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s)
+    for _ in range(args.steps):
+        F = R.fit(X, n_chunks=BLOCKS)
+    e1.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev = e0.elapsed_time(e1) * 1e-3
+    t_step = max(wall, ev) / args.steps
+    value = N / t_step
+
+    # ---------------------------------------------------------------- plain fit
+    plain = None
+    if not args.no_plain:
+        Fp = R.fit(X, n_chunks=BLOCKS, launch="plain")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            Fp = R.fit(X, n_chunks=BLOCKS, launch="plain")
+        torch.cuda.synchronize()
+        tp = (time.perf_counter() - t0) / args.plain_steps
+        same = bool(torch.equal(F.hsubset, Fp.hsubset) and torch.equal(F.outlier, Fp.outlier))
+        plain = {"value": N / tp, "unit": "rows/s", "ms_per_step": tp * 1e3,
+                 "batched_over_plain": tp / t_step, "identical_hsubsets_and_flags": same}
+
+    # ---------------------------------------------------------------- kernel roofline
+    # The distance kernel (float64 arithmetic on float32 rows) over all n rows
+    # against the fitted (mu, Sigma): the same row computation as every C-step
+    # distance pass, launched alone through rtdetmcd_score.
+    sig = F.sigma
+    Lc = torch.linalg.cholesky(sig.cpu()).to(dev)
+    Linv = torch.linalg.inv(Lc.cpu()).to(dev).contiguous()
+    mu = F.mu.contiguous()
+    dist = torch.empty(N, dtype=torch.float64, device=dev)
+    flag = torch.empty(N, dtype=torch.uint8, device=dev)
+    for _ in range(3):
+        R.score_into(X, mu, Linv, dist, flag)
+    t_k = _events_time(lambda: R.score_into(X, mu, Linv, dist, flag), args.kernel_reps, torch)
+    bytes_per_row = 4 * P + 8 + 1           # read a float32 row, write float64 RD and a flag
+    alg_bytes = N * bytes_per_row
+    achieved = alg_bytes / t_k / 1e9
+    flops = N * (P * (P + 1) + 3 * P)       # triangular product, squares, centring
+    roofline = {"kernel": "k_score (distance + flag; same row code as the C-step distance pass)",
+                "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "launch_us": t_k * 1e6, "algorithmic_bytes_per_launch": alg_bytes,
+                "fp64_tflops": flops / t_k / 1e12,
+                "note": "input is 80 MB, resident in the 256 MB MALL across launches"}
+
+    # ---------------------------------------------------------------- CPU oracle
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        from threadpoolctl import threadpool_limits
+        ns = args.cpu_sample_blocks * m
+        Xs = ds.X[:ns]
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            oracle.fit(Xs, n_chunks=args.cpu_sample_blocks)
+            tc = time.perf_counter() - t0
+        cpu = {"value": ns / tc, "unit": "rows/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {args.cpu_sample_blocks} blocks ({ns} rows, p={P}) of the "
+                         f"same data, fitted with {args.cpu_sample_blocks} blocks; {tc:.1f} s"}
+
+    out = {
+        "metric": "rows/sec fitted (RT-DetMCD, p=20), batched launch",
+        "value": value, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_step * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "RT-DetMCD one dataset n=1,000,000 p=20 float32 input, "
+                               "64 blocks of 15,625 rows, AR(0.75) with 10% cluster outliers",
+                   "n": N, "p": P, "blocks": q, "m": m, "h": h, "input_dtype": "f32",
+                   "launch": "batched"},
+        "plain": plain,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fit_check": {"n_w": int(F.n_w.item()),
+                      "outliers_flagged": int(F.outlier.sum().item()),
+                      "blocks_valid": int((F.block_status < 3).sum().item())},
+    }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

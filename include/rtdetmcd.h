@@ -163,6 +163,17 @@ rtdetmcd_status rtdetmcd_distances(rtdetmcd_handle h, const void* X, int32_t dty
                                    int32_t p, int64_t ld, const double* mu, const double* L,
                                    double* d2);
 
+/* Robust distances and outlier flags of n rows against a stored fit: the
+ * last step of Sec. 4 (step 10), used on its own to score new data against a
+ * trained fit (Sec. 6).  mu [p] and Linv [p*p] are device float64; Linv is the
+ * inverse of the lower Cholesky factor of Sigma, row-major (lower triangle
+ * read), so that d2_i = ||Linv (x_i - mu)||^2.  dist [n] (float64, nullable)
+ * receives sqrt(d2_i); outlier [n] (nullable) receives d2_i > cut, with
+ * cut <= 0 meaning chi2_{p,0.975}.  One kernel launch. */
+rtdetmcd_status rtdetmcd_score(rtdetmcd_handle h, const void* X, int32_t dtype, int64_t n,
+                               int32_t p, int64_t ld, const double* mu, const double* Linv,
+                               double cut, double* dist, uint8_t* outlier);
+
 /* Indices of the h_sub smallest d2 values, ties broken by the smaller index
  * (C-step steps 2-3 of Sec. 2.1).  idx [h_sub] receives them ascending; mask
  * [m] (nullable) receives 1 for selected rows and 0 otherwise.  Exact: the

@@ -18,7 +18,7 @@ SYMBOLS = [
     "rtdetmcd_create", "rtdetmcd_destroy", "rtdetmcd_set_stream", "rtdetmcd_last_error",
     "rtdetmcd_default_opts", "rtdetmcd_plan", "rtdetmcd_fit", "rtdetmcd_fit_batched",
     "rtdetmcd_chi2_quantile", "rtdetmcd_chi2_cdf", "rtdetmcd_consistency",
-    "rtdetmcd_distances", "rtdetmcd_select", "rtdetmcd_cstep",
+    "rtdetmcd_distances", "rtdetmcd_score", "rtdetmcd_select", "rtdetmcd_cstep",
 ]
 
 
@@ -67,6 +67,8 @@ def load() -> C.CDLL:
         "rtdetmcd_chi2_cdf": (c_f64, [c_f64, c_i32]),
         "rtdetmcd_consistency": (c_f64, [c_f64, c_i32]),
         "rtdetmcd_distances": (c_i32, [c_vp, c_vp, c_i32, c_i64, c_i32, c_i64, c_vp, c_vp, c_vp]),
+        "rtdetmcd_score": (c_i32, [c_vp, c_vp, c_i32, c_i64, c_i32, c_i64, c_vp, c_vp, c_f64,
+                                   c_vp, c_vp]),
         "rtdetmcd_select": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_vp, c_vp]),
         "rtdetmcd_cstep": (c_i32, [c_vp, c_vp, c_i32, c_i64, c_i32, c_i64, c_i64, c_vp, c_vp,
                                    c_vp, P(Opts), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),

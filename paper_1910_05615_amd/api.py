@@ -257,3 +257,31 @@ def fit_batched(Xs: Sequence[torch.Tensor], h_subs: Optional[Sequence[int]] = No
     st = lib.rtdetmcd_fit_batched(hd, k, arr, C.byref(o), status)
     _check(lib, hd, st, "rtdetmcd_fit_batched")
     return fits, [int(s) for s in status]
+
+
+def score(X: torch.Tensor, mu: torch.Tensor, Linv: torch.Tensor, cut: float = 0.0):
+    """Distances and flags of the rows of X against a stored fit (mu, Linv).
+
+    Linv is the inverse lower Cholesky factor of Sigma; cut <= 0 uses
+    chi2_{p,0.975}.  Returns (dist float64 [n], outlier uint8 [n])."""
+    _check_X(X)
+    n, p = X.shape
+    lib, h = _handle(X.device)
+    mu = mu.to(device=X.device, dtype=torch.float64).contiguous()
+    Linv = Linv.to(device=X.device, dtype=torch.float64).contiguous()
+    dist = torch.empty(n, dtype=torch.float64, device=X.device)
+    flag = torch.empty(n, dtype=torch.uint8, device=X.device)
+    st = lib.rtdetmcd_score(h, _ptr(X), _dtype_code(X), n, p, X.stride(0), _ptr(mu), _ptr(Linv),
+                            float(cut), _ptr(dist), _ptr(flag))
+    _check(lib, h, st, "rtdetmcd_score")
+    return dist, flag
+
+
+def score_into(X: torch.Tensor, mu: torch.Tensor, Linv: torch.Tensor, dist: torch.Tensor,
+               flag: torch.Tensor, cut: float = 0.0) -> None:
+    """score() into preallocated outputs (no allocation; for timing loops)."""
+    n, p = X.shape
+    lib, h = _handle(X.device)
+    st = lib.rtdetmcd_score(h, _ptr(X), _dtype_code(X), n, p, X.stride(0), _ptr(mu), _ptr(Linv),
+                            float(cut), _ptr(dist), _ptr(flag))
+    _check(lib, h, st, "rtdetmcd_score")

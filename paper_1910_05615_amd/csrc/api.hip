@@ -68,7 +68,7 @@ void layout_items(Layout& L, const ItemSet& S, size_t off[20]) {
   off[10] = L.add(I * PMAX * 8);     // muz
   off[11] = L.add(I * MSTRIDE * 8);  // sigz
   off[12] = L.add(I * MSTRIDE * 8);  // linv
-  off[13] = L.add(I * TRI * 8);      // mtri
+  off[13] = L.add(I * MSTRIDE * 8);  // mtri
   off[14] = L.add((size_t)S.rows * 8);   // d2
   off[15] = L.add((size_t)S.rows);       // mask
   off[16] = L.add((size_t)S.rows * 4);   // swap
@@ -341,6 +341,23 @@ rtdetmcd_status rtdetmcd_distances(rtdetmcd_handle ctx, const void* X, int32_t d
   // the distance kernel writes d2 + roff with roff = 0
   RTD_HIP(launch_dist(bucket_of(p), dtype, D.items, D.dtiles, (int)S.dtiles.size(), DIST_TILE,
                       D.A.mtri, D.A.mux, nullptr, d2, ctx->stream));
+  return RTDETMCD_OK;
+}
+
+rtdetmcd_status rtdetmcd_score(rtdetmcd_handle ctx, const void* X, int32_t dtype, int64_t n,
+                               int32_t p, int64_t ld, const double* mu, const double* Linv,
+                               double cut, double* dist, uint8_t* outlier) {
+  if (!ctx) return RTDETMCD_EINVAL;
+  if (!X || !mu || !Linv || n < 0 || p < 1 || ld < p || (dtype != 0 && dtype != 1)) {
+    ctx->err = "rtdetmcd_score: bad argument";
+    return RTDETMCD_EINVAL;
+  }
+  if (p > RTDETMCD_MAX_P) return RTDETMCD_EUNSUPPORTED;
+  if (n == 0) return RTDETMCD_OK;
+  RTD_HIP(hipSetDevice(ctx->device));
+  const double c = cut > 0.0 ? cut : chi2_quantile(0.975, p);
+  RTD_HIP(launch_score(bucket_of(p), dtype, X, n, ld, p, mu, Linv, p, c, dist, outlier,
+                       ctx->stream));
   return RTDETMCD_OK;
 }
 

@@ -51,7 +51,7 @@ struct ItemArrays {
   double* muz;       // [I*PMAX] current mean, standardised units
   double* sigz;      // [I*MSTRIDE] current covariance, standardised units
   double* linv;      // [I*MSTRIDE] inverse Cholesky factor of sigz
-  double* mtri;      // [I*TRI] packed L^{-1} D^{-1}: distances in data units
+  double* mtri;      // [I*MSTRIDE] L^{-1} D^{-1} (lower, row stride PMAX): distances in data units
   double* d2;        // [rows] squared distances
   uint8_t* mask;     // [rows] current subset
   int32_t* swap;     // [rows] entering rows from 0, leaving rows from m/2
@@ -106,7 +106,8 @@ hipError_t launch_chol_factor(const double* sigma, int p, double* mtri, hipStrea
 hipError_t launch_extract_subset(const ItemDesc* items, ItemArrays A, int first_item, int nitems,
                                  int32_t* out, int64_t out_stride, int global_rows,
                                  hipStream_t s);
-hipError_t launch_select_plain(const double* d2, int64_t m, int64_t h, int32_t* idx,
-                               uint8_t* mask, hipStream_t s);
+hipError_t launch_score(int bucket, int dtype, const void* X, int64_t n, int64_t ld, int p,
+                        const double* mu, const double* M, int ldm, double cut, double* dist,
+                        uint8_t* flag, hipStream_t s);
 
 }  // namespace rtd

@@ -283,12 +283,10 @@ __global__ __launch_bounds__(FIN_NT) void k_finalize(const ItemDesc* __restrict_
   }
   __syncthreads();
   double* __restrict__ linv = A.linv + (size_t)it * MSTRIDE;
-  double* __restrict__ mt = A.mtri + (size_t)it * TRI;
-  for (int e = tid; e < TRI; e += FIN_NT) {
-    int i = 0, k = e;
-    while (k > i) { k -= i + 1; ++i; }
-    const int j = k;
-    mt[e] = (i < p && j < p) ? Li[i * PMAX + j] / D.scale[j] : 0.0;
+  double* __restrict__ mt = A.mtri + (size_t)it * MSTRIDE;
+  for (int e = tid; e < p * PMAX; e += FIN_NT) {
+    const int i = e / PMAX, j = e % PMAX;
+    mt[e] = (j <= i) ? Li[i * PMAX + j] / D.scale[j] : 0.0;
   }
   for (int e = tid; e < p * p; e += FIN_NT) {
     const int i = e / p, j = e % p;
@@ -327,7 +325,7 @@ __global__ void k_fill_u8(uint8_t* p, uint8_t v, int64_t n) {
     p[i] = v;
 }
 
-// Packed inverse of a given lower Cholesky factor (for the low-level distance call).
+// Inverse of a given lower Cholesky factor, row stride PMAX (low-level distance call).
 __global__ void k_chol_factor(const double* __restrict__ L, int p, double* __restrict__ mt) {
   __shared__ double Li[PMAX * PMAX];
   const int tid = threadIdx.x;
@@ -341,10 +339,9 @@ __global__ void k_chol_factor(const double* __restrict__ L, int p, double* __res
     }
   }
   __syncthreads();
-  for (int e = tid; e < TRI; e += blockDim.x) {
-    int i = 0, k = e;
-    while (k > i) { k -= i + 1; ++i; }
-    mt[e] = (i < p && k < p) ? Li[i * PMAX + k] : 0.0;
+  for (int e = tid; e < p * PMAX; e += blockDim.x) {
+    const int i = e / PMAX, k = e % PMAX;
+    mt[e] = (k <= i) ? Li[i * PMAX + k] : 0.0;
   }
 }
 

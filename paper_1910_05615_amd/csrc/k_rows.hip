@@ -30,6 +30,27 @@ __device__ inline double wrap_g(double z) {
 // One thread per row; M and mu are uniform per block and are read through the
 // scalar cache.
 // ---------------------------------------------------------------------------
+// Squared distance of one row: z = x - mu, y = M z (M lower triangular,
+// row stride ldm), d2 = sum y_i^2.  M and mu are uniform per block.
+template <typename T, int P>
+__device__ inline double row_d2(const T* __restrict__ xr, int p, const double* muv,
+                                const double* __restrict__ M, int ldm) {
+  double z[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) z[j] = (j < p) ? ld_elem(xr, j) - muv[j] : 0.0;
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    if (i < p) {
+      double y = 0.0;
+#pragma unroll
+      for (int j = 0; j <= i; ++j) y = fma(M[i * ldm + j], z[j], y);
+      acc = fma(y, y, acc);
+    }
+  }
+  return acc;
+}
+
 template <typename T, int P>
 __global__ __launch_bounds__(256) void k_dist(const ItemDesc* __restrict__ items,
                                               const Tile* __restrict__ tiles, int tile_rows,
@@ -42,7 +63,7 @@ __global__ __launch_bounds__(256) void k_dist(const ItemDesc* __restrict__ items
   if (status != nullptr && status[it] != ACTIVE) return;
   const ItemDesc D = items[it];
   const int p = D.p;
-  const double* __restrict__ M = mtri + (size_t)it * TRI;
+  const double* __restrict__ M = mtri + (size_t)it * MSTRIDE;
   const double* __restrict__ mu = mux + (size_t)it * PMAX;
   const T* __restrict__ X = static_cast<const T*>(D.X) + D.row0 * D.ld;
   const int64_t r0 = (int64_t)tl.t * tile_rows;
@@ -50,21 +71,29 @@ __global__ __launch_bounds__(256) void k_dist(const ItemDesc* __restrict__ items
   double* __restrict__ out = d2 + D.roff;
   double muv[P];
 #pragma unroll
-  for (int j = 0; j < P; ++j) muv[j] = mu[j];
+  for (int j = 0; j < P; ++j) muv[j] = j < p ? mu[j] : 0.0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x)
+    out[r] = row_d2<T, P>(X + r * D.ld, p, muv, M, PMAX);
+}
+
+// Distances and flags of n rows against one stored fit (Sec. 4 step 10 as
+// used for scoring new data in Sec. 6): M is the inverse Cholesky factor
+// (row-major, stride ldm), dist = sqrt(d2), flag = d2 > cut.
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_score(const T* __restrict__ X, int64_t n, int64_t ld,
+                                               int p, const double* __restrict__ mu,
+                                               const double* __restrict__ M, int ldm, double cut,
+                                               int tile_rows, double* __restrict__ dist,
+                                               uint8_t* __restrict__ flag) {
+  double muv[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) muv[j] = j < p ? mu[j] : 0.0;
+  const int64_t r0 = (int64_t)blockIdx.x * tile_rows;
+  const int64_t r1 = min(r0 + (int64_t)tile_rows, n);
   for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-    const T* __restrict__ xr = X + r * D.ld;
-    double z[P];
-#pragma unroll
-    for (int j = 0; j < P; ++j) z[j] = (j < p) ? ld_elem(xr, j) - muv[j] : 0.0;
-    double acc = 0.0;
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-      double y = 0.0;
-#pragma unroll
-      for (int j = 0; j <= i; ++j) y = fma(M[i * (i + 1) / 2 + j], z[j], y);
-      acc = fma(y, y, acc);
-    }
-    out[r] = acc;
+    const double acc = row_d2<T, P>(X + r * ld, p, muv, M, ldm);
+    if (dist) dist[r] = sqrt(acc);
+    if (flag) flag[r] = acc > cut ? 1 : 0;
   }
 }
 
@@ -292,7 +321,7 @@ __global__ __launch_bounds__(256) void k_final_dist(const ItemDesc* __restrict__
   if (dd.err) return;
   const int p = D.p;
   const double cut = dd.chi2p;
-  const double* __restrict__ M = mtri + (size_t)it * TRI;
+  const double* __restrict__ M = mtri + (size_t)it * MSTRIDE;
   const double* __restrict__ mu = mux + (size_t)it * PMAX;
   const T* __restrict__ X = static_cast<const T*>(D.X) + D.row0 * D.ld;
   const int64_t r0 = (int64_t)tl.t * tile_rows;
@@ -303,20 +332,9 @@ __global__ __launch_bounds__(256) void k_final_dist(const ItemDesc* __restrict__
   if (of) of += D.row0;
   double muv[P];
 #pragma unroll
-  for (int j = 0; j < P; ++j) muv[j] = mu[j];
+  for (int j = 0; j < P; ++j) muv[j] = j < p ? mu[j] : 0.0;
   for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-    const T* __restrict__ xr = X + r * D.ld;
-    double z[P];
-#pragma unroll
-    for (int j = 0; j < P; ++j) z[j] = (j < p) ? ld_elem(xr, j) - muv[j] : 0.0;
-    double acc = 0.0;
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-      double y = 0.0;
-#pragma unroll
-      for (int j = 0; j <= i; ++j) y = fma(M[i * (i + 1) / 2 + j], z[j], y);
-      acc = fma(y, y, acc);
-    }
+    const double acc = row_d2<T, P>(X + r * D.ld, p, muv, M, PMAX);
     if (od) od[r] = sqrt(acc);
     if (of) of[r] = acc > cut ? 1 : 0;
   }
@@ -380,6 +398,30 @@ hipError_t launch_dist(int bucket, int dtype, const ItemDesc* items, const Tile*
                                           d2, s)                                              \
                       : dist_t<double, PB>(items, tiles, ntiles, tile_rows, mtri, mux, status, \
                                            d2, s);
+  switch (bucket) {
+    RTD_BUCKETS(CASE)
+    default: return hipErrorInvalidValue;
+  }
+#undef CASE
+}
+
+hipError_t launch_score(int bucket, int dtype, const void* X, int64_t n, int64_t ld, int p,
+                        const double* mu, const double* M, int ldm, double cut, double* dist,
+                        uint8_t* flag, hipStream_t s) {
+  const int tile_rows = 2048;
+  const int64_t nb = (n + tile_rows - 1) / tile_rows;
+  if (nb <= 0) return hipSuccess;
+#define CASE(PB)                                                                               \
+  case PB:                                                                                     \
+    if (dtype == 0)                                                                            \
+      hipLaunchKernelGGL((k_score<float, PB>), dim3((unsigned)nb), dim3(256), 0, s,            \
+                         static_cast<const float*>(X), n, ld, p, mu, M, ldm, cut, tile_rows,   \
+                         dist, flag);                                                          \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_score<double, PB>), dim3((unsigned)nb), dim3(256), 0, s,           \
+                         static_cast<const double*>(X), n, ld, p, mu, M, ldm, cut, tile_rows,  \
+                         dist, flag);                                                          \
+    return hipGetLastError();
   switch (bucket) {
     RTD_BUCKETS(CASE)
     default: return hipErrorInvalidValue;

@@ -158,3 +158,22 @@ def test_cstep_max_steps_and_ill_conditioned_start():
     bad = np.diag([1.0, 1.0, 1e-6])
     r3 = P.cstep(torch.from_numpy(X).to(_dev()), h, torch.from_numpy(mu0), torch.from_numpy(bad))
     assert r3.status == oracle.ST_DROP_FIRST
+
+
+@pytest.mark.parametrize("p,dtype", [(4, "f32"), (20, "f32"), (40, "f64"), (7, "f32")])
+def test_score_matches_oracle(p, dtype):
+    P = _P()
+    rng = np.random.default_rng(100 + p)
+    n = 10_000 + 33
+    X = (rng.standard_normal((n, p)) * 2 + 1).astype(np.float32 if dtype == "f32" else np.float64)
+    S = _spd(p, rng)
+    mu = rng.standard_normal(p)
+    L = np.linalg.cholesky(S)
+    Linv = np.linalg.inv(L)
+    d2 = oracle.mahalanobis2(X.astype(np.float64), mu, L)
+    cut = oracle.chi2_quantile(0.975, p)
+    dist, flag = P.score(torch.from_numpy(X).to(_dev()), torch.from_numpy(mu), torch.from_numpy(Linv))
+    np.testing.assert_allclose(dist.cpu().numpy(), np.sqrt(d2), rtol=1e-11)
+    # flags decided on float64 d2; compare away from the threshold
+    far = np.abs(d2 - cut) > 1e-9 * cut
+    assert np.array_equal(flag.cpu().numpy()[far], (d2 > cut).astype(np.uint8)[far])
