@@ -91,8 +91,16 @@ rtdetmcd_status sort_stats(rtdetmcd_ctx* ctx, const SortHost& H, SortDev& D, int
                            int mode, double q1, double crew1) {
   if (b <= a) return RTDETMCD_OK;
   SortPlan P = D.plan.sub(a, b, H.tile0.data());
+  const int64_t maxlen = *std::max_element(H.len.begin() + a, H.len.begin() + b);
+  if (maxlen <= lds_sort_capacity()) {
+    RTD_HIP(launch_seg_lds(P, D.craw + a, q1, crew1, mode, D.st + a, ctx->stream));
+    return RTDETMCD_OK;
+  }
   RTD_HIP(sort_segments(P, ctx->stream));
-  RTD_HIP(launch_segstats(P, D.craw + a, q1, crew1, mode, D.st + a, ctx->stream));
+  if (mode == SEGSTAT_UNIMCD)
+    RTD_HIP(launch_unimcd_multiblock(P, D.craw + a, q1, crew1, D.st + a, ctx->stream));
+  else
+    RTD_HIP(launch_segstats(P, D.craw + a, q1, crew1, mode, D.st + a, ctx->stream));
   return RTDETMCD_OK;
 }
 
@@ -262,6 +270,12 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
                                     SR.tiles.size()});
   const size_t o_keys = L.add((size_t)kbytes), o_tmp = L.add((size_t)kbytes);
   const size_t o_counts = L.add(maxtiles * 256 * 4), o_offs = L.add(maxtiles * 256 * 4);
+  const size_t maxseg = std::max({(size_t)S32.nseg() + S64.nseg(), (size_t)SN.nseg(),
+                                  (size_t)SR.nseg()});
+  size_t o_mb[9];
+  for (int k = 0; k < 7; ++k) o_mb[k] = L.add(maxtiles * 8);
+  o_mb[7] = L.add(maxseg * 2 * 8);
+  o_mb[8] = L.add(maxseg * 5 * 8);
   RTD_TRY(ensure_ws(ctx, L.off));
   char* base = static_cast<char*>(ctx->ws);
 
@@ -301,12 +315,23 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   char* tmp = base + o_tmp;
   int32_t* counts = reinterpret_cast<int32_t*>(base + o_counts);
   int32_t* offs = reinterpret_cast<int32_t*>(base + o_offs);
+  MbScratch mbs;
+  mbs.bs1 = reinterpret_cast<double*>(base + o_mb[0]);
+  mbs.bs2 = reinterpret_cast<double*>(base + o_mb[1]);
+  mbs.wbest = reinterpret_cast<double*>(base + o_mb[2]);
+  mbs.wj = reinterpret_cast<int64_t*>(base + o_mb[3]);
+  mbs.k0 = reinterpret_cast<double*>(base + o_mb[4]);
+  mbs.k1 = reinterpret_cast<double*>(base + o_mb[5]);
+  mbs.k2 = reinterpret_cast<double*>(base + o_mb[6]);
+  mbs.tot = reinterpret_cast<double*>(base + o_mb[7]);
+  mbs.prm = reinterpret_cast<double*>(base + o_mb[8]);
   // the 32-bit and 64-bit standardisation sorts share the key buffer
   bind_sort(base, S32, D32, keys, tmp, counts, offs);
   bind_sort(base, S64, D64, keys + S32.keys * 4, tmp + S32.keys * 4,
             counts + S32.tiles.size() * 256, offs + S32.tiles.size() * 256);
   bind_sort(base, SN, DN, keys, tmp, counts, offs);
   bind_sort(base, SR, DR, keys, tmp, counts, offs);
+  D32.plan.mb = D64.plan.mb = DN.plan.mb = DR.plan.mb = &mbs;
 
   ItemDev CD, BD, GD;
   bind_items(base, C, offC, CD);

@@ -176,96 +176,136 @@ __global__ void k_init_cov(int mode, const ItemDesc* __restrict__ bitems, int fi
 
 // ------------------------------------------------------------ refinement (Sec. 3.3)
 
-// Cyclic Jacobi eigen-decomposition of the initial scatter of each item, one
-// wave per matrix; eigenvalues in decreasing order (step 1) and the condition
-// check lambda_1 / lambda_p <= kappa_max (step 2).
-__global__ __launch_bounds__(64) void k_eig(const ItemDesc* __restrict__ items, ItemArrays A,
-                                            FitArrays F, int first, double kappa_max) {
+// Jacobi eigen-decomposition of the initial scatter of each item, one block
+// per matrix; eigenvalues in decreasing order (step 1) and the condition check
+// lambda_1 / lambda_p <= kappa_max (step 2).
+__global__ __launch_bounds__(256) void k_eig(const ItemDesc* __restrict__ items, ItemArrays A,
+                                             FitArrays F, int first, double kappa_max) {
+  // Parallel cyclic Jacobi: each step applies p/2 disjoint rotations chosen by
+  // the round-robin (circle) ordering, as one column pass A J and one row pass
+  // J^T A; p - 1 steps make a sweep over all pairs.
   __shared__ double a[PMAX * PMAX];
   __shared__ double v[PMAX * PMAX];
-  __shared__ double red[64];
+  __shared__ double cs_c[PMAX / 2], cs_s[PMAX / 2];
+  __shared__ int pi[PMAX / 2], pj[PMAX / 2];
+  __shared__ double red[256];
   __shared__ int ord[PMAX];
   const int it = first + blockIdx.x;
   if (A.status[it] != ACTIVE) return;
   const int p = items[it].p;
-  const int k = threadIdx.x;
+  const int tid = threadIdx.x;
   const double* S = A.sigz + (size_t)it * MSTRIDE;
-  for (int e = k; e < p * p; e += 64) {
+  for (int e = tid; e < p * p; e += 256) {
     const int i = e / p, j = e % p;
     a[i * PMAX + j] = 0.5 * (S[i * PMAX + j] + S[j * PMAX + i]);
     v[i * PMAX + j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  for (int sweep = 0; sweep < 60; ++sweep) {
+  const int np = (p + 1) & ~1;        // players, a dummy one when p is odd
+  const int npair = np / 2;
+  for (int sweep = 0; sweep < 60 && p > 1; ++sweep) {
     double off = 0.0, dia = 0.0;
-    if (k < p)
-      for (int j = 0; j < p; ++j) {
-        const double x = a[k * PMAX + j];
-        if (j != k) off += x * x;
-        else dia += x * x;
-      }
-    red[k] = off;
+    for (int e = tid; e < p * p; e += 256) {
+      const int i = e / p, j = e % p;
+      const double x = a[i * PMAX + j];
+      if (i != j) off = fma(x, x, off);
+      else dia = fma(x, x, dia);
+    }
+    red[tid] = off;
     __syncthreads();
-    double offt = 0.0;
-    for (int q = 0; q < 64; ++q) offt += red[q];
+    if (tid == 0) {
+      double s = 0.0;
+      for (int k = 0; k < 256; ++k) s += red[k];
+      red[0] = s;
+    }
     __syncthreads();
-    red[k] = dia;
+    const double offt = red[0];
     __syncthreads();
-    double diat = 0.0;
-    for (int q = 0; q < 64; ++q) diat += red[q];
+    red[tid] = dia;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int k = 0; k < 256; ++k) s += red[k];
+      red[0] = s;
+    }
+    __syncthreads();
+    const double diat = red[0];
     __syncthreads();
     if (!(offt > 1e-30 * diat)) break;
-    for (int i = 0; i < p - 1; ++i) {
-      for (int j = i + 1; j < p; ++j) {
-        const double apq = a[i * PMAX + j];
-        if (apq == 0.0) continue;
-        const double app = a[i * PMAX + i], aqq = a[j * PMAX + j];
-        const double tau = (aqq - app) / (2.0 * apq);
-        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
-        if (k < p) {
-          const double aki = a[k * PMAX + i], akj = a[k * PMAX + j];
-          a[k * PMAX + i] = c * aki - s * akj;
-          a[k * PMAX + j] = s * aki + c * akj;
+    for (int r = 0; r < np - 1; ++r) {
+      if (tid < npair) {
+        auto pl = [&](int q) { return q == 0 ? 0 : 1 + ((q - 1 + r) % (np - 1)); };
+        int i = pl(tid), j = pl(np - 1 - tid);
+        if (i > j) { const int t = i; i = j; j = t; }
+        double c = 1.0, s = 0.0;
+        if (j < p) {
+          const double apq = a[i * PMAX + j];
+          if (apq != 0.0) {
+            const double app = a[i * PMAX + i], aqq = a[j * PMAX + j];
+            const double tau = (aqq - app) / (2.0 * apq);
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+          }
         }
-        __syncthreads();
-        if (k < p) {
-          const double aik = a[i * PMAX + k], ajk = a[j * PMAX + k];
-          a[i * PMAX + k] = c * aik - s * ajk;
-          a[j * PMAX + k] = s * aik + c * ajk;
-          const double vki = v[k * PMAX + i], vkj = v[k * PMAX + j];
-          v[k * PMAX + i] = c * vki - s * vkj;
-          v[k * PMAX + j] = s * vki + c * vkj;
-        }
-        __syncthreads();
-        if (k == 0) {
-          a[i * PMAX + j] = 0.0;
-          a[j * PMAX + i] = 0.0;
-        }
-        __syncthreads();
+        pi[tid] = i;
+        pj[tid] = j < p ? j : i;   // a rotation with the dummy is the identity
+        cs_c[tid] = c;
+        cs_s[tid] = s;
       }
+      __syncthreads();
+      // columns: A <- A J, V <- V J
+      for (int e = tid; e < p * npair; e += 256) {
+        const int rr = e / npair, k = e % npair;
+        const int i = pi[k], j = pj[k];
+        if (i == j) continue;
+        const double c = cs_c[k], s = cs_s[k];
+        const double ari = a[rr * PMAX + i], arj = a[rr * PMAX + j];
+        a[rr * PMAX + i] = c * ari - s * arj;
+        a[rr * PMAX + j] = s * ari + c * arj;
+        const double vri = v[rr * PMAX + i], vrj = v[rr * PMAX + j];
+        v[rr * PMAX + i] = c * vri - s * vrj;
+        v[rr * PMAX + j] = s * vri + c * vrj;
+      }
+      __syncthreads();
+      // rows: A <- J^T A
+      for (int e = tid; e < p * npair; e += 256) {
+        const int cc = e / npair, k = e % npair;
+        const int i = pi[k], j = pj[k];
+        if (i == j) continue;
+        const double c = cs_c[k], s = cs_s[k];
+        const double aic = a[i * PMAX + cc], ajc = a[j * PMAX + cc];
+        a[i * PMAX + cc] = c * aic - s * ajc;
+        a[j * PMAX + cc] = s * aic + c * ajc;
+      }
+      __syncthreads();
+      if (tid < npair && pi[tid] != pj[tid] && cs_s[tid] != 0.0) {
+        a[pi[tid] * PMAX + pj[tid]] = 0.0;
+        a[pj[tid] * PMAX + pi[tid]] = 0.0;
+      }
+      __syncthreads();
     }
   }
   // order by decreasing eigenvalue (stable in the index)
-  if (k < p) {
-    const double lk = a[k * PMAX + k];
+  if (tid < p) {
+    const double lk = a[tid * PMAX + tid];
     int r = 0;
     for (int q = 0; q < p; ++q) {
       const double lq = a[q * PMAX + q];
-      if (lq > lk || (lq == lk && q < k)) ++r;
+      if (lq > lk || (lq == lk && q < tid)) ++r;
     }
-    ord[r] = k;
+    ord[r] = tid;
   }
   __syncthreads();
   double* V = F.vbuf + (size_t)it * MSTRIDE;
   double* W = F.wbuf + (size_t)it * MSTRIDE;
-  for (int e = k; e < p * p; e += 64) {
+  for (int e = tid; e < p * p; e += 256) {
     const int i = e / p, c = e % p;
     const double x = v[i * PMAX + ord[c]];
     V[i * PMAX + c] = x;         // column c = eigenvector of the c-th largest eigenvalue
     W[c * PMAX + i] = x;         // W = V^T: scores t_c = sum_i V_ic z_i
   }
-  if (k == 0) {
+  if (tid == 0) {
     const double l1 = a[ord[0] * PMAX + ord[0]], lp = a[ord[p - 1] * PMAX + ord[p - 1]];
     if (!(lp > 0.0) || !(l1 / lp <= kappa_max)) A.status[it] = ST_DROP_REFINE;
   }
@@ -751,7 +791,7 @@ hipError_t launch_init_cov(int mode, const ItemDesc* bitems, int first, int n, F
 hipError_t launch_eig(const ItemDesc* items, ItemArrays A, FitArrays F, int first, int n,
                       double kappa_max, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_eig, dim3(n), dim3(64), 0, s, items, A, F, first, kappa_max);
+  hipLaunchKernelGGL(k_eig, dim3(n), dim3(256), 0, s, items, A, F, first, kappa_max);
   return hipGetLastError();
 }
 

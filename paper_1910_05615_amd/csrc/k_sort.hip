@@ -227,25 +227,15 @@ __device__ inline double median_sorted(const K* __restrict__ v, int64_t L) {
   return 0.5 * (a + b);
 }
 
+// Estimator over one sorted segment v[0..L) (global or LDS memory), computed
+// by the whole block; the result is valid in thread 0.  Scratch: red, pfa,
+// pfb hold SS_NT doubles each.
 template <typename K>
-__global__ __launch_bounds__(SS_NT) void k_segstats(const K* __restrict__ keys,
-                                                    const int64_t* __restrict__ seg_off,
-                                                    const int64_t* __restrict__ seg_len,
-                                                    const double* __restrict__ seg_craw,
-                                                    double q1, double crew, int mode,
-                                                    SegStat* __restrict__ out) {
-  __shared__ double red[SS_NT];
-  __shared__ double s_best[SS_NT];
-  __shared__ int64_t s_bj[SS_NT];
-  const int sg = blockIdx.x;
-  const K* __restrict__ v = keys + seg_off[sg];
-  const int64_t L = seg_len[sg];
+__device__ __noinline__ SegStat segstat_body(const K* __restrict__ v, int64_t L, double craw, double q1,
+                                double crew, int mode, double* red, double* pfa, double* pfb) {
   const int tid = threadIdx.x;
   SegStat r{};
-  if (L <= 0) {
-    if (tid == 0) out[sg] = r;
-    return;
-  }
+  if (L <= 0) return r;
   if (mode == SEGSTAT_MEDMAD) {
     if (tid == 0) {
       const double med = median_sorted(v, L);
@@ -255,9 +245,8 @@ __global__ __launch_bounds__(SS_NT) void k_segstats(const K* __restrict__ keys,
       const double mad = 1.4826 * 0.5 * (a + b);
       r.var = r.var_raw = mad * mad;
       r.n_kept = L;
-      out[sg] = r;
     }
-    return;
+    return r;
   }
   if (mode == SEGSTAT_GSSCM) {
     // norms r sorted; s = r^(2/3) is sorted as well
@@ -266,7 +255,7 @@ __global__ __launch_bounds__(SS_NT) void k_segstats(const K* __restrict__ keys,
       const double sa = pow(val_of<K>(v[(L - 1) / 2]), 2.0 / 3.0);
       const double sb = pow(val_of<K>(v[L / 2]), 2.0 / 3.0);
       const double ms = 0.5 * (sa + sb);
-      // median of |s_i - ms| by bisection over the two monotone runs of s
+      // median of |s_i - ms| over the two monotone runs of s
       int64_t lo = 0, hi = L;
       while (lo < hi) {
         const int64_t mid = (lo + hi) / 2;
@@ -294,11 +283,10 @@ __global__ __launch_bounds__(SS_NT) void k_segstats(const K* __restrict__ keys,
       const double mad = 0.5 * (dev[0] + dev[1]);
       r.mu = A;
       r.var = pow(ms + mad, 1.5);
-      out[sg] = r;
     }
-    return;
+    return r;
   }
-  // ---- univariate reweighted MCD
+  // ---- univariate reweighted MCD (Sec. 3.1)
   const int64_t hh = L / 2 + 1;
   const double c = val_of<K>(v[L / 2]);
   const int64_t a0 = (L * tid) / SS_NT, a1 = (L * (tid + 1)) / SS_NT;
@@ -310,24 +298,22 @@ __global__ __launch_bounds__(SS_NT) void k_segstats(const K* __restrict__ keys,
   }
   const double P1a = block_excl_prefix(l1, red);
   const double P2a = block_excl_prefix(l2, red);
-  // prefix at a0 + hh: owner thread's prefix plus the part of its range
+  // prefix at a0 + hh: the owner thread's prefix plus part of its range
   double P1b = 0.0, P2b = 0.0;
   const int64_t nw = L - hh + 1;             // number of windows
   const int64_t j0 = a0, j1 = a1 < nw ? a1 : nw;
-  // share the thread prefixes
-  __shared__ double pf1[SS_NT + 1], pf2[SS_NT + 1];
-  pf1[tid] = P1a;
-  pf2[tid] = P2a;
+  pfa[tid] = P1a;
+  pfb[tid] = P2a;
   __syncthreads();
   if (j0 < j1) {
     const int64_t pos = j0 + hh;             // <= L
-    int ow = (int)((pos * SS_NT) / L);       // candidate owner
+    int ow = (int)((pos * SS_NT) / L);
     if (ow > SS_NT - 1) ow = SS_NT - 1;
     while (ow > 0 && (L * ow) / SS_NT > pos) --ow;
     while (ow < SS_NT - 1 && (L * (ow + 1)) / SS_NT <= pos) ++ow;
     const int64_t ob = (L * ow) / SS_NT;
-    P1b = pf1[ow];
-    P2b = pf2[ow];
+    P1b = pfa[ow];
+    P2b = pfb[ow];
     for (int64_t k = ob; k < pos; ++k) {
       const double d = val_of<K>(v[k]) - c;
       P1b += d;
@@ -353,6 +339,9 @@ __global__ __launch_bounds__(SS_NT) void k_segstats(const K* __restrict__ keys,
       }
     }
   }
+  __syncthreads();                           // owner prefixes no longer read
+  double* s_best = pfa;
+  int64_t* s_bj = reinterpret_cast<int64_t*>(pfb);
   s_best[tid] = best;
   s_bj[tid] = bj;
   __syncthreads();
@@ -370,7 +359,7 @@ __global__ __launch_bounds__(SS_NT) void k_segstats(const K* __restrict__ keys,
   const int64_t js = s_bj[0];
   const double wmin = s_best[0];
   __syncthreads();
-  // window sums at the optimum, recomputed directly in thread order
+  // window sum at the optimum, recomputed directly in thread order
   double w1 = 0.0;
   {
     const int64_t b0 = js + (hh * tid) / SS_NT, b1 = js + (hh * (tid + 1)) / SS_NT;
@@ -378,7 +367,7 @@ __global__ __launch_bounds__(SS_NT) void k_segstats(const K* __restrict__ keys,
   }
   const double S1w = block_sum_ordered(w1, red);
   const double mu_raw = c + S1w / (double)hh;
-  const double var_raw = wmin * seg_craw[sg];
+  const double var_raw = wmin * craw;
   // reweighting: keep (v - mu_raw)^2 <= q1 var_raw
   const double lim = q1 * var_raw;
   double c0 = 0.0, c1 = 0.0, c2 = 0.0;
@@ -402,8 +391,414 @@ __global__ __launch_bounds__(SS_NT) void k_segstats(const K* __restrict__ keys,
     r.n_kept = (int64_t)N;
     r.mu = N > 0 ? c + S1 / N : NAN;
     r.var = N > 1 ? (S2 - S1 * S1 / N) / (N - 1.0) * crew : 0.0;
-    out[sg] = r;
   }
+  return r;
+}
+
+// Estimator over segments already sorted in global memory.
+template <typename K>
+__global__ __launch_bounds__(SS_NT) void k_segstats(const K* __restrict__ keys,
+                                                    const int64_t* __restrict__ seg_off,
+                                                    const int64_t* __restrict__ seg_len,
+                                                    const double* __restrict__ seg_craw,
+                                                    double q1, double crew, int mode,
+                                                    SegStat* __restrict__ out) {
+  __shared__ double red[SS_NT], pfa[SS_NT], pfb[SS_NT];
+  const int sg = blockIdx.x;
+  const SegStat r = segstat_body<K>(keys + seg_off[sg], seg_len[sg], seg_craw[sg], q1, crew, mode,
+                                    red, pfa, pfb);
+  if (threadIdx.x == 0) out[sg] = r;
+}
+
+// Sort one segment of at most LDS_KEYS keys entirely in LDS (stable LSD
+// radix, 8-bit digits, wave-ballot ranking as in k_rs_scatter), then run the
+// estimator on the sorted LDS copy.  Wave w holds the keys at positions
+// w*1024 + i*64 + lane, i < 16, so ranks follow position order.
+constexpr int LDS_KEYS = SS_NT * 16;
+
+template <typename K>
+__global__ __launch_bounds__(SS_NT) void k_seg_lds(const K* __restrict__ keys,
+                                                   const int64_t* __restrict__ seg_off,
+                                                   const int64_t* __restrict__ seg_len,
+                                                   const double* __restrict__ seg_craw,
+                                                   int seg_first, double q1, double crew, int mode,
+                                                   SegStat* __restrict__ out) {
+  __shared__ K sk[LDS_KEYS];
+  __shared__ double scratch[3 * SS_NT];        // estimator scratch / wave digit counters
+  int* wc = reinterpret_cast<int*>(scratch);   // [16][256] during the sort
+  __shared__ int dbase[256];
+  const int sb = blockIdx.x;                   // index into seg_craw / out
+  const int sg = seg_first + sb;               // absolute segment
+  const K* __restrict__ src = keys + seg_off[sg];
+  const int64_t L = seg_len[sg];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const K pad = ~(K)0;
+  K kv[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int pos = w * 1024 + i * 64 + lane;
+    kv[i] = pos < L ? src[pos] : pad;
+  }
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (int shift = 0; shift < 8 * (int)sizeof(K); shift += 8) {
+    for (int e = tid; e < 16 * 256; e += SS_NT) wc[e] = 0;
+    __syncthreads();
+    int dr[16];   // digit << 16 | rank within (wave, digit)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int d = (int)((kv[i] >> shift) & (K)0xFF);
+      uint64_t match = ~0ull;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const uint64_t bb = __ballot((d >> b) & 1);
+        match &= ((d >> b) & 1) ? bb : ~bb;
+      }
+      const int before = __popcll(match & below);
+      const int cur = wc[w * 256 + d];
+      dr[i] = (d << 16) | (cur + before);
+      if (before == 0) wc[w * 256 + d] = cur + __popcll(match);
+    }
+    __syncthreads();
+    if (tid < 256) {
+      int acc = 0;
+      for (int k = 0; k < 16; ++k) {
+        const int v = wc[k * 256 + tid];
+        wc[k * 256 + tid] = acc;
+        acc += v;
+      }
+      dbase[tid] = acc;     // digit total
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int acc = 0;
+      for (int d = 0; d < 256; ++d) {
+        const int v = dbase[d];
+        dbase[d] = acc;
+        acc += v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int d = dr[i] >> 16;
+      sk[dbase[d] + wc[w * 256 + d] + (dr[i] & 0xFFFF)] = kv[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) kv[i] = sk[w * 1024 + i * 64 + lane];
+  }
+  const SegStat r = segstat_body<K>(sk, L, seg_craw[sb], q1, crew, mode, scratch,
+                                    scratch + SS_NT, scratch + 2 * SS_NT);
+  if (tid == 0) out[sb] = r;
+}
+
+// ---------------------------------------------------------------------------
+// Univariate MCD over long sorted segments, spread over many blocks (the
+// radix tiles, RS_TILE keys each): block sums -> per-segment prefix -> window
+// minima per block -> per-segment choice of the window -> kept-row sums ->
+// per-segment result.  Same estimator as segstat_body, every reduction in a
+// fixed order.
+// ---------------------------------------------------------------------------
+constexpr int MB_NT = RS_NT;                  // 256 threads, RS_ITEMS keys each
+
+template <int NT>
+__device__ inline double blk_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+template <int NT>
+__device__ inline double blk_excl(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double run = 0.0;
+    for (int k = 0; k < NT; ++k) {
+      const double t = red[k];
+      red[k] = run;
+      run += t;
+    }
+  }
+  __syncthreads();
+  const double r = red[threadIdx.x];
+  __syncthreads();
+  return r;
+}
+
+// Centred partial sums of v[a, b) by the whole block (thread-contiguous runs).
+template <typename K, int NT>
+__device__ inline void blk_range_sums(const K* __restrict__ v, int64_t a, int64_t b, double c,
+                                      double* red, double& s1, double& s2) {
+  double l1 = 0.0, l2 = 0.0;
+  const int64_t n = b > a ? b - a : 0;
+  const int64_t t0 = a + (n * threadIdx.x) / NT, t1 = a + (n * (threadIdx.x + 1)) / NT;
+  for (int64_t k = t0; k < t1; ++k) {
+    const double d = val_of<K>(v[k]) - c;
+    l1 += d;
+    l2 = fma(d, d, l2);
+  }
+  s1 = blk_sum<NT>(l1, red);
+  s2 = blk_sum<NT>(l2, red);
+}
+
+template <typename K>
+__global__ __launch_bounds__(MB_NT) void k_mb_sums(const K* __restrict__ keys,
+                                                   const SegTile* __restrict__ tiles,
+                                                   const int64_t* __restrict__ seg_off,
+                                                   const int64_t* __restrict__ seg_len,
+                                                   double* __restrict__ bs1,
+                                                   double* __restrict__ bs2) {
+  __shared__ double red[MB_NT];
+  const SegTile t = tiles[blockIdx.x];
+  const K* __restrict__ v = keys + seg_off[t.seg];
+  const int64_t L = seg_len[t.seg];
+  const double c = val_of<K>(v[L / 2]);
+  const int64_t a = (int64_t)t.tile * RS_TILE, b = min(a + (int64_t)RS_TILE, L);
+  double s1, s2;
+  blk_range_sums<K, MB_NT>(v, a, b, c, red, s1, s2);
+  if (threadIdx.x == 0) {
+    bs1[blockIdx.x] = s1;
+    bs2[blockIdx.x] = s2;
+  }
+}
+
+// Per segment: block sums -> exclusive prefixes; totals kept aside.
+__global__ void k_mb_scan(const int32_t* __restrict__ seg_tile0, int tile_first,
+                          double* __restrict__ bs1, double* __restrict__ bs2,
+                          double* __restrict__ tot) {
+  const int s = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  const int t0 = seg_tile0[s] - tile_first, t1 = seg_tile0[s + 1] - tile_first;
+  double r1 = 0.0, r2 = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const double a = bs1[t], b = bs2[t];
+    bs1[t] = r1;
+    bs2[t] = r2;
+    r1 += a;
+    r2 += b;
+  }
+  tot[2 * s] = r1;
+  tot[2 * s + 1] = r2;
+}
+
+// Prefix sums P(x) of the centred values at any position x of a segment.
+template <typename K>
+__device__ inline void prefix_at(const K* __restrict__ v, int64_t L, double c, int64_t x,
+                                 const double* bs1, const double* bs2, const double* tot,
+                                 int t0rel, int s_rel, double* red, double& p1, double& p2) {
+  const int64_t bx = x / RS_TILE;
+  const int64_t nb = (L + RS_TILE - 1) / RS_TILE;
+  if (bx >= nb) {
+    p1 = tot[2 * s_rel];
+    p2 = tot[2 * s_rel + 1];
+    return;
+  }
+  double q1, q2;
+  blk_range_sums<K, MB_NT>(v, bx * RS_TILE, x, c, red, q1, q2);
+  p1 = bs1[t0rel + bx] + q1;
+  p2 = bs2[t0rel + bx] + q2;
+}
+
+template <typename K>
+__global__ __launch_bounds__(MB_NT) void k_mb_window(const K* __restrict__ keys,
+                                                     const SegTile* __restrict__ tiles,
+                                                     const int64_t* __restrict__ seg_off,
+                                                     const int64_t* __restrict__ seg_len,
+                                                     const int32_t* __restrict__ seg_tile0,
+                                                     int tile_first, int seg_first,
+                                                     const double* __restrict__ bs1,
+                                                     const double* __restrict__ bs2,
+                                                     const double* __restrict__ tot,
+                                                     double* __restrict__ wbest,
+                                                     int64_t* __restrict__ wj) {
+  __shared__ double red[MB_NT];
+  __shared__ double sb[MB_NT];
+  __shared__ int64_t sj[MB_NT];
+  const SegTile t = tiles[blockIdx.x];
+  const K* __restrict__ v = keys + seg_off[t.seg];
+  const int64_t L = seg_len[t.seg];
+  const int s_rel = t.seg - seg_first;
+  const int t0rel = seg_tile0[s_rel] - tile_first;
+  const double c = val_of<K>(v[L / 2]);
+  const int64_t hh = L / 2 + 1, nw = L - hh + 1;
+  const int64_t a = (int64_t)t.tile * RS_TILE;
+  const int64_t e = min(a + (int64_t)RS_TILE, nw);
+  const int tid = threadIdx.x;
+  double best = INFINITY;
+  int64_t bj = -1;
+  if (a < nw) {   // uniform over the block
+    // P at this thread's first window start and at start + hh
+    const int64_t ja = a + (int64_t)tid * RS_ITEMS;
+    double l1 = 0.0, l2 = 0.0, m1 = 0.0, m2 = 0.0;
+    for (int64_t k = ja; k < min(ja + RS_ITEMS, L); ++k) {
+      const double d = val_of<K>(v[k]) - c;
+      l1 += d;
+      l2 = fma(d, d, l2);
+    }
+    for (int64_t k = ja + hh; k < min(ja + hh + RS_ITEMS, L); ++k) {
+      const double d = val_of<K>(v[k]) - c;
+      m1 += d;
+      m2 = fma(d, d, m2);
+    }
+    const double pa1 = blk_excl<MB_NT>(l1, red), pa2 = blk_excl<MB_NT>(l2, red);
+    const double pb1 = blk_excl<MB_NT>(m1, red), pb2 = blk_excl<MB_NT>(m2, red);
+    double x1, x2;
+    prefix_at<K>(v, L, c, a + hh, bs1, bs2, tot, t0rel, s_rel, red, x1, x2);
+    double q1l = bs1[t0rel + t.tile] + pa1, q2l = bs2[t0rel + t.tile] + pa2;
+    double q1h = x1 + pb1, q2h = x2 + pb2;
+    const double hd = (double)hh;
+    for (int64_t j = ja; j < min(ja + RS_ITEMS, e); ++j) {
+      const double s1 = q1h - q1l, s2 = q2h - q2l;
+      const double wv = (s2 - s1 * s1 / hd) / (hd - 1.0);
+      if (wv < best) { best = wv; bj = j; }
+      const double dl = val_of<K>(v[j]) - c;
+      q1l += dl;
+      q2l = fma(dl, dl, q2l);
+      if (j + hh < L) {
+        const double dh = val_of<K>(v[j + hh]) - c;
+        q1h += dh;
+        q2h = fma(dh, dh, q2h);
+      }
+    }
+  }
+  sb[tid] = best;
+  sj[tid] = bj;
+  __syncthreads();
+  for (int o = MB_NT / 2; o > 0; o >>= 1) {
+    if (tid < o) {
+      const double b2 = sb[tid + o];
+      const int64_t j2 = sj[tid + o];
+      if (j2 >= 0 && (sj[tid] < 0 || b2 < sb[tid] || (b2 == sb[tid] && j2 < sj[tid]))) {
+        sb[tid] = b2;
+        sj[tid] = j2;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    wbest[blockIdx.x] = sb[0];
+    wj[blockIdx.x] = sj[0];
+  }
+}
+
+// Per segment: the window of smallest variance (lowest start on ties), the
+// raw location / variance, the reweighting bound.  prm[s] = {c, mu_raw,
+// var_raw, lim, start}.
+template <typename K>
+__global__ __launch_bounds__(MB_NT) void k_mb_mid(const K* __restrict__ keys,
+                                                  const int64_t* __restrict__ seg_off,
+                                                  const int64_t* __restrict__ seg_len,
+                                                  const int32_t* __restrict__ seg_tile0,
+                                                  int tile_first, int seg_first,
+                                                  const double* __restrict__ bs1,
+                                                  const double* __restrict__ bs2,
+                                                  const double* __restrict__ tot,
+                                                  const double* __restrict__ wbest,
+                                                  const int64_t* __restrict__ wj,
+                                                  const double* __restrict__ seg_craw, double q1,
+                                                  double* __restrict__ prm) {
+  __shared__ double red[MB_NT];
+  __shared__ double s_w;
+  __shared__ int64_t s_j;
+  const int s_rel = blockIdx.x;
+  const int sg = seg_first + s_rel;
+  const K* __restrict__ v = keys + seg_off[sg];
+  const int64_t L = seg_len[sg];
+  const int t0rel = seg_tile0[s_rel] - tile_first, t1rel = seg_tile0[s_rel + 1] - tile_first;
+  if (threadIdx.x == 0) {
+    double b = INFINITY;
+    int64_t j = -1;
+    for (int t = t0rel; t < t1rel; ++t) {
+      const int64_t j2 = wj[t];
+      if (j2 >= 0 && (j < 0 || wbest[t] < b)) { b = wbest[t]; j = j2; }
+    }
+    s_w = b;
+    s_j = j;
+  }
+  __syncthreads();
+  const double c = val_of<K>(v[L / 2]);
+  const int64_t hh = L / 2 + 1, js = s_j;
+  double pa1, pa2, pb1, pb2;
+  prefix_at<K>(v, L, c, js, bs1, bs2, tot, t0rel, s_rel, red, pa1, pa2);
+  prefix_at<K>(v, L, c, js + hh, bs1, bs2, tot, t0rel, s_rel, red, pb1, pb2);
+  if (threadIdx.x == 0) {
+    const double mu_raw = c + (pb1 - pa1) / (double)hh;
+    const double var_raw = s_w * seg_craw[s_rel];
+    double* P = prm + 5 * s_rel;
+    P[0] = c;
+    P[1] = mu_raw;
+    P[2] = var_raw;
+    P[3] = q1 * var_raw;
+    P[4] = (double)js;
+  }
+}
+
+template <typename K>
+__global__ __launch_bounds__(MB_NT) void k_mb_kept(const K* __restrict__ keys,
+                                                   const SegTile* __restrict__ tiles,
+                                                   const int64_t* __restrict__ seg_off,
+                                                   const int64_t* __restrict__ seg_len,
+                                                   int seg_first, const double* __restrict__ prm,
+                                                   double* __restrict__ k0, double* __restrict__ k1,
+                                                   double* __restrict__ k2) {
+  __shared__ double red[MB_NT];
+  const SegTile t = tiles[blockIdx.x];
+  const K* __restrict__ v = keys + seg_off[t.seg];
+  const int64_t L = seg_len[t.seg];
+  const double* P = prm + 5 * (t.seg - seg_first);
+  const double c = P[0], mu = P[1], lim = P[3];
+  const int64_t a = (int64_t)t.tile * RS_TILE, b = min(a + (int64_t)RS_TILE, L);
+  const int64_t n = b - a;
+  const int64_t t0 = a + (n * threadIdx.x) / MB_NT, t1 = a + (n * (threadIdx.x + 1)) / MB_NT;
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+  for (int64_t k = t0; k < t1; ++k) {
+    const double x = val_of<K>(v[k]);
+    const double e = x - mu;
+    if (e * e <= lim) {
+      const double d = x - c;
+      c0 += 1.0;
+      c1 += d;
+      c2 = fma(d, d, c2);
+    }
+  }
+  const double r0 = blk_sum<MB_NT>(c0, red), r1 = blk_sum<MB_NT>(c1, red),
+               r2 = blk_sum<MB_NT>(c2, red);
+  if (threadIdx.x == 0) {
+    k0[blockIdx.x] = r0;
+    k1[blockIdx.x] = r1;
+    k2[blockIdx.x] = r2;
+  }
+}
+
+__global__ void k_mb_final(const int32_t* __restrict__ seg_tile0, int tile_first,
+                           const double* __restrict__ prm, const double* __restrict__ k0,
+                           const double* __restrict__ k1, const double* __restrict__ k2,
+                           double crew, SegStat* __restrict__ out) {
+  const int s = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  const int t0 = seg_tile0[s] - tile_first, t1 = seg_tile0[s + 1] - tile_first;
+  double N = 0.0, S1 = 0.0, S2 = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    N += k0[t];
+    S1 += k1[t];
+    S2 += k2[t];
+  }
+  const double* P = prm + 5 * s;
+  SegStat r{};
+  r.mu_raw = P[1];
+  r.var_raw = P[2];
+  r.start = (int64_t)P[4];
+  r.n_kept = (int64_t)N;
+  r.mu = N > 0 ? P[0] + S1 / N : NAN;
+  r.var = N > 1 ? (S2 - S1 * S1 / N) / (N - 1.0) * crew : 0.0;
+  out[s] = r;
 }
 
 }  // namespace
@@ -432,6 +827,51 @@ hipError_t sort_segments_t(SortPlan& P, hipStream_t s) {
 hipError_t sort_segments(SortPlan& P, hipStream_t s) {
   if (P.ntiles <= 0) return hipSuccess;
   return P.key_bytes == 4 ? sort_segments_t<uint32_t>(P, s) : sort_segments_t<uint64_t>(P, s);
+}
+
+hipError_t launch_seg_lds(const SortPlan& P, const double* seg_craw, double q1, double crew,
+                          int mode, SegStat* out, hipStream_t s) {
+  if (P.nseg <= 0) return hipSuccess;
+  if (P.key_bytes == 4)
+    hipLaunchKernelGGL((k_seg_lds<uint32_t>), dim3(P.nseg), dim3(SS_NT), 0, s,
+                       static_cast<const uint32_t*>(P.keys), P.seg_off, P.seg_len, seg_craw,
+                       P.seg_first, q1, crew, mode, out);
+  else
+    hipLaunchKernelGGL((k_seg_lds<uint64_t>), dim3(P.nseg), dim3(SS_NT), 0, s,
+                       static_cast<const uint64_t*>(P.keys), P.seg_off, P.seg_len, seg_craw,
+                       P.seg_first, q1, crew, mode, out);
+  return hipGetLastError();
+}
+
+int lds_sort_capacity() { return LDS_KEYS; }
+
+template <typename K>
+hipError_t unimcd_multiblock_t(const SortPlan& P, const double* seg_craw, double q1, double crew,
+                               SegStat* out, hipStream_t s) {
+  const MbScratch& M = *P.mb;
+  const K* keys = static_cast<const K*>(P.keys);
+  hipLaunchKernelGGL((k_mb_sums<K>), dim3(P.ntiles), dim3(MB_NT), 0, s, keys, P.tiles, P.seg_off,
+                     P.seg_len, M.bs1, M.bs2);
+  hipLaunchKernelGGL(k_mb_scan, dim3(P.nseg), dim3(64), 0, s, P.seg_tile0, P.tile_first, M.bs1,
+                     M.bs2, M.tot);
+  hipLaunchKernelGGL((k_mb_window<K>), dim3(P.ntiles), dim3(MB_NT), 0, s, keys, P.tiles,
+                     P.seg_off, P.seg_len, P.seg_tile0, P.tile_first, P.seg_first, M.bs1, M.bs2,
+                     M.tot, M.wbest, M.wj);
+  hipLaunchKernelGGL((k_mb_mid<K>), dim3(P.nseg), dim3(MB_NT), 0, s, keys, P.seg_off, P.seg_len,
+                     P.seg_tile0, P.tile_first, P.seg_first, M.bs1, M.bs2, M.tot, M.wbest, M.wj,
+                     seg_craw, q1, M.prm);
+  hipLaunchKernelGGL((k_mb_kept<K>), dim3(P.ntiles), dim3(MB_NT), 0, s, keys, P.tiles, P.seg_off,
+                     P.seg_len, P.seg_first, M.prm, M.k0, M.k1, M.k2);
+  hipLaunchKernelGGL(k_mb_final, dim3(P.nseg), dim3(64), 0, s, P.seg_tile0, P.tile_first, M.prm,
+                     M.k0, M.k1, M.k2, crew, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_unimcd_multiblock(const SortPlan& P, const double* seg_craw, double q1,
+                                    double crew, SegStat* out, hipStream_t s) {
+  if (P.nseg <= 0) return hipSuccess;
+  return P.key_bytes == 4 ? unimcd_multiblock_t<uint32_t>(P, seg_craw, q1, crew, out, s)
+                          : unimcd_multiblock_t<uint64_t>(P, seg_craw, q1, crew, out, s);
 }
 
 hipError_t launch_segstats(const SortPlan& P, const double* seg_craw, double q1, double crew,

@@ -10,8 +10,19 @@ struct SegTile {
   int32_t tile;
 };
 
+// Scratch of the multi-block univariate MCD (per tile / per segment arrays).
+struct MbScratch {
+  double *bs1, *bs2;     // [ntiles] block sums, then exclusive prefixes
+  double *wbest;         // [ntiles] smallest window variance per block
+  int64_t* wj;           // [ntiles] its window start
+  double *k0, *k1, *k2;  // [ntiles] kept-row partial sums
+  double* tot;           // [2 nseg] segment totals
+  double* prm;           // [5 nseg] per-segment parameters
+};
+
 // One sort call: nseg segments of keys, segment s at [seg_off[s], +seg_len[s]).
 struct SortPlan {
+  const MbScratch* mb = nullptr;   // device pointers, for the multi-block estimator
   int key_bytes = 8;            // 4: keys of float32 values, 8: keys of float64 values
   int nseg = 0;
   int ntiles = 0;
@@ -57,5 +68,13 @@ hipError_t sort_segments(SortPlan& P, hipStream_t s);
 // MEDMAD: mu = median, var = (1.4826 MAD)^2.  GSSCM: mu = A, var = B.
 hipError_t launch_segstats(const SortPlan& P, const double* seg_craw, double q1, double crew,
                            int mode, SegStat* out, hipStream_t s);
+// Sort and estimator in one launch for plans whose segments all hold at most
+// lds_sort_capacity() keys (the sort happens in LDS; P.keys is left unsorted).
+int lds_sort_capacity();
+// Univariate MCD over sorted segments of any length, spread over the tiles.
+hipError_t launch_unimcd_multiblock(const SortPlan& P, const double* seg_craw, double q1,
+                                    double crew, SegStat* out, hipStream_t s);
+hipError_t launch_seg_lds(const SortPlan& P, const double* seg_craw, double q1, double crew,
+                          int mode, SegStat* out, hipStream_t s);
 
 }  // namespace rtd
