@@ -74,6 +74,7 @@ void layout_items(Layout& L, const ItemSet& S, size_t off[20]) {
   off[16] = L.add((size_t)S.rows * 4);   // swap
   off[17] = L.add(S.stiles.size() * PSTRIDE * 8);  // partials
   off[18] = L.add(64);                   // nactive
+  off[19] = L.add(S.ptiles.size() * sizeof(Tile));
 }
 
 void bind_items(char* base, const ItemSet& S, const size_t off[20], ItemDev& D) {
@@ -97,6 +98,7 @@ void bind_items(char* base, const ItemSet& S, const size_t off[20], ItemDev& D) 
   A.swap = reinterpret_cast<int32_t*>(base + off[16]);
   A.part = reinterpret_cast<double*>(base + off[17]);
   A.nactive = reinterpret_cast<int32_t*>(base + off[18]);
+  D.ptiles = reinterpret_cast<Tile*>(base + off[19]);
   (void)S;
 }
 
@@ -106,17 +108,21 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
   hipStream_t st = ctx->stream;
   const int maxs = o.max_csteps;
   if (o.launch == RTDETMCD_LAUNCH_BATCHED) {
-    // tiles of the items [first, first+n) are contiguous in both tables
-    const int dt0 = S.dt_first[first];
-    const int dtn = S.dt_first[first + n - 1] + S.dt_count[first + n - 1] - dt0;
+    // tiles of the items [first, first+n) are contiguous in all tables; when
+    // the range is made of whole start pairs, one distance pass serves both
+    const bool pairs = (n % 2 == 0) && S.pt_first[first] >= 0 && S.pt_first[first + n - 2] >= 0;
+    const Tile* dtl = pairs ? D.ptiles : D.dtiles;
+    const int dt0 = pairs ? S.pt_first[first] : S.dt_first[first];
+    const int dtn = pairs ? S.pt_first[first + n - 2] + S.pt_count[first + n - 2] - dt0
+                          : S.dt_first[first + n - 1] + S.dt_count[first + n - 1] - dt0;
     const int st0 = S.items[first].tile0;
     const int stn = S.items[first + n - 1].tile0 + S.items[first + n - 1].ntiles - st0;
     RTD_HIP(launch_finalize(D.items, D.A, first, n, 1, maxs, o.kappa_max, SSCP_TILE, st));
     const int R = std::max(1, o.rounds_per_sync);
     for (int t = 1; t <= maxs; ++t) {
       RTD_HIP(launch_fill_i32(D.A.nactive, 0, 1, st));
-      RTD_HIP(launch_dist(bucket, dtype, D.items, D.dtiles + dt0, dtn, DIST_TILE, D.A.mtri,
-                          D.A.mux, D.A.status, D.A.d2, st));
+      RTD_HIP(launch_dist(bucket, dtype, pairs ? 2 : 1, D.items, dtl + dt0, dtn, DIST_TILE,
+                          D.A.mtri, D.A.mux, D.A.status, D.A.d2, st));
       RTD_HIP(launch_select(D.items, D.A, first, n, o.cstep_mode, st));
       RTD_HIP(launch_sscp(bucket, dtype, SSCP_CSTEP, D.items, D.A, D.stiles + st0, stn,
                           SSCP_TILE, nullptr, 0, nullptr, st));
@@ -137,7 +143,7 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
     RTD_HIP(hipStreamSynchronize(st));
     if (*pin_flag != ACTIVE) continue;
     for (int t = 1; t <= maxs; ++t) {
-      RTD_HIP(launch_dist(bucket, dtype, D.items, D.dtiles + S.dt_first[i], S.dt_count[i],
+      RTD_HIP(launch_dist(bucket, dtype, 1, D.items, D.dtiles + S.dt_first[i], S.dt_count[i],
                           DIST_TILE, D.A.mtri, D.A.mux, D.A.status, D.A.d2, st));
       RTD_HIP(launch_select(D.items, D.A, i, 1, o.cstep_mode, st));
       RTD_HIP(launch_sscp(bucket, dtype, SSCP_CSTEP, D.items, D.A, D.stiles + d.tile0,
@@ -339,7 +345,7 @@ rtdetmcd_status rtdetmcd_distances(rtdetmcd_handle ctx, const void* X, int32_t d
   RTD_HIP(hipGetLastError());
   RTD_HIP(launch_chol_factor(L, p, D.A.mtri, ctx->stream));
   // the distance kernel writes d2 + roff with roff = 0
-  RTD_HIP(launch_dist(bucket_of(p), dtype, D.items, D.dtiles, (int)S.dtiles.size(), DIST_TILE,
+  RTD_HIP(launch_dist(bucket_of(p), dtype, 1, D.items, D.dtiles, (int)S.dtiles.size(), DIST_TILE,
                       D.A.mtri, D.A.mux, nullptr, d2, ctx->stream));
   return RTDETMCD_OK;
 }

@@ -89,9 +89,11 @@ inline int bucket_of(int p) {
 }
 
 // Launch helpers implemented in the .hip files (all enqueue on `s`).
-hipError_t launch_dist(int bucket, int dtype, const ItemDesc* items, const Tile* tiles, int ntiles,
-                       int tile_rows, const double* mtri, const double* mux, const int32_t* status,
-                       double* d2, hipStream_t s);
+// ipt = 2: every tile names the first of two items (the two starts of a
+// block) that share their rows; ipt = 1: one item per tile.
+hipError_t launch_dist(int bucket, int dtype, int ipt, const ItemDesc* items, const Tile* tiles,
+                       int ntiles, int tile_rows, const double* mtri, const double* mux,
+                       const int32_t* status, double* d2, hipStream_t s);
 hipError_t launch_select(const ItemDesc* items, ItemArrays A, int first_item, int nitems,
                          int cstep_mode, hipStream_t s);
 hipError_t launch_sscp(int bucket, int dtype, int mode, const ItemDesc* items, ItemArrays A,

@@ -11,7 +11,7 @@
 
 namespace rtd {
 
-constexpr int DIST_TILE = 2048;   // rows per block of the distance kernel
+constexpr int DIST_TILE = 1024;   // rows per block of the distance kernel
 constexpr int SSCP_TILE = 4096;   // candidate rows per block of the sscp kernel
 
 #define RTD_HIP(expr)                                                              \
@@ -60,8 +60,9 @@ struct Uploader {
 // per-item launches).
 struct ItemSet {
   std::vector<ItemDesc> items;
-  std::vector<Tile> dtiles, stiles;
+  std::vector<Tile> dtiles, stiles, ptiles;
   std::vector<int> dt_first, dt_count;   // per item, into dtiles
+  std::vector<int> pt_first, pt_count;   // per item, into ptiles (pair leaders only)
   int64_t rows = 0;                      // sum of m
   void add(const ItemDesc& d) {
     ItemDesc e = d;
@@ -74,6 +75,16 @@ struct ItemSet {
     const int nd = (int)((e.m + DIST_TILE - 1) / DIST_TILE);
     for (int t = 0; t < nd; ++t) dtiles.push_back({(int)items.size(), t});
     dt_count.push_back(nd);
+    pt_first.push_back(-1);
+    pt_count.push_back(0);
+    // the two starts of a block share their rows: one distance tile serves both
+    if (e.start == 1 && !items.empty() && items.back().start == 0 && items.back().ds == e.ds &&
+        items.back().blk == e.blk) {
+      const int lead = (int)items.size() - 1;
+      pt_first[lead] = (int)ptiles.size();
+      pt_count[lead] = nd;
+      for (int t = 0; t < nd; ++t) ptiles.push_back({lead, t});
+    }
     rows += e.m;
     items.push_back(e);
   }
@@ -84,10 +95,11 @@ struct ItemDev {
   ItemDesc* items = nullptr;
   Tile* dtiles = nullptr;
   Tile* stiles = nullptr;
+  Tile* ptiles = nullptr;
   ItemArrays A{};
 };
 
-void layout_items(Layout& L, const ItemSet& S, size_t off[20]);
+void layout_items(Layout& L, const ItemSet& S, size_t off[20]);  // uses off[0..19]
 void bind_items(char* base, const ItemSet& S, const size_t off[20], ItemDev& D);
 
 // Enqueue the C-step loop for items [first, first+n) of a bucket/dtype class.

@@ -1,8 +1,8 @@
-// Row-streaming kernels: statistical distances and weighted sscp partial sums.
+// Row-streaming kernel: weighted sscp partial sums.
 //
-// Both read the rows of X exactly once per launch and compute in float64;
-// float32 inputs are widened exactly.  Each kernel is instantiated per
-// p-bucket P (p <= P, the padding contributes exact zeros).
+// Reads the rows of X once per launch and computes in float64; float32 inputs
+// are widened exactly.  Instantiated per p-bucket P (p <= P, the padding
+// contributes exact zeros).
 #include "common.h"
 #include "fitk.h"
 
@@ -22,79 +22,6 @@ __device__ inline double wrap_g(double z) {
   if (a <= b) return z;
   if (a <= c) return copysign(q1 * tanh(q2 * (c - a)), z);
   return 0.0;
-}
-
-// ---------------------------------------------------------------------------
-// Distances (Sec. 3.4): d2 = ||M (x - mu)||^2 with M = L^{-1} D^{-1} packed
-// lower-triangular, so that the standardisation is folded into M and mu.
-// One thread per row; M and mu are uniform per block and are read through the
-// scalar cache.
-// ---------------------------------------------------------------------------
-// Squared distance of one row: z = x - mu, y = M z (M lower triangular,
-// row stride ldm), d2 = sum y_i^2.  M and mu are uniform per block.
-template <typename T, int P>
-__device__ inline double row_d2(const T* __restrict__ xr, int p, const double* muv,
-                                const double* __restrict__ M, int ldm) {
-  double z[P];
-#pragma unroll
-  for (int j = 0; j < P; ++j) z[j] = (j < p) ? ld_elem(xr, j) - muv[j] : 0.0;
-  double acc = 0.0;
-#pragma unroll
-  for (int i = 0; i < P; ++i) {
-    if (i < p) {
-      double y = 0.0;
-#pragma unroll
-      for (int j = 0; j <= i; ++j) y = fma(M[i * ldm + j], z[j], y);
-      acc = fma(y, y, acc);
-    }
-  }
-  return acc;
-}
-
-template <typename T, int P>
-__global__ __launch_bounds__(256) void k_dist(const ItemDesc* __restrict__ items,
-                                              const Tile* __restrict__ tiles, int tile_rows,
-                                              const double* __restrict__ mtri,
-                                              const double* __restrict__ mux,
-                                              const int32_t* __restrict__ status,
-                                              double* __restrict__ d2) {
-  const Tile tl = tiles[blockIdx.x];
-  const int it = tl.item;
-  if (status != nullptr && status[it] != ACTIVE) return;
-  const ItemDesc D = items[it];
-  const int p = D.p;
-  const double* __restrict__ M = mtri + (size_t)it * MSTRIDE;
-  const double* __restrict__ mu = mux + (size_t)it * PMAX;
-  const T* __restrict__ X = static_cast<const T*>(D.X) + D.row0 * D.ld;
-  const int64_t r0 = (int64_t)tl.t * tile_rows;
-  const int64_t r1 = min(r0 + (int64_t)tile_rows, D.m);
-  double* __restrict__ out = d2 + D.roff;
-  double muv[P];
-#pragma unroll
-  for (int j = 0; j < P; ++j) muv[j] = j < p ? mu[j] : 0.0;
-  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x)
-    out[r] = row_d2<T, P>(X + r * D.ld, p, muv, M, PMAX);
-}
-
-// Distances and flags of n rows against one stored fit (Sec. 4 step 10 as
-// used for scoring new data in Sec. 6): M is the inverse Cholesky factor
-// (row-major, stride ldm), dist = sqrt(d2), flag = d2 > cut.
-template <typename T, int P>
-__global__ __launch_bounds__(256) void k_score(const T* __restrict__ X, int64_t n, int64_t ld,
-                                               int p, const double* __restrict__ mu,
-                                               const double* __restrict__ M, int ldm, double cut,
-                                               int tile_rows, double* __restrict__ dist,
-                                               uint8_t* __restrict__ flag) {
-  double muv[P];
-#pragma unroll
-  for (int j = 0; j < P; ++j) muv[j] = j < p ? mu[j] : 0.0;
-  const int64_t r0 = (int64_t)blockIdx.x * tile_rows;
-  const int64_t r1 = min(r0 + (int64_t)tile_rows, n);
-  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-    const double acc = row_d2<T, P>(X + r * ld, p, muv, M, ldm);
-    if (dist) dist[r] = sqrt(acc);
-    if (flag) flag[r] = acc > cut ? 1 : 0;
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -305,61 +232,6 @@ __global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items
   }
 }
 
-// Final robust distances and flags (Sec. 4 step 10): RD = sqrt(d2) and
-// outlier = d2 > chi2_{p,q}; the decision is taken on the float64 d2.
-template <typename T, int P>
-__global__ __launch_bounds__(256) void k_final_dist(const ItemDesc* __restrict__ items,
-                                                    const Tile* __restrict__ tiles, int tile_rows,
-                                                    const double* __restrict__ mtri,
-                                                    const double* __restrict__ mux,
-                                                    const DsInfo* __restrict__ ds,
-                                                    const rtdetmcd_out* __restrict__ outs) {
-  const Tile tl = tiles[blockIdx.x];
-  const int it = tl.item;
-  const ItemDesc D = items[it];
-  const DsInfo dd = ds[D.ds];
-  if (dd.err) return;
-  const int p = D.p;
-  const double cut = dd.chi2p;
-  const double* __restrict__ M = mtri + (size_t)it * MSTRIDE;
-  const double* __restrict__ mu = mux + (size_t)it * PMAX;
-  const T* __restrict__ X = static_cast<const T*>(D.X) + D.row0 * D.ld;
-  const int64_t r0 = (int64_t)tl.t * tile_rows;
-  const int64_t r1 = min(r0 + (int64_t)tile_rows, D.m);
-  double* __restrict__ od = outs[D.ds].dist;
-  uint8_t* __restrict__ of = outs[D.ds].outlier;
-  if (od) od += D.row0;
-  if (of) of += D.row0;
-  double muv[P];
-#pragma unroll
-  for (int j = 0; j < P; ++j) muv[j] = j < p ? mu[j] : 0.0;
-  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-    const double acc = row_d2<T, P>(X + r * D.ld, p, muv, M, PMAX);
-    if (od) od[r] = sqrt(acc);
-    if (of) of[r] = acc > cut ? 1 : 0;
-  }
-}
-
-template <typename T, int P>
-hipError_t final_t(const ItemDesc* items, const Tile* tiles, int ntiles, int tile_rows,
-                   const double* mtri, const double* mux, const DsInfo* ds,
-                   const rtdetmcd_out* outs, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_final_dist<T, P>), dim3(ntiles), dim3(256), 0, s, items, tiles, tile_rows,
-                     mtri, mux, ds, outs);
-  return hipGetLastError();
-}
-
-template <typename T, int P>
-hipError_t dist_t(const ItemDesc* items, const Tile* tiles, int ntiles, int tile_rows,
-                  const double* mtri, const double* mux, const int32_t* status, double* d2,
-                  hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_dist<T, P>), dim3(ntiles), dim3(256), 0, s, items, tiles, tile_rows,
-                     mtri, mux, status, d2);
-  return hipGetLastError();
-}
-
 template <typename T, int P>
 hipError_t sscp_t(int mode, const ItemDesc* items, ItemArrays A, const Tile* tiles, int ntiles,
                   int tile_rows, const double* pivot, int pivot_stride, const double* cut,
@@ -388,62 +260,6 @@ hipError_t sscp_t(int mode, const ItemDesc* items, ItemArrays A, const Tile* til
 }  // namespace
 
 #define RTD_BUCKETS(X) X(4) X(5) X(8) X(10) X(16) X(20) X(24) X(32) X(40) X(48) X(64)
-
-hipError_t launch_dist(int bucket, int dtype, const ItemDesc* items, const Tile* tiles, int ntiles,
-                       int tile_rows, const double* mtri, const double* mux, const int32_t* status,
-                       double* d2, hipStream_t s) {
-#define CASE(PB)                                                                              \
-  case PB:                                                                                    \
-    return dtype == 0 ? dist_t<float, PB>(items, tiles, ntiles, tile_rows, mtri, mux, status, \
-                                          d2, s)                                              \
-                      : dist_t<double, PB>(items, tiles, ntiles, tile_rows, mtri, mux, status, \
-                                           d2, s);
-  switch (bucket) {
-    RTD_BUCKETS(CASE)
-    default: return hipErrorInvalidValue;
-  }
-#undef CASE
-}
-
-hipError_t launch_score(int bucket, int dtype, const void* X, int64_t n, int64_t ld, int p,
-                        const double* mu, const double* M, int ldm, double cut, double* dist,
-                        uint8_t* flag, hipStream_t s) {
-  const int tile_rows = 2048;
-  const int64_t nb = (n + tile_rows - 1) / tile_rows;
-  if (nb <= 0) return hipSuccess;
-#define CASE(PB)                                                                               \
-  case PB:                                                                                     \
-    if (dtype == 0)                                                                            \
-      hipLaunchKernelGGL((k_score<float, PB>), dim3((unsigned)nb), dim3(256), 0, s,            \
-                         static_cast<const float*>(X), n, ld, p, mu, M, ldm, cut, tile_rows,   \
-                         dist, flag);                                                          \
-    else                                                                                       \
-      hipLaunchKernelGGL((k_score<double, PB>), dim3((unsigned)nb), dim3(256), 0, s,           \
-                         static_cast<const double*>(X), n, ld, p, mu, M, ldm, cut, tile_rows,  \
-                         dist, flag);                                                          \
-    return hipGetLastError();
-  switch (bucket) {
-    RTD_BUCKETS(CASE)
-    default: return hipErrorInvalidValue;
-  }
-#undef CASE
-}
-
-hipError_t launch_final_dist(int bucket, int dtype, const ItemDesc* items, const Tile* tiles,
-                             int ntiles, int tile_rows, const double* mtri, const double* mux,
-                             const DsInfo* ds, const rtdetmcd_out* outs, hipStream_t s) {
-#define CASE(PB)                                                                              \
-  case PB:                                                                                    \
-    return dtype == 0 ? final_t<float, PB>(items, tiles, ntiles, tile_rows, mtri, mux, ds,    \
-                                           outs, s)                                           \
-                      : final_t<double, PB>(items, tiles, ntiles, tile_rows, mtri, mux, ds,   \
-                                            outs, s);
-  switch (bucket) {
-    RTD_BUCKETS(CASE)
-    default: return hipErrorInvalidValue;
-  }
-#undef CASE
-}
 
 hipError_t launch_sscp(int bucket, int dtype, int mode, const ItemDesc* items, ItemArrays A,
                        const Tile* tiles, int ntiles, int tile_rows, const double* pivot,
