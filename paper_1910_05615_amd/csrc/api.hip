@@ -117,13 +117,15 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
                           : S.dt_first[first + n - 1] + S.dt_count[first + n - 1] - dt0;
     const int st0 = S.items[first].tile0;
     const int stn = S.items[first + n - 1].tile0 + S.items[first + n - 1].ntiles - st0;
+    int64_t max_m = 0;
+    for (int i = first; i < first + n; ++i) max_m = std::max(max_m, S.items[i].m);
     RTD_HIP(launch_finalize(D.items, D.A, first, n, 1, maxs, o.kappa_max, SSCP_TILE, st));
     const int R = std::max(1, o.rounds_per_sync);
     for (int t = 1; t <= maxs; ++t) {
       RTD_HIP(launch_fill_i32(D.A.nactive, 0, 1, st));
       RTD_HIP(launch_dist(bucket, dtype, pairs ? 2 : 1, D.items, dtl + dt0, dtn, DIST_TILE,
                           D.A.mtri, D.A.mux, D.A.status, D.A.d2, st));
-      RTD_HIP(launch_select(D.items, D.A, first, n, o.cstep_mode, st));
+      RTD_HIP(launch_select(D.items, D.A, first, n, max_m, o.cstep_mode, st));
       RTD_HIP(launch_sscp(bucket, dtype, SSCP_CSTEP, D.items, D.A, D.stiles + st0, stn,
                           SSCP_TILE, nullptr, 0, nullptr, st));
       RTD_HIP(launch_finalize(D.items, D.A, first, n, 0, maxs, o.kappa_max, SSCP_TILE, st));
@@ -145,7 +147,7 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
     for (int t = 1; t <= maxs; ++t) {
       RTD_HIP(launch_dist(bucket, dtype, 1, D.items, D.dtiles + S.dt_first[i], S.dt_count[i],
                           DIST_TILE, D.A.mtri, D.A.mux, D.A.status, D.A.d2, st));
-      RTD_HIP(launch_select(D.items, D.A, i, 1, o.cstep_mode, st));
+      RTD_HIP(launch_select(D.items, D.A, i, 1, d.m, o.cstep_mode, st));
       RTD_HIP(launch_sscp(bucket, dtype, SSCP_CSTEP, D.items, D.A, D.stiles + d.tile0,
                           d.ntiles, SSCP_TILE, nullptr, 0, nullptr, st));
       RTD_HIP(launch_finalize(D.items, D.A, i, 1, 0, maxs, o.kappa_max, SSCP_TILE, st));
@@ -394,7 +396,7 @@ rtdetmcd_status rtdetmcd_select(rtdetmcd_handle ctx, const double* d2, int64_t m
   RTD_HIP(launch_fill_i32(A.status, ACTIVE, 1, st));
   RTD_HIP(launch_fill_i32(A.iter, 0, 1, st));
   RTD_HIP(launch_fill_u8(A.mask, 0, m, st));
-  RTD_HIP(launch_select(D.items, A, 0, 1, RTDETMCD_CSTEP_FULL, st));
+  RTD_HIP(launch_select(D.items, A, 0, 1, m, RTDETMCD_CSTEP_FULL, st));
   RTD_HIP(launch_extract_subset(D.items, A, 0, 1, idx, h_sub, 0, st));
   if (mask) RTD_HIP(hipMemcpyAsync(mask, A.mask, (size_t)m, hipMemcpyDeviceToDevice, st));
   return RTDETMCD_OK;

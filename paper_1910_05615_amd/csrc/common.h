@@ -94,8 +94,9 @@ inline int bucket_of(int p) {
 hipError_t launch_dist(int bucket, int dtype, int ipt, const ItemDesc* items, const Tile* tiles,
                        int ntiles, int tile_rows, const double* mtri, const double* mux,
                        const int32_t* status, double* d2, hipStream_t s);
+// max_m: largest m among the items (picks the register-resident variant).
 hipError_t launch_select(const ItemDesc* items, ItemArrays A, int first_item, int nitems,
-                         int cstep_mode, hipStream_t s);
+                         int64_t max_m, int cstep_mode, hipStream_t s);
 hipError_t launch_sscp(int bucket, int dtype, int mode, const ItemDesc* items, ItemArrays A,
                        const Tile* tiles, int ntiles, int tile_rows, const double* pivot,
                        int pivot_stride, const double* cut, hipStream_t s);

@@ -149,6 +149,181 @@ __global__ __launch_bounds__(SEL_NT) void k_select(const ItemDesc* __restrict__ 
   }
 }
 
+// Same selection for items of at most SEL_NT * SEL_KR rows, with the keys
+// held in registers (row i * SEL_NT + tid in slot i): the digit passes do not
+// re-read d2, and the row-order pass ranks rows with wave ballots and one
+// scan over the (slot, wave) counts instead of block scans per 1024 rows.
+// Row order is slot-major, then wave, then lane, i.e. plain index order.
+constexpr int SEL_KR = 16;
+constexpr int SEL_WV = SEL_NT / 64;
+
+// Exclusive scan, in place, of n <= 256 ints laid out in order, by the first
+// four waves; returns the total to every thread.  wsum: 4 ints.
+__device__ inline int scan256_excl(int* __restrict__ v, int n, int* __restrict__ wsum) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int x = 0, own = 0;
+  if (tid < 256) {
+    own = tid < n ? v[tid] : 0;
+    x = own;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+  }
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int t = wsum[k];
+    if (k < w) off += t;
+    tot += t;
+  }
+  if (tid < n) v[tid] = off + x - own;
+  __syncthreads();
+  return tot;
+}
+
+__global__ __launch_bounds__(SEL_NT) void k_select_reg(const ItemDesc* __restrict__ items,
+                                                       ItemArrays A, int first_item,
+                                                       int cstep_mode) {
+  __shared__ unsigned hist[8192];
+  __shared__ int wtot[SEL_WV];
+  __shared__ int tab[3][SEL_KR * SEL_WV];   // eq, entering, leaving per (slot, wave)
+  __shared__ int wsum[4];
+  __shared__ int s_bin, s_cnt;
+  __shared__ long long s_below;
+  const int it = first_item + blockIdx.x;
+  if (A.status[it] != ACTIVE) return;
+  const ItemDesc D = items[it];
+  const int m = (int)D.m;
+  const int64_t h = D.h;
+  const double* __restrict__ d2 = A.d2 + D.roff;
+  uint8_t* __restrict__ mask = A.mask + D.roff;
+  int32_t* __restrict__ swp = A.swap + D.roff;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint64_t below = (1ull << lane) - 1ull;
+
+  uint64_t key[SEL_KR];
+#pragma unroll
+  for (int i = 0; i < SEL_KR; ++i) {
+    const int r = i * SEL_NT + tid;
+    key[i] = r < m ? key_of(d2[r]) : 0ull;
+  }
+  const int shifts[5] = {52, 39, 26, 13, 0};
+  const int bitsv[5] = {12, 13, 13, 13, 13};
+  uint64_t prefix = 0, pmask = 0;
+  int64_t rank = h;
+  bool take_all = false;
+#pragma unroll
+  for (int ps = 0; ps < 5; ++ps) {
+    const int shift = shifts[ps], bits = bitsv[ps];
+    const int nbins = 1 << bits;
+    for (int b = tid; b < nbins; b += SEL_NT) hist[b] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < SEL_KR; ++i) {
+      const int r = i * SEL_NT + tid;
+      if (r < m && (key[i] & pmask) == prefix)
+        atomicAdd(&hist[(key[i] >> shift) & (uint64_t)(nbins - 1)], 1u);
+    }
+    __syncthreads();
+    const int per = nbins / SEL_NT;
+    int loc = 0;
+    for (int b = 0; b < per; ++b) loc += (int)hist[tid * per + b];
+    int tot;
+    const int before = block_excl_scan<SEL_NT>(loc, wtot, tot);
+    if ((int64_t)before < rank && rank <= (int64_t)(before + loc)) {
+      int64_t run = before;
+      for (int b = 0; b < per; ++b) {
+        const int c = (int)hist[tid * per + b];
+        if (rank <= run + c) { s_bin = tid * per + b; s_cnt = c; s_below = run; break; }
+        run += c;
+      }
+    }
+    __syncthreads();
+    prefix |= (uint64_t)s_bin << shift;
+    pmask |= (uint64_t)(nbins - 1) << shift;
+    rank -= s_below;
+    const int cnt = s_cnt;
+    __syncthreads();
+    if ((int64_t)cnt == rank) { take_all = true; break; }
+  }
+
+  // membership; ties at the threshold key go to the lowest row indices
+  uint32_t selb = 0;
+#pragma unroll
+  for (int i = 0; i < SEL_KR; ++i) {
+    const int r = i * SEL_NT + tid;
+    const bool valid = r < m;
+    const bool sel = take_all ? (valid && (key[i] & pmask) <= prefix) : (valid && key[i] < prefix);
+    if (sel) selb |= 1u << i;
+  }
+  if (!take_all) {   // uniform over the block
+    uint32_t eqb = 0;
+#pragma unroll
+    for (int i = 0; i < SEL_KR; ++i) {
+      const bool eq = (i * SEL_NT + tid) < m && key[i] == prefix;
+      const uint64_t b = __ballot(eq);
+      if (eq) eqb |= 1u << i;
+      if (lane == 0) tab[0][i * SEL_WV + w] = __popcll(b);
+    }
+    __syncthreads();
+    scan256_excl(tab[0], SEL_KR * SEL_WV, wsum);
+#pragma unroll
+    for (int i = 0; i < SEL_KR; ++i) {
+      const bool eq = (eqb >> i) & 1u;
+      const uint64_t b = __ballot(eq);
+      const int64_t er = tab[0][i * SEL_WV + w] + __popcll(b & below);
+      if (eq && er < rank) selb |= 1u << i;
+    }
+  }
+  const int it0 = A.iter[it];
+  const bool first = (it0 == 0);
+  uint32_t entb = 0, lftb = 0;
+#pragma unroll
+  for (int i = 0; i < SEL_KR; ++i) {
+    const int r = i * SEL_NT + tid;
+    const bool valid = r < m;
+    const bool sel = (selb >> i) & 1u;
+    const bool old = valid && mask[r] != 0;
+    const bool ent = sel && !old, lft = valid && !sel && old;
+    if (ent) entb |= 1u << i;
+    if (lft) lftb |= 1u << i;
+    const uint64_t be = __ballot(ent), bl = __ballot(lft);
+    if (lane == 0) {
+      tab[1][i * SEL_WV + w] = __popcll(be);
+      tab[2][i * SEL_WV + w] = __popcll(bl);
+    }
+    if (valid) mask[r] = sel ? 1 : 0;
+  }
+  __syncthreads();
+  const int nin = scan256_excl(tab[1], SEL_KR * SEL_WV, wsum);
+  const int nout = scan256_excl(tab[2], SEL_KR * SEL_WV, wsum);
+  if (!first) {
+    const int half = m / 2;
+#pragma unroll
+    for (int i = 0; i < SEL_KR; ++i) {
+      const int r = i * SEL_NT + tid;
+      const bool ent = (entb >> i) & 1u, lft = (lftb >> i) & 1u;
+      const uint64_t be = __ballot(ent), bl = __ballot(lft);
+      if (ent) swp[tab[1][i * SEL_WV + w] + __popcll(be & below)] = r;
+      if (lft) swp[half + tab[2][i * SEL_WV + w] + __popcll(bl & below)] = r;
+    }
+  }
+  if (tid == 0) {
+    A.iter[it] = it0 + 1;
+    A.kswap[it] = first ? 0 : nin;
+    int full;
+    if (first || cstep_mode == 0) full = 1;
+    else if (cstep_mode == 1) full = 0;
+    else full = (8 * (int64_t)nin > h) ? 1 : 0;
+    A.full[it] = full;
+    if (!first && nin == 0) A.status[it] = ST_CONVERGED;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Statistics and Cholesky step of one item (Sec. 2.1 eq. cstep4a/cstep4b,
 // Sec. 3.4, Sec. 3.5), all in float64:
@@ -369,10 +544,14 @@ __global__ __launch_bounds__(1024) void k_extract_subset(const ItemDesc* __restr
 }  // namespace
 
 hipError_t launch_select(const ItemDesc* items, ItemArrays A, int first_item, int nitems,
-                         int cstep_mode, hipStream_t s) {
+                         int64_t max_m, int cstep_mode, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_select, dim3(nitems), dim3(SEL_NT), 0, s, items, A, first_item,
-                     cstep_mode);
+  if (max_m <= (int64_t)SEL_NT * SEL_KR)
+    hipLaunchKernelGGL(k_select_reg, dim3(nitems), dim3(SEL_NT), 0, s, items, A, first_item,
+                       cstep_mode);
+  else
+    hipLaunchKernelGGL(k_select, dim3(nitems), dim3(SEL_NT), 0, s, items, A, first_item,
+                       cstep_mode);
   return hipGetLastError();
 }
 

@@ -42,32 +42,60 @@ __global__ __launch_bounds__(RS_NT) void k_rs_count(const K* __restrict__ keys,
 }
 
 // Per segment: offsets[tile][d] = base(d) + counts of digit d in earlier tiles.
-__global__ __launch_bounds__(256) void k_rs_scan(const int32_t* __restrict__ counts,
-                                                 const int32_t* __restrict__ seg_tile0,
-                                                 int tile_first, int32_t* __restrict__ offs) {
-  __shared__ int tot[256];
+// Thread (g, d) walks a quarter g of the segment's tiles for digit d, eight
+// independent loads at a time; digit bases come from a wave scan.
+constexpr int SCAN_NT = 1024;
+constexpr int SCAN_U = 8;
+
+__global__ __launch_bounds__(SCAN_NT) void k_rs_scan(const int32_t* __restrict__ counts,
+                                                     const int32_t* __restrict__ seg_tile0,
+                                                     int tile_first, int32_t* __restrict__ offs) {
+  __shared__ int gt[4][256];
+  __shared__ int wsum[4];
   const int s = blockIdx.x;
   const int t0 = seg_tile0[s] - tile_first, t1 = seg_tile0[s + 1] - tile_first;
-  const int d = threadIdx.x;
-  int run = 0;
-  for (int t = t0; t < t1; ++t) {
-    const int c = counts[(size_t)t * 256 + d];
-    offs[(size_t)t * 256 + d] = run;
-    run += c;
+  const int tid = threadIdx.x, d = tid & 255, g = tid >> 8, lane = tid & 63, w = tid >> 6;
+  const int nt = t1 - t0;
+  const int a = t0 + (nt * g) / 4, b = t0 + (nt * (g + 1)) / 4;
+  int tot = 0;
+  for (int t = a; t < b; t += SCAN_U) {
+    int c[SCAN_U];
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u) c[u] = (t + u < b) ? counts[(size_t)(t + u) * 256 + d] : 0;
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u) tot += c[u];
   }
-  tot[d] = run;
+  gt[g][d] = tot;
   __syncthreads();
-  if (d == 0) {
-    int acc = 0;
-    for (int k = 0; k < 256; ++k) {
-      const int v = tot[k];
-      tot[k] = acc;
-      acc += v;
+  if (tid < 256) {   // digit d = tid: total over groups, scan over digits
+    const int g0 = gt[0][d], g1 = gt[1][d], g2 = gt[2][d], g3 = gt[3][d];
+    const int T = g0 + g1 + g2 + g3;
+    int x = T;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    const int ex = x - T;
+    gt[0][d] = ex;
+    gt[1][d] = ex + g0;
+    gt[2][d] = ex + g0 + g1;
+    gt[3][d] = ex + g0 + g1 + g2;
+  }
+  __syncthreads();
+  int run = gt[g][d];
+  for (int k = 0; k < (d >> 6); ++k) run += wsum[k];
+  for (int t = a; t < b; t += SCAN_U) {
+    int c[SCAN_U];
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u) c[u] = (t + u < b) ? counts[(size_t)(t + u) * 256 + d] : 0;
+#pragma unroll
+    for (int u = 0; u < SCAN_U; ++u) {
+      if (t + u < b) offs[(size_t)(t + u) * 256 + d] = run;
+      run += c[u];
     }
   }
-  __syncthreads();
-  const int b = tot[d];
-  for (int t = t0; t < t1; ++t) offs[(size_t)t * 256 + d] += b;
 }
 
 // Stable scatter of one tile.  Wave w owns keys [w*1024, (w+1)*1024) of the
@@ -414,7 +442,91 @@ __global__ __launch_bounds__(SS_NT) void k_segstats(const K* __restrict__ keys,
 // radix, 8-bit digits, wave-ballot ranking as in k_rs_scatter), then run the
 // estimator on the sorted LDS copy.  Wave w holds the keys at positions
 // w*1024 + i*64 + lane, i < 16, so ranks follow position order.
+//
+// 64-bit keys are first sorted on their high 32 bits only (4 passes).  The
+// high half is monotone in the key, so what is left is to order each run of
+// keys sharing a high half; such runs are short for continuous data (the
+// high half keeps 20 mantissa bits) and are finished by insertion sort.  A
+// run that is too long or needs too many moves sends the whole segment
+// through the full 8-pass sort instead, so heavy ties and coarse data stay
+// exact and the fix-up's cost bounded.
 constexpr int LDS_KEYS = SS_NT * 16;
+constexpr int FIXUP_RUN = 256;      // longest run finished by insertion sort
+constexpr int FIXUP_MOVES = 2048;   // insertion-sort budget per run
+
+// One stable LSD pass over the block's keys (kv in position order on entry
+// and on exit).  wc: [16][256] ints, gs: [4][256] ints, wt: [4] ints.
+template <typename K>
+__device__ inline void lds_radix_pass(K (&kv)[16], int shift, K* __restrict__ sk,
+                                      int* __restrict__ wc, int* __restrict__ gs,
+                                      int* __restrict__ wt) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (int e = tid; e < 16 * 256; e += SS_NT) wc[e] = 0;
+  __syncthreads();
+  int dr[16];   // digit << 16 | rank within (wave, digit)
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int d = (int)((kv[i] >> shift) & (K)0xFF);
+    uint64_t match = ~0ull;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t bb = __ballot((d >> b) & 1);
+      match &= ((d >> b) & 1) ? bb : ~bb;
+    }
+    const int before = __popcll(match & below);
+    const int cur = wc[w * 256 + d];
+    dr[i] = (d << 16) | (cur + before);
+    if (before == 0) wc[w * 256 + d] = cur + __popcll(match);
+  }
+  __syncthreads();
+  // offsets of (wave, digit): digit base + earlier waves of the same digit.
+  // Thread (g, d) scans waves 4g..4g+3 of digit d.
+  const int d = tid & 255, g = tid >> 8;
+  int c[4];
+  {
+    int run = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      c[k] = run;
+      run += wc[(g * 4 + k) * 256 + d];
+    }
+    gs[g * 256 + d] = run;
+  }
+  __syncthreads();
+  if (tid < 256) {   // waves 0..3: digit d = tid, scan of digit totals
+    const int t0 = gs[d], t1 = gs[256 + d], t2 = gs[512 + d], t3 = gs[768 + d];
+    const int tot = t0 + t1 + t2 + t3;
+    int x = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wt[w] = x;
+    const int ex = x - tot;   // exclusive within this wave's 64 digits
+    gs[d] = ex;
+    gs[256 + d] = ex + t0;
+    gs[512 + d] = ex + t0 + t1;
+    gs[768 + d] = ex + t0 + t1 + t2;
+  }
+  __syncthreads();
+  {
+    int base = gs[g * 256 + d];
+    for (int k = 0; k < (d >> 6); ++k) base += wt[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) wc[(g * 4 + k) * 256 + d] = base + c[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int di = dr[i] >> 16;
+    sk[wc[w * 256 + di] + (dr[i] & 0xFFFF)] = kv[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 16; ++i) kv[i] = sk[w * 1024 + i * 64 + lane];
+}
 
 template <typename K>
 __global__ __launch_bounds__(SS_NT) void k_seg_lds(const K* __restrict__ keys,
@@ -426,66 +538,73 @@ __global__ __launch_bounds__(SS_NT) void k_seg_lds(const K* __restrict__ keys,
   __shared__ K sk[LDS_KEYS];
   __shared__ double scratch[3 * SS_NT];        // estimator scratch / wave digit counters
   int* wc = reinterpret_cast<int*>(scratch);   // [16][256] during the sort
-  __shared__ int dbase[256];
+  __shared__ int gs[4 * 256 + 8];              // group sums, wave totals, flag
+  int* wt = gs + 4 * 256;
+  int* redo = gs + 4 * 256 + 4;
   const int sb = blockIdx.x;                   // index into seg_craw / out
   const int sg = seg_first + sb;               // absolute segment
   const K* __restrict__ src = keys + seg_off[sg];
-  const int64_t L = seg_len[sg];
+  const int L = (int)seg_len[sg];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const K pad = ~(K)0;
   K kv[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int pos = w * 1024 + i * 64 + lane;
-    kv[i] = pos < L ? src[pos] : pad;
-  }
-  const uint64_t below = (1ull << lane) - 1ull;
-  for (int shift = 0; shift < 8 * (int)sizeof(K); shift += 8) {
-    for (int e = tid; e < 16 * 256; e += SS_NT) wc[e] = 0;
-    __syncthreads();
-    int dr[16];   // digit << 16 | rank within (wave, digit)
+  auto load = [&]() {
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      const int d = (int)((kv[i] >> shift) & (K)0xFF);
-      uint64_t match = ~0ull;
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const uint64_t bb = __ballot((d >> b) & 1);
-        match &= ((d >> b) & 1) ? bb : ~bb;
-      }
-      const int before = __popcll(match & below);
-      const int cur = wc[w * 256 + d];
-      dr[i] = (d << 16) | (cur + before);
-      if (before == 0) wc[w * 256 + d] = cur + __popcll(match);
+      const int pos = w * 1024 + i * 64 + lane;
+      kv[i] = pos < L ? src[pos] : pad;
     }
-    __syncthreads();
-    if (tid < 256) {
-      int acc = 0;
-      for (int k = 0; k < 16; ++k) {
-        const int v = wc[k * 256 + tid];
-        wc[k * 256 + tid] = acc;
-        acc += v;
-      }
-      dbase[tid] = acc;     // digit total
-    }
-    __syncthreads();
-    if (tid == 0) {
-      int acc = 0;
-      for (int d = 0; d < 256; ++d) {
-        const int v = dbase[d];
-        dbase[d] = acc;
-        acc += v;
-      }
-    }
-    __syncthreads();
+  };
+  load();
+  constexpr int KB = 8 * (int)sizeof(K);
+  if constexpr (sizeof(K) == 8) {
+    if (tid == 0) *redo = 0;
+    for (int shift = 32; shift < KB; shift += 8) lds_radix_pass<K>(kv, shift, sk, wc, gs, wt);
+    // runs of equal high halves: find their starts, then sort each
+    uint32_t starts = 0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      const int d = dr[i] >> 16;
-      sk[dbase[d] + wc[w * 256 + d] + (dr[i] & 0xFFFF)] = kv[i];
+      const int pos = w * 1024 + i * 64 + lane;
+      if (pos + 1 < L) {
+        const uint32_t hi = (uint32_t)(kv[i] >> 32);
+        const bool next_eq = (uint32_t)(sk[pos + 1] >> 32) == hi;
+        const bool prev_eq = pos > 0 && (uint32_t)(sk[pos - 1] >> 32) == hi;
+        if (next_eq && !prev_eq) starts |= 1u << i;
+      }
     }
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 16; ++i) kv[i] = sk[w * 1024 + i * 64 + lane];
+    int moves = 0;
+    for (int i = 0; i < 16; ++i) {
+      if (!((starts >> i) & 1u)) continue;
+      const int s0 = w * 1024 + i * 64 + lane;
+      const uint32_t hi = (uint32_t)(sk[s0] >> 32);
+      int e = s0 + 1;
+      while (e < L && e - s0 <= FIXUP_RUN && (uint32_t)(sk[e] >> 32) == hi) ++e;
+      if (e - s0 > FIXUP_RUN) {
+        *redo = 1;
+        break;
+      }
+      moves = 0;
+      for (int a = s0 + 1; a < e && moves <= FIXUP_MOVES; ++a) {
+        const K x = sk[a];
+        int b = a;
+        while (b > s0 && sk[b - 1] > x && moves <= FIXUP_MOVES) {
+          sk[b] = sk[b - 1];
+          --b;
+          ++moves;
+        }
+        sk[b] = x;
+      }
+      if (moves > FIXUP_MOVES) *redo = 1;
+    }
+    __syncthreads();
+    if (*redo) {   // uniform: every thread reads the flag after the barrier
+      __syncthreads();
+      load();
+      for (int shift = 0; shift < KB; shift += 8) lds_radix_pass<K>(kv, shift, sk, wc, gs, wt);
+    }
+  } else {
+    for (int shift = 0; shift < KB; shift += 8) lds_radix_pass<K>(kv, shift, sk, wc, gs, wt);
   }
   const SegStat r = segstat_body<K>(sk, L, seg_craw[sb], q1, crew, mode, scratch,
                                     scratch + SS_NT, scratch + 2 * SS_NT);
@@ -812,7 +931,7 @@ hipError_t sort_segments_t(SortPlan& P, hipStream_t s) {
     const int shift = 8 * ps;
     hipLaunchKernelGGL((k_rs_count<K>), dim3(P.ntiles), dim3(RS_NT), 0, s, a, P.tiles,
                        P.seg_off, P.seg_len, shift, P.counts);
-    hipLaunchKernelGGL(k_rs_scan, dim3(P.nseg), dim3(256), 0, s, P.counts, P.seg_tile0,
+    hipLaunchKernelGGL(k_rs_scan, dim3(P.nseg), dim3(SCAN_NT), 0, s, P.counts, P.seg_tile0,
                        P.tile_first, P.offs);
     hipLaunchKernelGGL((k_rs_scatter<K>), dim3(P.ntiles), dim3(RS_NT), 0, s, a, b, P.tiles,
                        P.seg_off, P.seg_len, shift, P.offs);

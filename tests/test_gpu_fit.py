@@ -115,6 +115,18 @@ def test_fit_batched_uneven_datasets():
         check_fit(F, oracle.fit(s.X), s.name)
 
 
+def test_fit_heavy_ties_in_one_column():
+    # one column on 12 integer levels: runs of equal keys far longer than the
+    # sorter's insertion-sort fix-up accepts, so those segments take the
+    # full-width radix path; the other columns keep the fix-up path busy
+    ds = synthdata.small_gaussian(12_000, 4, seed=5, dtype=np.float64, rho=0.5, eps=0.1,
+                                  kind="shift", gamma=8)
+    X = ds.X.copy()
+    X[:, 2] = np.clip(np.round(X[:, 2] * 2.0), -6, 5)
+    ref = oracle.fit(X)
+    check_fit(_run(X), ref, "ties")
+
+
 def test_fit_constant_column_is_an_error():
     P = _P()
     X = np.random.default_rng(0).standard_normal((3000, 3))
