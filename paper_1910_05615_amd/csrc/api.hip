@@ -119,6 +119,7 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
     const int stn = S.items[first + n - 1].tile0 + S.items[first + n - 1].ntiles - st0;
     int64_t max_m = 0;
     for (int i = first; i < first + n; ++i) max_m = std::max(max_m, S.items[i].m);
+    const int max_nt = S.max_ntiles(first, first + n);
     RTD_HIP(launch_finalize(D.items, D.A, first, n, 1, maxs, o.kappa_max, SSCP_TILE, st));
     const int R = std::max(1, o.rounds_per_sync);
     for (int t = 1; t <= maxs; ++t) {
@@ -128,6 +129,7 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
       RTD_HIP(launch_select(D.items, D.A, first, n, max_m, o.cstep_mode, st));
       RTD_HIP(launch_sscp(bucket, dtype, SSCP_CSTEP, D.items, D.A, D.stiles + st0, stn,
                           SSCP_TILE, nullptr, 0, nullptr, st));
+      RTD_HIP(launch_collapse(D.items, D.A, first, n, max_nt, 1, SSCP_TILE, st));
       RTD_HIP(launch_finalize(D.items, D.A, first, n, 0, maxs, o.kappa_max, SSCP_TILE, st));
       if (t % R == 0 || t == maxs) {
         RTD_HIP(hipMemcpyAsync(pin_flag, D.A.nactive, 4, hipMemcpyDeviceToHost, st));
@@ -150,6 +152,7 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
       RTD_HIP(launch_select(D.items, D.A, i, 1, d.m, o.cstep_mode, st));
       RTD_HIP(launch_sscp(bucket, dtype, SSCP_CSTEP, D.items, D.A, D.stiles + d.tile0,
                           d.ntiles, SSCP_TILE, nullptr, 0, nullptr, st));
+      RTD_HIP(launch_collapse(D.items, D.A, i, 1, d.ntiles, 1, SSCP_TILE, st));
       RTD_HIP(launch_finalize(D.items, D.A, i, 1, 0, maxs, o.kappa_max, SSCP_TILE, st));
       RTD_HIP(hipMemcpyAsync(pin_flag, D.A.status + i, 4, hipMemcpyDeviceToHost, st));
       RTD_HIP(hipStreamSynchronize(st));

@@ -100,6 +100,12 @@ hipError_t launch_select(const ItemDesc* items, ItemArrays A, int first_item, in
 hipError_t launch_sscp(int bucket, int dtype, int mode, const ItemDesc* items, ItemArrays A,
                        const Tile* tiles, int ntiles, int tile_rows, const double* pivot,
                        int pivot_stride, const double* cut, hipStream_t s);
+// Sums each item's sscp tile partials into the partial of its first tile
+// (every consumer of the partials reads that one only).  cstep: the partials
+// come from the C-step sscp (valid tiles depend on full/kswap, inactive
+// items skipped).  max_ntiles: largest ntiles among the items.
+hipError_t launch_collapse(const ItemDesc* items, ItemArrays A, int first, int nitems,
+                           int max_ntiles, int cstep, int tile_rows, hipStream_t s);
 hipError_t launch_finalize(const ItemDesc* items, ItemArrays A, int first_item, int nitems,
                            int from_start, int max_csteps, double kappa_max, int tile_rows,
                            hipStream_t s);

@@ -12,7 +12,7 @@
 namespace rtd {
 
 constexpr int DIST_TILE = 1024;   // rows per block of the distance kernel
-constexpr int SSCP_TILE = 4096;   // candidate rows per block of the sscp kernel
+constexpr int SSCP_TILE = 1024;   // candidate rows per block of the sscp kernel
 
 #define RTD_HIP(expr)                                                              \
   do {                                                                             \
@@ -87,6 +87,11 @@ struct ItemSet {
     }
     rows += e.m;
     items.push_back(e);
+  }
+  int max_ntiles(int a, int b) const {   // over items [a, b)
+    int r = 0;
+    for (int i = a; i < b; ++i) r = items[i].ntiles > r ? items[i].ntiles : r;
+    return r;
   }
 };
 

@@ -417,6 +417,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     const int dt0 = B.dt_first[b0], dtn = B.dt_first[b1 - 1] + B.dt_count[b1 - 1] - dt0;
     RTD_HIP(launch_sscp(g.bucket, g.dtype, SSCP_WRAP, BD.items, BD.A, BD.stiles + st0, stn,
                         SSCP_TILE, nullptr, 0, nullptr, st));
+    RTD_HIP(launch_collapse(BD.items, BD.A, b0, b1 - b0, B.max_ntiles(b0, b1), 0, SSCP_TILE, st));
     RTD_HIP(launch_reduce_partials(BD.items, BD.A.part, b0, b1 - b0, F.rcnt, F.rsum, F.rS, st));
     RTD_HIP(launch_init_cov(0, BD.items, b0, b1 - b0, F, CD.A, dds, cut, DN.st, st));
     RTD_HIP(launch_project(g.bucket, g.dtype, 1, BD.items, BD.dtiles + dt0, dtn, DIST_TILE,
@@ -425,6 +426,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     RTD_HIP(launch_init_cov(2, BD.items, b0, b1 - b0, F, CD.A, dds, cut, DN.st, st));
     RTD_HIP(launch_sscp(g.bucket, g.dtype, SSCP_GSSCM, BD.items, BD.A, BD.stiles + st0, stn,
                         SSCP_TILE, nullptr, 0, cut, st));
+    RTD_HIP(launch_collapse(BD.items, BD.A, b0, b1 - b0, B.max_ntiles(b0, b1), 0, SSCP_TILE, st));
     RTD_HIP(launch_reduce_partials(BD.items, BD.A.part, b0, b1 - b0, F.rcnt, F.rsum, F.rS, st));
     RTD_HIP(launch_init_cov(1, BD.items, b0, b1 - b0, F, CD.A, dds, cut, DN.st, st));
     return RTDETMCD_OK;
@@ -487,6 +489,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
                         GD.A.mux, nullptr, GD.A.d2, st));
     RTD_HIP(launch_sscp(g.bucket, g.dtype, SSCP_D2CUT, GD.items, GD.A, GD.stiles + st0, stn,
                         SSCP_TILE, nullptr, 0, dchi, st));
+    RTD_HIP(launch_collapse(GD.items, GD.A, a, b - a, G.max_ntiles(a, b), 0, SSCP_TILE, st));
   }
   RTD_HIP(launch_rew(dds, GD.items, GD.A, F, 0, ND, st));
   RTD_HIP(launch_fill_i32(GD.A.status + ND, ACTIVE, ND, st));

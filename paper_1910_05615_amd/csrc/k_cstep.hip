@@ -360,16 +360,10 @@ __global__ __launch_bounds__(FIN_NT) void k_finalize(const ItemDesc* __restrict_
 
   if (!from_start) {
     const int full = A.full[it];
-    const int64_t nsrc = full ? D.m : 2 * (int64_t)A.kswap[it];
-    int ntv = (int)((nsrc + tile_rows - 1) / tile_rows);
-    if (ntv < 1) ntv = 1;
+    // tile partials already collapsed into the first tile's
+    const double* __restrict__ P0 = A.part + (size_t)D.tile0 * PSTRIDE;
     // count and sum vector
-    for (int e = tid; e <= p; e += FIN_NT) {
-      const int idx = (e == 0) ? 0 : e;
-      double s = 0.0;
-      for (int t = 0; t < ntv; ++t) s += A.part[(size_t)(D.tile0 + t) * PSTRIDE + idx];
-      sv[e] = s;
-    }
+    for (int e = tid; e <= p; e += FIN_NT) sv[e] = P0[e];
     __syncthreads();
     // mean update (sv[1..p] is the pivot-centred sum)
     for (int j = tid; j < p; j += FIN_NT) cs[0][j] = sv[1 + j] / h;   // mu_new - c
@@ -377,9 +371,7 @@ __global__ __launch_bounds__(FIN_NT) void k_finalize(const ItemDesc* __restrict_
     for (int e = tid; e < p * p; e += FIN_NT) {
       const int i = e / p, j = e % p;
       const int a = i >= j ? i : j, b = i >= j ? j : i;
-      double s = 0.0;
-      for (int t = 0; t < ntv; ++t)
-        s += A.part[(size_t)(D.tile0 + t) * PSTRIDE + 1 + PMAX + a * (a + 1) / 2 + b];
+      const double s = P0[1 + PMAX + a * (a + 1) / 2 + b];
       const double old = full ? 0.0 : lam[i * PMAX + j];
       const double v = old + s - h * cs[0][i] * cs[0][j];
       lam[i * PMAX + j] = v;

@@ -130,8 +130,7 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const ItemDesc* __restr
       const int a = i >= j ? i : j, b = i >= j ? j : i;
       idx = 1 + PMAX + a * (a + 1) / 2 + b;
     }
-    double s = 0.0;
-    for (int t = 0; t < D.ntiles; ++t) s += part[(size_t)(D.tile0 + t) * PSTRIDE + idx];
+    const double s = part[(size_t)D.tile0 * PSTRIDE + idx];   // collapsed partial
     if (e == 0) cnt[it] = s;
     else if (e <= p) sum[(size_t)it * PMAX + e - 1] = s;
     else {
@@ -610,11 +609,8 @@ __global__ __launch_bounds__(256) void k_rew(DsInfo* __restrict__ ds,
   const int p = d.p;
   const int g0 = d.glob0, g1 = d.glob1;
   const ItemDesc D = gitems[g0];
-  for (int e = threadIdx.x; e <= p; e += blockDim.x) {
-    double s = 0.0;
-    for (int t = 0; t < D.ntiles; ++t) s += G.part[(size_t)(D.tile0 + t) * PSTRIDE + e];
-    sv[e] = s;
-  }
+  const double* __restrict__ P0 = G.part + (size_t)D.tile0 * PSTRIDE;   // collapsed partial
+  for (int e = threadIdx.x; e <= p; e += blockDim.x) sv[e] = P0[e];
   __syncthreads();
   const double nw = sv[0];
   if (!(nw > (double)p)) {
@@ -625,9 +621,7 @@ __global__ __launch_bounds__(256) void k_rew(DsInfo* __restrict__ ds,
   for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
     const int i = e / p, j = e % p;
     const int a = i >= j ? i : j, bb = i >= j ? j : i;
-    double s = 0.0;
-    for (int t = 0; t < D.ntiles; ++t)
-      s += G.part[(size_t)(D.tile0 + t) * PSTRIDE + 1 + PMAX + a * (a + 1) / 2 + bb];
+    const double s = P0[1 + PMAX + a * (a + 1) / 2 + bb];
     const double lam = s - sv[1 + i] * sv[1 + j] / nw;
     const double sx = lam / (nw - 1.0) * d.crew;
     G.sigz[(size_t)g1 * MSTRIDE + i * PMAX + j] =

@@ -37,7 +37,7 @@ struct SscpShape {
   static constexpr int NB = (P + 3) / 4;              // 4-wide column blocks
   static constexpr int NBLK = NB * (NB + 1) / 2;      // lower blocks
   static constexpr int NRL = 256 / NBLK;              // row lanes
-  static constexpr int BR = P <= 24 ? 256 : (P <= 40 ? 128 : 64);   // rows per batch
+  static constexpr int BR = P <= 40 ? 128 : 64;      // rows per batch
   static constexpr int PP = NB * 4 + 1;               // padded LDS row pitch (doubles)
   static constexpr int XS = BR * PP;
   static constexpr int RED = NRL * NBLK * 16;
@@ -79,15 +79,10 @@ __global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items
   if (s0 >= nsrc && !(s0 == 0)) return;   // tile beyond the update list: no partial
   const int64_t s1 = min(s0 + (int64_t)tile_rows, nsrc);
 
-  double c[P];
-#pragma unroll
-  for (int j = 0; j < P; ++j) {
-    double v = 0.0;
-    if (j < p) {
-      if (MODE == SSCP_CSTEP || MODE == SSCP_D2CUT) v = A.mux[(size_t)it * PMAX + j];
-    }
-    c[j] = v;
-  }
+  __shared__ double c[P];   // centre of the rows (the item's current mean)
+  for (int j = tid; j < P; j += 256)
+    c[j] = ((MODE == SSCP_CSTEP || MODE == SSCP_D2CUT) && j < p) ? A.mux[(size_t)it * PMAX + j]
+                                                                 : 0.0;
   double gA = 0.0, gB = 0.0, dcut = 0.0;
   if (MODE == SSCP_GSSCM) { gA = cut[2 * it]; gB = cut[2 * it + 1]; }
   if (MODE == SSCP_D2CUT) dcut = cut[D.ds];
@@ -158,17 +153,37 @@ __global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items
     }
     if (sel) { rsh[off + pos_w] = row; wsh[off + pos_w] = w; }
     __syncthreads();
-    // 2. load the selected rows, transformed, into LDS
-    for (int e = tid; e < nb * P; e += 256) {
-      const int r = e / P, j = e - r * P;
-      double v = 0.0;
-      if (j < p) {
-        const double x = ld_elem(X + rsh[r] * D.ld, j);
-        if (MODE == SSCP_WRAP) v = wrap_g((x - D.loc[j]) / D.scale[j]);
-        else if (MODE == SSCP_GSSCM) v = (x - D.loc[j]) / D.scale[j];
-        else v = x - c[j];
+    // 2. load the selected rows, transformed, into LDS (a fixed trip count so
+    // that every load of the batch is issued before the first one is used)
+    {
+      constexpr int NE = (S::BR * P + 255) / 256;
+      double xv[NE];
+#pragma unroll
+      for (int k = 0; k < NE; ++k) {
+        const int e = tid + k * 256;
+        const int r = e / P, j = e - r * P;
+        xv[k] = (e < nb * P && j < p) ? ld_elem(X + rsh[r] * D.ld, j) : 0.0;
       }
-      lds[r * S::PP + j] = v;
+#pragma unroll
+      for (int k = 0; k < NE; ++k) {
+        const int e = tid + k * 256;
+        if (e < nb * P) {
+          const int r = e / P, j = e - r * P;
+          double v = 0.0;
+          if (j < p) v = (MODE == SSCP_CSTEP || MODE == SSCP_D2CUT) ? xv[k] - c[j] : xv[k];
+          lds[r * S::PP + j] = v;
+        }
+      }
+      if (MODE == SSCP_WRAP || MODE == SSCP_GSSCM) {
+        // standardise (and wrap) in place: the same thread wrote these entries
+        for (int e = tid; e < nb * P; e += 256) {
+          const int r = e / P, j = e - r * P;
+          if (j < p) {
+            const double z = (lds[r * S::PP + j] - D.loc[j]) / D.scale[j];
+            lds[r * S::PP + j] = MODE == SSCP_WRAP ? wrap_g(z) : z;
+          }
+        }
+      }
     }
     for (int e = tid; e < nb * (S::PP - P); e += 256) {
       const int r = e / (S::PP - P), j = P + e % (S::PP - P);
@@ -257,7 +272,69 @@ hipError_t sscp_t(int mode, const ItemDesc* items, ItemArrays A, const Tile* til
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Collapse of an item's tile partials into the partial of its first tile, in
+// a fixed order: level 0 sums runs of COL_CT consecutive tiles into the first
+// tile of each run, level 1 sums the run heads.  cstep = 1: only the tiles
+// the C-step sscp wrote (all in full mode, those covering the swap list in
+// update mode) take part, and inactive items are skipped.
+// ---------------------------------------------------------------------------
+constexpr int COL_CT = 32;
+constexpr int COL_U = 8;
+
+__global__ __launch_bounds__(256) void k_collapse(const ItemDesc* __restrict__ items, ItemArrays A,
+                                                  int first, int cstep, int tile_rows, int level) {
+  const int it = first + blockIdx.x;
+  if (cstep && A.status[it] != ACTIVE) return;
+  const ItemDesc D = items[it];
+  int nv = D.ntiles;
+  if (cstep) {
+    const int64_t nsrc = A.full[it] ? D.m : 2 * (int64_t)A.kswap[it];
+    nv = (int)((nsrc + tile_rows - 1) / tile_rows);
+    if (nv < 1) nv = 1;
+  }
+  int t0, t1, stride;
+  if (level == 0) {
+    t0 = (int)blockIdx.y * COL_CT;
+    t1 = min(t0 + COL_CT, nv);
+    stride = 1;
+  } else {
+    t0 = 0;
+    t1 = (nv + COL_CT - 1) / COL_CT;
+    stride = COL_CT;
+  }
+  if (t1 - t0 <= 1) return;
+  const int p = D.p;
+  const int E = 1 + p + p * (p + 1) / 2;
+  double* __restrict__ base = A.part + (size_t)D.tile0 * PSTRIDE;
+  for (int e = threadIdx.x; e < E; e += blockDim.x) {
+    const int idx = e <= p ? e : 1 + PMAX + (e - 1 - p);
+    double s = 0.0;
+    for (int k = t0; k < t1; k += COL_U) {
+      double v[COL_U];
+#pragma unroll
+      for (int u = 0; u < COL_U; ++u)
+        v[u] = (k + u < t1) ? base[(size_t)(k + u) * stride * PSTRIDE + idx] : 0.0;
+#pragma unroll
+      for (int u = 0; u < COL_U; ++u) s += v[u];
+    }
+    base[(size_t)t0 * stride * PSTRIDE + idx] = s;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_collapse(const ItemDesc* items, ItemArrays A, int first, int nitems,
+                           int max_ntiles, int cstep, int tile_rows, hipStream_t s) {
+  if (nitems <= 0 || max_ntiles <= 1) return hipSuccess;
+  const int nch = (max_ntiles + COL_CT - 1) / COL_CT;
+  hipLaunchKernelGGL(k_collapse, dim3(nitems, nch), dim3(256), 0, s, items, A, first, cstep,
+                     tile_rows, 0);
+  if (nch > 1)
+    hipLaunchKernelGGL(k_collapse, dim3(nitems), dim3(256), 0, s, items, A, first, cstep,
+                       tile_rows, 1);
+  return hipGetLastError();
+}
 
 #define RTD_BUCKETS(X) X(4) X(5) X(8) X(10) X(16) X(20) X(24) X(32) X(40) X(48) X(64)
 

@@ -177,44 +177,58 @@ __device__ inline double val_of<uint64_t>(uint64_t k) {
   return __longlong_as_double((long long)b);
 }
 
-__device__ inline double block_sum_ordered(double v, double* red) {
-  // fixed-order reduction: per-thread values summed in thread order
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int o = SS_NT / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
+constexpr int SS_WV = SS_NT / 64;
+
+// Sums over the block of NV doubles per thread, in a fixed order (xor tree
+// within each wave, then the waves in index order); every thread receives
+// the sums.  red: NV * SS_WV doubles.
+template <int NV>
+__device__ inline void block_sums(double (&v)[NV], double* __restrict__ red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) red[k * SS_WV + w] = x;
   }
-  const double r = red[0];
   __syncthreads();
-  return r;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < SS_WV; ++q) t += red[k * SS_WV + q];
+    v[k] = t;
+  }
+  __syncthreads();
 }
 
-// Exclusive prefix (in thread order) of one double per thread.
-__device__ inline double block_excl_prefix(double v, double* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    // each of 64 lanes scans a run of SS_NT/64 entries, then a wave scan
-    constexpr int R = SS_NT / 64;
-    double s = 0.0;
-    for (int k = 0; k < R; ++k) s += red[threadIdx.x * R + k];
-    double x = s;
+// Exclusive prefix sums in thread order of NV doubles per thread (wave scans,
+// then the totals of earlier waves).  red: NV * SS_WV doubles.
+template <int NV>
+__device__ inline void block_excl_prefix(double (&v)[NV], double* __restrict__ red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double ex[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double x = v[k];
+#pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const double y = __shfl_up(x, o, 64);
-      if ((int)threadIdx.x >= o) x += y;
+      if (lane >= o) x += y;
     }
-    double run = x - s;
-    for (int k = 0; k < R; ++k) {
-      const double t = red[threadIdx.x * R + k];
-      red[threadIdx.x * R + k] = run;
-      run += t;
-    }
+    if (lane == 63) red[k * SS_WV + w] = x;
+    const double e = __shfl_up(x, 1, 64);
+    ex[k] = lane == 0 ? 0.0 : e;
   }
   __syncthreads();
-  const double r = red[threadIdx.x];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double off = 0.0;
+    for (int q = 0; q < w; ++q) off += red[k * SS_WV + q];
+    v[k] = off + ex[k];
+  }
   __syncthreads();
-  return r;
 }
 
 // k-th smallest (0-based) of |v_i - c| for a sorted segment v, by bisection on
@@ -318,14 +332,14 @@ __device__ __noinline__ SegStat segstat_body(const K* __restrict__ v, int64_t L,
   const int64_t hh = L / 2 + 1;
   const double c = val_of<K>(v[L / 2]);
   const int64_t a0 = (L * tid) / SS_NT, a1 = (L * (tid + 1)) / SS_NT;
-  double l1 = 0.0, l2 = 0.0;
+  double pa[2] = {0.0, 0.0};
   for (int64_t k = a0; k < a1; ++k) {
     const double d = val_of<K>(v[k]) - c;
-    l1 += d;
-    l2 = fma(d, d, l2);
+    pa[0] += d;
+    pa[1] = fma(d, d, pa[1]);
   }
-  const double P1a = block_excl_prefix(l1, red);
-  const double P2a = block_excl_prefix(l2, red);
+  block_excl_prefix<2>(pa, red);
+  const double P1a = pa[0], P2a = pa[1];
   // prefix at a0 + hh: the owner thread's prefix plus part of its range
   double P1b = 0.0, P2b = 0.0;
   const int64_t nw = L - hh + 1;             // number of windows
@@ -367,25 +381,35 @@ __device__ __noinline__ SegStat segstat_body(const K* __restrict__ v, int64_t L,
       }
     }
   }
-  __syncthreads();                           // owner prefixes no longer read
-  double* s_best = pfa;
-  int64_t* s_bj = reinterpret_cast<int64_t*>(pfb);
-  s_best[tid] = best;
-  s_bj[tid] = bj;
-  __syncthreads();
-  for (int o = SS_NT / 2; o > 0; o >>= 1) {
-    if (tid < o) {
-      const double b2 = s_best[tid + o];
-      const int64_t j2 = s_bj[tid + o];
-      if (j2 >= 0 && (s_bj[tid] < 0 || b2 < s_best[tid] || (b2 == s_best[tid] && j2 < s_bj[tid]))) {
-        s_best[tid] = b2;
-        s_bj[tid] = j2;
+  // smallest window variance, ties to the lowest start (an exact min, so
+  // every lane of the xor tree agrees)
+  {
+    const int lane = tid & 63, w = tid >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double b2 = __shfl_xor(best, o, 64);
+      const int64_t j2 = __shfl_xor(bj, o, 64);
+      if (j2 >= 0 && (bj < 0 || b2 < best || (b2 == best && j2 < bj))) {
+        best = b2;
+        bj = j2;
       }
     }
-    __syncthreads();
+    if (lane == 0) {
+      red[w] = best;
+      reinterpret_cast<int64_t*>(red)[SS_WV + w] = bj;
+    }
   }
-  const int64_t js = s_bj[0];
-  const double wmin = s_best[0];
+  __syncthreads();
+  double wmin = INFINITY;
+  int64_t js = -1;
+  for (int q = 0; q < SS_WV; ++q) {
+    const double b2 = red[q];
+    const int64_t j2 = reinterpret_cast<const int64_t*>(red)[SS_WV + q];
+    if (j2 >= 0 && (js < 0 || b2 < wmin)) {   // waves hold increasing starts
+      wmin = b2;
+      js = j2;
+    }
+  }
   __syncthreads();
   // window sum at the optimum, recomputed directly in thread order
   double w1 = 0.0;
@@ -393,7 +417,9 @@ __device__ __noinline__ SegStat segstat_body(const K* __restrict__ v, int64_t L,
     const int64_t b0 = js + (hh * tid) / SS_NT, b1 = js + (hh * (tid + 1)) / SS_NT;
     for (int64_t k = b0; k < b1; ++k) w1 += val_of<K>(v[k]) - c;
   }
-  const double S1w = block_sum_ordered(w1, red);
+  double sw[1] = {w1};
+  block_sums<1>(sw, red);
+  const double S1w = sw[0];
   const double mu_raw = c + S1w / (double)hh;
   const double var_raw = wmin * craw;
   // reweighting: keep (v - mu_raw)^2 <= q1 var_raw
@@ -409,9 +435,9 @@ __device__ __noinline__ SegStat segstat_body(const K* __restrict__ v, int64_t L,
       c2 = fma(d, d, c2);
     }
   }
-  const double N = block_sum_ordered(c0, red);
-  const double S1 = block_sum_ordered(c1, red);
-  const double S2 = block_sum_ordered(c2, red);
+  double cs[3] = {c0, c1, c2};
+  block_sums<3>(cs, red);
+  const double N = cs[0], S1 = cs[1], S2 = cs[2];
   if (tid == 0) {
     r.mu_raw = mu_raw;
     r.var_raw = var_raw;
@@ -438,25 +464,46 @@ __global__ __launch_bounds__(SS_NT) void k_segstats(const K* __restrict__ keys,
   if (threadIdx.x == 0) out[sg] = r;
 }
 
-// Sort one segment of at most LDS_KEYS keys entirely in LDS (stable LSD
-// radix, 8-bit digits, wave-ballot ranking as in k_rs_scatter), then run the
-// estimator on the sorted LDS copy.  Wave w holds the keys at positions
-// w*1024 + i*64 + lane, i < 16, so ranks follow position order.
+// Sort one segment of at most LDS_KEYS keys entirely in LDS (LSD radix on
+// 8-bit digits), then run the estimator on the sorted LDS copy.  Wave w holds
+// the keys at positions w*1024 + i*64 + lane, i < 16, so ranks follow
+// position order.
 //
-// 64-bit keys are first sorted on their high 32 bits only (4 passes).  The
-// high half is monotone in the key, so what is left is to order each run of
-// keys sharing a high half; such runs are short for continuous data (the
-// high half keeps 20 mantissa bits) and are finished by insertion sort.  A
-// run that is too long or needs too many moves sends the whole segment
-// through the full 8-pass sort instead, so heavy ties and coarse data stay
-// exact and the fix-up's cost bounded.
+// The passes run on a 32-bit key: the key itself for float data, and for
+// double data the order key of the value rounded to float (rounding is
+// monotone, so the order of the rounded keys never contradicts the order of
+// the values).  Runs of equal rounded keys are then ordered by insertion sort
+// on the full key; they are short for continuous data (24 mantissa bits).
+//
+// Ranks within a wave come from LDS atomics on per-(wave, digit) counters in
+// the passes whose digits spread well; those ranks follow lane order on this
+// hardware, which keeps each pass stable.  The top digit (sign and exponent,
+// few distinct values: atomics would serialise) is ranked with wave ballots,
+// which are stable by construction.  Nothing is taken on trust: the sorted
+// segment is checked, and a segment that is out of order, has a run that is
+// too long or too costly for the fix-up, goes through the full-width sort
+// with ballot ranking only.
 constexpr int LDS_KEYS = SS_NT * 16;
 constexpr int FIXUP_RUN = 256;      // longest run finished by insertion sort
 constexpr int FIXUP_MOVES = 2048;   // insertion-sort budget per run
 
-// One stable LSD pass over the block's keys (kv in position order on entry
-// and on exit).  wc: [16][256] ints, gs: [4][256] ints, wt: [4] ints.
-template <typename K>
+// Order key of a double key's value rounded to float.
+__device__ inline uint32_t key32_of(uint64_t k) {
+  const float f = (float)val_of<uint64_t>(k);
+  const uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+template <typename K, bool K32>
+__device__ inline int digit_at(K k, int shift) {
+  if constexpr (K32 && sizeof(K) == 8) return (int)((key32_of(k) >> shift) & 0xFFu);
+  else return (int)((k >> shift) & (K)0xFF);
+}
+
+// One LSD pass over the block's keys (kv in position order on entry and on
+// exit).  ATOM: ranks from LDS atomics, else from wave ballots.  K32: digits
+// of the 32-bit sort key.  wc: [16][256] ints, gs: [4][256] ints, wt: [4].
+template <typename K, bool ATOM, bool K32>
 __device__ inline void lds_radix_pass(K (&kv)[16], int shift, K* __restrict__ sk,
                                       int* __restrict__ wc, int* __restrict__ gs,
                                       int* __restrict__ wt) {
@@ -467,17 +514,21 @@ __device__ inline void lds_radix_pass(K (&kv)[16], int shift, K* __restrict__ sk
   int dr[16];   // digit << 16 | rank within (wave, digit)
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
-    const int d = (int)((kv[i] >> shift) & (K)0xFF);
-    uint64_t match = ~0ull;
+    const int d = digit_at<K, K32>(kv[i], shift);
+    if constexpr (ATOM) {
+      dr[i] = (d << 16) | atomicAdd(&wc[w * 256 + d], 1);
+    } else {
+      uint64_t match = ~0ull;
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const uint64_t bb = __ballot((d >> b) & 1);
-      match &= ((d >> b) & 1) ? bb : ~bb;
+      for (int b = 0; b < 8; ++b) {
+        const uint64_t bb = __ballot((d >> b) & 1);
+        match &= ((d >> b) & 1) ? bb : ~bb;
+      }
+      const int before = __popcll(match & below);
+      const int cur = wc[w * 256 + d];
+      dr[i] = (d << 16) | (cur + before);
+      if (before == 0) wc[w * 256 + d] = cur + __popcll(match);
     }
-    const int before = __popcll(match & below);
-    const int cur = wc[w * 256 + d];
-    dr[i] = (d << 16) | (cur + before);
-    if (before == 0) wc[w * 256 + d] = cur + __popcll(match);
   }
   __syncthreads();
   // offsets of (wave, digit): digit base + earlier waves of the same digit.
@@ -556,35 +607,37 @@ __global__ __launch_bounds__(SS_NT) void k_seg_lds(const K* __restrict__ keys,
     }
   };
   load();
-  constexpr int KB = 8 * (int)sizeof(K);
+  if (tid == 0) *redo = 0;
+  lds_radix_pass<K, true, true>(kv, 0, sk, wc, gs, wt);
+  lds_radix_pass<K, true, true>(kv, 8, sk, wc, gs, wt);
+  lds_radix_pass<K, true, true>(kv, 16, sk, wc, gs, wt);
+  lds_radix_pass<K, false, true>(kv, 24, sk, wc, gs, wt);
   if constexpr (sizeof(K) == 8) {
-    if (tid == 0) *redo = 0;
-    for (int shift = 32; shift < KB; shift += 8) lds_radix_pass<K>(kv, shift, sk, wc, gs, wt);
-    // runs of equal high halves: find their starts, then sort each
+    // runs of equal 32-bit keys: find their starts, then sort each
     uint32_t starts = 0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int pos = w * 1024 + i * 64 + lane;
       if (pos + 1 < L) {
-        const uint32_t hi = (uint32_t)(kv[i] >> 32);
-        const bool next_eq = (uint32_t)(sk[pos + 1] >> 32) == hi;
-        const bool prev_eq = pos > 0 && (uint32_t)(sk[pos - 1] >> 32) == hi;
+        const uint32_t k32 = key32_of(kv[i]);
+        const bool next_eq = key32_of(sk[pos + 1]) == k32;
+        const bool prev_eq = pos > 0 && key32_of(sk[pos - 1]) == k32;
         if (next_eq && !prev_eq) starts |= 1u << i;
       }
     }
     __syncthreads();
-    int moves = 0;
-    for (int i = 0; i < 16; ++i) {
-      if (!((starts >> i) & 1u)) continue;
+    while (starts) {
+      const int i = __ffs(starts) - 1;
+      starts &= starts - 1;
       const int s0 = w * 1024 + i * 64 + lane;
-      const uint32_t hi = (uint32_t)(sk[s0] >> 32);
+      const uint32_t k32 = key32_of(sk[s0]);
       int e = s0 + 1;
-      while (e < L && e - s0 <= FIXUP_RUN && (uint32_t)(sk[e] >> 32) == hi) ++e;
+      while (e < L && e - s0 <= FIXUP_RUN && key32_of(sk[e]) == k32) ++e;
       if (e - s0 > FIXUP_RUN) {
         *redo = 1;
         break;
       }
-      moves = 0;
+      int moves = 0;
       for (int a = s0 + 1; a < e && moves <= FIXUP_MOVES; ++a) {
         const K x = sk[a];
         int b = a;
@@ -595,16 +648,25 @@ __global__ __launch_bounds__(SS_NT) void k_seg_lds(const K* __restrict__ keys,
         }
         sk[b] = x;
       }
-      if (moves > FIXUP_MOVES) *redo = 1;
+      if (moves > FIXUP_MOVES) {
+        *redo = 1;
+        break;
+      }
     }
     __syncthreads();
-    if (*redo) {   // uniform: every thread reads the flag after the barrier
-      __syncthreads();
-      load();
-      for (int shift = 0; shift < KB; shift += 8) lds_radix_pass<K>(kv, shift, sk, wc, gs, wt);
-    }
-  } else {
-    for (int shift = 0; shift < KB; shift += 8) lds_radix_pass<K>(kv, shift, sk, wc, gs, wt);
+  }
+  // the order is checked, not assumed
+  {
+    bool bad = false;
+    for (int pos = tid; pos + 1 < L; pos += SS_NT) bad = bad || (sk[pos] > sk[pos + 1]);
+    if (bad) *redo = 1;
+  }
+  __syncthreads();
+  if (*redo) {   // uniform: every thread reads the flag after the barrier
+    __syncthreads();
+    load();
+    for (int shift = 0; shift < 8 * (int)sizeof(K); shift += 8)
+      lds_radix_pass<K, false, false>(kv, shift, sk, wc, gs, wt);
   }
   const SegStat r = segstat_body<K>(sk, L, seg_craw[sb], q1, crew, mode, scratch,
                                     scratch + SS_NT, scratch + 2 * SS_NT);
