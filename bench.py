@@ -51,8 +51,9 @@ def main() -> int:
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: runs on more than one GPU are not part of this "
-              "build (the fit shards by blocks; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only; multi-GPU runs are not supported "
+              "(the fit would shard by blocks, a design that is not implemented)",
+              file=sys.stderr)
         return 2
 
     import numpy as np

@@ -11,3 +11,4 @@ Parity status of each function is stated in its docstring; functions without a
 pin say "parity unpinned".
 """
 from .rtdetmcd import *  # noqa: F401,F403
+from . import adjoint  # noqa: F401

@@ -465,6 +465,7 @@ class Fit:
     m: int
     h: int
     n_w: int
+    rew_mask: np.ndarray         # n, 1 for the rows kept by the reweighting (Sec. 4 step 8)
     diag: dict
 
 
@@ -559,6 +560,8 @@ def fit(X: np.ndarray, alpha: float = 0.75, h_sub: int = 0, n_chunks: int = 0,
     # Step 10: final distances and flags for every row.
     Lw = np.linalg.cholesky(sig_rew)
     d2all = mahalanobis2(Z, mu_rew, Lw)
+    rew_mask = np.zeros(n, np.uint8)
+    rew_mask[order[: q * m][W]] = 1
 
     D = np.diag(scale)
     logs = 2.0 * float(np.sum(np.log(scale)))
@@ -570,6 +573,7 @@ def fit(X: np.ndarray, alpha: float = 0.75, h_sub: int = 0, n_chunks: int = 0,
         dist=np.sqrt(d2all), outlier=(d2all > chi2).astype(np.uint8),
         hsubset=hsub, chunk_status=chunk_status, chunk_start=chunk_start,
         chunk_iters=chunk_iters, loc=loc, scale=scale, q=q, m=m, h=h, n_w=n_w,
+        rew_mask=rew_mask,
         diag=dict(starts=starts_diag, kl_keys=keys, keep=np.asarray(valid)[keep],
                   d2_final=d2all, d2_reweight=d2, valid=np.asarray(valid),
                   mu_raw_z=mu_raw, sigma_raw_z=sig_raw, mu_rew_z=mu_rew,

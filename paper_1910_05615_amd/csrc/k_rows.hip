@@ -28,21 +28,42 @@ __device__ inline double wrap_g(double z) {
 // Weighted sscp partial sums over one tile of candidate rows:
 //   count = sum w,  s = sum w v,  S = sum w v v^T (lower triangle)
 // where v is the row value of the mode (see SscpMode) and w its weight.
-// Selected rows are compacted into LDS in batches and the lower triangle is
-// accumulated in 4x4 register blocks; every reduction has a fixed order, so
+//
+// This is a contraction over rows, so it runs on the float64 matrix cores
+// (16x16x4 MFMA: 16x16 output block, 4 rows per instruction).  The row is
+// extended by a constant 1 in column p, so that the block products also
+// deliver the weighted sums (row p of the result) and the count (entry
+// (p, p)).  Each wave stages chunks of CR rows in its own LDS region
+// (contiguous rows with 16-byte loads, the next chunk's loads in flight
+// while the current one is multiplied; gathered rows element by element);
+// then lane l takes, for column group g, column 16 g + (l mod 16) of row
+// (l div 16) of each four-row step.  That one value is the A operand (times
+// the weight) of the group's block row and the B operand of its block
+// column; only lower blocks (gi >= gj) are formed.  Rows of weight 0
+// contribute exact zeros (their values never enter a product).  Each wave
+// sums its own rows and the four waves are added in a fixed order, so
 // results do not depend on scheduling.
 // ---------------------------------------------------------------------------
-template <int P>
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Candidates per tile in an update step: the swap list (at most 2 (m - h)
+// rows) is spread over all of the item's tiles, at least 256 per tile, so
+// that short lists still keep many waves busy.
+__device__ inline int64_t list_tile_rows(const ItemDesc& D) {
+  const int64_t most = 2 * (D.m - D.h);
+  const int64_t t = (most + D.ntiles - 1) / D.ntiles;
+  return t > 256 ? t : 256;
+}
+
+template <typename T, int P>
 struct SscpShape {
-  static constexpr int NB = (P + 3) / 4;              // 4-wide column blocks
-  static constexpr int NBLK = NB * (NB + 1) / 2;      // lower blocks
-  static constexpr int NRL = 256 / NBLK;              // row lanes
-  static constexpr int BR = P <= 40 ? 128 : 64;      // rows per batch
-  static constexpr int PP = NB * 4 + 1;               // padded LDS row pitch (doubles)
-  static constexpr int XS = BR * PP;
-  static constexpr int RED = NRL * NBLK * 16;
-  static constexpr int LDSD = XS > RED ? XS : RED;
-  static constexpr int NRR = 256 / P;                 // row lanes of the sum vector
+  static constexpr int NG = (P + 1 + 15) / 16;        // 16-column groups (with the 1 column)
+  static constexpr int NBL = NG * (NG + 1) / 2;       // lower blocks
+  // rows per staged chunk: at most 8 KB of row data per wave, multiple of 4
+  static constexpr int CR0 = 8192 / (P * (int)sizeof(T));
+  static constexpr int CR = CR0 >= 64 ? 64 : (CR0 / 4) * 4;
+  static constexpr int XS = CR * P;                   // staged elements per wave
+  static constexpr int NV = (XS * (int)sizeof(T) / 16 + 63) / 64;   // 16-byte loads per lane
 };
 
 template <typename T, int P, int MODE>
@@ -50,12 +71,11 @@ __global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items
                                               const Tile* __restrict__ tiles, int tile_rows,
                                               const double* __restrict__ pivot, int pivot_stride,
                                               const double* __restrict__ cut) {
-  using S = SscpShape<P>;
-  __shared__ double lds[S::LDSD];
-  __shared__ double wsh[S::BR];
-  __shared__ int64_t rsh[S::BR];
-  __shared__ int wcount[4];
-  __shared__ double sred[256];
+  using S = SscpShape<T, P>;
+  constexpr int NG = S::NG, NBL = S::NBL, CR = S::CR;
+  __shared__ T xs_all[4][S::XS];          // per-wave row staging
+  __shared__ double red[NBL][4][64];      // block accumulators, summed wave by wave
+  __shared__ int64_t rows_all[4][CR];     // gathered row indices (update steps)
 
   const Tile tl = tiles[blockIdx.x];
   const int it = tl.item;
@@ -63,6 +83,8 @@ __global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items
   const int p = D.p;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
+  T* __restrict__ xs = xs_all[wv];
+  int64_t* __restrict__ rws = rows_all[wv];
 
   bool list_mode = false;
   int64_t nsrc = D.m;
@@ -75,175 +97,171 @@ __global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items
       nsrc = 2 * (int64_t)kin;
     }
   }
-  const int64_t s0 = (int64_t)tl.t * tile_rows;
+  const int64_t trows = list_mode ? list_tile_rows(D) : tile_rows;
+  const int64_t s0 = (int64_t)tl.t * trows;
   if (s0 >= nsrc && !(s0 == 0)) return;   // tile beyond the update list: no partial
-  const int64_t s1 = min(s0 + (int64_t)tile_rows, nsrc);
+  const int64_t s1 = min(s0 + trows, nsrc);
 
-  __shared__ double c[P];   // centre of the rows (the item's current mean)
-  for (int j = tid; j < P; j += 256)
-    c[j] = ((MODE == SSCP_CSTEP || MODE == SSCP_D2CUT) && j < p) ? A.mux[(size_t)it * PMAX + j]
-                                                                 : 0.0;
   double gA = 0.0, gB = 0.0, dcut = 0.0;
   if (MODE == SSCP_GSSCM) { gA = cut[2 * it]; gB = cut[2 * it + 1]; }
   if (MODE == SSCP_D2CUT) dcut = cut[D.ds];
-
   const T* __restrict__ X = static_cast<const T*>(D.X) + D.row0 * D.ld;
 
-  // block accumulators
-  const int blk = tid % S::NBLK;
-  const int rl = tid / S::NBLK;
-  int bi = 0, bj = 0;
-  {
-    int k = blk;
-    while (k > bi) { k -= bi + 1; ++bi; }
-    bj = k;
+  // per-lane column constants: centre (or standardisation) of each group column
+  const int kr = lane >> 4, cc = lane & 15;
+  double cen[NG], isc[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const int col = 16 * g + cc;
+    cen[g] = 0.0;
+    isc[g] = 1.0;
+    if (col < p) {
+      if (MODE == SSCP_CSTEP || MODE == SSCP_D2CUT) cen[g] = A.mux[(size_t)it * PMAX + col];
+      else { cen[g] = D.loc[col]; isc[g] = D.scale[col]; }
+    }
   }
-  double acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-  const int sj = tid % P, srr = tid / P;
-  double sacc = 0.0, wacc = 0.0;
 
-  for (int64_t base = s0; base < s1; base += S::BR) {
-    // 1. evaluate candidates and compact the selected rows (order preserving)
-    int64_t row = -1;
-    double w = 0.0;
-    const int64_t cand = base + tid;
-    if (tid < S::BR && cand < s1) {
-      if (MODE == SSCP_CSTEP) {
-        if (list_mode) {
-          const int64_t half = D.m / 2;
-          if (cand < kin) { row = A.swap[D.roff + cand]; w = 1.0; }
-          else { row = A.swap[D.roff + half + (cand - kin)]; w = -1.0; }
-        } else if (A.mask[D.roff + cand]) {
-          row = cand; w = 1.0;
-        }
-      } else if (MODE == SSCP_D2CUT) {
-        if (A.d2[D.roff + cand] <= dcut) { row = cand; w = 1.0; }
-      } else if (MODE == SSCP_WRAP) {
-        row = cand; w = 1.0;
-      } else {  // GSSCM: weight xi^2(||z||) of eq. (LR)
-        const T* xr = X + cand * D.ld;
-        double r2 = 0.0;
+  dbl4 acc[NBL];
 #pragma unroll
-        for (int j = 0; j < P; ++j)
-          if (j < p) {
-            const double z = (ld_elem(xr, j) - D.loc[j]) / D.scale[j];
-            r2 = fma(z, z, r2);
-          }
-        const double r = sqrt(r2);
-        double xi;
-        if (gB <= gA) xi = (r <= gA) ? 1.0 : 0.0;
-        else xi = (r <= gA) ? 1.0 : ((r <= gB) ? (gB - r) / (gB - gA) : 0.0);
-        row = cand; w = xi * xi;
-      }
+  for (int q = 0; q < NBL; ++q) acc[q] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  // this wave's candidates: a contiguous quarter of the tile
+  const int64_t wrows = (trows + 3) / 4;
+  const int64_t q0 = s0 + (int64_t)wv * wrows;
+  const int64_t q1 = min(q0 + wrows, s1);
+  const int64_t half = D.m / 2;
+  // contiguous rows of exactly P elements, 16-byte aligned: vector staging
+  const bool vec = !list_mode && p == P && D.ld == P &&
+                   ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+  typedef unsigned V __attribute__((ext_vector_type(4)));   // 16 bytes
+  V nx[S::NV];
+  // selection of row b + lane in the dense modes (loaded a chunk ahead too)
+  auto dense_sel = [&](int64_t b, int nn) -> bool {
+    if (lane >= nn) return false;
+    if (MODE == SSCP_CSTEP) return A.mask[D.roff + b + lane] != 0;
+    if (MODE == SSCP_D2CUT) return A.d2[D.roff + b + lane] <= dcut;
+    return true;
+  };
+  int64_t base = q0;
+  int n = (int)max((int64_t)0, min((int64_t)CR, q1 - base));
+  bool sel_next = list_mode ? false : dense_sel(base, n);
+  if (vec && base < q1) {   // vector loads of the first chunk's rows
+    const V* __restrict__ src = reinterpret_cast<const V*>(X + base * P);
+    const int nv = (n * P * (int)sizeof(T)) / 16;
+#pragma unroll
+    for (int k = 0; k < S::NV; ++k)
+      if (lane + 64 * k < nv) nx[k] = src[lane + 64 * k];
+  }
+  for (; base < q1; base += CR) {
+    // weight of row base + lane (lanes < n), and the chunk's rows into LDS
+    bool sel = sel_next, neg = false;
+    if (list_mode && lane < n) {
+      const int64_t cand = base + lane;
+      if (cand < kin) rws[lane] = A.swap[D.roff + cand];
+      else { rws[lane] = A.swap[D.roff + half + (cand - kin)]; neg = true; }
+      sel = true;
     }
-    const bool sel = row >= 0 && w != 0.0;
-    const uint64_t bal = __ballot(sel);
-    const int pos_w = __popcll(bal & ((1ull << lane) - 1ull));
-    if (lane == 0) wcount[wv] = __popcll(bal);
-    __syncthreads();
-    int off = 0, nb = 0;
+    const uint64_t selm = __ballot(sel), negm = __ballot(neg);
+    __syncwarp();   // previous chunk's reads of xs are done
+    if (vec) {   // the staged loads (and a tail of single elements) into LDS
+      const int nv = (n * P * (int)sizeof(T)) / 16;
+      V* __restrict__ dst = reinterpret_cast<V*>(xs);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (k < wv) off += wcount[k];
-      nb += wcount[k];
-    }
-    if (sel) { rsh[off + pos_w] = row; wsh[off + pos_w] = w; }
-    __syncthreads();
-    // 2. load the selected rows, transformed, into LDS (a fixed trip count so
-    // that every load of the batch is issued before the first one is used)
-    {
-      constexpr int NE = (S::BR * P + 255) / 256;
-      double xv[NE];
-#pragma unroll
-      for (int k = 0; k < NE; ++k) {
-        const int e = tid + k * 256;
+      for (int k = 0; k < S::NV; ++k)
+        if (lane + 64 * k < nv) dst[lane + 64 * k] = nx[k];
+      for (int e = nv * (16 / (int)sizeof(T)) + lane; e < n * P; e += 64) xs[e] = X[base * P + e];
+    } else if (list_mode) {
+      __syncwarp();
+      for (int e = lane; e < n * P; e += 64) {
         const int r = e / P, j = e - r * P;
-        xv[k] = (e < nb * P && j < p) ? ld_elem(X + rsh[r] * D.ld, j) : 0.0;
+        xs[e] = j < p ? X[rws[r] * D.ld + j] : (T)0;
       }
+    } else {
+      for (int e = lane; e < n * P; e += 64) {
+        const int r = e / P, j = e - r * P;
+        xs[e] = j < p ? X[(base + r) * D.ld + j] : (T)0;
+      }
+    }
+    const int64_t bn = base + CR;
+    const int nn = bn < q1 ? (int)min((int64_t)CR, q1 - bn) : 0;
+    if (!list_mode) sel_next = dense_sel(bn, nn);
+    if (vec && nn > 0) {   // next chunk's loads in flight
+      const V* __restrict__ src = reinterpret_cast<const V*>(X + bn * P);
+      const int nv = (nn * P * (int)sizeof(T)) / 16;
 #pragma unroll
-      for (int k = 0; k < NE; ++k) {
-        const int e = tid + k * 256;
-        if (e < nb * P) {
-          const int r = e / P, j = e - r * P;
-          double v = 0.0;
-          if (j < p) v = (MODE == SSCP_CSTEP || MODE == SSCP_D2CUT) ? xv[k] - c[j] : xv[k];
-          lds[r * S::PP + j] = v;
+      for (int k = 0; k < S::NV; ++k)
+        if (lane + 64 * k < nv) nx[k] = src[lane + 64 * k];
+    }
+    __syncwarp();   // staged rows visible to the whole wave
+    for (int st = 0; st < n; st += 4) {
+      const int r = st + kr;
+      const bool on = r < n && ((selm >> r) & 1ull);
+      double w = on ? (((negm >> r) & 1ull) ? -1.0 : 1.0) : 0.0;
+      double v[NG];
+      double r2 = 0.0;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const int col = 16 * g + cc;
+        double z = 0.0;
+        if (col < p) {
+          const double x = r < n ? (double)xs[r * P + col] : 0.0;
+          if (MODE == SSCP_CSTEP || MODE == SSCP_D2CUT) z = x - cen[g];
+          else z = (x - cen[g]) / isc[g];
+          if (MODE == SSCP_WRAP) z = wrap_g(z);
+          if (MODE == SSCP_GSSCM) r2 = fma(z, z, r2);
+        } else if (col == p) {
+          z = 1.0;
         }
+        v[g] = z;
       }
-      if (MODE == SSCP_WRAP || MODE == SSCP_GSSCM) {
-        // standardise (and wrap) in place: the same thread wrote these entries
-        for (int e = tid; e < nb * P; e += 256) {
-          const int r = e / P, j = e - r * P;
-          if (j < p) {
-            const double z = (lds[r * S::PP + j] - D.loc[j]) / D.scale[j];
-            lds[r * S::PP + j] = MODE == SSCP_WRAP ? wrap_g(z) : z;
-          }
-        }
-      }
-    }
-    for (int e = tid; e < nb * (S::PP - P); e += 256) {
-      const int r = e / (S::PP - P), j = P + e % (S::PP - P);
-      lds[r * S::PP + j] = 0.0;
-    }
-    __syncthreads();
-    // 3. accumulate the lower-triangular 4x4 blocks
-    if (rl < S::NRL) {
-      for (int r = rl; r < nb; r += S::NRL) {
-        const double* xr = lds + r * S::PP;
-        const double wr = wsh[r];
-        double a[4], b[4];
+      if (MODE == SSCP_GSSCM) {
+        // weight xi^2(||z||) of eq. (LR); the 16 lanes of a row add their parts
 #pragma unroll
-        for (int k = 0; k < 4; ++k) { a[k] = wr * xr[4 * bi + k]; b[k] = xr[4 * bj + k]; }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+        for (int o = 8; o > 0; o >>= 1) r2 += __shfl_xor(r2, o, 16);
+        const double rr = sqrt(r2);
+        double xi;
+        if (gB <= gA) xi = (rr <= gA) ? 1.0 : 0.0;
+        else xi = (rr <= gA) ? 1.0 : ((rr <= gB) ? (gB - rr) / (gB - gA) : 0.0);
+        w = on ? xi * xi : 0.0;
       }
-    }
-    if (srr < S::NRR) {
-      for (int r = srr; r < nb; r += S::NRR) {
-        sacc = fma(wsh[r], lds[r * S::PP + sj], sacc);
-        if (sj == 0) wacc += wsh[r];
+      double av[NG];
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        if (w == 0.0) v[g] = 0.0;
+        av[g] = w * v[g];
       }
+      int q = 0;
+#pragma unroll
+      for (int gi = 0; gi < NG; ++gi)
+#pragma unroll
+        for (int gj = 0; gj <= gi; ++gj, ++q)
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[gi], v[gj], acc[q], 0, 0, 0);
     }
-    __syncthreads();
+    n = nn;
   }
 
-  // 4. fixed-order reductions and the tile partial
+  // fixed-order sum over the four waves (wave 0 first) and the tile partial
+  for (int k = 0; k < 4; ++k) {
+    if (wv == k) {
+#pragma unroll
+      for (int q = 0; q < NBL; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) red[q][e][lane] = k == 0 ? acc[q][e] : red[q][e][lane] + acc[q][e];
+    }
+    __syncthreads();
+  }
   double* __restrict__ part = A.part + (size_t)(D.tile0 + tl.t) * PSTRIDE;
-  if (rl < S::NRL) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) lds[(rl * S::NBLK + blk) * 16 + u * 4 + v] = acc[u][v];
-  }
-  sred[tid] = (srr < S::NRR) ? sacc : 0.0;
-  __syncthreads();
-  for (int o = tid; o < S::NBLK * 16; o += 256) {
-    const int b = o / 16, e = o % 16;
-    double s = 0.0;
-    for (int k = 0; k < S::NRL; ++k) s += lds[(k * S::NBLK + b) * 16 + e];
-    int bi2 = 0, k2 = b;
-    while (k2 > bi2) { k2 -= bi2 + 1; ++bi2; }
-    const int i = 4 * bi2 + e / 4, j = 4 * k2 + e % 4;
-    if (i < p && j <= i) part[1 + PMAX + i * (i + 1) / 2 + j] = s;
-  }
-  if (tid < P && tid < p) {
-    double s = 0.0;
-    for (int k = 0; k < S::NRR; ++k) s += sred[k * P + tid];
-    part[1 + tid] = s;
-  }
-  __syncthreads();
-  sred[tid] = (sj == 0 && srr < S::NRR) ? wacc : 0.0;
-  __syncthreads();
-  if (tid == 0) {
-    double s = 0.0;
-    for (int k = 0; k < S::NRR; ++k) s += sred[k * P];
-    part[0] = s;
+  for (int o = tid; o < NBL * 4 * 64; o += 256) {
+    const int q = o / 256, e = (o / 64) % 4, l = o % 64;
+    const double sum = red[q][e][l];
+    // block q = (gi, gj); lane l, register e hold entry (16 gi + l/16 + 4 e, 16 gj + l%16)
+    int gi = 0, k = q;
+    while (k > gi) { k -= gi + 1; ++gi; }
+    const int gj = k;
+    const int I = 16 * gi + (l >> 4) + 4 * e, J = 16 * gj + (l & 15);
+    if (I < p && J <= I) part[1 + PMAX + I * (I + 1) / 2 + J] = sum;
+    else if (I == p && J < p) part[1 + J] = sum;
+    else if (I == p && J == p) part[0] = sum;
   }
 }
 
@@ -289,8 +307,10 @@ __global__ __launch_bounds__(256) void k_collapse(const ItemDesc* __restrict__ i
   const ItemDesc D = items[it];
   int nv = D.ntiles;
   if (cstep) {
-    const int64_t nsrc = A.full[it] ? D.m : 2 * (int64_t)A.kswap[it];
-    nv = (int)((nsrc + tile_rows - 1) / tile_rows);
+    const bool full = A.full[it] != 0;
+    const int64_t nsrc = full ? D.m : 2 * (int64_t)A.kswap[it];
+    const int64_t trows = full ? tile_rows : list_tile_rows(D);
+    nv = (int)((nsrc + trows - 1) / trows);
     if (nv < 1) nv = 1;
   }
   int t0, t1, stride;
