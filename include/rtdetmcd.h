@@ -101,6 +101,9 @@ typedef struct rtdetmcd_out {
   double*  loc;           /* [p]   standardisation location (Sec. 3.1) */
   double*  scale;         /* [p]   standardisation scale */
   int64_t* n_w;           /* [1]   rows kept by the reweighting */
+  uint8_t* rew_mask;      /* [n]   1 for the rows kept by the reweighting (Sec. 4 step 8:
+                           *       fitted rows whose squared distance under the raw fit
+                           *       does not exceed chi2_{p,cutoff_q}), 0 otherwise */
 } rtdetmcd_out;
 
 typedef struct rtdetmcd_ctx* rtdetmcd_handle;
@@ -193,6 +196,27 @@ rtdetmcd_status rtdetmcd_cstep(rtdetmcd_handle h, const void* X, int32_t dtype, 
                                const rtdetmcd_opts* o, double* mu, double* sigma,
                                int32_t* hsubset, int32_t* status, int32_t* iters,
                                double* logdet);
+
+/* ---- adjoint -------------------------------------------------------------- */
+
+/* Gradient with respect to X of <g_dist, dist> + <g_mu, mu> + <g_sigma, sigma>
+ * for a finished fit, with the reweighting set held fixed.  The fit ends with
+ * mu = mean and sigma = c_rew * covariance (divisor n_w - 1) of the rows of W,
+ * and dist_i = ||sigma^{-1/2}(x_i - mu)|| for every row (Sec. 4 steps 9-10,
+ * eq. statdist).  W, like the h-subsets, is constant away from ties at the
+ * cutoff, so this is the derivative of the fit wherever it exists.
+ * Inputs (device): X and its shape as given to the fit; mu [p], sigma [p*p],
+ * dist [n], rew_mask [n] and n_w [1] from the fit's rtdetmcd_out; c_rew (host)
+ * the scatter factor of the fit (1, or the consistency factor when
+ * rew_consistency was set).  Cotangents (device float64, each nullable = 0):
+ * g_dist [n], g_mu [p], g_sigma [p*p] (row-major; its symmetric part acts).
+ * Output: g_X [n*p] float64, row-major with row stride p.  Rows with
+ * dist_i = 0 receive no term from their own distance.  Asynchronous. */
+rtdetmcd_status rtdetmcd_backward(rtdetmcd_handle h, const void* X, int32_t dtype, int64_t n,
+                                  int32_t p, int64_t ld, const double* mu, const double* sigma,
+                                  const double* dist, const uint8_t* rew_mask,
+                                  const int64_t* n_w, double c_rew, const double* g_dist,
+                                  const double* g_mu, const double* g_sigma, double* g_X);
 
 #ifdef __cplusplus
 }

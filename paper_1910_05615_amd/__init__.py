@@ -3,5 +3,6 @@
 The compute path is the in-tree shared library ``librtdetmcd.so`` (C ABI in
 ``include/rtdetmcd.h``); this package only marshals arguments to it.
 """
-from .api import (Fit, RTDetMCDError, chi2_cdf, chi2_quantile, consistency, cstep,  # noqa: F401
-                  distances, fit, fit_batched, make_opts, plan, score, score_into, select)
+from .api import (Fit, RobustMCD, RTDetMCDError, backward, chi2_cdf, chi2_quantile,  # noqa: F401
+                  consistency, cstep, distances, fit, fit_batched, make_opts, plan, score,
+                  score_into, select)

@@ -19,6 +19,7 @@ SYMBOLS = [
     "rtdetmcd_default_opts", "rtdetmcd_plan", "rtdetmcd_fit", "rtdetmcd_fit_batched",
     "rtdetmcd_chi2_quantile", "rtdetmcd_chi2_cdf", "rtdetmcd_consistency",
     "rtdetmcd_distances", "rtdetmcd_score", "rtdetmcd_select", "rtdetmcd_cstep",
+    "rtdetmcd_backward",
 ]
 
 
@@ -34,7 +35,7 @@ class Out(C.Structure):
     _fields_ = [("mu", c_vp), ("sigma", c_vp), ("mu_raw", c_vp), ("sigma_raw", c_vp),
                 ("logdet", c_vp), ("dist", c_vp), ("outlier", c_vp), ("hsubset", c_vp),
                 ("block_status", c_vp), ("block_start", c_vp), ("block_iters", c_vp),
-                ("loc", c_vp), ("scale", c_vp), ("n_w", c_vp)]
+                ("loc", c_vp), ("scale", c_vp), ("n_w", c_vp), ("rew_mask", c_vp)]
 
 
 class DatasetDesc(C.Structure):
@@ -72,6 +73,8 @@ def load() -> C.CDLL:
         "rtdetmcd_select": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_vp, c_vp]),
         "rtdetmcd_cstep": (c_i32, [c_vp, c_vp, c_i32, c_i64, c_i32, c_i64, c_i64, c_vp, c_vp,
                                    c_vp, P(Opts), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+        "rtdetmcd_backward": (c_i32, [c_vp, c_vp, c_i32, c_i64, c_i32, c_i64, c_vp, c_vp, c_vp,
+                                      c_vp, c_vp, c_f64, c_vp, c_vp, c_vp, c_vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -192,9 +192,11 @@ class Fit:
     loc: torch.Tensor
     scale: torch.Tensor
     n_w: torch.Tensor
+    rew_mask: torch.Tensor        # rows kept by the reweighting (u8)
     q: int
     m: int
     h: int
+    c_rew: float = 1.0            # factor of the reweighted scatter
 
 
 def _alloc_fit(X: torch.Tensor, q: int, m: int, h: int):
@@ -209,13 +211,15 @@ def _alloc_fit(X: torch.Tensor, q: int, m: int, h: int):
             hsubset=torch.empty(q, h, **i32), block_status=torch.empty(q, **i32),
             block_start=torch.empty(q, **i32), block_iters=torch.empty(q, **i32),
             loc=torch.empty(p, **f64), scale=torch.empty(p, **f64),
-            n_w=torch.empty(1, dtype=torch.int64, device=dev), q=q, m=m, h=h)
+            n_w=torch.empty(1, dtype=torch.int64, device=dev),
+            rew_mask=torch.empty(n, dtype=torch.uint8, device=dev), q=q, m=m, h=h)
     out = _lib.Out(mu=F.mu.data_ptr(), sigma=F.sigma.data_ptr(), mu_raw=F.mu_raw.data_ptr(),
                    sigma_raw=F.sigma_raw.data_ptr(), logdet=F.logdet.data_ptr(),
                    dist=F.dist.data_ptr(), outlier=F.outlier.data_ptr(),
                    hsubset=F.hsubset.data_ptr(), block_status=F.block_status.data_ptr(),
                    block_start=F.block_start.data_ptr(), block_iters=F.block_iters.data_ptr(),
-                   loc=F.loc.data_ptr(), scale=F.scale.data_ptr(), n_w=F.n_w.data_ptr())
+                   loc=F.loc.data_ptr(), scale=F.scale.data_ptr(), n_w=F.n_w.data_ptr(),
+                   rew_mask=F.rew_mask.data_ptr())
     return F, out
 
 
@@ -227,10 +231,59 @@ def fit(X: torch.Tensor, h_sub: int = 0, n_chunks: int = 0, **opts) -> Fit:
     lib, hd = _handle(X.device)
     o = make_opts(**opts)
     F, out = _alloc_fit(X, q, m, h)
+    F.c_rew = lib.rtdetmcd_consistency(o.cutoff_q, p) if o.rew_consistency else 1.0
     st = lib.rtdetmcd_fit(hd, _ptr(X), _dtype_code(X), n, p, X.stride(0), h_sub, n_chunks,
                           C.byref(o), C.byref(out))
     _check(lib, hd, st, "rtdetmcd_fit")
     return F
+
+
+def backward(X: torch.Tensor, F: Fit, g_dist: Optional[torch.Tensor] = None,
+             g_mu: Optional[torch.Tensor] = None,
+             g_sigma: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Gradient with respect to X (float64, n x p) of <g_dist, dist> +
+    <g_mu, mu> + <g_sigma, sigma> for the fit F of X, with the h-subsets and
+    the reweighting set held fixed (rtdetmcd_backward)."""
+    _check_X(X)
+    n, p = X.shape
+    lib, hd = _handle(X.device)
+
+    def cot(t, shape):
+        if t is None:
+            return None
+        t = t.to(device=X.device, dtype=torch.float64).contiguous()
+        if tuple(t.shape) != shape:
+            raise ValueError(f"cotangent of shape {tuple(t.shape)}, expected {shape}")
+        return t
+
+    gd, gm, gs = cot(g_dist, (n,)), cot(g_mu, (p,)), cot(g_sigma, (p, p))
+    gX = torch.empty(n, p, dtype=torch.float64, device=X.device)
+    st = lib.rtdetmcd_backward(hd, _ptr(X), _dtype_code(X), n, p, X.stride(0), _ptr(F.mu),
+                               _ptr(F.sigma), _ptr(F.dist), _ptr(F.rew_mask), _ptr(F.n_w),
+                               float(F.c_rew), _ptr(gd), _ptr(gm), _ptr(gs), _ptr(gX))
+    _check(lib, hd, st, "rtdetmcd_backward")
+    return gX
+
+
+class RobustMCD(torch.autograd.Function):
+    """(mu, sigma, dist) of an RT-DetMCD fit as a differentiable function of X.
+
+    The backward holds the h-subsets and the reweighting set fixed; the fit is
+    piecewise smooth in X and this is its derivative wherever it exists.
+    ``fit_kw`` is a dict of keyword arguments of ``fit``."""
+
+    @staticmethod
+    def forward(ctx, X, fit_kw=None):
+        F = fit(X.detach(), **(fit_kw or {}))
+        ctx.save_for_backward(X)
+        ctx.fit_result = F
+        return F.mu, F.sigma, F.dist
+
+    @staticmethod
+    def backward(ctx, g_mu, g_sigma, g_dist):
+        (X,) = ctx.saved_tensors
+        gX = backward(X.detach(), ctx.fit_result, g_dist, g_mu, g_sigma)
+        return gX.to(X.dtype), None
 
 
 def fit_batched(Xs: Sequence[torch.Tensor], h_subs: Optional[Sequence[int]] = None,
@@ -250,6 +303,7 @@ def fit_batched(Xs: Sequence[torch.Tensor], h_subs: Optional[Sequence[int]] = No
         n, p = X.shape
         q, m, h = plan(n, p, h_subs[i], n_chunks[i], **opts)
         F, out = _alloc_fit(X, q, m, h)
+        F.c_rew = lib.rtdetmcd_consistency(o.cutoff_q, p) if o.rew_consistency else 1.0
         fits.append(F)
         arr[i] = _lib.DatasetDesc(X=X.data_ptr(), dtype=_dtype_code(X), n=n, p=p, ld=X.stride(0),
                                   h_sub=h_subs[i], n_chunks=n_chunks[i], out=out)

@@ -128,7 +128,7 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
                           D.A.mtri, D.A.mux, D.A.status, D.A.d2, st));
       RTD_HIP(launch_select(D.items, D.A, first, n, max_m, o.cstep_mode, st));
       RTD_HIP(launch_sscp(bucket, dtype, SSCP_CSTEP, D.items, D.A, D.stiles + st0, stn,
-                          SSCP_TILE, nullptr, 0, nullptr, st));
+                          SSCP_TILE, nullptr, nullptr, st));
       RTD_HIP(launch_collapse(D.items, D.A, first, n, max_nt, 1, SSCP_TILE, st));
       RTD_HIP(launch_finalize(D.items, D.A, first, n, 0, maxs, o.kappa_max, SSCP_TILE, st));
       if (t % R == 0 || t == maxs) {
@@ -151,7 +151,7 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
                           DIST_TILE, D.A.mtri, D.A.mux, D.A.status, D.A.d2, st));
       RTD_HIP(launch_select(D.items, D.A, i, 1, d.m, o.cstep_mode, st));
       RTD_HIP(launch_sscp(bucket, dtype, SSCP_CSTEP, D.items, D.A, D.stiles + d.tile0,
-                          d.ntiles, SSCP_TILE, nullptr, 0, nullptr, st));
+                          d.ntiles, SSCP_TILE, nullptr, nullptr, st));
       RTD_HIP(launch_collapse(D.items, D.A, i, 1, d.ntiles, 1, SSCP_TILE, st));
       RTD_HIP(launch_finalize(D.items, D.A, i, 1, 0, maxs, o.kappa_max, SSCP_TILE, st));
       RTD_HIP(hipMemcpyAsync(pin_flag, D.A.status + i, 4, hipMemcpyDeviceToHost, st));

@@ -64,9 +64,10 @@ constexpr int PSTRIDE = 1 + PMAX + TRI;  // count, sum, packed sscp
 // Row-source modes of the SSCP kernel.
 enum SscpMode : int {
   SSCP_CSTEP = 0,    // subset rows (full) or swapped rows (update), about mux
-  SSCP_D2CUT = 1,    // rows with d2 <= cut, about the given pivot (reweighting)
+  SSCP_D2CUT = 1,    // rows with d2 <= cut, about the item's mean (reweighting)
   SSCP_WRAP = 2,     // all rows, wrapped standardised values, about 0
   SSCP_GSSCM = 3,    // all rows, standardised values weighted by xi^2(||z||)
+  SSCP_ADJ = 4,      // all rows about the item's mean, weight wsrc_i / d_i (0 if d_i = 0)
 };
 
 struct Tile {
@@ -97,9 +98,10 @@ hipError_t launch_dist(int bucket, int dtype, int ipt, const ItemDesc* items, co
 // max_m: largest m among the items (picks the register-resident variant).
 hipError_t launch_select(const ItemDesc* items, ItemArrays A, int first_item, int nitems,
                          int64_t max_m, int cstep_mode, hipStream_t s);
+// wsrc: per-row cotangents of SSCP_ADJ (rows indexed like d2), else unused.
 hipError_t launch_sscp(int bucket, int dtype, int mode, const ItemDesc* items, ItemArrays A,
-                       const Tile* tiles, int ntiles, int tile_rows, const double* pivot,
-                       int pivot_stride, const double* cut, hipStream_t s);
+                       const Tile* tiles, int ntiles, int tile_rows, const double* wsrc,
+                       const double* cut, hipStream_t s);
 // Sums each item's sscp tile partials into the partial of its first tile
 // (every consumer of the partials reads that one only).  cstep: the partials
 // come from the C-step sscp (valid tiles depend on full/kswap, inactive

@@ -416,7 +416,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     const int st0 = B.items[b0].tile0, stn = B.items[b1 - 1].tile0 + B.items[b1 - 1].ntiles - st0;
     const int dt0 = B.dt_first[b0], dtn = B.dt_first[b1 - 1] + B.dt_count[b1 - 1] - dt0;
     RTD_HIP(launch_sscp(g.bucket, g.dtype, SSCP_WRAP, BD.items, BD.A, BD.stiles + st0, stn,
-                        SSCP_TILE, nullptr, 0, nullptr, st));
+                        SSCP_TILE, nullptr, nullptr, st));
     RTD_HIP(launch_collapse(BD.items, BD.A, b0, b1 - b0, B.max_ntiles(b0, b1), 0, SSCP_TILE, st));
     RTD_HIP(launch_reduce_partials(BD.items, BD.A.part, b0, b1 - b0, F.rcnt, F.rsum, F.rS, st));
     RTD_HIP(launch_init_cov(0, BD.items, b0, b1 - b0, F, CD.A, dds, cut, DN.st, st));
@@ -425,7 +425,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     RTD_TRY(sort_stats(ctx, SN, DN, b0, b1, SEGSTAT_GSSCM, 0.0, 1.0));
     RTD_HIP(launch_init_cov(2, BD.items, b0, b1 - b0, F, CD.A, dds, cut, DN.st, st));
     RTD_HIP(launch_sscp(g.bucket, g.dtype, SSCP_GSSCM, BD.items, BD.A, BD.stiles + st0, stn,
-                        SSCP_TILE, nullptr, 0, cut, st));
+                        SSCP_TILE, nullptr, cut, st));
     RTD_HIP(launch_collapse(BD.items, BD.A, b0, b1 - b0, B.max_ntiles(b0, b1), 0, SSCP_TILE, st));
     RTD_HIP(launch_reduce_partials(BD.items, BD.A.part, b0, b1 - b0, F.rcnt, F.rsum, F.rS, st));
     RTD_HIP(launch_init_cov(1, BD.items, b0, b1 - b0, F, CD.A, dds, cut, DN.st, st));
@@ -488,7 +488,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     RTD_HIP(launch_dist(g.bucket, g.dtype, 1, GD.items, GD.dtiles + dt0, dtn, DIST_TILE, GD.A.mtri,
                         GD.A.mux, nullptr, GD.A.d2, st));
     RTD_HIP(launch_sscp(g.bucket, g.dtype, SSCP_D2CUT, GD.items, GD.A, GD.stiles + st0, stn,
-                        SSCP_TILE, nullptr, 0, dchi, st));
+                        SSCP_TILE, nullptr, dchi, st));
     RTD_HIP(launch_collapse(GD.items, GD.A, a, b - a, G.max_ntiles(a, b), 0, SSCP_TILE, st));
   }
   RTD_HIP(launch_rew(dds, GD.items, GD.A, F, 0, ND, st));
@@ -499,7 +499,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     const int a = ND + g.ds0, b = ND + g.ds1;
     const int dt0 = G.dt_first[a], dtn = G.dt_first[b - 1] + G.dt_count[b - 1] - dt0;
     RTD_HIP(launch_final_dist(g.bucket, g.dtype, GD.items, GD.dtiles + dt0, dtn, DIST_TILE,
-                              GD.A.mtri, GD.A.mux, dds, douts, st));
+                              GD.A.mtri, GD.A.mux, GD.A.d2, dds, douts, st));
   }
   RTD_HIP(launch_hsub(CD.items, CD.A, F, dds, douts, 0, NB, st));
   RTD_HIP(launch_outputs(dds, GD.A, F, douts, 0, ND, st));

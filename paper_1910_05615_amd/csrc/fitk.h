@@ -74,7 +74,8 @@ hipError_t launch_rew(DsInfo* ds, const ItemDesc* gitems, ItemArrays G, FitArray
                       int nds, hipStream_t s);
 hipError_t launch_final_dist(int bucket, int dtype, const ItemDesc* items, const Tile* tiles,
                              int ntiles, int tile_rows, const double* mtri, const double* mux,
-                             const DsInfo* ds, const struct rtdetmcd_out* outs, hipStream_t s);
+                             const double* d2, const DsInfo* ds,
+                             const struct rtdetmcd_out* outs, hipStream_t s);
 hipError_t launch_hsub(const ItemDesc* citems, ItemArrays A, FitArrays F, const DsInfo* ds,
                        const struct rtdetmcd_out* outs, int first, int n, hipStream_t s);
 hipError_t launch_outputs(const DsInfo* ds, ItemArrays G, FitArrays F,

@@ -263,6 +263,7 @@ __global__ __launch_bounds__(CH) void k_final_dist(const ItemDesc* __restrict__ 
                                                    const Tile* __restrict__ tiles, int tile_rows,
                                                    const double* __restrict__ mtri,
                                                    const double* __restrict__ mux,
+                                                   const double* __restrict__ d2,
                                                    const DsInfo* __restrict__ ds,
                                                    const rtdetmcd_out* __restrict__ outs) {
   __shared__ double Ml[P * (P + 1) / 2];
@@ -276,6 +277,11 @@ __global__ __launch_bounds__(CH) void k_final_dist(const ItemDesc* __restrict__ 
   const double cut = dd.chi2p;
   double* __restrict__ od = outs[D.ds].dist;
   uint8_t* __restrict__ of = outs[D.ds].outlier;
+  uint8_t* __restrict__ ow = outs[D.ds].rew_mask;
+  // reweighting set: fitted rows whose distance under the raw fit (the
+  // dataset's first global item) is within the cutoff
+  const ItemDesc R = items[dd.glob0];
+  const double* __restrict__ d2r = d2 + R.roff;
   const int64_t r0 = (int64_t)tl.t * tile_rows;
   const int64_t r1 = min(r0 + (int64_t)tile_rows, D.m);
   const T* __restrict__ X = static_cast<const T*>(D.X) + D.row0 * D.ld;
@@ -285,6 +291,10 @@ __global__ __launch_bounds__(CH) void k_final_dist(const ItemDesc* __restrict__ 
                            [&](int, int64_t r, double v) {
                              if (od) od[D.row0 + r] = sqrt(v);
                              if (of) of[D.row0 + r] = v > cut ? 1 : 0;
+                             if (ow) {
+                               const int64_t rr = D.row0 + r - R.row0;
+                               ow[D.row0 + r] = (rr >= 0 && rr < R.m && d2r[rr] <= cut) ? 1 : 0;
+                             }
                            });
 }
 
@@ -340,16 +350,17 @@ hipError_t launch_dist(int bucket, int dtype, int ipt, const ItemDesc* items, co
 
 hipError_t launch_final_dist(int bucket, int dtype, const ItemDesc* items, const Tile* tiles,
                              int ntiles, int tile_rows, const double* mtri, const double* mux,
-                             const DsInfo* ds, const rtdetmcd_out* outs, hipStream_t s) {
+                             const double* d2, const DsInfo* ds, const rtdetmcd_out* outs,
+                             hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
 #define CASE(PB)                                                                                \
   case PB:                                                                                      \
     if (dtype == 0)                                                                             \
       hipLaunchKernelGGL((k_final_dist<float, PB>), dim3(ntiles), dim3(CH), 0, s, items, tiles, \
-                         tile_rows, mtri, mux, ds, outs);                                       \
+                         tile_rows, mtri, mux, d2, ds, outs);                                   \
     else                                                                                        \
       hipLaunchKernelGGL((k_final_dist<double, PB>), dim3(ntiles), dim3(CH), 0, s, items,       \
-                         tiles, tile_rows, mtri, mux, ds, outs);                                \
+                         tiles, tile_rows, mtri, mux, d2, ds, outs);                            \
     return hipGetLastError();
   switch (bucket) {
     RTD_BUCKETS(CASE)

@@ -69,7 +69,7 @@ struct SscpShape {
 template <typename T, int P, int MODE>
 __global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items, ItemArrays A,
                                               const Tile* __restrict__ tiles, int tile_rows,
-                                              const double* __restrict__ pivot, int pivot_stride,
+                                              const double* __restrict__ wsrc,
                                               const double* __restrict__ cut) {
   using S = SscpShape<T, P>;
   constexpr int NG = S::NG, NBL = S::NBL, CR = S::CR;
@@ -116,7 +116,8 @@ __global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items
     cen[g] = 0.0;
     isc[g] = 1.0;
     if (col < p) {
-      if (MODE == SSCP_CSTEP || MODE == SSCP_D2CUT) cen[g] = A.mux[(size_t)it * PMAX + col];
+      if (MODE == SSCP_CSTEP || MODE == SSCP_D2CUT || MODE == SSCP_ADJ)
+        cen[g] = A.mux[(size_t)it * PMAX + col];
       else { cen[g] = D.loc[col]; isc[g] = D.scale[col]; }
     }
   }
@@ -142,9 +143,16 @@ __global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items
     if (MODE == SSCP_D2CUT) return A.d2[D.roff + b + lane] <= dcut;
     return true;
   };
+  // real weight of row b + lane in SSCP_ADJ: cotangent / distance
+  auto adj_w = [&](int64_t b, int nn) -> double {
+    if (MODE != SSCP_ADJ || lane >= nn) return 0.0;
+    const double dd = A.d2[D.roff + b + lane];
+    return dd > 0.0 ? wsrc[D.roff + b + lane] / dd : 0.0;
+  };
   int64_t base = q0;
   int n = (int)max((int64_t)0, min((int64_t)CR, q1 - base));
   bool sel_next = list_mode ? false : dense_sel(base, n);
+  double w_next = adj_w(base, n);
   if (vec && base < q1) {   // vector loads of the first chunk's rows
     const V* __restrict__ src = reinterpret_cast<const V*>(X + base * P);
     const int nv = (n * P * (int)sizeof(T)) / 16;
@@ -155,6 +163,7 @@ __global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items
   for (; base < q1; base += CR) {
     // weight of row base + lane (lanes < n), and the chunk's rows into LDS
     bool sel = sel_next, neg = false;
+    const double wcur = w_next;
     if (list_mode && lane < n) {
       const int64_t cand = base + lane;
       if (cand < kin) rws[lane] = A.swap[D.roff + cand];
@@ -185,6 +194,7 @@ __global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items
     const int64_t bn = base + CR;
     const int nn = bn < q1 ? (int)min((int64_t)CR, q1 - bn) : 0;
     if (!list_mode) sel_next = dense_sel(bn, nn);
+    w_next = adj_w(bn, nn);
     if (vec && nn > 0) {   // next chunk's loads in flight
       const V* __restrict__ src = reinterpret_cast<const V*>(X + bn * P);
       const int nv = (nn * P * (int)sizeof(T)) / 16;
@@ -205,7 +215,7 @@ __global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items
         double z = 0.0;
         if (col < p) {
           const double x = r < n ? (double)xs[r * P + col] : 0.0;
-          if (MODE == SSCP_CSTEP || MODE == SSCP_D2CUT) z = x - cen[g];
+          if (MODE == SSCP_CSTEP || MODE == SSCP_D2CUT || MODE == SSCP_ADJ) z = x - cen[g];
           else z = (x - cen[g]) / isc[g];
           if (MODE == SSCP_WRAP) z = wrap_g(z);
           if (MODE == SSCP_GSSCM) r2 = fma(z, z, r2);
@@ -213,6 +223,10 @@ __global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items
           z = 1.0;
         }
         v[g] = z;
+      }
+      if (MODE == SSCP_ADJ) {
+        const double wr = __shfl(wcur, r < n ? r : 0, 64);
+        w = on ? wr : 0.0;
       }
       if (MODE == SSCP_GSSCM) {
         // weight xi^2(||z||) of eq. (LR); the 16 lanes of a row add their parts
@@ -267,25 +281,32 @@ __global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items
 
 template <typename T, int P>
 hipError_t sscp_t(int mode, const ItemDesc* items, ItemArrays A, const Tile* tiles, int ntiles,
-                  int tile_rows, const double* pivot, int pivot_stride, const double* cut,
+                  int tile_rows, const double* wsrc, const double* cut,
                   hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   switch (mode) {
     case SSCP_CSTEP:
       hipLaunchKernelGGL((k_sscp<T, P, SSCP_CSTEP>), dim3(ntiles), dim3(256), 0, s, items, A,
-                         tiles, tile_rows, pivot, pivot_stride, cut);
+                         tiles, tile_rows, wsrc, cut);
       break;
     case SSCP_D2CUT:
       hipLaunchKernelGGL((k_sscp<T, P, SSCP_D2CUT>), dim3(ntiles), dim3(256), 0, s, items, A,
-                         tiles, tile_rows, pivot, pivot_stride, cut);
+                         tiles, tile_rows, wsrc, cut);
       break;
     case SSCP_WRAP:
       hipLaunchKernelGGL((k_sscp<T, P, SSCP_WRAP>), dim3(ntiles), dim3(256), 0, s, items, A,
-                         tiles, tile_rows, pivot, pivot_stride, cut);
+                         tiles, tile_rows, wsrc, cut);
+      break;
+    case SSCP_GSSCM:
+      hipLaunchKernelGGL((k_sscp<T, P, SSCP_GSSCM>), dim3(ntiles), dim3(256), 0, s, items, A,
+                         tiles, tile_rows, wsrc, cut);
+      break;
+    case SSCP_ADJ:
+      hipLaunchKernelGGL((k_sscp<T, P, SSCP_ADJ>), dim3(ntiles), dim3(256), 0, s, items, A,
+                         tiles, tile_rows, wsrc, cut);
       break;
     default:
-      hipLaunchKernelGGL((k_sscp<T, P, SSCP_GSSCM>), dim3(ntiles), dim3(256), 0, s, items, A,
-                         tiles, tile_rows, pivot, pivot_stride, cut);
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
@@ -359,14 +380,14 @@ hipError_t launch_collapse(const ItemDesc* items, ItemArrays A, int first, int n
 #define RTD_BUCKETS(X) X(4) X(5) X(8) X(10) X(16) X(20) X(24) X(32) X(40) X(48) X(64)
 
 hipError_t launch_sscp(int bucket, int dtype, int mode, const ItemDesc* items, ItemArrays A,
-                       const Tile* tiles, int ntiles, int tile_rows, const double* pivot,
-                       int pivot_stride, const double* cut, hipStream_t s) {
+                       const Tile* tiles, int ntiles, int tile_rows, const double* wsrc,
+                       const double* cut, hipStream_t s) {
 #define CASE(PB)                                                                         \
   case PB:                                                                               \
-    return dtype == 0 ? sscp_t<float, PB>(mode, items, A, tiles, ntiles, tile_rows, pivot, \
-                                          pivot_stride, cut, s)                          \
-                      : sscp_t<double, PB>(mode, items, A, tiles, ntiles, tile_rows, pivot, \
-                                           pivot_stride, cut, s);
+    return dtype == 0 ? sscp_t<float, PB>(mode, items, A, tiles, ntiles, tile_rows, wsrc, \
+                                          cut, s)                                      \
+                      : sscp_t<double, PB>(mode, items, A, tiles, ntiles, tile_rows, wsrc, \
+                                           cut, s);
   switch (bucket) {
     RTD_BUCKETS(CASE)
     default: return hipErrorInvalidValue;
