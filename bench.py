@@ -48,6 +48,7 @@ def main() -> int:
     ap.add_argument("--cpu-sample-blocks", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -68,22 +69,34 @@ def main() -> int:
     q, m, h = R.plan(N, P, 0, BLOCKS)
 
     # ---------------------------------------------------------------- batched fit
-    for _ in range(args.warmup):
-        R.fit(X, n_chunks=BLOCKS)
-    torch.cuda.synchronize()
-    s = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(s)
-    for _ in range(args.steps):
-        F = R.fit(X, n_chunks=BLOCKS)
-    e1.record(s)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ev = e0.elapsed_time(e1) * 1e-3
-    t_step = max(wall, ev) / args.steps
+    def timed(**kw):
+        for _ in range(args.warmup):
+            R.fit(X, n_chunks=BLOCKS, **kw)
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(s)
+        for _ in range(args.steps):
+            Fk = R.fit(X, n_chunks=BLOCKS, **kw)
+        e1.record(s)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ev = e0.elapsed_time(e1) * 1e-3
+        return Fk, max(wall, ev) / args.steps
+
+    # the batched launches enqueued one by one (value), and the same with the
+    # C-step rounds replayed from captured hipGraphs
+    F, t_step = timed(graph=False)
     value = N / t_step
+    graph = None
+    if not args.no_graph:
+        Fg, t_g = timed(graph=True)
+        graph = {"value": N / t_g, "unit": "rows/s", "ms_per_step": t_g * 1e3,
+                 "identical_to_eager": bool(torch.equal(F.hsubset, Fg.hsubset) and
+                                            torch.equal(F.outlier, Fg.outlier) and
+                                            torch.equal(F.sigma, Fg.sigma))}
 
     # ---------------------------------------------------------------- plain fit
     plain = None
@@ -147,6 +160,7 @@ def main() -> int:
                                "64 blocks of 15,625 rows, AR(0.75) with 10% cluster outliers",
                    "n": N, "p": P, "blocks": q, "m": m, "h": h, "input_dtype": "f32",
                    "launch": "batched"},
+        "batched_graph": graph,
         "plain": plain,
         "roofline": roofline,
         "cpu_baseline": cpu,

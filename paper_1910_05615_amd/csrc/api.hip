@@ -8,11 +8,19 @@
 
 namespace rtd {
 
+void drop_graphs(rtdetmcd_ctx* ctx) {
+  for (rtd_graph& g : ctx->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  ctx->graphs.clear();
+}
+
 rtdetmcd_status ensure_ws(rtdetmcd_ctx* ctx, size_t bytes) {
   if (bytes <= ctx->ws_size) return RTDETMCD_OK;
   RTD_HIP(hipSetDevice(ctx->device));
   if (ctx->ws) {
     RTD_HIP(hipStreamSynchronize(ctx->stream));
+    if (ctx->gstream) RTD_HIP(hipStreamSynchronize(ctx->gstream));
+    drop_graphs(ctx);   // their kernel arguments point into the old workspace
     RTD_HIP(hipFree(ctx->ws));
     ctx->ws = nullptr;
     ctx->ws_size = 0;
@@ -102,6 +110,51 @@ void bind_items(char* base, const ItemSet& S, const size_t off[20], ItemDev& D) 
   (void)S;
 }
 
+// The executable graph of R C-steps for `key`: from the cache, or captured
+// now on the handle's replay stream (no memset nodes: counters are cleared by
+// a fill kernel).
+template <typename Step>
+rtdetmcd_status graph_for(rtdetmcd_ctx* ctx, const int64_t (&key)[16], int R, Step& step,
+                          hipGraphExec_t* out) {
+  for (rtd_graph& g : ctx->graphs) {
+    if (std::equal(key, key + 16, g.key)) {
+      *out = g.exec;
+      return RTDETMCD_OK;
+    }
+  }
+  if (!ctx->gstream) {
+    RTD_HIP(hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking));
+    RTD_HIP(hipEventCreateWithFlags(&ctx->gev[0], hipEventDisableTiming));
+    RTD_HIP(hipEventCreateWithFlags(&ctx->gev[1], hipEventDisableTiming));
+  }
+  constexpr size_t kMaxGraphs = 16;
+  if (ctx->graphs.size() >= kMaxGraphs) {
+    RTD_HIP(hipStreamSynchronize(ctx->gstream));
+    (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+    ctx->graphs.erase(ctx->graphs.begin());
+  }
+  hipGraph_t g = nullptr;
+  RTD_HIP(hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal));
+  rtdetmcd_status s = RTDETMCD_OK;
+  for (int r = 0; r < R && s == RTDETMCD_OK; ++r) s = step(ctx->gstream);
+  const hipError_t ec = hipStreamEndCapture(ctx->gstream, &g);
+  if (s != RTDETMCD_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  RTD_HIP(ec);
+  hipGraphExec_t ge = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  RTD_HIP(ei);
+  rtd_graph e;
+  std::copy(key, key + 16, e.key);
+  e.exec = ge;
+  ctx->graphs.push_back(e);
+  *out = ge;
+  return RTDETMCD_OK;
+}
+
 rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int bucket,
                            int dtype, int first, int n, const rtdetmcd_opts& o,
                            int32_t* pin_flag) {
@@ -122,15 +175,44 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
     const int max_nt = S.max_ntiles(first, first + n);
     RTD_HIP(launch_finalize(D.items, D.A, first, n, 1, maxs, o.kappa_max, SSCP_TILE, st));
     const int R = std::max(1, o.rounds_per_sync);
-    for (int t = 1; t <= maxs; ++t) {
-      RTD_HIP(launch_fill_i32(D.A.nactive, 0, 1, st));
+    // one C-step of every active item
+    auto step = [&](hipStream_t s) -> rtdetmcd_status {
+      RTD_HIP(launch_fill_i32(D.A.nactive, 0, 1, s));
       RTD_HIP(launch_dist(bucket, dtype, pairs ? 2 : 1, D.items, dtl + dt0, dtn, DIST_TILE,
-                          D.A.mtri, D.A.mux, D.A.status, D.A.d2, st));
-      RTD_HIP(launch_select(D.items, D.A, first, n, max_m, o.cstep_mode, st));
+                          D.A.mtri, D.A.mux, D.A.status, D.A.d2, s));
+      RTD_HIP(launch_select(D.items, D.A, first, n, max_m, o.cstep_mode, s));
       RTD_HIP(launch_sscp(bucket, dtype, SSCP_CSTEP, D.items, D.A, D.stiles + st0, stn,
-                          SSCP_TILE, nullptr, nullptr, st));
-      RTD_HIP(launch_collapse(D.items, D.A, first, n, max_nt, 1, SSCP_TILE, st));
-      RTD_HIP(launch_finalize(D.items, D.A, first, n, 0, maxs, o.kappa_max, SSCP_TILE, st));
+                          SSCP_TILE, nullptr, nullptr, s));
+      RTD_HIP(launch_collapse(D.items, D.A, first, n, max_nt, 1, SSCP_TILE, s));
+      RTD_HIP(launch_finalize(D.items, D.A, first, n, 0, maxs, o.kappa_max, SSCP_TILE, s));
+      return RTDETMCD_OK;
+    };
+    int t = 1;
+    if (o.graph && maxs >= R) {
+      // whole rounds of R steps replayed from a captured graph on the
+      // handle's replay stream, ordered after / before the caller's stream
+      const int64_t key[16] = {(int64_t)(uintptr_t)ctx->ws, (int64_t)(uintptr_t)D.items,
+                               (int64_t)(uintptr_t)dtl, bucket, dtype, first, n, pairs ? 2 : 1,
+                               dt0, dtn, st0, stn, max_nt, max_m,
+                               (int64_t)o.cstep_mode * 1000000 + maxs,
+                               (int64_t)R * 4096 + (int64_t)(o.kappa_max * 16.0)};
+      hipGraphExec_t ge = nullptr;
+      RTD_TRY(graph_for(ctx, key, R, step, &ge));
+      RTD_HIP(hipEventRecord(ctx->gev[0], st));
+      RTD_HIP(hipStreamWaitEvent(ctx->gstream, ctx->gev[0], 0));
+      bool done = false;
+      for (; t + R - 1 <= maxs; t += R) {
+        RTD_HIP(hipGraphLaunch(ge, ctx->gstream));
+        RTD_HIP(hipMemcpyAsync(pin_flag, D.A.nactive, 4, hipMemcpyDeviceToHost, ctx->gstream));
+        RTD_HIP(hipStreamSynchronize(ctx->gstream));
+        if (*pin_flag == 0) { done = true; break; }
+      }
+      RTD_HIP(hipEventRecord(ctx->gev[1], ctx->gstream));
+      RTD_HIP(hipStreamWaitEvent(st, ctx->gev[1], 0));
+      if (done) return RTDETMCD_OK;
+    }
+    for (; t <= maxs; ++t) {
+      RTD_TRY(step(st));
       if (t % R == 0 || t == maxs) {
         RTD_HIP(hipMemcpyAsync(pin_flag, D.A.nactive, 4, hipMemcpyDeviceToHost, st));
         RTD_HIP(hipStreamSynchronize(st));
@@ -279,6 +361,11 @@ rtdetmcd_status rtdetmcd_destroy(rtdetmcd_handle ctx) {
   if (!ctx) return RTDETMCD_EINVAL;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->gstream) (void)hipStreamSynchronize(ctx->gstream);
+  drop_graphs(ctx);
+  if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
+  for (hipEvent_t e : ctx->gev)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->pin) (void)hipHostFree(ctx->pin);
   if (ctx->pin_ev) (void)hipEventDestroy(ctx->pin_ev);

@@ -39,6 +39,7 @@ struct Layout {
 };
 
 rtdetmcd_status ensure_ws(rtdetmcd_ctx* ctx, size_t bytes);
+void drop_graphs(rtdetmcd_ctx* ctx);   // destroy the captured C-step rounds
 
 // Collects host->device copies and issues them from pinned staging.
 struct Uploader {

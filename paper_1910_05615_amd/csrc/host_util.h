@@ -71,6 +71,13 @@ inline double consistency(double alpha, int p) {
 
 }  // namespace rtd
 
+// A captured round of C-steps and what its kernel arguments were made of:
+// a replay is valid only for the same workspace, item tables and options.
+struct rtd_graph {
+  int64_t key[16];
+  hipGraphExec_t exec = nullptr;
+};
+
 struct rtdetmcd_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -82,4 +89,7 @@ struct rtdetmcd_ctx {
   hipEvent_t pin_ev = nullptr; // last upload out of the staging buffer
   bool pin_pending = false;
   int32_t* flag = nullptr;     // pinned readback word
+  hipStream_t gstream = nullptr;          // capture / replay stream (created on first use)
+  hipEvent_t gev[2] = {nullptr, nullptr}; // ordering with `stream`
+  std::vector<rtd_graph> graphs;          // captured C-step rounds, most recent last
 };

@@ -115,6 +115,34 @@ def test_fit_batched_uneven_datasets():
         check_fit(F, oracle.fit(s.X), s.name)
 
 
+_ALL = ("mu", "sigma", "mu_raw", "sigma_raw", "logdet", "dist", "outlier", "hsubset",
+        "block_status", "block_start", "block_iters", "loc", "scale", "n_w", "rew_mask")
+
+
+@pytest.mark.parametrize("rounds", [1, 3, 4])
+def test_graph_replays_equal_eager(rounds):
+    # captured C-step rounds replayed several times, with eager fits and
+    # synchronisations in between; every replayed fit equals the eager one
+    P = _P()
+    a = synthdata.workload_chunked_p20(n=60_000)
+    b = synthdata.small_gaussian(30_011, 7, seed=31, dtype=np.float32, rho=0.6, eps=0.15,
+                                 kind="point", gamma=6)
+    Xa = torch.from_numpy(a.X).to(_dev())
+    Xb = torch.from_numpy(b.X).to(_dev())
+    ref_a = _P().fit(Xa, n_chunks=4, rounds_per_sync=rounds)
+    ref_b = _P().fit(Xb, n_chunks=3, rounds_per_sync=rounds)
+    for _ in range(3):
+        ga = P.fit(Xa, n_chunks=4, graph=True, rounds_per_sync=rounds)
+        gb = P.fit(Xb, n_chunks=3, graph=True, rounds_per_sync=rounds)
+        torch.cuda.synchronize()
+        ea = P.fit(Xa, n_chunks=4, rounds_per_sync=rounds)
+        for name in _ALL:
+            assert torch.equal(getattr(ga, name), getattr(ref_a, name)), name
+            assert torch.equal(getattr(gb, name), getattr(ref_b, name)), name
+            assert torch.equal(getattr(ea, name), getattr(ref_a, name)), name
+    check_fit(ga, oracle.fit(a.X, n_chunks=4), "graph")
+
+
 def test_fit_heavy_ties_in_one_column():
     # one column on 12 integer levels: runs of equal keys far longer than the
     # sorter's insertion-sort fix-up accepts, so those segments take the
