@@ -83,6 +83,51 @@ def _roofline(R, torch, X, F, dev, reps):
             "note": "input is 80 MB, resident in the 256 MB MALL across launches"}
 
 
+def _other_workload(args, R, torch, synthdata, dev):
+    """rows/s of the batched-uneven (512 datasets, one batched call against one
+    call per dataset) or the large (10^7 x 40, 1,024 blocks, batched against
+    per-block launches) workload."""
+    def clock(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    if args.workload == "batched_uneven":
+        sets = synthdata.workload_batched_uneven()
+        Xs = [torch.from_numpy(s.X).to(dev) for s in sets]
+        rows = sum(int(X.shape[0]) for X in Xs)
+        t_b = clock(lambda: R.fit_batched(Xs), args.steps)
+        t_s = clock(lambda: [R.fit(X) for X in Xs], max(1, args.plain_steps))
+        cfg = {"workload": "512 datasets, n log-uniform [2e3, 2e5], p in {5,10,20,40}, "
+                           "float32, point outliers (eps in {0,.1,.2}), blocks by the omega rule",
+               "datasets": len(Xs), "rows": rows}
+        other = {"per_dataset_calls": {"value": rows / t_s, "unit": "rows/s",
+                                       "ms_per_step": t_s * 1e3,
+                                       "batched_over_per_dataset": t_s / t_b}}
+        t = t_b
+    else:
+        ds = synthdata.workload_large_p40()
+        X = torch.from_numpy(ds.X).to(dev)
+        rows = int(X.shape[0])
+        kw = dict(n_chunks=1024, cstep_mode="update")
+        t = clock(lambda: R.fit(X, **kw), args.steps)
+        t_p = clock(lambda: R.fit(X, launch="plain", **kw), 1)
+        cfg = {"workload": "n=10,000,000 p=40 float32, random correlation (eigenvalues "
+                           "U[0.1,10]), 5% N(0,25I); 1,024 blocks, update-based C-steps",
+               "n": rows, "p": 40, "blocks": 1024}
+        other = {"plain": {"value": rows / t_p, "unit": "rows/s", "ms_per_step": t_p * 1e3,
+                           "batched_over_plain": t_p / t}}
+    out = {"metric": "rows/sec fitted (RT-DetMCD), batched launch", "value": rows / t,
+           "unit": "rows/s", "n_gpus": 1, "steps": args.steps, "ms_per_step": t * 1e3,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic", "config": cfg}
+    out.update(other)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +139,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--workload", default="chunked_p20",
+                    choices=["chunked_p20", "batched_uneven", "large_p40"],
+                    help="chunked_p20 (the headline line) or one of the other workloads")
     ap.add_argument("--only-roofline", action="store_true",
                     help="one fit, a 64 MiB device copy (counter calibration), then the "
                          "distance-kernel launches only (for counter collection)")
@@ -112,6 +160,9 @@ def main() -> int:
     import synthdata
 
     dev = torch.device("cuda:0")
+    if args.workload != "chunked_p20":
+        print(json.dumps(_other_workload(args, R, torch, synthdata, dev)))
+        return 0
     ds = synthdata.workload_chunked_p20(n=N, p=P)
     X = torch.from_numpy(ds.X).to(dev)
     q, m, h = R.plan(N, P, 0, BLOCKS)
