@@ -713,12 +713,113 @@ __global__ __launch_bounds__(256) void k_outputs(const DsInfo* __restrict__ ds, 
   }
 }
 
+// MODE 0 for p >= 16 on the float64 matrix cores: the scores of 16 rows at a
+// time, D = W_tile (16 output columns x 4) x Z^T (4 x 16 rows) over the k
+// steps (16x16x4 MFMA).  Each wave stages chunks of its rows in its own LDS
+// region; lane l supplies z of row (l mod 16), column 4 s + l/16 (each
+// element standardised once) and receives output columns 16 t + l/16 + 4 v
+// of that row, which it stores as keys (16 consecutive rows of a column per
+// 16 lanes).
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int P>
+struct PShape {
+  static constexpr int NG = (P + 15) / 16;
+  static constexpr int KS = (P + 3) / 4;
+  static constexpr int CR = P <= 32 ? 64 : 32;   // rows per wave chunk
+};
+
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_project_mfma(const ItemDesc* __restrict__ items,
+                                                      const Tile* __restrict__ tiles,
+                                                      int tile_rows,
+                                                      const int32_t* __restrict__ status,
+                                                      const double* __restrict__ W,
+                                                      const int64_t* __restrict__ kbase,
+                                                      uint64_t* __restrict__ keys) {
+  using S = PShape<T, P>;
+  constexpr int NG = S::NG, KS = S::KS, CR = S::CR;
+  __shared__ double Wl[NG * KS * 64];
+  __shared__ double sloc[P], sisc[P];
+  __shared__ T xw[4 * CR * P];
+  const Tile tl = tiles[blockIdx.x];
+  const int it = tl.item;
+  if (status != nullptr && status[it] != ACTIVE) return;
+  const ItemDesc D = items[it];
+  const int p = D.p;
+  const T* __restrict__ X = static_cast<const T*>(D.X) + D.row0 * D.ld;
+  const double* __restrict__ Wi = W + (size_t)it * MSTRIDE;
+  uint64_t* __restrict__ ko = keys + kbase[it];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int e = tid; e < NG * KS * 64; e += 256) {
+    const int l = e & 63, ts = e >> 6, t = ts / KS, sidx = ts % KS;
+    const int i = 16 * t + (l & 15), k = 4 * sidx + (l >> 4);
+    Wl[e] = (i < p && k < p) ? Wi[i * PMAX + k] : 0.0;
+  }
+  for (int j = tid; j < P; j += 256) {
+    sloc[j] = j < p ? D.loc[j] : 0.0;
+    sisc[j] = j < p ? D.scale[j] : 1.0;
+  }
+  __syncthreads();
+  const int64_t r0 = (int64_t)tl.t * tile_rows;
+  const int64_t r1 = min(r0 + (int64_t)tile_rows, D.m);
+  const int64_t per = (((r1 - r0) + 3) / 4 + 15) / 16 * 16;
+  const int64_t w0 = r0 + wv * per, w1 = min(w0 + per, r1);
+  T* __restrict__ xs = xw + wv * CR * P;
+  const bool vec = p == P && D.ld == P && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+  for (int64_t base = w0; base < w1; base += CR) {
+    const int n = (int)min((int64_t)CR, w1 - base);
+    __syncwarp();   // the previous chunk's reads of xs are done
+    if (vec) {
+      typedef unsigned V __attribute__((ext_vector_type(4)));
+      const V* __restrict__ src = reinterpret_cast<const V*>(X + base * P);
+      V* __restrict__ dst = reinterpret_cast<V*>(xs);
+      const int nv = (n * P * (int)sizeof(T)) / 16;
+      for (int k = lane; k < nv; k += 64) dst[k] = src[k];
+      for (int e = nv * (16 / (int)sizeof(T)) + lane; e < n * P; e += 64) xs[e] = X[base * P + e];
+    } else {
+      for (int e = lane; e < n * P; e += 64) {
+        const int r = e / P, j = e - r * P;
+        xs[e] = j < p ? X[(base + r) * D.ld + j] : (T)0;
+      }
+    }
+    __syncwarp();   // staged rows visible to the whole wave
+    for (int g = 0; g < n; g += 16) {
+      const int rb = g + lr;
+      double zb[KS];
+#pragma unroll
+      for (int sidx = 0; sidx < KS; ++sidx) {
+        const int k = 4 * sidx + lk;
+        zb[sidx] = (rb < n && k < p) ? ((double)xs[rb * P + k] - sloc[k]) / sisc[k] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < NG; ++t) {
+        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int sidx = 0; sidx < KS; ++sidx)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Wl[(t * KS + sidx) * 64 + lane], zb[sidx],
+                                                     acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int col = 16 * t + lk + 4 * v;
+          if (col < p && rb < n) ko[(size_t)col * D.m + base + rb] = fkey64(acc[v]);
+        }
+      }
+    }
+  }
+}
+
 template <typename T, int P, int MODE>
 hipError_t project_t(const ItemDesc* items, const Tile* tiles, int ntiles, int tile_rows,
                      const int32_t* status, const double* W, const int64_t* kbase, uint64_t* keys,
                      hipStream_t s) {
-  hipLaunchKernelGGL((k_project<T, P, MODE>), dim3(ntiles), dim3(256), 0, s, items, tiles,
-                     tile_rows, status, W, kbase, keys);
+  if constexpr (MODE == 0 && P >= 16)
+    hipLaunchKernelGGL((k_project_mfma<T, P>), dim3(ntiles), dim3(256), 0, s, items, tiles,
+                       tile_rows, status, W, kbase, keys);
+  else
+    hipLaunchKernelGGL((k_project<T, P, MODE>), dim3(ntiles), dim3(256), 0, s, items, tiles,
+                       tile_rows, status, W, kbase, keys);
   return hipGetLastError();
 }
 
