@@ -93,7 +93,7 @@ rtdetmcd_status sort_stats(rtdetmcd_ctx* ctx, const SortHost& H, SortDev& D, int
   SortPlan P = D.plan.sub(a, b, H.tile0.data());
   const int64_t maxlen = *std::max_element(H.len.begin() + a, H.len.begin() + b);
   if (maxlen <= lds_sort_capacity()) {
-    RTD_HIP(launch_seg_lds(P, D.craw + a, q1, crew1, mode, D.st + a, ctx->stream));
+    RTD_HIP(launch_seg_lds(P, D.craw + a, q1, crew1, mode, D.st + a, maxlen, ctx->stream));
     return RTDETMCD_OK;
   }
   RTD_HIP(sort_segments(P, ctx->stream));

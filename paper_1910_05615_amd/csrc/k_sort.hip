@@ -465,9 +465,10 @@ __global__ __launch_bounds__(SS_NT) void k_segstats(const K* __restrict__ keys,
 }
 
 // Sort one segment of at most LDS_KEYS keys entirely in LDS (LSD radix on
-// 8-bit digits), then run the estimator on the sorted LDS copy.  Wave w holds
-// the keys at positions w*1024 + i*64 + lane, i < 16, so ranks follow
-// position order.
+// 8-bit digits), then run the estimator on the sorted LDS copy.  With KPT
+// keys per thread, wave w holds the keys at positions w*KPT*64 + i*64 + lane,
+// i < KPT, so ranks follow position order; KPT is the smallest of 4, 8, 12, 16
+// that holds the segment, so short segments sort no padding.
 //
 // The passes run on a 32-bit key: the key itself for float data, and for
 // double data the order key of the value rounded to float (rounding is
@@ -479,10 +480,11 @@ __global__ __launch_bounds__(SS_NT) void k_segstats(const K* __restrict__ keys,
 // the passes whose digits spread well; those ranks follow lane order on this
 // hardware, which keeps each pass stable.  The top digit (sign and exponent,
 // few distinct values: atomics would serialise) is ranked with wave ballots,
-// which are stable by construction.  Nothing is taken on trust: the sorted
-// segment is checked, and a segment that is out of order, has a run that is
-// too long or too costly for the fix-up, goes through the full-width sort
-// with ballot ranking only.
+// which are stable by construction.  Nothing is taken on trust: every
+// adjacent pair of 32-bit keys is checked in the same sweep that finds the
+// runs, and a segment that is out of order, or has a run that is too long or
+// too costly for the fix-up, goes through the full-width sort with ballot
+// ranking only.
 constexpr int LDS_KEYS = SS_NT * 16;
 constexpr int FIXUP_RUN = 256;      // longest run finished by insertion sort
 constexpr int FIXUP_MOVES = 2048;   // insertion-sort budget per run
@@ -503,17 +505,17 @@ __device__ inline int digit_at(K k, int shift) {
 // One LSD pass over the block's keys (kv in position order on entry and on
 // exit).  ATOM: ranks from LDS atomics, else from wave ballots.  K32: digits
 // of the 32-bit sort key.  wc: [16][256] ints, gs: [4][256] ints, wt: [4].
-template <typename K, bool ATOM, bool K32>
-__device__ inline void lds_radix_pass(K (&kv)[16], int shift, K* __restrict__ sk,
+template <typename K, bool ATOM, bool K32, int KPT>
+__device__ inline void lds_radix_pass(K (&kv)[KPT], int shift, K* __restrict__ sk,
                                       int* __restrict__ wc, int* __restrict__ gs,
                                       int* __restrict__ wt) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint64_t below = (1ull << lane) - 1ull;
   for (int e = tid; e < 16 * 256; e += SS_NT) wc[e] = 0;
   __syncthreads();
-  int dr[16];   // digit << 16 | rank within (wave, digit)
+  int dr[KPT];   // digit << 16 | rank within (wave, digit)
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
+  for (int i = 0; i < KPT; ++i) {
     const int d = digit_at<K, K32>(kv[i], shift);
     if constexpr (ATOM) {
       dr[i] = (d << 16) | atomicAdd(&wc[w * 256 + d], 1);
@@ -570,23 +572,24 @@ __device__ inline void lds_radix_pass(K (&kv)[16], int shift, K* __restrict__ sk
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
+  for (int i = 0; i < KPT; ++i) {
     const int di = dr[i] >> 16;
     sk[wc[w * 256 + di] + (dr[i] & 0xFFFF)] = kv[i];
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < 16; ++i) kv[i] = sk[w * 1024 + i * 64 + lane];
+  for (int i = 0; i < KPT; ++i) kv[i] = sk[w * KPT * 64 + i * 64 + lane];
 }
 
-template <typename K>
+template <typename K, int KPT>
 __global__ __launch_bounds__(SS_NT) void k_seg_lds(const K* __restrict__ keys,
                                                    const int64_t* __restrict__ seg_off,
                                                    const int64_t* __restrict__ seg_len,
                                                    const double* __restrict__ seg_craw,
                                                    int seg_first, double q1, double crew, int mode,
                                                    SegStat* __restrict__ out) {
-  __shared__ K sk[LDS_KEYS];
+  constexpr int CAP = SS_NT * KPT;             // keys per block
+  __shared__ K sk[CAP];
   __shared__ double scratch[3 * SS_NT];        // estimator scratch / wave digit counters
   int* wc = reinterpret_cast<int*>(scratch);   // [16][256] during the sort
   __shared__ int gs[4 * 256 + 8];              // group sums, wave totals, flag
@@ -598,38 +601,49 @@ __global__ __launch_bounds__(SS_NT) void k_seg_lds(const K* __restrict__ keys,
   const int L = (int)seg_len[sg];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const K pad = ~(K)0;
-  K kv[16];
+  K kv[KPT];
   auto load = [&]() {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int pos = w * 1024 + i * 64 + lane;
+    for (int i = 0; i < KPT; ++i) {
+      const int pos = w * KPT * 64 + i * 64 + lane;
       kv[i] = pos < L ? src[pos] : pad;
     }
   };
   load();
   if (tid == 0) *redo = 0;
-  lds_radix_pass<K, true, true>(kv, 0, sk, wc, gs, wt);
-  lds_radix_pass<K, true, true>(kv, 8, sk, wc, gs, wt);
-  lds_radix_pass<K, true, true>(kv, 16, sk, wc, gs, wt);
-  lds_radix_pass<K, false, true>(kv, 24, sk, wc, gs, wt);
-  if constexpr (sizeof(K) == 8) {
-    // runs of equal 32-bit keys: find their starts, then sort each
-    uint32_t starts = 0;
+  lds_radix_pass<K, true, true, KPT>(kv, 0, sk, wc, gs, wt);
+  lds_radix_pass<K, true, true, KPT>(kv, 8, sk, wc, gs, wt);
+  lds_radix_pass<K, true, true, KPT>(kv, 16, sk, wc, gs, wt);
+  lds_radix_pass<K, false, true, KPT>(kv, 24, sk, wc, gs, wt);
+  // One look at every adjacent pair: a 32-bit key that decreases means the
+  // passes went wrong (the order is checked, not assumed); equal 32-bit keys
+  // of double data start runs to be ordered on the full key.
+  uint32_t starts = 0;
+  {
+    bool bad = false;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int pos = w * 1024 + i * 64 + lane;
+    for (int i = 0; i < KPT; ++i) {
+      const int pos = w * KPT * 64 + i * 64 + lane;
       if (pos + 1 < L) {
-        const uint32_t k32 = key32_of(kv[i]);
-        const bool next_eq = key32_of(sk[pos + 1]) == k32;
-        const bool prev_eq = pos > 0 && key32_of(sk[pos - 1]) == k32;
-        if (next_eq && !prev_eq) starts |= 1u << i;
+        const K nx = sk[pos + 1];
+        uint32_t a, b;
+        if constexpr (sizeof(K) == 8) { a = key32_of(kv[i]); b = key32_of(nx); }
+        else { a = kv[i]; b = nx; }
+        bad = bad || a > b;
+        if constexpr (sizeof(K) == 8) {
+          const bool prev_eq = pos > 0 && key32_of(sk[pos - 1]) == a;
+          if (a == b && !prev_eq) starts |= 1u << i;
+        }
       }
     }
+    if (bad) *redo = 1;
+  }
+  if constexpr (sizeof(K) == 8) {
     __syncthreads();
     while (starts) {
       const int i = __ffs(starts) - 1;
       starts &= starts - 1;
-      const int s0 = w * 1024 + i * 64 + lane;
+      const int s0 = w * KPT * 64 + i * 64 + lane;
       const uint32_t k32 = key32_of(sk[s0]);
       int e = s0 + 1;
       while (e < L && e - s0 <= FIXUP_RUN && key32_of(sk[e]) == k32) ++e;
@@ -653,20 +667,13 @@ __global__ __launch_bounds__(SS_NT) void k_seg_lds(const K* __restrict__ keys,
         break;
       }
     }
-    __syncthreads();
-  }
-  // the order is checked, not assumed
-  {
-    bool bad = false;
-    for (int pos = tid; pos + 1 < L; pos += SS_NT) bad = bad || (sk[pos] > sk[pos + 1]);
-    if (bad) *redo = 1;
   }
   __syncthreads();
   if (*redo) {   // uniform: every thread reads the flag after the barrier
     __syncthreads();
     load();
     for (int shift = 0; shift < 8 * (int)sizeof(K); shift += 8)
-      lds_radix_pass<K, false, false>(kv, shift, sk, wc, gs, wt);
+      lds_radix_pass<K, false, false, KPT>(kv, shift, sk, wc, gs, wt);
   }
   const SegStat r = segstat_body<K>(sk, L, seg_craw[sb], q1, crew, mode, scratch,
                                     scratch + SS_NT, scratch + 2 * SS_NT);
@@ -1011,16 +1018,26 @@ hipError_t sort_segments(SortPlan& P, hipStream_t s) {
 }
 
 hipError_t launch_seg_lds(const SortPlan& P, const double* seg_craw, double q1, double crew,
-                          int mode, SegStat* out, hipStream_t s) {
+                          int mode, SegStat* out, int64_t max_len, hipStream_t s) {
   if (P.nseg <= 0) return hipSuccess;
-  if (P.key_bytes == 4)
-    hipLaunchKernelGGL((k_seg_lds<uint32_t>), dim3(P.nseg), dim3(SS_NT), 0, s,
-                       static_cast<const uint32_t*>(P.keys), P.seg_off, P.seg_len, seg_craw,
-                       P.seg_first, q1, crew, mode, out);
-  else
-    hipLaunchKernelGGL((k_seg_lds<uint64_t>), dim3(P.nseg), dim3(SS_NT), 0, s,
-                       static_cast<const uint64_t*>(P.keys), P.seg_off, P.seg_len, seg_craw,
-                       P.seg_first, q1, crew, mode, out);
+  // keys per thread: the smallest of 4, 8, 12, 16 that holds the longest segment
+  const int kpt = max_len <= 4 * SS_NT ? 4 : max_len <= 8 * SS_NT ? 8 : max_len <= 12 * SS_NT ? 12 : 16;
+#define SEG_LDS(K, KPT)                                                                        \
+  hipLaunchKernelGGL((k_seg_lds<K, KPT>), dim3(P.nseg), dim3(SS_NT), 0, s,                     \
+                     static_cast<const K*>(P.keys), P.seg_off, P.seg_len, seg_craw, P.seg_first, \
+                     q1, crew, mode, out)
+  if (P.key_bytes == 4) {
+    if (kpt == 4) SEG_LDS(uint32_t, 4);
+    else if (kpt == 8) SEG_LDS(uint32_t, 8);
+    else if (kpt == 12) SEG_LDS(uint32_t, 12);
+    else SEG_LDS(uint32_t, 16);
+  } else {
+    if (kpt == 4) SEG_LDS(uint64_t, 4);
+    else if (kpt == 8) SEG_LDS(uint64_t, 8);
+    else if (kpt == 12) SEG_LDS(uint64_t, 12);
+    else SEG_LDS(uint64_t, 16);
+  }
+#undef SEG_LDS
   return hipGetLastError();
 }
 

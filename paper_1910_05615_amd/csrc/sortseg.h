@@ -75,6 +75,6 @@ int lds_sort_capacity();
 hipError_t launch_unimcd_multiblock(const SortPlan& P, const double* seg_craw, double q1,
                                     double crew, SegStat* out, hipStream_t s);
 hipError_t launch_seg_lds(const SortPlan& P, const double* seg_craw, double q1, double crew,
-                          int mode, SegStat* out, hipStream_t s);
+                          int mode, SegStat* out, int64_t max_len, hipStream_t s);
 
 }  // namespace rtd
