@@ -7,6 +7,8 @@
 #include "common.h"
 #include "sortseg.h"
 
+#include <type_traits>
+
 namespace rtd {
 
 namespace {
@@ -175,6 +177,15 @@ template <>
 __device__ inline double val_of<uint64_t>(uint64_t k) {
   const uint64_t b = (k & 0x8000000000000000ull) ? (k ^ 0x8000000000000000ull) : ~k;
   return __longlong_as_double((long long)b);
+}
+// segments already converted back to values
+template <>
+__device__ inline double val_of<float>(float k) {
+  return (double)k;
+}
+template <>
+__device__ inline double val_of<double>(double k) {
+  return k;
 }
 
 constexpr int SS_WV = SS_NT / 64;
@@ -362,15 +373,17 @@ __device__ __noinline__ SegStat segstat_body(const K* __restrict__ v, int64_t L,
       P2b = fma(d, d, P2b);
     }
   }
-  double best = INFINITY;
+  // windows are ranked by hd * s2 - s1^2 = hd (hd - 1) var (no division in
+  // the loop); the variance itself is formed from the best window's sums
+  double best = INFINITY, b1 = 0.0, b2 = 0.0;
   int64_t bj = -1;
+  const double hd = (double)hh;
   {
     double q1l = P1a, q2l = P2a, q1h = P1b, q2h = P2b;
-    const double hd = (double)hh;
     for (int64_t j = j0; j < j1; ++j) {
       const double s1 = q1h - q1l, s2 = q2h - q2l;
-      const double wv = (s2 - s1 * s1 / hd) / (hd - 1.0);
-      if (wv < best) { best = wv; bj = j; }
+      const double cr = fma(s2, hd, -(s1 * s1));
+      if (cr < best) { best = cr; bj = j; b1 = s1; b2 = s2; }
       const double dl = val_of<K>(v[j]) - c;
       q1l += dl;
       q2l = fma(dl, dl, q2l);
@@ -381,32 +394,37 @@ __device__ __noinline__ SegStat segstat_body(const K* __restrict__ v, int64_t L,
       }
     }
   }
-  // smallest window variance, ties to the lowest start (an exact min, so
-  // every lane of the xor tree agrees)
+  double bv = bj >= 0 ? (b2 - b1 * b1 / hd) / (hd - 1.0) : INFINITY;
+  // smallest window criterion, ties to the lowest start (an exact min, so
+  // every lane of the xor tree agrees); the variance travels with it
   {
     const int lane = tid & 63, w = tid >> 6;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-      const double b2 = __shfl_xor(best, o, 64);
+      const double c2 = __shfl_xor(best, o, 64);
+      const double v2 = __shfl_xor(bv, o, 64);
       const int64_t j2 = __shfl_xor(bj, o, 64);
-      if (j2 >= 0 && (bj < 0 || b2 < best || (b2 == best && j2 < bj))) {
-        best = b2;
+      if (j2 >= 0 && (bj < 0 || c2 < best || (c2 == best && j2 < bj))) {
+        best = c2;
+        bv = v2;
         bj = j2;
       }
     }
     if (lane == 0) {
       red[w] = best;
-      reinterpret_cast<int64_t*>(red)[SS_WV + w] = bj;
+      red[SS_WV + w] = bv;
+      reinterpret_cast<int64_t*>(red)[2 * SS_WV + w] = bj;
     }
   }
   __syncthreads();
-  double wmin = INFINITY;
+  double cmin = INFINITY, wmin = INFINITY;
   int64_t js = -1;
   for (int q = 0; q < SS_WV; ++q) {
-    const double b2 = red[q];
-    const int64_t j2 = reinterpret_cast<const int64_t*>(red)[SS_WV + q];
-    if (j2 >= 0 && (js < 0 || b2 < wmin)) {   // waves hold increasing starts
-      wmin = b2;
+    const double c2 = red[q];
+    const int64_t j2 = reinterpret_cast<const int64_t*>(red)[2 * SS_WV + q];
+    if (j2 >= 0 && (js < 0 || c2 < cmin)) {   // waves hold increasing starts
+      cmin = c2;
+      wmin = red[SS_WV + q];
       js = j2;
     }
   }
@@ -471,16 +489,17 @@ __global__ __launch_bounds__(SS_NT) void k_segstats(const K* __restrict__ keys,
 // that holds the segment, so short segments sort no padding.
 //
 // The passes run on a 32-bit key: the key itself for float data, and for
-// double data the order key of the value rounded to float (rounding is
-// monotone, so the order of the rounded keys never contradicts the order of
-// the values).  Runs of equal rounded keys are then ordered by insertion sort
-// on the full key; they are short for continuous data (24 mantissa bits).
+// double data the high half of the order key (sign, exponent and 20 mantissa
+// bits: a monotone function of the key, so its order never contradicts the
+// order of the values).  Runs of equal high halves are then ordered by
+// insertion sort on the full key; they are short for continuous data.
 //
 // Ranks within a wave come from LDS atomics on per-(wave, digit) counters in
 // the passes whose digits spread well; those ranks follow lane order on this
-// hardware, which keeps each pass stable.  The top digit (sign and exponent,
-// few distinct values: atomics would serialise) is ranked with wave ballots,
-// which are stable by construction.  Nothing is taken on trust: every
+// hardware, which keeps each pass stable.  The top digit (sign and the high
+// exponent bits: few distinct values in a wave, so atomics would serialise)
+// is ranked by peeling: one wave ballot per distinct digit present, stable
+// by construction.  Nothing is taken on trust: every
 // adjacent pair of 32-bit keys is checked in the same sweep that finds the
 // runs, and a segment that is out of order, or has a run that is too long or
 // too costly for the fix-up, goes through the full-width sort with ballot
@@ -489,12 +508,13 @@ constexpr int LDS_KEYS = SS_NT * 16;
 constexpr int FIXUP_RUN = 256;      // longest run finished by insertion sort
 constexpr int FIXUP_MOVES = 2048;   // insertion-sort budget per run
 
-// Order key of a double key's value rounded to float.
-__device__ inline uint32_t key32_of(uint64_t k) {
-  const float f = (float)val_of<uint64_t>(k);
-  const uint32_t b = __float_as_uint(f);
-  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-}
+// 32-bit sort key of a double's order key: its high half.
+__device__ inline uint32_t key32_of(uint64_t k) { return (uint32_t)(k >> 32); }
+
+// How a pass ranks keys within a wave (all three follow lane order).
+constexpr int RK_ATOM = 0;     // LDS atomics on per-(wave, digit) counters
+constexpr int RK_BALLOT = 1;   // match by eight bit ballots: any digit mix
+constexpr int RK_PEEL = 2;     // one ballot per distinct digit in the wave
 
 template <typename K, bool K32>
 __device__ inline int digit_at(K k, int shift) {
@@ -503,9 +523,9 @@ __device__ inline int digit_at(K k, int shift) {
 }
 
 // One LSD pass over the block's keys (kv in position order on entry and on
-// exit).  ATOM: ranks from LDS atomics, else from wave ballots.  K32: digits
-// of the 32-bit sort key.  wc: [16][256] ints, gs: [4][256] ints, wt: [4].
-template <typename K, bool ATOM, bool K32, int KPT>
+// exit).  RK: how ranks are found (RK_*).  K32: digits of the 32-bit sort
+// key.  wc: [16][256] ints, gs: [4][256] ints, wt: [4].
+template <typename K, int RK, bool K32, int KPT>
 __device__ inline void lds_radix_pass(K (&kv)[KPT], int shift, K* __restrict__ sk,
                                       int* __restrict__ wc, int* __restrict__ gs,
                                       int* __restrict__ wt) {
@@ -517,8 +537,23 @@ __device__ inline void lds_radix_pass(K (&kv)[KPT], int shift, K* __restrict__ s
 #pragma unroll
   for (int i = 0; i < KPT; ++i) {
     const int d = digit_at<K, K32>(kv[i], shift);
-    if constexpr (ATOM) {
+    if constexpr (RK == RK_ATOM) {
       dr[i] = (d << 16) | atomicAdd(&wc[w * 256 + d], 1);
+    } else if constexpr (RK == RK_PEEL) {
+      // every lane is active here; each round takes the lanes that share the
+      // lowest remaining lane's digit
+      uint64_t left = ~0ull;
+      int rank = 0;
+      while (left) {
+        const int lead = __ffsll((long long)left) - 1;
+        const int dl = __builtin_amdgcn_readlane(d, lead);
+        const uint64_t m = __ballot(d == dl);
+        const int cur = wc[w * 256 + dl];
+        if (d == dl) rank = cur + __popcll(m & below);
+        if (lane == lead) wc[w * 256 + dl] = cur + __popcll(m);
+        left &= ~m;
+      }
+      dr[i] = (d << 16) | rank;
     } else {
       uint64_t match = ~0ull;
 #pragma unroll
@@ -611,10 +646,10 @@ __global__ __launch_bounds__(SS_NT) void k_seg_lds(const K* __restrict__ keys,
   };
   load();
   if (tid == 0) *redo = 0;
-  lds_radix_pass<K, true, true, KPT>(kv, 0, sk, wc, gs, wt);
-  lds_radix_pass<K, true, true, KPT>(kv, 8, sk, wc, gs, wt);
-  lds_radix_pass<K, true, true, KPT>(kv, 16, sk, wc, gs, wt);
-  lds_radix_pass<K, false, true, KPT>(kv, 24, sk, wc, gs, wt);
+  lds_radix_pass<K, RK_ATOM, true, KPT>(kv, 0, sk, wc, gs, wt);
+  lds_radix_pass<K, RK_ATOM, true, KPT>(kv, 8, sk, wc, gs, wt);
+  lds_radix_pass<K, RK_ATOM, true, KPT>(kv, 16, sk, wc, gs, wt);
+  lds_radix_pass<K, RK_PEEL, true, KPT>(kv, 24, sk, wc, gs, wt);
   // One look at every adjacent pair: a 32-bit key that decreases means the
   // passes went wrong (the order is checked, not assumed); equal 32-bit keys
   // of double data start runs to be ordered on the full key.
@@ -673,9 +708,14 @@ __global__ __launch_bounds__(SS_NT) void k_seg_lds(const K* __restrict__ keys,
     __syncthreads();
     load();
     for (int shift = 0; shift < 8 * (int)sizeof(K); shift += 8)
-      lds_radix_pass<K, false, false, KPT>(kv, shift, sk, wc, gs, wt);
+      lds_radix_pass<K, RK_BALLOT, false, KPT>(kv, shift, sk, wc, gs, wt);
   }
-  const SegStat r = segstat_body<K>(sk, L, seg_craw[sb], q1, crew, mode, scratch,
+  // the estimator reads values: turn the order keys back into them in place
+  using V = typename std::conditional<sizeof(K) == 8, double, float>::type;
+  V* sv = reinterpret_cast<V*>(sk);
+  for (int pos = tid; pos < L; pos += SS_NT) sv[pos] = (V)val_of<K>(sk[pos]);
+  __syncthreads();
+  const SegStat r = segstat_body<V>(sv, L, seg_craw[sb], q1, crew, mode, scratch,
                                     scratch + SS_NT, scratch + 2 * SS_NT);
   if (tid == 0) out[sb] = r;
 }
