@@ -280,63 +280,73 @@ __device__ inline double median_sorted(const K* __restrict__ v, int64_t L) {
   return 0.5 * (a + b);
 }
 
-// Estimator over one sorted segment v[0..L) (global or LDS memory), computed
-// by the whole block; the result is valid in thread 0.  Scratch: red, pfa,
-// pfb hold SS_NT doubles each.
+// Order-statistic estimators of a sorted segment v[0..L), L > 0, computed by
+// one thread: median/MAD and the GSSCM cutoffs.  Kept out of line: it is
+// cold next to the univariate MCD.
 template <typename K>
-__device__ __noinline__ SegStat segstat_body(const K* __restrict__ v, int64_t L, double craw, double q1,
-                                double crew, int mode, double* red, double* pfa, double* pfb) {
-  const int tid = threadIdx.x;
+__device__ __noinline__ SegStat segstat_order(const K* __restrict__ v, int64_t L, int mode) {
   SegStat r{};
-  if (L <= 0) return r;
   if (mode == SEGSTAT_MEDMAD) {
-    if (tid == 0) {
-      const double med = median_sorted(v, L);
-      const double a = kth_abs_dev(v, L, med, (L - 1) / 2);
-      const double b = kth_abs_dev(v, L, med, L / 2);
-      r.mu = r.mu_raw = med;
-      const double mad = 1.4826 * 0.5 * (a + b);
-      r.var = r.var_raw = mad * mad;
-      r.n_kept = L;
-    }
+    const double med = median_sorted(v, L);
+    const double a = kth_abs_dev(v, L, med, (L - 1) / 2);
+    const double b = kth_abs_dev(v, L, med, L / 2);
+    r.mu = r.mu_raw = med;
+    const double mad = 1.4826 * 0.5 * (a + b);
+    r.var = r.var_raw = mad * mad;
+    r.n_kept = L;
     return r;
   }
   if (mode == SEGSTAT_GSSCM) {
     // norms r sorted; s = r^(2/3) is sorted as well
-    if (tid == 0) {
-      const double A = median_sorted(v, L);
-      const double sa = pow(val_of<K>(v[(L - 1) / 2]), 2.0 / 3.0);
-      const double sb = pow(val_of<K>(v[L / 2]), 2.0 / 3.0);
-      const double ms = 0.5 * (sa + sb);
-      // median of |s_i - ms| over the two monotone runs of s
-      int64_t lo = 0, hi = L;
-      while (lo < hi) {
-        const int64_t mid = (lo + hi) / 2;
-        if (pow(val_of<K>(v[mid]), 2.0 / 3.0) < ms) lo = mid + 1;
-        else hi = mid;
-      }
-      const int64_t s0 = lo, nl = s0, nr = L - s0;
-      double dev[2];
-      for (int q = 0; q < 2; ++q) {
-        const int64_t k = q == 0 ? (L - 1) / 2 : L / 2;
-        int64_t a_lo = k + 1 > nr ? k + 1 - nr : 0;
-        int64_t a_hi = k + 1 < nl ? k + 1 : nl;
-        while (a_lo < a_hi) {
-          const int64_t i = (a_lo + a_hi) / 2, j = k + 1 - i;
-          const double Ai = (i < nl) ? ms - pow(val_of<K>(v[s0 - 1 - i]), 2.0 / 3.0) : INFINITY;
-          const double Bj1 = (j > 0) ? pow(val_of<K>(v[s0 + j - 1]), 2.0 / 3.0) - ms : -INFINITY;
-          if (Ai < Bj1) a_lo = i + 1;
-          else a_hi = i;
-        }
-        const int64_t i = a_lo, j = k + 1 - i;
-        const double Ai1 = (i > 0) ? ms - pow(val_of<K>(v[s0 - i]), 2.0 / 3.0) : -INFINITY;
-        const double Bj1 = (j > 0) ? pow(val_of<K>(v[s0 + j - 1]), 2.0 / 3.0) - ms : -INFINITY;
-        dev[q] = Ai1 > Bj1 ? Ai1 : Bj1;
-      }
-      const double mad = 0.5 * (dev[0] + dev[1]);
-      r.mu = A;
-      r.var = pow(ms + mad, 1.5);
+    const double A = median_sorted(v, L);
+    const double sa = pow(val_of<K>(v[(L - 1) / 2]), 2.0 / 3.0);
+    const double sb = pow(val_of<K>(v[L / 2]), 2.0 / 3.0);
+    const double ms = 0.5 * (sa + sb);
+    // median of |s_i - ms| over the two monotone runs of s
+    int64_t lo = 0, hi = L;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) / 2;
+      if (pow(val_of<K>(v[mid]), 2.0 / 3.0) < ms) lo = mid + 1;
+      else hi = mid;
     }
+    const int64_t s0 = lo, nl = s0, nr = L - s0;
+    double dev[2];
+    for (int q = 0; q < 2; ++q) {
+      const int64_t k = q == 0 ? (L - 1) / 2 : L / 2;
+      int64_t a_lo = k + 1 > nr ? k + 1 - nr : 0;
+      int64_t a_hi = k + 1 < nl ? k + 1 : nl;
+      while (a_lo < a_hi) {
+        const int64_t i = (a_lo + a_hi) / 2, j = k + 1 - i;
+        const double Ai = (i < nl) ? ms - pow(val_of<K>(v[s0 - 1 - i]), 2.0 / 3.0) : INFINITY;
+        const double Bj1 = (j > 0) ? pow(val_of<K>(v[s0 + j - 1]), 2.0 / 3.0) - ms : -INFINITY;
+        if (Ai < Bj1) a_lo = i + 1;
+        else a_hi = i;
+      }
+      const int64_t i = a_lo, j = k + 1 - i;
+      const double Ai1 = (i > 0) ? ms - pow(val_of<K>(v[s0 - i]), 2.0 / 3.0) : -INFINITY;
+      const double Bj1 = (j > 0) ? pow(val_of<K>(v[s0 + j - 1]), 2.0 / 3.0) - ms : -INFINITY;
+      dev[q] = Ai1 > Bj1 ? Ai1 : Bj1;
+    }
+    const double mad = 0.5 * (dev[0] + dev[1]);
+    r.mu = A;
+    r.var = pow(ms + mad, 1.5);
+    return r;
+  }
+  return r;
+}
+
+// Estimator over one sorted segment v[0..L) (global or LDS memory), computed
+// by the whole block; the result is valid in thread 0.  Scratch: red, pfa,
+// pfb hold SS_NT doubles each.
+template <typename K>
+__device__ __forceinline__ SegStat segstat_body(const K* __restrict__ v, int64_t L, double craw,
+                                                double q1, double crew, int mode, double* red,
+                                                double* pfa, double* pfb) {
+  const int tid = threadIdx.x;
+  SegStat r{};
+  if (L <= 0) return r;
+  if (mode != SEGSTAT_UNIMCD) {
+    if (tid == 0) r = segstat_order<K>(v, L, mode);
     return r;
   }
   // ---- univariate reweighted MCD (Sec. 3.1)
