@@ -190,33 +190,10 @@ __device__ inline double val_of<double>(double k) {
 
 constexpr int SS_WV = SS_NT / 64;
 
-// Sums over the block of NV doubles per thread, in a fixed order (xor tree
-// within each wave, then the waves in index order); every thread receives
-// the sums.  red: NV * SS_WV doubles.
-template <int NV>
-__device__ inline void block_sums(double (&v)[NV], double* __restrict__ red) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double x = v[k];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    if (lane == 0) red[k * SS_WV + w] = x;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double t = 0.0;
-#pragma unroll
-    for (int q = 0; q < SS_WV; ++q) t += red[k * SS_WV + q];
-    v[k] = t;
-  }
-  __syncthreads();
-}
-
 // Exclusive prefix sums in thread order of NV doubles per thread (wave scans,
-// then the totals of earlier waves).  red: NV * SS_WV doubles.
-template <int NV>
+// then the totals of earlier waves).  red: NV * SS_WV doubles.  TRAIL: end
+// with a barrier, so that red may be written again at once.
+template <int NV, bool TRAIL = true>
 __device__ inline void block_excl_prefix(double (&v)[NV], double* __restrict__ red) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double ex[NV];
@@ -239,7 +216,7 @@ __device__ inline void block_excl_prefix(double (&v)[NV], double* __restrict__ r
     for (int q = 0; q < w; ++q) off += red[k * SS_WV + q];
     v[k] = off + ex[k];
   }
-  __syncthreads();
+  if (TRAIL) __syncthreads();
 }
 
 // k-th smallest (0-based) of |v_i - c| for a sorted segment v, by bisection on
@@ -350,7 +327,11 @@ __device__ __forceinline__ SegStat segstat_body(const K* __restrict__ v, int64_t
     return r;
   }
   // ---- univariate reweighted MCD (Sec. 3.1)
+  // red is split so that no region is written again after its barrier:
+  // [0, 2 SS_WV) prefix totals, [64, 128) best windows, [128, 176) sums.
+  const int lane = tid & 63, w = tid >> 6;
   const int64_t hh = L / 2 + 1;
+  const double hd = (double)hh;
   const double c = val_of<K>(v[L / 2]);
   const int64_t a0 = (L * tid) / SS_NT, a1 = (L * (tid + 1)) / SS_NT;
   double pa[2] = {0.0, 0.0};
@@ -359,7 +340,7 @@ __device__ __forceinline__ SegStat segstat_body(const K* __restrict__ v, int64_t
     pa[0] += d;
     pa[1] = fma(d, d, pa[1]);
   }
-  block_excl_prefix<2>(pa, red);
+  block_excl_prefix<2, false>(pa, red);
   const double P1a = pa[0], P2a = pa[1];
   // prefix at a0 + hh: the owner thread's prefix plus part of its range
   double P1b = 0.0, P2b = 0.0;
@@ -370,7 +351,8 @@ __device__ __forceinline__ SegStat segstat_body(const K* __restrict__ v, int64_t
   __syncthreads();
   if (j0 < j1) {
     const int64_t pos = j0 + hh;             // <= L
-    int ow = (int)((pos * SS_NT) / L);
+    // owner of pos: the estimate is off by at most one either way
+    int ow = (int)((double)pos * ((double)SS_NT / (double)L));
     if (ow > SS_NT - 1) ow = SS_NT - 1;
     while (ow > 0 && (L * ow) / SS_NT > pos) --ow;
     while (ow < SS_NT - 1 && (L * (ow + 1)) / SS_NT <= pos) ++ow;
@@ -387,7 +369,6 @@ __device__ __forceinline__ SegStat segstat_body(const K* __restrict__ v, int64_t
   // the loop); the variance itself is formed from the best window's sums
   double best = INFINITY, b1 = 0.0, b2 = 0.0;
   int64_t bj = -1;
-  const double hd = (double)hh;
   {
     double q1l = P1a, q2l = P2a, q1h = P1b, q2h = P2b;
     for (int64_t j = j0; j < j1; ++j) {
@@ -404,69 +385,76 @@ __device__ __forceinline__ SegStat segstat_body(const K* __restrict__ v, int64_t
       }
     }
   }
-  double bv = bj >= 0 ? (b2 - b1 * b1 / hd) / (hd - 1.0) : INFINITY;
-  // smallest window criterion, ties to the lowest start (an exact min, so
-  // every lane of the xor tree agrees); the variance travels with it
+  // smallest criterion, ties to the lowest start (an exact min, so every
+  // lane of the xor tree agrees); the lane that owns the winning window
+  // publishes its variance and window sum
+  double* __restrict__ rb = red + 64;
   {
-    const int lane = tid & 63, w = tid >> 6;
+    const int64_t own = bj;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       const double c2 = __shfl_xor(best, o, 64);
-      const double v2 = __shfl_xor(bv, o, 64);
       const int64_t j2 = __shfl_xor(bj, o, 64);
       if (j2 >= 0 && (bj < 0 || c2 < best || (c2 == best && j2 < bj))) {
         best = c2;
-        bv = v2;
         bj = j2;
       }
     }
+    if (own >= 0 && own == bj) {
+      rb[SS_WV + w] = (b2 - b1 * b1 / hd) / (hd - 1.0);
+      rb[2 * SS_WV + w] = b1;
+    }
     if (lane == 0) {
-      red[w] = best;
-      red[SS_WV + w] = bv;
-      reinterpret_cast<int64_t*>(red)[2 * SS_WV + w] = bj;
+      rb[w] = best;
+      reinterpret_cast<int64_t*>(rb)[3 * SS_WV + w] = bj;
     }
   }
   __syncthreads();
-  double cmin = INFINITY, wmin = INFINITY;
+  double cmin = INFINITY, wmin = INFINITY, s1w = 0.0;
   int64_t js = -1;
   for (int q = 0; q < SS_WV; ++q) {
-    const double c2 = red[q];
-    const int64_t j2 = reinterpret_cast<const int64_t*>(red)[2 * SS_WV + q];
+    const double c2 = rb[q];
+    const int64_t j2 = reinterpret_cast<const int64_t*>(rb)[3 * SS_WV + q];
     if (j2 >= 0 && (js < 0 || c2 < cmin)) {   // waves hold increasing starts
       cmin = c2;
-      wmin = red[SS_WV + q];
+      wmin = rb[SS_WV + q];
+      s1w = rb[2 * SS_WV + q];
       js = j2;
     }
   }
-  __syncthreads();
-  // window sum at the optimum, recomputed directly in thread order
-  double w1 = 0.0;
-  {
-    const int64_t b0 = js + (hh * tid) / SS_NT, b1 = js + (hh * (tid + 1)) / SS_NT;
-    for (int64_t k = b0; k < b1; ++k) w1 += val_of<K>(v[k]) - c;
-  }
-  double sw[1] = {w1};
-  block_sums<1>(sw, red);
-  const double S1w = sw[0];
-  const double mu_raw = c + S1w / (double)hh;
+  const double mu_raw = c + s1w / hd;
   const double var_raw = wmin * craw;
   // reweighting: keep (v - mu_raw)^2 <= q1 var_raw
   const double lim = q1 * var_raw;
-  double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+  double cs[3] = {0.0, 0.0, 0.0};
   for (int64_t k = a0; k < a1; ++k) {
     const double x = val_of<K>(v[k]);
     const double e = x - mu_raw;
     if (e * e <= lim) {
       const double d = x - c;
-      c0 += 1.0;
-      c1 += d;
-      c2 = fma(d, d, c2);
+      cs[0] += 1.0;
+      cs[1] += d;
+      cs[2] = fma(d, d, cs[2]);
     }
   }
-  double cs[3] = {c0, c1, c2};
-  block_sums<3>(cs, red);
-  const double N = cs[0], S1 = cs[1], S2 = cs[2];
+  // sums over the block (xor tree in each wave, then the waves in order),
+  // needed by thread 0 only
+  double* __restrict__ rs = red + 128;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double x = cs[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) rs[k * SS_WV + w] = x;
+  }
+  __syncthreads();
   if (tid == 0) {
+    double N = 0.0, S1 = 0.0, S2 = 0.0;
+    for (int q = 0; q < SS_WV; ++q) {
+      N += rs[q];
+      S1 += rs[SS_WV + q];
+      S2 += rs[2 * SS_WV + q];
+    }
     r.mu_raw = mu_raw;
     r.var_raw = var_raw;
     r.start = js;
