@@ -111,7 +111,11 @@ typedef struct rtdetmcd_ctx* rtdetmcd_handle;
 
 /* Create a handle on `device` that enqueues on `hip_stream` (a hipStream_t;
  * NULL = the null stream).  The handle owns a device workspace that grows on
- * demand and is freed by rtdetmcd_destroy. */
+ * demand and is freed by rtdetmcd_destroy.  Sorts of columns longer than one
+ * LDS segment rank equal radix digits with LDS atomics and check the order
+ * of the result; a fit that finds a segment out of order is run again with
+ * ballot ranking.  RTDETMCD_SAFE_SORT=1 in the environment at creation makes
+ * the handle rank with ballots from the start. */
 rtdetmcd_status rtdetmcd_create(rtdetmcd_handle* out, int32_t device, void* hip_stream);
 rtdetmcd_status rtdetmcd_destroy(rtdetmcd_handle h);
 rtdetmcd_status rtdetmcd_set_stream(rtdetmcd_handle h, void* hip_stream);

@@ -2,6 +2,7 @@
 // and the C-step loop driver.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "driver.h"
@@ -347,6 +348,8 @@ rtdetmcd_status rtdetmcd_create(rtdetmcd_handle* out, int32_t device, void* hip_
   rtdetmcd_ctx* c = new rtdetmcd_ctx();
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  const char* safe = std::getenv("RTDETMCD_SAFE_SORT");
+  c->sort_safe = (safe && safe[0] == '1') ? 1 : 0;
   if (hipSetDevice(device) != hipSuccess ||
       hipEventCreateWithFlags(&c->pin_ev, hipEventDisableTiming) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c->flag), 256, hipHostMallocDefault) != hipSuccess) {

@@ -260,6 +260,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   const size_t o_std_seg0 = L.add((size_t)ND * 4), o_in64 = L.add((size_t)ND * 4);
   const size_t o_nkb = L.add((size_t)NB * 8), o_rkb = L.add((size_t)NC * 8);
   const size_t o_rseg0 = L.add((size_t)NC * 4);
+  const size_t o_sflag = L.add(8);
   SortDev D32, D64, DN, DR;
   layout_sort(L, S32, D32);
   layout_sort(L, S64, D64);
@@ -332,6 +333,11 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   bind_sort(base, SN, DN, keys, tmp, counts, offs);
   bind_sort(base, SR, DR, keys, tmp, counts, offs);
   D32.plan.mb = D64.plan.mb = DN.plan.mb = DR.plan.mb = &mbs;
+  int32_t* sflag = reinterpret_cast<int32_t*>(base + o_sflag);
+  for (SortDev* sd : {&D32, &D64, &DN, &DR}) {
+    sd->plan.safe = ctx->sort_safe;
+    sd->plan.flag = sflag;
+  }
 
   ItemDev CD, BD, GD;
   bind_items(base, C, offC, CD);
@@ -389,6 +395,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   const int smode = o.standardize == RTDETMCD_STD_MEDMAD ? SEGSTAT_MEDMAD : SEGSTAT_UNIMCD;
 
   // ---------------------------------------------------------------- step 0: standardisation
+  RTD_HIP(launch_fill_i32(sflag, 0, 1, st));
   for (int k = 0; k < ND; ++k) {
     const SortHost& Hs = D[k].dtype == 0 ? S32 : S64;
     SortDev& Ds = D[k].dtype == 0 ? D32 : D64;
@@ -505,7 +512,16 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   RTD_HIP(launch_outputs(dds, GD.A, F, douts, 0, ND, st));
   // ---------------------------------------------------------------- status
   RTD_HIP(hipMemcpyAsync(dinfo.data(), dds, ND * sizeof(DsInfo), hipMemcpyDeviceToHost, st));
+  RTD_HIP(hipMemcpyAsync(ctx->flag, sflag, 4, hipMemcpyDeviceToHost, st));
   RTD_HIP(hipStreamSynchronize(st));
+  if (*ctx->flag && !ctx->sort_safe) {
+    // a sort whose atomic ranks came out of lane order: fit again with
+    // ballot ranking throughout
+    ctx->sort_safe = 1;
+    const rtdetmcd_status again = fit_many(ctx, nd, sets, o, status);
+    ctx->sort_safe = 0;
+    return again;
+  }
   rtdetmcd_status ret = RTDETMCD_OK;
   for (int k = 0; k < ND; ++k) {
     const int orig = (int)(D[k].in - sets);

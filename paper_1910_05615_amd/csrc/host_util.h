@@ -89,6 +89,7 @@ struct rtdetmcd_ctx {
   hipEvent_t pin_ev = nullptr; // last upload out of the staging buffer
   bool pin_pending = false;
   int32_t* flag = nullptr;     // pinned readback word
+  int sort_safe = 0;           // 1: global sorts rank with ballots (no order check)
   hipStream_t gstream = nullptr;          // capture / replay stream (created on first use)
   hipEvent_t gev[2] = {nullptr, nullptr}; // ordering with `stream`
   std::vector<rtd_graph> graphs;          // captured C-step rounds, most recent last

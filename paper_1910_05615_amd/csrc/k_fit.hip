@@ -22,16 +22,39 @@ __device__ inline double ldx(const T* __restrict__ p, int64_t i) { return (doubl
 
 // ------------------------------------------------------------ standardisation
 
+// Column-major order keys of the columns of X: a tile of CK_ROWS rows is read
+// row by row (contiguous when ld == p), turned into keys in LDS and written
+// column by column, so that both sides are coalesced.
+constexpr int CK_ROWS = 128;
+constexpr int CK_NT = 256;
+
 template <typename T, typename K>
-__global__ void k_colkeys(const T* __restrict__ X, int64_t n, int64_t ld, int p,
-                          K* __restrict__ keys) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const T* xr = X + i * ld;
-    for (int j = 0; j < p; ++j) {
-      if constexpr (sizeof(K) == 4) keys[(size_t)j * n + i] = fkey32((float)xr[j]);
-      else keys[(size_t)j * n + i] = fkey64((double)xr[j]);
+__global__ __launch_bounds__(CK_NT) void k_colkeys(const T* __restrict__ X, int64_t n, int64_t ld,
+                                                   int p, K* __restrict__ keys) {
+  __shared__ K tile[CK_ROWS * (PMAX + 1)];   // row-major, row stride p + 1
+  const int64_t r0 = (int64_t)blockIdx.x * CK_ROWS;
+  const int nr = (int)min((int64_t)CK_ROWS, n - r0);
+  const int pp = p + 1, tid = threadIdx.x;
+  {
+    int i = tid / p, j = tid - (tid / p) * p;
+    const int di = CK_NT / p, dj = CK_NT - (CK_NT / p) * p;
+    const T* __restrict__ xb = X + r0 * ld;
+    for (int e = tid; e < nr * p; e += CK_NT) {
+      const T x = xb[(int64_t)i * ld + j];
+      if constexpr (sizeof(K) == 4) tile[i * pp + j] = fkey32((float)x);
+      else tile[i * pp + j] = fkey64((double)x);
+      i += di;
+      j += dj;
+      if (j >= p) {
+        j -= p;
+        ++i;
+      }
     }
+  }
+  __syncthreads();
+  for (int e = tid; e < p * CK_ROWS; e += CK_NT) {
+    const int j = e / CK_ROWS, i = e % CK_ROWS;
+    if (i < nr) keys[(size_t)j * n + r0 + i] = tile[i * pp + j];
   }
 }
 
@@ -827,14 +850,14 @@ hipError_t project_t(const ItemDesc* items, const Tile* tiles, int ntiles, int t
 
 hipError_t launch_colkeys(int dtype, const void* X, int64_t n, int64_t ld, int p, void* keys,
                           hipStream_t s) {
-  int64_t nb = (n + 255) / 256;
-  if (nb > 8192) nb = 8192;
-  if (nb < 1) return hipSuccess;
+  const int64_t nb = (n + CK_ROWS - 1) / CK_ROWS;
+  if (nb < 1 || p < 1) return hipSuccess;
+  if (nb > 0x7fffffff || p > PMAX) return hipErrorInvalidValue;
   if (dtype == 0)
-    hipLaunchKernelGGL((k_colkeys<float, uint32_t>), dim3((unsigned)nb), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_colkeys<float, uint32_t>), dim3((unsigned)nb), dim3(CK_NT), 0, s,
                        static_cast<const float*>(X), n, ld, p, static_cast<uint32_t*>(keys));
   else
-    hipLaunchKernelGGL((k_colkeys<double, uint64_t>), dim3((unsigned)nb), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_colkeys<double, uint64_t>), dim3((unsigned)nb), dim3(CK_NT), 0, s,
                        static_cast<const double*>(X), n, ld, p, static_cast<uint64_t*>(keys));
   return hipGetLastError();
 }

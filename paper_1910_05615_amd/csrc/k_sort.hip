@@ -101,9 +101,12 @@ __global__ __launch_bounds__(SCAN_NT) void k_rs_scan(const int32_t* __restrict__
 }
 
 // Stable scatter of one tile.  Wave w owns keys [w*1024, (w+1)*1024) of the
-// tile, visited 64 at a time in index order; equal digits are ranked with
-// eight ballots, so the tile order is preserved.
-template <typename K>
+// tile, visited 64 at a time in index order.  Equal digits are ranked within
+// a wave by LDS atomics on per-(wave, digit) counters (their results follow
+// lane order on this hardware) or, with SAFE, by eight ballots (stable by
+// construction).  The tile is then ordered by digit in LDS, so that the
+// global writes of each digit run are contiguous.
+template <typename K, bool SAFE>
 __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K* __restrict__ kin,
                                                       K* __restrict__ kout,
                                                       const SegTile* __restrict__ tiles,
@@ -112,38 +115,47 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K* __restrict__ kin,
                                                       int shift,
                                                       const int32_t* __restrict__ offs) {
   __shared__ int wc[RS_WAVES][256];
+  __shared__ int td[256];            // tile-local start of each digit
+  __shared__ int go[256];            // global position of a tile slot: go[d] + slot
+  __shared__ int wtot[RS_WAVES];
+  __shared__ K sl[RS_TILE];
   const SegTile t = tiles[blockIdx.x];
   const int64_t so = seg_off[t.seg];
   const int64_t base = so + (int64_t)t.tile * RS_TILE;
   const int64_t end = so + seg_len[t.seg];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int d = threadIdx.x; d < RS_WAVES * 256; d += RS_NT) (&wc[0][0])[d] = 0;
+  const int nvalid = (int)min((int64_t)RS_TILE, end - base);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int d = tid; d < RS_WAVES * 256; d += RS_NT) (&wc[0][0])[d] = 0;
   __syncthreads();
   K kv[RS_ITEMS];
   int dg[RS_ITEMS], rk[RS_ITEMS];
   const uint64_t below = (1ull << lane) - 1ull;
 #pragma unroll
   for (int i = 0; i < RS_ITEMS; ++i) {
-    const int64_t k = base + (int64_t)w * (RS_ITEMS * 64) + i * 64 + lane;
-    const bool valid = k < end;
-    kv[i] = valid ? kin[k] : (K)0;
+    const int q = w * (RS_ITEMS * 64) + i * 64 + lane;
+    const bool valid = q < nvalid;
+    kv[i] = valid ? kin[base + q] : (K)0;
     const int d = digit_of(kv[i], shift);
     dg[i] = d;
-    uint64_t match = __ballot(valid);
+    if constexpr (SAFE) {
+      uint64_t match = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const uint64_t bb = __ballot((d >> b) & 1);
-      match &= ((d >> b) & 1) ? bb : ~bb;
+      for (int b = 0; b < 8; ++b) {
+        const uint64_t bb = __ballot((d >> b) & 1);
+        match &= ((d >> b) & 1) ? bb : ~bb;
+      }
+      const int before = __popcll(match & below);
+      const int cur = wc[w][d];
+      rk[i] = cur + before;
+      if (valid && before == 0) wc[w][d] = cur + __popcll(match);
+    } else {
+      rk[i] = valid ? atomicAdd(&wc[w][d], 1) : 0;
     }
-    const int before = __popcll(match & below);
-    const int cur = wc[w][d];
-    rk[i] = cur + before;
-    if (valid && before == 0) wc[w][d] = cur + __popcll(match);
   }
   __syncthreads();
-  // exclusive scan over waves, per digit
+  // per digit d = tid: exclusive scan over waves, then over digits
   {
-    const int d = threadIdx.x;
+    const int d = tid;
     int acc = 0;
 #pragma unroll
     for (int k = 0; k < RS_WAVES; ++k) {
@@ -151,14 +163,54 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K* __restrict__ kin,
       wc[k][d] = acc;
       acc += v;
     }
+    int x = acc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wtot[w] = x;
+    __syncthreads();
+    int ex = x - acc;
+    for (int k = 0; k < w; ++k) ex += wtot[k];
+    td[d] = ex;
+    go[d] = offs[(size_t)blockIdx.x * 256 + d] - ex;
   }
   __syncthreads();
-  const int32_t* __restrict__ o = offs + (size_t)blockIdx.x * 256;
 #pragma unroll
   for (int i = 0; i < RS_ITEMS; ++i) {
-    const int64_t k = base + (int64_t)w * (RS_ITEMS * 64) + i * 64 + lane;
-    if (k < end) kout[so + o[dg[i]] + wc[w][dg[i]] + rk[i]] = kv[i];
+    const int q = w * (RS_ITEMS * 64) + i * 64 + lane;
+    if (q < nvalid) sl[td[dg[i]] + wc[w][dg[i]] + rk[i]] = kv[i];
   }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < RS_ITEMS; ++i) {
+    const int q = i * RS_NT + tid;
+    if (q < nvalid) {
+      const K k = sl[q];
+      kout[so + go[digit_of(k, shift)] + q] = k;
+    }
+  }
+}
+
+// Order check of sorted segments: any adjacent pair out of order sets *flag.
+template <typename K>
+__global__ __launch_bounds__(RS_NT) void k_rs_check(const K* __restrict__ keys,
+                                                    const SegTile* __restrict__ tiles,
+                                                    const int64_t* __restrict__ seg_off,
+                                                    const int64_t* __restrict__ seg_len,
+                                                    int32_t* __restrict__ flag) {
+  const SegTile t = tiles[blockIdx.x];
+  const int64_t so = seg_off[t.seg];
+  const int64_t base = so + (int64_t)t.tile * RS_TILE;
+  const int64_t end = so + seg_len[t.seg];
+  bool bad = false;
+#pragma unroll 4
+  for (int i = 0; i < RS_ITEMS; ++i) {
+    const int64_t k = base + i * RS_NT + threadIdx.x;
+    if (k + 1 < end) bad = bad || keys[k] > keys[k + 1];
+  }
+  if (bad) *flag = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -1040,13 +1092,21 @@ hipError_t sort_segments_t(SortPlan& P, hipStream_t s) {
                        P.seg_off, P.seg_len, shift, P.counts);
     hipLaunchKernelGGL(k_rs_scan, dim3(P.nseg), dim3(SCAN_NT), 0, s, P.counts, P.seg_tile0,
                        P.tile_first, P.offs);
-    hipLaunchKernelGGL((k_rs_scatter<K>), dim3(P.ntiles), dim3(RS_NT), 0, s, a, b, P.tiles,
-                       P.seg_off, P.seg_len, shift, P.offs);
+    if (P.safe)
+      hipLaunchKernelGGL((k_rs_scatter<K, true>), dim3(P.ntiles), dim3(RS_NT), 0, s, a, b,
+                         P.tiles, P.seg_off, P.seg_len, shift, P.offs);
+    else
+      hipLaunchKernelGGL((k_rs_scatter<K, false>), dim3(P.ntiles), dim3(RS_NT), 0, s, a, b,
+                         P.tiles, P.seg_off, P.seg_len, shift, P.offs);
     K* t = a;
     a = b;
     b = t;
   }
-  // an even number of passes leaves the result in P.keys
+  // an even number of passes leaves the result in P.keys; the atomic ranks
+  // are checked through the order of the result
+  if (!P.safe)
+    hipLaunchKernelGGL((k_rs_check<K>), dim3(P.ntiles), dim3(RS_NT), 0, s, a, P.tiles, P.seg_off,
+                       P.seg_len, P.flag);
   return hipGetLastError();
 }
 

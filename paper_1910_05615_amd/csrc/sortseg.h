@@ -35,6 +35,8 @@ struct SortPlan {
   int32_t* counts = nullptr;    // [ntiles * 256]
   int32_t* offs = nullptr;      // [ntiles * 256]
   int tile_first = 0;           // absolute index of tiles[0] (seg_tile0 holds absolute indices)
+  int safe = 0;                 // 1: rank equal digits with ballots, not LDS atomics
+  int32_t* flag = nullptr;      // set to 1 when a sorted segment is found out of order
   int seg_first = 0;            // absolute index of the first segment of the plan
   // The plan restricted to segments [a, b): pointers offset, tile counts
   // given by the host copy of the absolute seg_tile0 table.
