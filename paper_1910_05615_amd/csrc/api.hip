@@ -174,7 +174,7 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
     int64_t max_m = 0;
     for (int i = first; i < first + n; ++i) max_m = std::max(max_m, S.items[i].m);
     const int max_nt = S.max_ntiles(first, first + n);
-    RTD_HIP(launch_finalize(D.items, D.A, first, n, 1, maxs, o.kappa_max, SSCP_TILE, st));
+    RTD_HIP(launch_finalize(bucket, D.items, D.A, first, n, 1, maxs, o.kappa_max, st));
     const int R = std::max(1, o.rounds_per_sync);
     // one C-step of every active item
     auto step = [&](hipStream_t s) -> rtdetmcd_status {
@@ -185,7 +185,7 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
       RTD_HIP(launch_sscp(bucket, dtype, SSCP_CSTEP, D.items, D.A, D.stiles + st0, stn,
                           SSCP_TILE, nullptr, nullptr, s));
       RTD_HIP(launch_collapse(D.items, D.A, first, n, max_nt, 1, SSCP_TILE, s));
-      RTD_HIP(launch_finalize(D.items, D.A, first, n, 0, maxs, o.kappa_max, SSCP_TILE, s));
+      RTD_HIP(launch_finalize(bucket, D.items, D.A, first, n, 0, maxs, o.kappa_max, s));
       return RTDETMCD_OK;
     };
     int t = 1;
@@ -225,7 +225,7 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
   // plain: one item at a time, host-driven, one host check per step
   for (int i = first; i < first + n; ++i) {
     const ItemDesc& d = S.items[i];
-    RTD_HIP(launch_finalize(D.items, D.A, i, 1, 1, maxs, o.kappa_max, SSCP_TILE, st));
+    RTD_HIP(launch_finalize(bucket, D.items, D.A, i, 1, 1, maxs, o.kappa_max, st));
     RTD_HIP(hipMemcpyAsync(pin_flag, D.A.status + i, 4, hipMemcpyDeviceToHost, st));
     RTD_HIP(hipStreamSynchronize(st));
     if (*pin_flag != ACTIVE) continue;
@@ -236,7 +236,7 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
       RTD_HIP(launch_sscp(bucket, dtype, SSCP_CSTEP, D.items, D.A, D.stiles + d.tile0,
                           d.ntiles, SSCP_TILE, nullptr, nullptr, st));
       RTD_HIP(launch_collapse(D.items, D.A, i, 1, d.ntiles, 1, SSCP_TILE, st));
-      RTD_HIP(launch_finalize(D.items, D.A, i, 1, 0, maxs, o.kappa_max, SSCP_TILE, st));
+      RTD_HIP(launch_finalize(bucket, D.items, D.A, i, 1, 0, maxs, o.kappa_max, st));
       RTD_HIP(hipMemcpyAsync(pin_flag, D.A.status + i, 4, hipMemcpyDeviceToHost, st));
       RTD_HIP(hipStreamSynchronize(st));
       if (*pin_flag != ACTIVE) break;

@@ -108,8 +108,9 @@ hipError_t launch_sscp(int bucket, int dtype, int mode, const ItemDesc* items, I
 // items skipped).  max_ntiles: largest ntiles among the items.
 hipError_t launch_collapse(const ItemDesc* items, ItemArrays A, int first, int nitems,
                            int max_ntiles, int cstep, int tile_rows, hipStream_t s);
-hipError_t launch_finalize(const ItemDesc* items, ItemArrays A, int first_item, int nitems,
-                           int from_start, int max_csteps, double kappa_max, int tile_rows,
+// bucket: a p bucket (bucket_of) no smaller than any item's p.
+hipError_t launch_finalize(int bucket, const ItemDesc* items, ItemArrays A, int first_item,
+                           int nitems, int from_start, int max_csteps, double kappa_max,
                            hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);

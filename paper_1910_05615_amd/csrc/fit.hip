@@ -486,7 +486,8 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   RTD_HIP(launch_kl(dds, CD.A, F, 0, NB, st));
   RTD_HIP(launch_fill_i32(GD.A.status, ACTIVE, NG, st));
   RTD_HIP(launch_pool(dds, GD.A, F, 0, ND, o.pool_mode, st));
-  RTD_HIP(launch_finalize(GD.items, GD.A, 0, ND, 1, 1, 1e300, SSCP_TILE, st));
+  for (const Group& g : groups)
+    RTD_HIP(launch_finalize(g.bucket, GD.items, GD.A, g.ds0, g.ds1 - g.ds0, 1, 1, 1e300, st));
   // ---------------------------------------------------------------- steps 8-9: reweighting
   for (const Group& g : groups) {
     const int a = g.ds0, b = g.ds1;
@@ -500,7 +501,9 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   }
   RTD_HIP(launch_rew(dds, GD.items, GD.A, F, 0, ND, st));
   RTD_HIP(launch_fill_i32(GD.A.status + ND, ACTIVE, ND, st));
-  RTD_HIP(launch_finalize(GD.items, GD.A, ND, ND, 1, 1, 1e300, SSCP_TILE, st));
+  for (const Group& g : groups)
+    RTD_HIP(launch_finalize(g.bucket, GD.items, GD.A, ND + g.ds0, g.ds1 - g.ds0, 1, 1, 1e300,
+                            st));
   // ---------------------------------------------------------------- step 10: distances, flags
   for (const Group& g : groups) {
     const int a = ND + g.ds0, b = ND + g.ds1;

@@ -335,137 +335,136 @@ __global__ __launch_bounds__(SEL_NT) void k_select_reg(const ItemDesc* __restric
 //     factor, log det, inverse factor and exact 1-norm condition number;
 //   * M = L^{-1} D^{-1} packed for the distance kernel.
 // from_start: (muz, sigz) already hold the start; nothing is reduced.
+//
+// One wave per item, P >= p a compile-time bound: lane i holds row i of
+// Sigma, then of L, in registers (rows and columns p..P-1 are the identity,
+// so the factor and its inverse carry an identity block that is never
+// written); the inverse is formed one column per lane.  Every loop is
+// unrolled over P and entries of other lanes are read with readlane, so no
+// step waits on shared memory.  The operations and their order are those of
+// a right-looking Cholesky and of column-wise forward substitution.
 // ---------------------------------------------------------------------------
-constexpr int FIN_NT = 256;
+__device__ inline double lane_bcast(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
 
-__global__ __launch_bounds__(FIN_NT) void k_finalize(const ItemDesc* __restrict__ items,
-                                                     ItemArrays A, int first_item, int from_start,
-                                                     int max_csteps, double kappa_max,
-                                                     int tile_rows) {
-  __shared__ double Sg[PMAX * PMAX];   // Sigma (standardised), then L in the lower triangle
-  __shared__ double Li[PMAX * PMAX];   // L^{-1}
-  __shared__ double sv[PMAX + 1];
-  __shared__ double cs[2][PMAX];
-  __shared__ int fail;
+template <int P>
+__global__ __launch_bounds__(64) void k_finalize(const ItemDesc* __restrict__ items,
+                                                 ItemArrays A, int first_item, int from_start,
+                                                 int max_csteps, double kappa_max) {
   const int it = first_item + blockIdx.x;
   if (A.status[it] != ACTIVE) return;
   const ItemDesc D = items[it];
-  const int p = D.p;
-  const int tid = threadIdx.x;
+  const int p = D.p;                       // p <= P
+  const int lane = threadIdx.x;            // row i (Sigma, L), column j (L^{-1})
+  const bool in = lane < p;
   const double h = (double)D.h;
   double* __restrict__ mux = A.mux + (size_t)it * PMAX;
   double* __restrict__ lam = A.lamx + (size_t)it * MSTRIDE;
   double* __restrict__ muz = A.muz + (size_t)it * PMAX;
   double* __restrict__ sigz = A.sigz + (size_t)it * MSTRIDE;
-
+  const double sc = in ? D.scale[lane] : 1.0;
+  double a[P];
   if (!from_start) {
     const int full = A.full[it];
     // tile partials already collapsed into the first tile's
     const double* __restrict__ P0 = A.part + (size_t)D.tile0 * PSTRIDE;
-    // count and sum vector
-    for (int e = tid; e <= p; e += FIN_NT) sv[e] = P0[e];
-    __syncthreads();
-    // mean update (sv[1..p] is the pivot-centred sum)
-    for (int j = tid; j < p; j += FIN_NT) cs[0][j] = sv[1 + j] / h;   // mu_new - c
-    __syncthreads();
-    for (int e = tid; e < p * p; e += FIN_NT) {
-      const int i = e / p, j = e % p;
-      const int a = i >= j ? i : j, b = i >= j ? j : i;
-      const double s = P0[1 + PMAX + a * (a + 1) / 2 + b];
-      const double old = full ? 0.0 : lam[i * PMAX + j];
-      const double v = old + s - h * cs[0][i] * cs[0][j];
-      lam[i * PMAX + j] = v;
-      Sg[i * PMAX + j] = v / (D.scale[i] * D.scale[j]) / (h - 1.0);
+    const double dm = in ? P0[1 + lane] / h : 0.0;   // mu_new - c (pivot-centred sum / h)
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const double dmj = lane_bcast(dm, j), scj = lane_bcast(sc, j);
+      if (in && j < p) {
+        const int hi = lane >= j ? lane : j, lo = lane >= j ? j : lane;
+        const double sj = P0[1 + PMAX + hi * (hi + 1) / 2 + lo];
+        const double old = full ? 0.0 : lam[lane * PMAX + j];
+        const double v = old + sj - h * (dm * dmj);
+        lam[lane * PMAX + j] = v;
+        a[j] = v / (sc * scj) / (h - 1.0);
+      } else {
+        a[j] = j == lane ? 1.0 : 0.0;
+      }
     }
-    __syncthreads();
-    for (int j = tid; j < p; j += FIN_NT) {
-      const double mnew = mux[j] + cs[0][j];
-      mux[j] = mnew;
-      muz[j] = (mnew - D.loc[j]) / D.scale[j];
+    if (in) {
+      const double mnew = mux[lane] + dm;
+      mux[lane] = mnew;
+      muz[lane] = (mnew - D.loc[lane]) / sc;
     }
   } else {
-    for (int e = tid; e < p * p; e += FIN_NT) {
-      const int i = e / p, j = e % p;
-      Sg[i * PMAX + j] = 0.5 * (sigz[i * PMAX + j] + sigz[j * PMAX + i]);
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+      a[j] = (in && j < p) ? 0.5 * (sigz[lane * PMAX + j] + sigz[j * PMAX + lane])
+                           : (j == lane ? 1.0 : 0.0);
+    if (in) mux[lane] = D.loc[lane] + sc * muz[lane];
+    __syncthreads();   // every lane has read sigz before any lane writes it
+  }
+  double n1 = 0.0;     // 1-norm of Sigma: largest absolute row sum (symmetric)
+  if (in) {
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+      if (j < p) {
+        sigz[lane * PMAX + j] = a[j];
+        n1 += fabs(a[j]);
+      }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) n1 = fmax(n1, __shfl_xor(n1, o, 64));
+  // Cholesky: column k of L from row k (lane k) and each lane's own row
+  double diag = 1.0;   // L[lane][lane]
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    double sk = a[k];
+#pragma unroll
+    for (int j = 0; j < k; ++j) sk = fma(-a[j], lane_bcast(a[j], k), sk);
+    const double d = lane_bcast(sk, k);
+    if (!(d > 0.0) || !(d < 1e300)) {    // uniform
+      if (lane == 0) A.status[it] = from_start ? ST_DROP_FIRST : ST_SINGULAR;
+      return;
     }
-    for (int j = tid; j < p; j += FIN_NT) mux[j] = D.loc[j] + D.scale[j] * muz[j];
+    const double lkk = sqrt(d);
+    if (lane == k) diag = lkk;
+    a[k] = lane == k ? lkk : (lane > k ? sk / lkk : 0.0);
   }
-  __syncthreads();
-  for (int e = tid; e < p * p; e += FIN_NT) {
-    const int i = e / p, j = e % p;
-    sigz[i * PMAX + j] = Sg[i * PMAX + j];
+  // inverse factor X = L^{-1}: column `lane`, rows in order
+  double x[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    double si = lane == i ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < i; ++k) si = fma(-lane_bcast(a[k], i), x[k], si);
+    x[i] = si / lane_bcast(diag, i);
   }
-  // column 1-norms of Sigma
-  for (int j = tid; j < p; j += FIN_NT) {
-    double s = 0.0;
-    for (int i = 0; i < p; ++i) s += fabs(Sg[i * PMAX + j]);
-    cs[0][j] = s;
-  }
-  if (tid == 0) fail = 0;
-  __syncthreads();
-  // Cholesky (right-looking, in place in the lower triangle)
-  for (int k = 0; k < p; ++k) {
-    if (tid == 0) {
-      const double d = Sg[k * PMAX + k];
-      if (!(d > 0.0) || !(d < 1e300)) fail = 1;
-      else Sg[k * PMAX + k] = sqrt(d);
-    }
-    __syncthreads();
-    if (fail) break;
-    const double lkk = Sg[k * PMAX + k];
-    for (int i = k + 1 + tid; i < p; i += FIN_NT) Sg[i * PMAX + k] /= lkk;
-    __syncthreads();
-    const int n = p - k - 1;
-    for (int e = tid; e < n * n; e += FIN_NT) {
-      const int i = k + 1 + e / n, j = k + 1 + e % n;
-      if (j <= i) Sg[i * PMAX + j] -= Sg[i * PMAX + k] * Sg[j * PMAX + k];
-    }
-    __syncthreads();
-  }
-  if (fail) {
-    if (tid == 0) A.status[it] = from_start ? ST_DROP_FIRST : ST_SINGULAR;
-    return;
-  }
-  // inverse factor, one column per thread
-  for (int j = tid; j < p; j += FIN_NT) {
-    for (int i = 0; i < j; ++i) Li[i * PMAX + j] = 0.0;
-    Li[j * PMAX + j] = 1.0 / Sg[j * PMAX + j];
-    for (int i = j + 1; i < p; ++i) {
-      double s = 0.0;
-      for (int k = j; k < i; ++k) s = fma(Sg[i * PMAX + k], Li[k * PMAX + j], s);
-      Li[i * PMAX + j] = -s / Sg[i * PMAX + i];
-    }
-  }
-  __syncthreads();
-  // column 1-norms of Sigma^{-1} = L^{-T} L^{-1}
-  for (int j = tid; j < p; j += FIN_NT) {
-    double s = 0.0;
-    for (int i = 0; i < p; ++i) {
-      const int k0 = i > j ? i : j;
+  // 1-norm of Sigma^{-1} = X^T X: column `lane`, entries b in order
+  double n2 = 0.0;
+#pragma unroll
+  for (int b = 0; b < P; ++b) {
+    if (b < p) {
       double v = 0.0;
-      for (int k = k0; k < p; ++k) v = fma(Li[k * PMAX + i], Li[k * PMAX + j], v);
-      s += fabs(v);
+#pragma unroll
+      for (int k = b; k < P; ++k) v = fma(x[k], lane_bcast(x[k], b), v);
+      n2 += fabs(v);
     }
-    cs[1][j] = s;
   }
-  __syncthreads();
+  if (!in) n2 = 0.0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) n2 = fmax(n2, __shfl_xor(n2, o, 64));
   double* __restrict__ linv = A.linv + (size_t)it * MSTRIDE;
   double* __restrict__ mt = A.mtri + (size_t)it * MSTRIDE;
-  for (int e = tid; e < p * PMAX; e += FIN_NT) {
-    const int i = e / PMAX, j = e % PMAX;
-    mt[e] = (j <= i) ? Li[i * PMAX + j] / D.scale[j] : 0.0;
-  }
-  for (int e = tid; e < p * p; e += FIN_NT) {
-    const int i = e / p, j = e % p;
-    linv[i * PMAX + j] = Li[i * PMAX + j];
-  }
-  if (tid == 0) {
-    double ld = 0.0, n1 = 0.0, n2 = 0.0;
-    for (int j = 0; j < p; ++j) {
-      ld += log(Sg[j * PMAX + j]);
-      n1 = fmax(n1, cs[0][j]);
-      n2 = fmax(n2, cs[1][j]);
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    if (i < p) {
+      mt[i * PMAX + lane] = lane <= i ? x[i] / sc : 0.0;
+      if (in) linv[i * PMAX + lane] = x[i];
     }
+  }
+  const double lg = log(diag);
+  double ld = 0.0;
+#pragma unroll
+  for (int j = 0; j < P; ++j)
+    if (j < p) ld += lane_bcast(lg, j);
+  if (lane == 0) {
     A.logdet[it] = 2.0 * ld;
     const double kap = n1 * n2;
     int st = ACTIVE;
@@ -547,12 +546,21 @@ hipError_t launch_select(const ItemDesc* items, ItemArrays A, int first_item, in
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const ItemDesc* items, ItemArrays A, int first_item, int nitems,
-                           int from_start, int max_csteps, double kappa_max, int tile_rows,
+hipError_t launch_finalize(int bucket, const ItemDesc* items, ItemArrays A, int first_item,
+                           int nitems, int from_start, int max_csteps, double kappa_max,
                            hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize, dim3(nitems), dim3(FIN_NT), 0, s, items, A, first_item,
-                     from_start, max_csteps, kappa_max, tile_rows);
+#define CASE(PB)                                                                              \
+  case PB:                                                                                    \
+    hipLaunchKernelGGL((k_finalize<PB>), dim3(nitems), dim3(64), 0, s, items, A, first_item, \
+                       from_start, max_csteps, kappa_max);                                    \
+    break;
+  switch (bucket) {
+    CASE(4) CASE(5) CASE(8) CASE(10) CASE(16) CASE(20) CASE(24) CASE(32) CASE(40) CASE(48)
+    CASE(64)
+    default: return hipErrorInvalidValue;
+  }
+#undef CASE
   return hipGetLastError();
 }
 
