@@ -444,7 +444,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     const int dt0 = C.dt_first[c0], dtn = C.dt_first[c1 - 1] + C.dt_count[c1 - 1] - dt0;
     const int s0 = rseg0[c0], s1 = rseg0[c1 - 1] + C.items[c1 - 1].p;
     uint64_t* rk = reinterpret_cast<uint64_t*>(DR.plan.keys);
-    RTD_HIP(launch_eig(CD.items, CD.A, F, c0, c1 - c0, o.kappa_max, st));
+    RTD_HIP(launch_eig(g.bucket, CD.items, CD.A, F, c0, c1 - c0, o.kappa_max, st));
     RTD_HIP(launch_project(g.bucket, g.dtype, 0, CD.items, CD.dtiles + dt0, dtn, DIST_TILE,
                            CD.A.status, F.wbuf, drkb, rk, st));
     RTD_TRY(sort_stats(ctx, SR, DR, s0, s1, SEGSTAT_UNIMCD, q1, crew1));

@@ -58,8 +58,8 @@ hipError_t launch_reduce_partials(const ItemDesc* items, const double* part, int
 hipError_t launch_init_cov(int mode, const ItemDesc* bitems, int first, int n, FitArrays F,
                            ItemArrays C, const DsInfo* ds, double* cut, const SegStat* gst,
                            hipStream_t s);
-hipError_t launch_eig(const ItemDesc* items, ItemArrays A, FitArrays F, int first, int n,
-                      double kappa_max, hipStream_t s);
+hipError_t launch_eig(int bucket, const ItemDesc* items, ItemArrays A, FitArrays F, int first,
+                      int n, double kappa_max, hipStream_t s);
 hipError_t launch_refine(int stage, const ItemDesc* items, ItemArrays A, FitArrays F, int first,
                          int n, const SegStat* st, const int32_t* seg0, hipStream_t s);
 hipError_t launch_choose(const ItemDesc* bitems, const ItemDesc* citems, ItemArrays A,

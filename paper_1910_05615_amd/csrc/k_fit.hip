@@ -201,134 +201,166 @@ __global__ void k_init_cov(int mode, const ItemDesc* __restrict__ bitems, int fi
 // Jacobi eigen-decomposition of the initial scatter of each item, one block
 // per matrix; eigenvalues in decreasing order (step 1) and the condition check
 // lambda_1 / lambda_p <= kappa_max (step 2).
-__global__ __launch_bounds__(256) void k_eig(const ItemDesc* __restrict__ items, ItemArrays A,
-                                             FitArrays F, int first, double kappa_max) {
-  // Parallel cyclic Jacobi: each step applies p/2 disjoint rotations chosen by
-  // the round-robin (circle) ordering, as one column pass A J and one row pass
-  // J^T A; p - 1 steps make a sweep over all pairs.
-  __shared__ double a[PMAX * PMAX];
-  __shared__ double v[PMAX * PMAX];
-  __shared__ double cs_c[PMAX / 2], cs_s[PMAX / 2];
-  __shared__ int pi[PMAX / 2], pj[PMAX / 2];
-  __shared__ double red[256];
-  __shared__ int ord[PMAX];
+// Parallel cyclic Jacobi on one wave per item: each step applies p/2
+// disjoint rotations chosen by the round-robin (circle) ordering, as one
+// column pass A J (V too) and one row pass J^T A; p - 1 steps make a sweep
+// over all pairs.  A and V sit in LDS with an odd row stride; with a single
+// wave the barriers between passes cost almost nothing.
+template <int P>
+__global__ __launch_bounds__(64) void k_eig(const ItemDesc* __restrict__ items, ItemArrays A,
+                                            FitArrays F, int first, double kappa_max) {
+  constexpr int LD = P + 1;
+  constexpr int NPM = (P + 1) / 2;
+  __shared__ double a[P * LD];
+  __shared__ double v[P * LD];
+  __shared__ double cs_c[NPM], cs_s[NPM];
+  __shared__ int pi[NPM], pj[NPM];
+  __shared__ int ord[P];
   const int it = first + blockIdx.x;
   if (A.status[it] != ACTIVE) return;
-  const int p = items[it].p;
-  const int tid = threadIdx.x;
+  const int p = items[it].p;          // p <= P
+  const int lane = threadIdx.x;
   const double* S = A.sigz + (size_t)it * MSTRIDE;
-  for (int e = tid; e < p * p; e += 256) {
-    const int i = e / p, j = e % p;
-    a[i * PMAX + j] = 0.5 * (S[i * PMAX + j] + S[j * PMAX + i]);
-    v[i * PMAX + j] = (i == j) ? 1.0 : 0.0;
+  if (lane < p) {
+    for (int j = 0; j < p; ++j) {
+      a[lane * LD + j] = 0.5 * (S[lane * PMAX + j] + S[j * PMAX + lane]);
+      v[lane * LD + j] = (lane == j) ? 1.0 : 0.0;
+    }
   }
   __syncthreads();
   const int np = (p + 1) & ~1;        // players, a dummy one when p is odd
   const int npair = np / 2;
   for (int sweep = 0; sweep < 60 && p > 1; ++sweep) {
     double off = 0.0, dia = 0.0;
-    for (int e = tid; e < p * p; e += 256) {
-      const int i = e / p, j = e % p;
-      const double x = a[i * PMAX + j];
-      if (i != j) off = fma(x, x, off);
-      else dia = fma(x, x, dia);
+    if (lane < p)
+      for (int j = 0; j < p; ++j) {
+        const double x = a[lane * LD + j];
+        if (j != lane) off = fma(x, x, off);
+        else dia = fma(x, x, dia);
+      }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o, 64);
+      dia += __shfl_xor(dia, o, 64);
     }
-    red[tid] = off;
-    __syncthreads();
-    if (tid == 0) {
-      double s = 0.0;
-      for (int k = 0; k < 256; ++k) s += red[k];
-      red[0] = s;
-    }
-    __syncthreads();
-    const double offt = red[0];
-    __syncthreads();
-    red[tid] = dia;
-    __syncthreads();
-    if (tid == 0) {
-      double s = 0.0;
-      for (int k = 0; k < 256; ++k) s += red[k];
-      red[0] = s;
-    }
-    __syncthreads();
-    const double diat = red[0];
-    __syncthreads();
-    if (!(offt > 1e-30 * diat)) break;
+    // converged once the off-diagonal mass is about 1e-14 of the diagonal's
+    // (the rounding floor of the rotations is near 1e-16 per entry, so a much
+    // tighter bound may never be met); uniform: every lane holds the sums
+    if (!(off > 1e-28 * dia)) break;
     for (int r = 0; r < np - 1; ++r) {
-      if (tid < npair) {
+      if (lane < npair) {
         auto pl = [&](int q) { return q == 0 ? 0 : 1 + ((q - 1 + r) % (np - 1)); };
-        int i = pl(tid), j = pl(np - 1 - tid);
+        int i = pl(lane), j = pl(np - 1 - lane);
         if (i > j) { const int t = i; i = j; j = t; }
-        double c = 1.0, s = 0.0;
+        double c = 1.0, sn = 0.0;
         if (j < p) {
-          const double apq = a[i * PMAX + j];
+          const double apq = a[i * LD + j];
           if (apq != 0.0) {
-            const double app = a[i * PMAX + i], aqq = a[j * PMAX + j];
+            const double app = a[i * LD + i], aqq = a[j * LD + j];
             const double tau = (aqq - app) / (2.0 * apq);
             const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
+            sn = t * c;
           }
         }
-        pi[tid] = i;
-        pj[tid] = j < p ? j : i;   // a rotation with the dummy is the identity
-        cs_c[tid] = c;
-        cs_s[tid] = s;
+        pi[lane] = i;
+        pj[lane] = j < p ? j : i;   // a rotation with the dummy is the identity
+        cs_c[lane] = c;
+        cs_s[lane] = sn;
       }
       __syncthreads();
-      // columns: A <- A J, V <- V J
-      for (int e = tid; e < p * npair; e += 256) {
-        const int rr = e / npair, k = e % npair;
-        const int i = pi[k], j = pj[k];
-        if (i == j) continue;
-        const double c = cs_c[k], s = cs_s[k];
-        const double ari = a[rr * PMAX + i], arj = a[rr * PMAX + j];
-        a[rr * PMAX + i] = c * ari - s * arj;
-        a[rr * PMAX + j] = s * ari + c * arj;
-        const double vri = v[rr * PMAX + i], vrj = v[rr * PMAX + j];
-        v[rr * PMAX + i] = c * vri - s * vrj;
-        v[rr * PMAX + j] = s * vri + c * vrj;
+      // A pass updates p x npair independent (row, pair) elements; the 64
+      // lanes take them four at a time (all loads first, then all stores:
+      // the pairs of a step touch disjoint columns, and rows).
+      const int ne = p * npair;
+      const float inv_np = 1.0f / (float)npair;
+      for (int e0 = 0; e0 < ne; e0 += 256) {   // columns: A <- A J, V <- V J
+        int ri[4], ii[4], jj[4];
+        double c[4], sn[4], xi[4], xj[4], yi[4], yj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = min(e0 + 64 * u + lane, ne - 1);
+          const int r = (int)(((float)e + 0.5f) * inv_np), k = e - r * npair;
+          ri[u] = r * LD;
+          ii[u] = pi[k];
+          jj[u] = pj[k];
+          c[u] = cs_c[k];
+          sn[u] = cs_s[k];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          xi[u] = a[ri[u] + ii[u]];
+          xj[u] = a[ri[u] + jj[u]];
+          yi[u] = v[ri[u] + ii[u]];
+          yj[u] = v[ri[u] + jj[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (e0 + 64 * u + lane < ne && ii[u] != jj[u]) {
+            a[ri[u] + ii[u]] = c[u] * xi[u] - sn[u] * xj[u];
+            a[ri[u] + jj[u]] = sn[u] * xi[u] + c[u] * xj[u];
+            v[ri[u] + ii[u]] = c[u] * yi[u] - sn[u] * yj[u];
+            v[ri[u] + jj[u]] = sn[u] * yi[u] + c[u] * yj[u];
+          }
+        }
       }
       __syncthreads();
-      // rows: A <- J^T A
-      for (int e = tid; e < p * npair; e += 256) {
-        const int cc = e / npair, k = e % npair;
-        const int i = pi[k], j = pj[k];
-        if (i == j) continue;
-        const double c = cs_c[k], s = cs_s[k];
-        const double aic = a[i * PMAX + cc], ajc = a[j * PMAX + cc];
-        a[i * PMAX + cc] = c * aic - s * ajc;
-        a[j * PMAX + cc] = s * aic + c * ajc;
+      for (int e0 = 0; e0 < ne; e0 += 256) {   // rows: A <- J^T A
+        int cl[4], ii[4], jj[4];
+        double c[4], sn[4], xi[4], xj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = min(e0 + 64 * u + lane, ne - 1);
+          const int cc = (int)(((float)e + 0.5f) * inv_np), k = e - cc * npair;
+          cl[u] = cc;
+          ii[u] = pi[k] * LD;
+          jj[u] = pj[k] * LD;
+          c[u] = cs_c[k];
+          sn[u] = cs_s[k];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          xi[u] = a[ii[u] + cl[u]];
+          xj[u] = a[jj[u] + cl[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (e0 + 64 * u + lane < ne && ii[u] != jj[u]) {
+            a[ii[u] + cl[u]] = c[u] * xi[u] - sn[u] * xj[u];
+            a[jj[u] + cl[u]] = sn[u] * xi[u] + c[u] * xj[u];
+          }
+        }
       }
       __syncthreads();
-      if (tid < npair && pi[tid] != pj[tid] && cs_s[tid] != 0.0) {
-        a[pi[tid] * PMAX + pj[tid]] = 0.0;
-        a[pj[tid] * PMAX + pi[tid]] = 0.0;
+      if (lane < npair && pi[lane] != pj[lane] && cs_s[lane] != 0.0) {
+        a[pi[lane] * LD + pj[lane]] = 0.0;
+        a[pj[lane] * LD + pi[lane]] = 0.0;
       }
       __syncthreads();
     }
   }
   // order by decreasing eigenvalue (stable in the index)
-  if (tid < p) {
-    const double lk = a[tid * PMAX + tid];
+  if (lane < p) {
+    const double lk = a[lane * LD + lane];
     int r = 0;
     for (int q = 0; q < p; ++q) {
-      const double lq = a[q * PMAX + q];
-      if (lq > lk || (lq == lk && q < tid)) ++r;
+      const double lq = a[q * LD + q];
+      if (lq > lk || (lq == lk && q < lane)) ++r;
     }
-    ord[r] = tid;
+    ord[r] = lane;
   }
   __syncthreads();
   double* V = F.vbuf + (size_t)it * MSTRIDE;
   double* W = F.wbuf + (size_t)it * MSTRIDE;
-  for (int e = tid; e < p * p; e += 256) {
-    const int i = e / p, c = e % p;
-    const double x = v[i * PMAX + ord[c]];
-    V[i * PMAX + c] = x;         // column c = eigenvector of the c-th largest eigenvalue
-    W[c * PMAX + i] = x;         // W = V^T: scores t_c = sum_i V_ic z_i
+  if (lane < p) {
+    for (int c = 0; c < p; ++c) {
+      const double x = v[lane * LD + ord[c]];
+      V[lane * PMAX + c] = x;       // column c = eigenvector of the c-th largest eigenvalue
+      W[c * PMAX + lane] = x;       // W = V^T: scores t_c = sum_i V_ic z_i
+    }
   }
-  if (tid == 0) {
-    const double l1 = a[ord[0] * PMAX + ord[0]], lp = a[ord[p - 1] * PMAX + ord[p - 1]];
+  if (lane == 0) {
+    const double l1 = a[ord[0] * LD + ord[0]], lp = a[ord[p - 1] * LD + ord[p - 1]];
     if (!(lp > 0.0) || !(l1 / lp <= kappa_max)) A.status[it] = ST_DROP_REFINE;
   }
 }
@@ -906,10 +938,19 @@ hipError_t launch_init_cov(int mode, const ItemDesc* bitems, int first, int n, F
   return hipGetLastError();
 }
 
-hipError_t launch_eig(const ItemDesc* items, ItemArrays A, FitArrays F, int first, int n,
-                      double kappa_max, hipStream_t s) {
+hipError_t launch_eig(int bucket, const ItemDesc* items, ItemArrays A, FitArrays F, int first,
+                      int n, double kappa_max, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_eig, dim3(n), dim3(256), 0, s, items, A, F, first, kappa_max);
+#define CASE(PB)                                                                             \
+  case PB:                                                                                   \
+    hipLaunchKernelGGL((k_eig<PB>), dim3(n), dim3(64), 0, s, items, A, F, first, kappa_max); \
+    break;
+  switch (bucket) {
+    CASE(4) CASE(5) CASE(8) CASE(10) CASE(16) CASE(20) CASE(24) CASE(32) CASE(40) CASE(48)
+    CASE(64)
+    default: return hipErrorInvalidValue;
+  }
+#undef CASE
   return hipGetLastError();
 }
 

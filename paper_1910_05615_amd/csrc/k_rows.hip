@@ -15,14 +15,9 @@ __device__ inline double ld_elem(const T* __restrict__ p, int64_t i) {
   return static_cast<double>(p[i]);
 }
 
-// Wrapping transform g of Sec. 3.2 (eq. wrapping) with the paper's defaults.
-__device__ inline double wrap_g(double z) {
-  const double b = 1.5, c = 4.0, q1 = 1.541, q2 = 0.862;
-  const double a = fabs(z);
-  if (a <= b) return z;
-  if (a <= c) return copysign(q1 * tanh(q2 * (c - a)), z);
-  return 0.0;
-}
+// Wrapping transform g of Sec. 3.2 (eq. wrapping) with the paper's defaults:
+// z for |z| <= b, sign(z) q1 tanh(q2 (c - |z|)) for b < |z| <= c, else 0.
+constexpr double WRAP_B = 1.5, WRAP_C = 4.0, WRAP_Q1 = 1.541, WRAP_Q2 = 0.862;
 
 // ---------------------------------------------------------------------------
 // Weighted sscp partial sums over one tile of candidate rows:
@@ -76,6 +71,9 @@ __global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items
   __shared__ T xs_all[4][S::XS];          // per-wave row staging
   __shared__ double red[NBL][4][64];      // block accumulators, summed wave by wave
   __shared__ int64_t rows_all[4][CR];     // gathered row indices (update steps)
+  // tanh arguments of the wrapped values of one step, gathered per wave
+  constexpr int TW = MODE == SSCP_WRAP ? 64 * NG : 1;
+  __shared__ double tw_all[4][TW];
 
   const Tile tl = tiles[blockIdx.x];
   const int it = tl.item;
@@ -217,12 +215,39 @@ __global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items
           const double x = r < n ? (double)xs[r * P + col] : 0.0;
           if (MODE == SSCP_CSTEP || MODE == SSCP_D2CUT || MODE == SSCP_ADJ) z = x - cen[g];
           else z = (x - cen[g]) / isc[g];
-          if (MODE == SSCP_WRAP) z = wrap_g(z);
           if (MODE == SSCP_GSSCM) r2 = fma(z, z, r2);
         } else if (col == p) {
           z = 1.0;
         }
         v[g] = z;
+      }
+      if (MODE == SSCP_WRAP) {
+        // g of every value of the step; the tanh branch (a minority of the
+        // values) is evaluated once for all of the wave's values that take
+        // it, gathered in LDS, instead of once per column group
+        double* __restrict__ tw = tw_all[wv];
+        const uint64_t below = (1ull << lane) - 1ull;
+        int cnt = 0, slot[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+          const double a = fabs(v[g]);
+          const bool mid = !(a <= WRAP_B) && a <= WRAP_C;
+          const uint64_t m = __ballot(mid);
+          slot[g] = mid ? cnt + __popcll(m & below) : -1;
+          if (mid) tw[slot[g]] = WRAP_Q2 * (WRAP_C - a);
+          cnt += __popcll(m);
+        }
+        __syncwarp();
+        for (int b0 = 0; b0 < cnt; b0 += 64)
+          if (b0 + lane < cnt) tw[b0 + lane] = tanh(tw[b0 + lane]);
+        __syncwarp();
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+          const double a = fabs(v[g]);
+          if (slot[g] >= 0) v[g] = copysign(WRAP_Q1 * tw[slot[g]], v[g]);
+          else if (!(a <= WRAP_C)) v[g] = 0.0;
+        }
+        __syncwarp();   // tw is free for the next step
       }
       if (MODE == SSCP_ADJ) {
         const double wr = __shfl(wcur, r < n ? r : 0, 64);

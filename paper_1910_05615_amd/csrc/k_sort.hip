@@ -541,7 +541,7 @@ __global__ __launch_bounds__(SS_NT) void k_segstats(const K* __restrict__ keys,
 // The passes run on a 32-bit key: the key itself for float data, and for
 // double data the high half of the order key (sign, exponent and 20 mantissa
 // bits: a monotone function of the key, so its order never contradicts the
-// order of the values).  Runs of equal high halves are then ordered by
+// order of the values).  Runs of equal sort keys are then ordered by
 // insertion sort on the full key; they are short for continuous data.
 //
 // Ranks within a wave come from LDS atomics on per-(wave, digit) counters in
@@ -666,6 +666,70 @@ __device__ inline void lds_radix_pass(K (&kv)[KPT], int shift, K* __restrict__ s
   for (int i = 0; i < KPT; ++i) kv[i] = sk[w * KPT * 64 + i * 64 + lane];
 }
 
+// 32-bit sort key of a key: the key itself (float data) or the high half of
+// a double's order key.
+template <typename K>
+__device__ inline uint32_t skey_of(K k) {
+  if constexpr (sizeof(K) == 8) return key32_of(k);
+  else return k;
+}
+
+// After passes that ordered the block's keys on skey (kv holds each thread's
+// keys in position order): one look at every adjacent pair checks that order
+// (it is not assumed), and runs of equal skey of double data are then put in
+// order on the full key by insertion sort, each by the thread that holds its
+// first position.  Sets *redo when the order is wrong or a run is too long or
+// too costly.  Ends with a barrier.
+template <typename K, int KPT>
+__device__ inline void check_and_fix(const K (&kv)[KPT], K* __restrict__ sk, int L,
+                                     int* __restrict__ redo) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  uint32_t starts = 0;
+  bool bad = false;
+#pragma unroll
+  for (int i = 0; i < KPT; ++i) {
+    const int pos = w * KPT * 64 + i * 64 + lane;
+    if (pos + 1 < L) {
+      const uint32_t a = skey_of<K>(kv[i]), b = skey_of<K>(sk[pos + 1]);
+      bad = bad || a > b;
+      if constexpr (sizeof(K) == 8) {   // equal sort keys, possibly unequal full keys
+        const bool prev_eq = pos > 0 && skey_of<K>(sk[pos - 1]) == a;
+        if (a == b && !prev_eq) starts |= 1u << i;
+      }
+    }
+  }
+  if (bad) *redo = 1;
+  __syncthreads();
+  while (starts) {
+    const int i = __ffs(starts) - 1;
+    starts &= starts - 1;
+    const int s0 = w * KPT * 64 + i * 64 + lane;
+    const uint32_t k0 = skey_of<K>(sk[s0]);
+    int e = s0 + 1;
+    while (e < L && e - s0 <= FIXUP_RUN && skey_of<K>(sk[e]) == k0) ++e;
+    if (e - s0 > FIXUP_RUN) {
+      *redo = 1;
+      break;
+    }
+    int moves = 0;
+    for (int a = s0 + 1; a < e && moves <= FIXUP_MOVES; ++a) {
+      const K x = sk[a];
+      int b = a;
+      while (b > s0 && sk[b - 1] > x && moves <= FIXUP_MOVES) {
+        sk[b] = sk[b - 1];
+        --b;
+        ++moves;
+      }
+      sk[b] = x;
+    }
+    if (moves > FIXUP_MOVES) {
+      *redo = 1;
+      break;
+    }
+  }
+  __syncthreads();
+}
+
 template <typename K, int KPT>
 __global__ __launch_bounds__(SS_NT) void k_seg_lds(const K* __restrict__ keys,
                                                    const int64_t* __restrict__ seg_off,
@@ -694,66 +758,16 @@ __global__ __launch_bounds__(SS_NT) void k_seg_lds(const K* __restrict__ keys,
       kv[i] = pos < L ? src[pos] : pad;
     }
   };
+  auto sort32 = [&]() {   // the four digits of the 32-bit sort key
+    lds_radix_pass<K, RK_ATOM, true, KPT>(kv, 0, sk, wc, gs, wt);
+    lds_radix_pass<K, RK_ATOM, true, KPT>(kv, 8, sk, wc, gs, wt);
+    lds_radix_pass<K, RK_ATOM, true, KPT>(kv, 16, sk, wc, gs, wt);
+    lds_radix_pass<K, RK_PEEL, true, KPT>(kv, 24, sk, wc, gs, wt);
+  };
   load();
   if (tid == 0) *redo = 0;
-  lds_radix_pass<K, RK_ATOM, true, KPT>(kv, 0, sk, wc, gs, wt);
-  lds_radix_pass<K, RK_ATOM, true, KPT>(kv, 8, sk, wc, gs, wt);
-  lds_radix_pass<K, RK_ATOM, true, KPT>(kv, 16, sk, wc, gs, wt);
-  lds_radix_pass<K, RK_PEEL, true, KPT>(kv, 24, sk, wc, gs, wt);
-  // One look at every adjacent pair: a 32-bit key that decreases means the
-  // passes went wrong (the order is checked, not assumed); equal 32-bit keys
-  // of double data start runs to be ordered on the full key.
-  uint32_t starts = 0;
-  {
-    bool bad = false;
-#pragma unroll
-    for (int i = 0; i < KPT; ++i) {
-      const int pos = w * KPT * 64 + i * 64 + lane;
-      if (pos + 1 < L) {
-        const K nx = sk[pos + 1];
-        uint32_t a, b;
-        if constexpr (sizeof(K) == 8) { a = key32_of(kv[i]); b = key32_of(nx); }
-        else { a = kv[i]; b = nx; }
-        bad = bad || a > b;
-        if constexpr (sizeof(K) == 8) {
-          const bool prev_eq = pos > 0 && key32_of(sk[pos - 1]) == a;
-          if (a == b && !prev_eq) starts |= 1u << i;
-        }
-      }
-    }
-    if (bad) *redo = 1;
-  }
-  if constexpr (sizeof(K) == 8) {
-    __syncthreads();
-    while (starts) {
-      const int i = __ffs(starts) - 1;
-      starts &= starts - 1;
-      const int s0 = w * KPT * 64 + i * 64 + lane;
-      const uint32_t k32 = key32_of(sk[s0]);
-      int e = s0 + 1;
-      while (e < L && e - s0 <= FIXUP_RUN && key32_of(sk[e]) == k32) ++e;
-      if (e - s0 > FIXUP_RUN) {
-        *redo = 1;
-        break;
-      }
-      int moves = 0;
-      for (int a = s0 + 1; a < e && moves <= FIXUP_MOVES; ++a) {
-        const K x = sk[a];
-        int b = a;
-        while (b > s0 && sk[b - 1] > x && moves <= FIXUP_MOVES) {
-          sk[b] = sk[b - 1];
-          --b;
-          ++moves;
-        }
-        sk[b] = x;
-      }
-      if (moves > FIXUP_MOVES) {
-        *redo = 1;
-        break;
-      }
-    }
-  }
-  __syncthreads();
+  sort32();
+  check_and_fix<K, KPT>(kv, sk, L, redo);
   if (*redo) {   // uniform: every thread reads the flag after the barrier
     __syncthreads();
     load();
@@ -1085,8 +1099,7 @@ template <typename K>
 hipError_t sort_segments_t(SortPlan& P, hipStream_t s) {
   K* a = static_cast<K*>(P.keys);
   K* b = static_cast<K*>(P.tmp);
-  const int passes = (int)sizeof(K);
-  for (int ps = 0; ps < passes; ++ps) {
+  for (int ps = 0; ps < (int)sizeof(K); ++ps) {
     const int shift = 8 * ps;
     hipLaunchKernelGGL((k_rs_count<K>), dim3(P.ntiles), dim3(RS_NT), 0, s, a, P.tiles,
                        P.seg_off, P.seg_len, shift, P.counts);
