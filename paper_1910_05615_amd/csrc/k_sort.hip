@@ -243,9 +243,9 @@ __device__ inline double val_of<double>(double k) {
 constexpr int SS_WV = SS_NT / 64;
 
 // Exclusive prefix sums in thread order of NV doubles per thread (wave scans,
-// then the totals of earlier waves).  red: NV * SS_WV doubles.  TRAIL: end
-// with a barrier, so that red may be written again at once.
-template <int NV, bool TRAIL = true>
+// then the totals of earlier waves) over a block of NW waves.  red: NV * NW
+// doubles.  TRAIL: end with a barrier, so that red may be written again.
+template <int NV, bool TRAIL = true, int NW = SS_WV>
 __device__ inline void block_excl_prefix(double (&v)[NV], double* __restrict__ red) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double ex[NV];
@@ -257,7 +257,7 @@ __device__ inline void block_excl_prefix(double (&v)[NV], double* __restrict__ r
       const double y = __shfl_up(x, o, 64);
       if (lane >= o) x += y;
     }
-    if (lane == 63) red[k * SS_WV + w] = x;
+    if (lane == 63) red[k * NW + w] = x;
     const double e = __shfl_up(x, 1, 64);
     ex[k] = lane == 0 ? 0.0 : e;
   }
@@ -265,10 +265,34 @@ __device__ inline void block_excl_prefix(double (&v)[NV], double* __restrict__ r
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     double off = 0.0;
-    for (int q = 0; q < w; ++q) off += red[k * SS_WV + q];
+    for (int q = 0; q < w; ++q) off += red[k * NW + q];
     v[k] = off + ex[k];
   }
   if (TRAIL) __syncthreads();
+}
+
+// Sums over a block of NW waves of NV doubles per thread, in a fixed order
+// (xor tree in each wave, then the waves in index order); every thread
+// receives them.  red: NV * NW doubles; ends with a barrier.
+template <int NV, int NW>
+__device__ inline void block_sums(double (&v)[NV], double* __restrict__ red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) red[k * NW + w] = x;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) t += red[k * NW + q];
+    v[k] = t;
+  }
+  __syncthreads();
 }
 
 // k-th smallest (0-based) of |v_i - c| for a sorted segment v, by bisection on
@@ -793,51 +817,22 @@ __global__ __launch_bounds__(SS_NT) void k_seg_lds(const K* __restrict__ keys,
 // ---------------------------------------------------------------------------
 constexpr int MB_NT = RS_NT;                  // 256 threads, RS_ITEMS keys each
 
-template <int NT>
-__device__ inline double blk_sum(double v, double* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int o = NT / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  const double r = red[0];
-  __syncthreads();
-  return r;
-}
+constexpr int MB_WV = MB_NT / 64;
 
-template <int NT>
-__device__ inline double blk_excl(double v, double* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double run = 0.0;
-    for (int k = 0; k < NT; ++k) {
-      const double t = red[k];
-      red[k] = run;
-      run += t;
-    }
-  }
-  __syncthreads();
-  const double r = red[threadIdx.x];
-  __syncthreads();
-  return r;
-}
-
-// Centred partial sums of v[a, b) by the whole block (thread-contiguous runs).
-template <typename K, int NT>
+// Centred partial sums of v[a, b) by the whole block: lane-strided (coalesced)
+// loads, a fixed order per thread, then block sums.
+template <typename K>
 __device__ inline void blk_range_sums(const K* __restrict__ v, int64_t a, int64_t b, double c,
                                       double* red, double& s1, double& s2) {
-  double l1 = 0.0, l2 = 0.0;
-  const int64_t n = b > a ? b - a : 0;
-  const int64_t t0 = a + (n * threadIdx.x) / NT, t1 = a + (n * (threadIdx.x + 1)) / NT;
-  for (int64_t k = t0; k < t1; ++k) {
+  double l[2] = {0.0, 0.0};
+  for (int64_t k = a + threadIdx.x; k < b; k += MB_NT) {
     const double d = val_of<K>(v[k]) - c;
-    l1 += d;
-    l2 = fma(d, d, l2);
+    l[0] += d;
+    l[1] = fma(d, d, l[1]);
   }
-  s1 = blk_sum<NT>(l1, red);
-  s2 = blk_sum<NT>(l2, red);
+  block_sums<2, MB_WV>(l, red);
+  s1 = l[0];
+  s2 = l[1];
 }
 
 template <typename K>
@@ -854,30 +849,44 @@ __global__ __launch_bounds__(MB_NT) void k_mb_sums(const K* __restrict__ keys,
   const double c = val_of<K>(v[L / 2]);
   const int64_t a = (int64_t)t.tile * RS_TILE, b = min(a + (int64_t)RS_TILE, L);
   double s1, s2;
-  blk_range_sums<K, MB_NT>(v, a, b, c, red, s1, s2);
+  blk_range_sums<K>(v, a, b, c, red, s1, s2);
   if (threadIdx.x == 0) {
     bs1[blockIdx.x] = s1;
     bs2[blockIdx.x] = s2;
   }
 }
 
-// Per segment: block sums -> exclusive prefixes; totals kept aside.
-__global__ void k_mb_scan(const int32_t* __restrict__ seg_tile0, int tile_first,
-                          double* __restrict__ bs1, double* __restrict__ bs2,
-                          double* __restrict__ tot) {
-  const int s = blockIdx.x;
-  if (threadIdx.x != 0) return;
+// Per segment: block sums -> exclusive prefixes; totals kept aside.  Each
+// thread takes a contiguous run of the segment's tiles, in order.
+__global__ __launch_bounds__(MB_NT) void k_mb_scan(const int32_t* __restrict__ seg_tile0,
+                                                   int tile_first, double* __restrict__ bs1,
+                                                   double* __restrict__ bs2,
+                                                   double* __restrict__ tot) {
+  __shared__ double red[2 * MB_WV];
+  const int s = blockIdx.x, tid = threadIdx.x;
   const int t0 = seg_tile0[s] - tile_first, t1 = seg_tile0[s + 1] - tile_first;
-  double r1 = 0.0, r2 = 0.0;
-  for (int t = t0; t < t1; ++t) {
-    const double a = bs1[t], b = bs2[t];
+  const int nt = t1 - t0;
+  const int a = t0 + (int)(((int64_t)nt * tid) / MB_NT);
+  const int b = t0 + (int)(((int64_t)nt * (tid + 1)) / MB_NT);
+  double r[2] = {0.0, 0.0};
+  for (int t = a; t < b; ++t) {
+    r[0] += bs1[t];
+    r[1] += bs2[t];
+  }
+  const double own1 = r[0], own2 = r[1];
+  block_excl_prefix<2, true, MB_WV>(r, red);
+  double r1 = r[0], r2 = r[1];
+  for (int t = a; t < b; ++t) {
+    const double x = bs1[t], y = bs2[t];
     bs1[t] = r1;
     bs2[t] = r2;
-    r1 += a;
-    r2 += b;
+    r1 += x;
+    r2 += y;
   }
-  tot[2 * s] = r1;
-  tot[2 * s + 1] = r2;
+  if (tid == MB_NT - 1) {
+    tot[2 * s] = r[0] + own1;
+    tot[2 * s + 1] = r[1] + own2;
+  }
 }
 
 // Prefix sums P(x) of the centred values at any position x of a segment.
@@ -893,7 +902,7 @@ __device__ inline void prefix_at(const K* __restrict__ v, int64_t L, double c, i
     return;
   }
   double q1, q2;
-  blk_range_sums<K, MB_NT>(v, bx * RS_TILE, x, c, red, q1, q2);
+  blk_range_sums<K>(v, bx * RS_TILE, x, c, red, q1, q2);
   p1 = bs1[t0rel + bx] + q1;
   p2 = bs2[t0rel + bx] + q2;
 }
@@ -939,17 +948,19 @@ __global__ __launch_bounds__(MB_NT) void k_mb_window(const K* __restrict__ keys,
       m1 += d;
       m2 = fma(d, d, m2);
     }
-    const double pa1 = blk_excl<MB_NT>(l1, red), pa2 = blk_excl<MB_NT>(l2, red);
-    const double pb1 = blk_excl<MB_NT>(m1, red), pb2 = blk_excl<MB_NT>(m2, red);
+    double pp[4] = {l1, l2, m1, m2};
+    block_excl_prefix<4, true, MB_WV>(pp, red);
+    const double pa1 = pp[0], pa2 = pp[1], pb1 = pp[2], pb2 = pp[3];
     double x1, x2;
     prefix_at<K>(v, L, c, a + hh, bs1, bs2, tot, t0rel, s_rel, red, x1, x2);
     double q1l = bs1[t0rel + t.tile] + pa1, q2l = bs2[t0rel + t.tile] + pa2;
     double q1h = x1 + pb1, q2h = x2 + pb2;
+    // windows ranked by hd * s2 - s1^2 = hd (hd - 1) var, as in segstat_body
     const double hd = (double)hh;
     for (int64_t j = ja; j < min(ja + RS_ITEMS, e); ++j) {
       const double s1 = q1h - q1l, s2 = q2h - q2l;
-      const double wv = (s2 - s1 * s1 / hd) / (hd - 1.0);
-      if (wv < best) { best = wv; bj = j; }
+      const double cr = fma(s2, hd, -(s1 * s1));
+      if (cr < best) { best = cr; bj = j; }
       const double dl = val_of<K>(v[j]) - c;
       q1l += dl;
       q2l = fma(dl, dl, q2l);
@@ -980,9 +991,10 @@ __global__ __launch_bounds__(MB_NT) void k_mb_window(const K* __restrict__ keys,
   }
 }
 
-// Per segment: the window of smallest variance (lowest start on ties), the
-// raw location / variance, the reweighting bound.  prm[s] = {c, mu_raw,
-// var_raw, lim, start}.
+// Per segment: the window of smallest variance (lowest start on ties; the
+// blocks rank windows by hd s2 - s1^2), the raw location and variance from
+// its prefix sums, the reweighting bound.  prm[s] = {c, mu_raw, var_raw,
+// lim, start}.
 template <typename K>
 __global__ __launch_bounds__(MB_NT) void k_mb_mid(const K* __restrict__ keys,
                                                   const int64_t* __restrict__ seg_off,
@@ -997,32 +1009,52 @@ __global__ __launch_bounds__(MB_NT) void k_mb_mid(const K* __restrict__ keys,
                                                   const double* __restrict__ seg_craw, double q1,
                                                   double* __restrict__ prm) {
   __shared__ double red[MB_NT];
-  __shared__ double s_w;
   __shared__ int64_t s_j;
   const int s_rel = blockIdx.x;
   const int sg = seg_first + s_rel;
   const K* __restrict__ v = keys + seg_off[sg];
   const int64_t L = seg_len[sg];
   const int t0rel = seg_tile0[s_rel] - tile_first, t1rel = seg_tile0[s_rel + 1] - tile_first;
-  if (threadIdx.x == 0) {
+  {
+    // smallest criterion over the segment's blocks, ties to the lowest start
+    // (an exact min: the order of the comparisons does not matter)
     double b = INFINITY;
     int64_t j = -1;
-    for (int t = t0rel; t < t1rel; ++t) {
+    for (int t = t0rel + (int)threadIdx.x; t < t1rel; t += MB_NT) {
       const int64_t j2 = wj[t];
-      if (j2 >= 0 && (j < 0 || wbest[t] < b)) { b = wbest[t]; j = j2; }
+      const double b2 = wbest[t];
+      if (j2 >= 0 && (j < 0 || b2 < b || (b2 == b && j2 < j))) { b = b2; j = j2; }
     }
-    s_w = b;
-    s_j = j;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double b2 = __shfl_xor(b, o, 64);
+      const int64_t j2 = __shfl_xor(j, o, 64);
+      if (j2 >= 0 && (j < 0 || b2 < b || (b2 == b && j2 < j))) { b = b2; j = j2; }
+    }
+    if ((threadIdx.x & 63) == 0) {
+      red[threadIdx.x >> 6] = b;
+      reinterpret_cast<int64_t*>(red)[MB_WV + (threadIdx.x >> 6)] = j;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int q = 0; q < MB_WV; ++q) {
+        const double b2 = red[q];
+        const int64_t j2 = reinterpret_cast<const int64_t*>(red)[MB_WV + q];
+        if (j2 >= 0 && (j < 0 || b2 < b || (b2 == b && j2 < j))) { b = b2; j = j2; }
+      }
+      s_j = j;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const double c = val_of<K>(v[L / 2]);
   const int64_t hh = L / 2 + 1, js = s_j;
   double pa1, pa2, pb1, pb2;
   prefix_at<K>(v, L, c, js, bs1, bs2, tot, t0rel, s_rel, red, pa1, pa2);
   prefix_at<K>(v, L, c, js + hh, bs1, bs2, tot, t0rel, s_rel, red, pb1, pb2);
   if (threadIdx.x == 0) {
-    const double mu_raw = c + (pb1 - pa1) / (double)hh;
-    const double var_raw = s_w * seg_craw[s_rel];
+    const double hd = (double)hh, s1 = pb1 - pa1, s2 = pb2 - pa2;
+    const double mu_raw = c + s1 / hd;
+    const double var_raw = (s2 - s1 * s1 / hd) / (hd - 1.0) * seg_craw[s_rel];
     double* P = prm + 5 * s_rel;
     P[0] = c;
     P[1] = mu_raw;
@@ -1047,41 +1079,43 @@ __global__ __launch_bounds__(MB_NT) void k_mb_kept(const K* __restrict__ keys,
   const double* P = prm + 5 * (t.seg - seg_first);
   const double c = P[0], mu = P[1], lim = P[3];
   const int64_t a = (int64_t)t.tile * RS_TILE, b = min(a + (int64_t)RS_TILE, L);
-  const int64_t n = b - a;
-  const int64_t t0 = a + (n * threadIdx.x) / MB_NT, t1 = a + (n * (threadIdx.x + 1)) / MB_NT;
-  double c0 = 0.0, c1 = 0.0, c2 = 0.0;
-  for (int64_t k = t0; k < t1; ++k) {
+  double cs[3] = {0.0, 0.0, 0.0};
+  for (int64_t k = a + threadIdx.x; k < b; k += MB_NT) {
     const double x = val_of<K>(v[k]);
     const double e = x - mu;
     if (e * e <= lim) {
       const double d = x - c;
-      c0 += 1.0;
-      c1 += d;
-      c2 = fma(d, d, c2);
+      cs[0] += 1.0;
+      cs[1] += d;
+      cs[2] = fma(d, d, cs[2]);
     }
   }
-  const double r0 = blk_sum<MB_NT>(c0, red), r1 = blk_sum<MB_NT>(c1, red),
-               r2 = blk_sum<MB_NT>(c2, red);
+  block_sums<3, MB_WV>(cs, red);
   if (threadIdx.x == 0) {
-    k0[blockIdx.x] = r0;
-    k1[blockIdx.x] = r1;
-    k2[blockIdx.x] = r2;
+    k0[blockIdx.x] = cs[0];
+    k1[blockIdx.x] = cs[1];
+    k2[blockIdx.x] = cs[2];
   }
 }
 
-__global__ void k_mb_final(const int32_t* __restrict__ seg_tile0, int tile_first,
-                           const double* __restrict__ prm, const double* __restrict__ k0,
-                           const double* __restrict__ k1, const double* __restrict__ k2,
-                           double crew, SegStat* __restrict__ out) {
+__global__ __launch_bounds__(MB_NT) void k_mb_final(const int32_t* __restrict__ seg_tile0,
+                                                    int tile_first, const double* __restrict__ prm,
+                                                    const double* __restrict__ k0,
+                                                    const double* __restrict__ k1,
+                                                    const double* __restrict__ k2, double crew,
+                                                    SegStat* __restrict__ out) {
+  __shared__ double red[3 * MB_WV];
   const int s = blockIdx.x;
-  if (threadIdx.x != 0) return;
   const int t0 = seg_tile0[s] - tile_first, t1 = seg_tile0[s + 1] - tile_first;
-  double N = 0.0, S1 = 0.0, S2 = 0.0;
-  for (int t = t0; t < t1; ++t) {
-    N += k0[t];
-    S1 += k1[t];
-    S2 += k2[t];
+  double cs[3] = {0.0, 0.0, 0.0};
+  for (int t = t0 + (int)threadIdx.x; t < t1; t += MB_NT) {
+    cs[0] += k0[t];
+    cs[1] += k1[t];
+    cs[2] += k2[t];
   }
+  block_sums<3, MB_WV>(cs, red);
+  if (threadIdx.x != 0) return;
+  const double N = cs[0], S1 = cs[1], S2 = cs[2];
   const double* P = prm + 5 * s;
   SegStat r{};
   r.mu_raw = P[1];
@@ -1161,7 +1195,7 @@ hipError_t unimcd_multiblock_t(const SortPlan& P, const double* seg_craw, double
   const K* keys = static_cast<const K*>(P.keys);
   hipLaunchKernelGGL((k_mb_sums<K>), dim3(P.ntiles), dim3(MB_NT), 0, s, keys, P.tiles, P.seg_off,
                      P.seg_len, M.bs1, M.bs2);
-  hipLaunchKernelGGL(k_mb_scan, dim3(P.nseg), dim3(64), 0, s, P.seg_tile0, P.tile_first, M.bs1,
+  hipLaunchKernelGGL(k_mb_scan, dim3(P.nseg), dim3(MB_NT), 0, s, P.seg_tile0, P.tile_first, M.bs1,
                      M.bs2, M.tot);
   hipLaunchKernelGGL((k_mb_window<K>), dim3(P.ntiles), dim3(MB_NT), 0, s, keys, P.tiles,
                      P.seg_off, P.seg_len, P.seg_tile0, P.tile_first, P.seg_first, M.bs1, M.bs2,
@@ -1171,7 +1205,7 @@ hipError_t unimcd_multiblock_t(const SortPlan& P, const double* seg_craw, double
                      seg_craw, q1, M.prm);
   hipLaunchKernelGGL((k_mb_kept<K>), dim3(P.ntiles), dim3(MB_NT), 0, s, keys, P.tiles, P.seg_off,
                      P.seg_len, P.seg_first, M.prm, M.k0, M.k1, M.k2);
-  hipLaunchKernelGGL(k_mb_final, dim3(P.nseg), dim3(64), 0, s, P.seg_tile0, P.tile_first, M.prm,
+  hipLaunchKernelGGL(k_mb_final, dim3(P.nseg), dim3(MB_NT), 0, s, P.seg_tile0, P.tile_first, M.prm,
                      M.k0, M.k1, M.k2, crew, out);
   return hipGetLastError();
 }

@@ -13,7 +13,7 @@ struct SegTile {
 // Scratch of the multi-block univariate MCD (per tile / per segment arrays).
 struct MbScratch {
   double *bs1, *bs2;     // [ntiles] block sums, then exclusive prefixes
-  double *wbest;         // [ntiles] smallest window variance per block
+  double *wbest;         // [ntiles] smallest window criterion hd s2 - s1^2 per block
   int64_t* wj;           // [ntiles] its window start
   double *k0, *k1, *k2;  // [ntiles] kept-row partial sums
   double* tot;           // [2 nseg] segment totals
