@@ -37,24 +37,46 @@ rtdetmcd_status ensure_ws(rtdetmcd_ctx* ctx, size_t bytes) {
   return RTDETMCD_OK;
 }
 
+// All tables of a flush go to the device in one copy (header of (dst,
+// offset, bytes) records, then the payload) into a staging buffer, and one
+// kernel scatters them to their places: one copy and one launch instead of
+// one copy per table.
 rtdetmcd_status Uploader::flush(rtdetmcd_ctx* ctx) {
   if (ents.empty()) return RTDETMCD_OK;
   if (ctx->pin_pending) {
     RTD_HIP(hipEventSynchronize(ctx->pin_ev));
     ctx->pin_pending = false;
   }
-  if (buf.size() > ctx->pin_size) {
+  const size_t n = ents.size();
+  const size_t hdr = (n * 3 * sizeof(uint64_t) + 255) & ~(size_t)255;
+  const size_t total = hdr + buf.size();
+  if (total > ctx->pin_size) {
     if (ctx->pin) RTD_HIP(hipHostFree(ctx->pin));
     ctx->pin = nullptr;
-    const size_t want = buf.size() + (1u << 16);
+    const size_t want = total + (1u << 16);
     RTD_HIP(hipHostMalloc(&ctx->pin, want, hipHostMallocDefault));
     ctx->pin_size = want;
   }
-  std::memcpy(ctx->pin, buf.data(), buf.size());
-  for (const E& e : ents)
-    if (e.bytes)
-      RTD_HIP(hipMemcpyAsync(e.dst, static_cast<char*>(ctx->pin) + e.off, e.bytes,
-                             hipMemcpyHostToDevice, ctx->stream));
+  if (total > ctx->stage_size) {
+    if (ctx->stage) {
+      RTD_HIP(hipStreamSynchronize(ctx->stream));
+      RTD_HIP(hipFree(ctx->stage));
+    }
+    ctx->stage = nullptr;
+    ctx->stage_size = 0;
+    const size_t want = total + (1u << 16);
+    RTD_HIP(hipMalloc(&ctx->stage, want));
+    ctx->stage_size = want;
+  }
+  uint64_t* h = static_cast<uint64_t*>(ctx->pin);
+  for (size_t k = 0; k < n; ++k) {
+    h[3 * k] = (uint64_t)(uintptr_t)ents[k].dst;
+    h[3 * k + 1] = (uint64_t)(hdr + ents[k].off);
+    h[3 * k + 2] = (uint64_t)ents[k].bytes;
+  }
+  std::memcpy(static_cast<char*>(ctx->pin) + hdr, buf.data(), buf.size());
+  RTD_HIP(hipMemcpyAsync(ctx->stage, ctx->pin, total, hipMemcpyHostToDevice, ctx->stream));
+  RTD_HIP(launch_upload_scatter(ctx->stage, (int)n, ctx->stream));
   RTD_HIP(hipEventRecord(ctx->pin_ev, ctx->stream));
   ctx->pin_pending = true;
   ents.clear();
@@ -373,6 +395,7 @@ rtdetmcd_status rtdetmcd_destroy(rtdetmcd_handle ctx) {
   if (ctx->pin) (void)hipHostFree(ctx->pin);
   if (ctx->pin_ev) (void)hipEventDestroy(ctx->pin_ev);
   if (ctx->flag) (void)hipHostFree(ctx->flag);
+  if (ctx->stage) (void)hipFree(ctx->stage);
   delete ctx;
   return RTDETMCD_OK;
 }

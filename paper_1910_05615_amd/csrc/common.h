@@ -113,6 +113,9 @@ hipError_t launch_finalize(int bucket, const ItemDesc* items, ItemArrays A, int 
                            int nitems, int from_start, int max_csteps, double kappa_max,
                            hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+// stage: n records (dst, offset, bytes) of 3 uint64 each, then the payload at
+// those offsets from stage; copies every record's bytes to its dst.
+hipError_t launch_upload_scatter(const void* stage, int n, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t s);
 hipError_t launch_chol_factor(const double* sigma, int p, double* mtri, hipStream_t s);
 hipError_t launch_extract_subset(const ItemDesc* items, ItemArrays A, int first_item, int nitems,

@@ -87,6 +87,8 @@ struct rtdetmcd_ctx {
   void* pin = nullptr;         // pinned host staging (grow only)
   size_t pin_size = 0;
   hipEvent_t pin_ev = nullptr; // last upload out of the staging buffer
+  void* stage = nullptr;       // device copy of the pinned staging buffer (grow only)
+  size_t stage_size = 0;
   bool pin_pending = false;
   int32_t* flag = nullptr;     // pinned readback word
   int sort_safe = 0;           // 1: global sorts rank with ballots (no order check)

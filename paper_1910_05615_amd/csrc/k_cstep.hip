@@ -480,6 +480,22 @@ __global__ __launch_bounds__(64) void k_finalize(const ItemDesc* __restrict__ it
   }
 }
 
+__global__ __launch_bounds__(256) void k_upload_scatter(const char* __restrict__ stage) {
+  const uint64_t* __restrict__ h = reinterpret_cast<const uint64_t*>(stage) + 3 * blockIdx.x;
+  char* __restrict__ dst = reinterpret_cast<char*>((uintptr_t)h[0]);
+  const char* __restrict__ src = stage + h[1];
+  const uint64_t bytes = h[2];
+  uint64_t k0 = 0;
+  if ((((uintptr_t)dst | h[1]) & 15) == 0) {   // 16-byte words, then the tail
+    typedef unsigned V __attribute__((ext_vector_type(4)));
+    const V* __restrict__ s4 = reinterpret_cast<const V*>(src);
+    V* __restrict__ d4 = reinterpret_cast<V*>(dst);
+    for (uint64_t k = threadIdx.x; k < bytes / 16; k += 256) d4[k] = s4[k];
+    k0 = bytes & ~(uint64_t)15;
+  }
+  for (uint64_t k = k0 + threadIdx.x; k < bytes; k += 256) dst[k] = src[k];
+}
+
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -561,6 +577,13 @@ hipError_t launch_finalize(int bucket, const ItemDesc* items, ItemArrays A, int 
     default: return hipErrorInvalidValue;
   }
 #undef CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_upload_scatter(const void* stage, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_upload_scatter, dim3(n), dim3(256), 0, s,
+                     static_cast<const char*>(stage));
   return hipGetLastError();
 }
 

@@ -919,9 +919,14 @@ __global__ __launch_bounds__(MB_NT) void k_mb_window(const K* __restrict__ keys,
                                                      const double* __restrict__ tot,
                                                      double* __restrict__ wbest,
                                                      int64_t* __restrict__ wj) {
-  __shared__ double red[MB_NT];
-  __shared__ double sb[MB_NT];
-  __shared__ int64_t sj[MB_NT];
+  // the tile's window starts v[a, a + RS_TILE) and ends v[a + hh, ...) are
+  // staged once, coalesced, in LDS; each thread then walks RS_ITEMS
+  // consecutive starts, at a padded stride that keeps lanes off one bank
+  constexpr int PADN = RS_TILE + RS_TILE / RS_ITEMS;
+  __shared__ K sl[PADN], sh[PADN];
+  __shared__ double red[4 * MB_WV];
+  __shared__ double sb[MB_WV];
+  __shared__ int64_t sj[MB_WV];
   const SegTile t = tiles[blockIdx.x];
   const K* __restrict__ v = keys + seg_off[t.seg];
   const int64_t L = seg_len[t.seg];
@@ -931,63 +936,86 @@ __global__ __launch_bounds__(MB_NT) void k_mb_window(const K* __restrict__ keys,
   const int64_t hh = L / 2 + 1, nw = L - hh + 1;
   const int64_t a = (int64_t)t.tile * RS_TILE;
   const int64_t e = min(a + (int64_t)RS_TILE, nw);
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double best = INFINITY;
   int64_t bj = -1;
   if (a < nw) {   // uniform over the block
-    // P at this thread's first window start and at start + hh
-    const int64_t ja = a + (int64_t)tid * RS_ITEMS;
-    double l1 = 0.0, l2 = 0.0, m1 = 0.0, m2 = 0.0;
-    for (int64_t k = ja; k < min(ja + RS_ITEMS, L); ++k) {
-      const double d = val_of<K>(v[k]) - c;
-      l1 += d;
-      l2 = fma(d, d, l2);
-    }
-    for (int64_t k = ja + hh; k < min(ja + hh + RS_ITEMS, L); ++k) {
-      const double d = val_of<K>(v[k]) - c;
-      m1 += d;
-      m2 = fma(d, d, m2);
-    }
-    double pp[4] = {l1, l2, m1, m2};
-    block_excl_prefix<4, true, MB_WV>(pp, red);
-    const double pa1 = pp[0], pa2 = pp[1], pb1 = pp[2], pb2 = pp[3];
-    double x1, x2;
-    prefix_at<K>(v, L, c, a + hh, bs1, bs2, tot, t0rel, s_rel, red, x1, x2);
-    double q1l = bs1[t0rel + t.tile] + pa1, q2l = bs2[t0rel + t.tile] + pa2;
-    double q1h = x1 + pb1, q2h = x2 + pb2;
-    // windows ranked by hd * s2 - s1^2 = hd (hd - 1) var, as in segstat_body
-    const double hd = (double)hh;
-    for (int64_t j = ja; j < min(ja + RS_ITEMS, e); ++j) {
-      const double s1 = q1h - q1l, s2 = q2h - q2l;
-      const double cr = fma(s2, hd, -(s1 * s1));
-      if (cr < best) { best = cr; bj = j; }
-      const double dl = val_of<K>(v[j]) - c;
-      q1l += dl;
-      q2l = fma(dl, dl, q2l);
-      if (j + hh < L) {
-        const double dh = val_of<K>(v[j + hh]) - c;
-        q1h += dh;
-        q2h = fma(dh, dh, q2h);
-      }
-    }
-  }
-  sb[tid] = best;
-  sj[tid] = bj;
-  __syncthreads();
-  for (int o = MB_NT / 2; o > 0; o >>= 1) {
-    if (tid < o) {
-      const double b2 = sb[tid + o];
-      const int64_t j2 = sj[tid + o];
-      if (j2 >= 0 && (sj[tid] < 0 || b2 < sb[tid] || (b2 == sb[tid] && j2 < sj[tid]))) {
-        sb[tid] = b2;
-        sj[tid] = j2;
-      }
+    for (int q = tid; q < RS_TILE; q += MB_NT) {
+      const int qs = q + q / RS_ITEMS;
+      const int64_t pl = a + q, ph = a + hh + q;
+      sl[qs] = pl < L ? v[pl] : v[L - 1];
+      sh[qs] = ph < L ? v[ph] : v[L - 1];
     }
     __syncthreads();
+    double x1, x2;   // P at a + hh (block-wide, ends with a barrier)
+    prefix_at<K>(v, L, c, a + hh, bs1, bs2, tot, t0rel, s_rel, red, x1, x2);
+    // this thread's starts a + ja .. + RS_ITEMS; P there and at start + hh
+    const int ja = tid * RS_ITEMS;
+    const K* __restrict__ ml = sl + tid * (RS_ITEMS + 1);
+    const K* __restrict__ mh = sh + tid * (RS_ITEMS + 1);
+    double pp[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+      if (a + ja + i < L) {
+        const double d = val_of<K>(ml[i]) - c;
+        pp[0] += d;
+        pp[1] = fma(d, d, pp[1]);
+      }
+      if (a + hh + ja + i < L) {
+        const double d = val_of<K>(mh[i]) - c;
+        pp[2] += d;
+        pp[3] = fma(d, d, pp[3]);
+      }
+    }
+    block_excl_prefix<4, true, MB_WV>(pp, red);
+    double q1l = bs1[t0rel + t.tile] + pp[0], q2l = bs2[t0rel + t.tile] + pp[1];
+    double q1h = x1 + pp[2], q2h = x2 + pp[3];
+    // windows ranked by hd * s2 - s1^2 = hd (hd - 1) var, as in segstat_body
+    const double hd = (double)hh;
+#pragma unroll
+    for (int i = 0; i < RS_ITEMS; ++i) {
+      const int64_t j = a + ja + i;
+      if (j < e) {
+        const double s1 = q1h - q1l, s2 = q2h - q2l;
+        const double cr = fma(s2, hd, -(s1 * s1));
+        if (cr < best) { best = cr; bj = j; }
+        const double dl = val_of<K>(ml[i]) - c;
+        q1l += dl;
+        q2l = fma(dl, dl, q2l);
+        if (j + hh < L) {
+          const double dh = val_of<K>(mh[i]) - c;
+          q1h += dh;
+          q2h = fma(dh, dh, q2h);
+        }
+      }
+    }
   }
+  // smallest criterion, ties to the lowest start (an exact min)
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double b2 = __shfl_xor(best, o, 64);
+    const int64_t j2 = __shfl_xor(bj, o, 64);
+    if (j2 >= 0 && (bj < 0 || b2 < best || (b2 == best && j2 < bj))) {
+      best = b2;
+      bj = j2;
+    }
+  }
+  if (lane == 0) {
+    sb[w] = best;
+    sj[w] = bj;
+  }
+  __syncthreads();
   if (tid == 0) {
-    wbest[blockIdx.x] = sb[0];
-    wj[blockIdx.x] = sj[0];
+    for (int q = 1; q < MB_WV; ++q) {
+      const double b2 = sb[q];
+      const int64_t j2 = sj[q];
+      if (j2 >= 0 && (bj < 0 || b2 < best || (b2 == best && j2 < bj))) {
+        best = b2;
+        bj = j2;
+      }
+    }
+    wbest[blockIdx.x] = best;
+    wj[blockIdx.x] = bj;
   }
 }
 
