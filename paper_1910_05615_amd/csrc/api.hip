@@ -199,11 +199,11 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
     RTD_HIP(launch_finalize(bucket, D.items, D.A, first, n, 1, maxs, o.kappa_max, st));
     const int R = std::max(1, o.rounds_per_sync);
     // one C-step of every active item
+    // one C-step of every active item; the selection zeroes the active count
     auto step = [&](hipStream_t s) -> rtdetmcd_status {
-      RTD_HIP(launch_fill_i32(D.A.nactive, 0, 1, s));
       RTD_HIP(launch_dist(bucket, dtype, pairs ? 2 : 1, D.items, dtl + dt0, dtn, DIST_TILE,
                           D.A.mtri, D.A.mux, D.A.status, D.A.d2, s));
-      RTD_HIP(launch_select(D.items, D.A, first, n, max_m, o.cstep_mode, s));
+      RTD_HIP(launch_select(D.items, D.A, first, n, max_m, o.cstep_mode, s, 1));
       RTD_HIP(launch_sscp(bucket, dtype, SSCP_CSTEP, D.items, D.A, D.stiles + st0, stn,
                           SSCP_TILE, nullptr, nullptr, s));
       RTD_HIP(launch_collapse(D.items, D.A, first, n, max_nt, 1, SSCP_TILE, s));

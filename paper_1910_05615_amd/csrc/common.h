@@ -96,8 +96,10 @@ hipError_t launch_dist(int bucket, int dtype, int ipt, const ItemDesc* items, co
                        int ntiles, int tile_rows, const double* mtri, const double* mux,
                        const int32_t* status, double* d2, hipStream_t s);
 // max_m: largest m among the items (picks the register-resident variant).
+// reset_nactive: the first block zeroes *A.nactive before anything else (the
+// C-step loop counts the items left active by the step's finalize).
 hipError_t launch_select(const ItemDesc* items, ItemArrays A, int first_item, int nitems,
-                         int64_t max_m, int cstep_mode, hipStream_t s);
+                         int64_t max_m, int cstep_mode, hipStream_t s, int reset_nactive = 0);
 // wsrc: per-row cotangents of SSCP_ADJ (rows indexed like d2), else unused.
 hipError_t launch_sscp(int bucket, int dtype, int mode, const ItemDesc* items, ItemArrays A,
                        const Tile* tiles, int ntiles, int tile_rows, const double* wsrc,

@@ -144,9 +144,9 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     d.m = m;
     d.h = h;
     d.ld = s.ld;
-    d.chi2p = chi2_quantile(o.cutoff_q, s.p);
-    d.calpha = consistency((double)h / (double)m, s.p);
-    d.crew = o.rew_consistency ? consistency(o.cutoff_q, s.p) : 1.0;
+    d.chi2p = chi2_quantile_memo(o.cutoff_q, s.p);
+    d.calpha = consistency_memo((double)h / (double)m, s.p);
+    d.crew = o.rew_consistency ? consistency_memo(o.cutoff_q, s.p) : 1.0;
     order.push_back((int)dsh.size());
     dsh.push_back(d);
   }
@@ -212,7 +212,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     SortHost& Hs = D[k].dtype == 0 ? S32 : S64;
     std_in64[k] = D[k].dtype;
     std_seg0[k] = Hs.nseg();
-    const double cr = consistency((double)(D[k].n / 2 + 1) / (double)D[k].n, 1);
+    const double cr = consistency_memo((double)(D[k].n / 2 + 1) / (double)D[k].n, 1);
     for (int j = 0; j < D[k].p; ++j) Hs.add(D[k].n, cr);
   }
   std::vector<int64_t> nkbase(NB), rkbase(NC);
@@ -225,7 +225,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     const ItemDesc& e = C.items[c];
     rkbase[c] = SR.keys;
     rseg0[c] = SR.nseg();
-    const double cr = consistency((double)(e.m / 2 + 1) / (double)e.m, 1);
+    const double cr = consistency_memo((double)(e.m / 2 + 1) / (double)e.m, 1);
     for (int j = 0; j < e.p; ++j) SR.add(e.m, cr);
   }
   // aggregation entries
@@ -390,8 +390,8 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   RTD_TRY(up.flush(ctx));
 
   const bool plain = o.launch == RTDETMCD_LAUNCH_PLAIN;
-  const double q1 = chi2_quantile(o.cutoff_q, 1);
-  const double crew1 = consistency(o.cutoff_q, 1);
+  const double q1 = chi2_quantile_memo(o.cutoff_q, 1);
+  const double crew1 = consistency_memo(o.cutoff_q, 1);
   const int smode = o.standardize == RTDETMCD_STD_MEDMAD ? SEGSTAT_MEDMAD : SEGSTAT_UNIMCD;
 
   // ---------------------------------------------------------------- step 0: standardisation

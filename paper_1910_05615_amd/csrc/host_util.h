@@ -6,7 +6,9 @@
 #include <stdint.h>
 
 #include <cmath>
+#include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -67,6 +69,40 @@ inline double chi2_quantile(double q, double df) {
 inline double consistency(double alpha, int p) {
   if (alpha >= 1.0) return 1.0;
   return alpha / chi2_cdf(chi2_quantile(alpha, p), p + 2);
+}
+
+// The same two functions remembered per thread: a fit asks for the same few
+// values (one per block length and p) many times, and each costs a bisection
+// over the incomplete gamma function.
+inline double memo_lookup(int kind, double x, double df, double (*f)(double, double)) {
+  struct Key {
+    int kind;
+    uint64_t x, df;
+    bool operator==(const Key& o) const { return kind == o.kind && x == o.x && df == o.df; }
+  };
+  struct Hash {
+    size_t operator()(const Key& k) const {
+      return std::hash<uint64_t>()(k.x * 0x9E3779B97F4A7C15ull ^ k.df) ^ (size_t)k.kind;
+    }
+  };
+  thread_local std::unordered_map<Key, double, Hash> memo;
+  uint64_t bx, bd;
+  std::memcpy(&bx, &x, 8);
+  std::memcpy(&bd, &df, 8);
+  const Key k{kind, bx, bd};
+  const auto it = memo.find(k);
+  if (it != memo.end()) return it->second;
+  const double v = f(x, df);
+  if (memo.size() > 65536) memo.clear();
+  memo.emplace(k, v);
+  return v;
+}
+inline double chi2_quantile_memo(double q, double df) {
+  return memo_lookup(0, q, df, [](double a, double b) { return chi2_quantile(a, b); });
+}
+inline double consistency_memo(double alpha, int p) {
+  return memo_lookup(1, alpha, (double)p,
+                     [](double a, double b) { return consistency(a, (int)b); });
 }
 
 }  // namespace rtd

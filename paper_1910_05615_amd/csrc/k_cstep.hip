@@ -48,7 +48,8 @@ constexpr int SEL_NT = 1024;
 
 __global__ __launch_bounds__(SEL_NT) void k_select(const ItemDesc* __restrict__ items,
                                                    ItemArrays A, int first_item,
-                                                   int cstep_mode) {
+                                                   int cstep_mode, int reset_nactive) {
+  if (reset_nactive && blockIdx.x == 0 && threadIdx.x == 0) *A.nactive = 0;
   __shared__ unsigned hist[8192];
   __shared__ int wtot[3][SEL_NT / 64];
   __shared__ int s_bin, s_cnt;
@@ -187,7 +188,8 @@ __device__ inline int scan256_excl(int* __restrict__ v, int n, int* __restrict__
 
 __global__ __launch_bounds__(SEL_NT) void k_select_reg(const ItemDesc* __restrict__ items,
                                                        ItemArrays A, int first_item,
-                                                       int cstep_mode) {
+                                                       int cstep_mode, int reset_nactive) {
+  if (reset_nactive && blockIdx.x == 0 && threadIdx.x == 0) *A.nactive = 0;
   __shared__ unsigned hist[8192];
   __shared__ int wtot[SEL_WV];
   __shared__ int tab[3][SEL_KR * SEL_WV];   // eq, entering, leaving per (slot, wave)
@@ -551,14 +553,14 @@ __global__ __launch_bounds__(1024) void k_extract_subset(const ItemDesc* __restr
 }  // namespace
 
 hipError_t launch_select(const ItemDesc* items, ItemArrays A, int first_item, int nitems,
-                         int64_t max_m, int cstep_mode, hipStream_t s) {
+                         int64_t max_m, int cstep_mode, hipStream_t s, int reset_nactive) {
   if (nitems <= 0) return hipSuccess;
   if (max_m <= (int64_t)SEL_NT * SEL_KR)
     hipLaunchKernelGGL(k_select_reg, dim3(nitems), dim3(SEL_NT), 0, s, items, A, first_item,
-                       cstep_mode);
+                       cstep_mode, reset_nactive);
   else
     hipLaunchKernelGGL(k_select, dim3(nitems), dim3(SEL_NT), 0, s, items, A, first_item,
-                       cstep_mode);
+                       cstep_mode, reset_nactive);
   return hipGetLastError();
 }
 
