@@ -4,9 +4,12 @@
 //
 // Rows stream through LDS in chunks loaded with 16-byte coalesced loads, the
 // next chunk's loads in flight while the current one is evaluated in
-// float64.  M and mu are staged (packed, zero-padded to the p-bucket) in LDS
-// and read as broadcasts.  The C-step variant evaluates the two starts of a
-// block from one read of each row.
+// float64.  With one factor per launch (scoring, final distances) M is read
+// from global memory at uniform offsets, so the loads go through the scalar
+// unit and each FMA takes its entry from SGPRs; the C-step variant, which
+// evaluates the two starts of a block from one read of each row, stages both
+// factors (packed, zero-padded to the p-bucket) in LDS and reads them as
+// broadcasts (two factors in SGPRs measured slower).  mu is staged in LDS.
 #include <stdint.h>
 
 #include "common.h"
@@ -90,6 +93,26 @@ __device__ inline void tri_norm2_r(const double* __restrict__ Ml, const double (
   }
 }
 
+// ||M z||^2 with M read from global memory at uniform, compile-time offsets
+// (row stride LDM): the loads go through the scalar unit and every FMA takes
+// its M entry from SGPRs.
+template <int P>
+__device__ inline double tri_norm2_g(const double* __restrict__ Mg, int ldm, int p,
+                                     const double (&z)[P]) {
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    if (i < p) {
+      const double* __restrict__ mr = Mg + i * ldm;
+      double y = 0.0;
+#pragma unroll
+      for (int j = 0; j <= i; ++j) y = fma(mr[j], z[j], y);
+      acc = fma(y, y, acc);
+    }
+  }
+  return acc;
+}
+
 template <int P>
 __device__ inline double tri_norm2_l(const double* __restrict__ Ml, const double (&z)[P]) {
   double acc = 0.0;
@@ -170,7 +193,8 @@ __device__ inline void dist_rows(const T* __restrict__ X, int64_t ld, int p, int
               for (int j = 0; j < P; ++j)
                 z[r][j] = (double)xs[(tid + r * CH) * S::PP + j] - mul[q * P + j];
             double acc[S::R];
-            tri_norm2_r<P, S::R>(Ml + q * (P * (P + 1) / 2), z, acc);
+            if constexpr (NI == 1 && S::R == 1) acc[0] = tri_norm2_g<P>(Mg[q], ldm, p, z[0]);
+            else tri_norm2_r<P, S::R>(Ml + q * (P * (P + 1) / 2), z, acc);
 #pragma unroll
             for (int r = 0; r < S::R; ++r)
               if (tid + r * CH < n) emit(q, rc + tid + r * CH, acc[r]);
