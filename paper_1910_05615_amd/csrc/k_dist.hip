@@ -397,7 +397,10 @@ hipError_t launch_score(int bucket, int dtype, const void* X, int64_t n, int64_t
                         const double* mu, const double* M, int ldm, double cut, double* dist,
                         uint8_t* flag, hipStream_t s) {
   if (ldm != p) return hipErrorInvalidValue;   // the factor is p x p, row stride p
-  const int tile_rows = 2048;
+  // one 256-row chunk per block keeps the most loads in flight for narrow
+  // rows (1M x 20: 21 us against 29 us with 2,048-row tiles); wide factors
+  // are cheaper to stage in fewer, longer blocks (10M x 40: 675 against 760)
+  const int tile_rows = bucket <= 24 ? 256 : 2048;
   const int64_t nb = (n + tile_rows - 1) / tile_rows;
   if (nb <= 0) return hipSuccess;
 #define CASE(PB)                                                                                \
