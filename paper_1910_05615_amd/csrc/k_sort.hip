@@ -13,6 +13,89 @@ namespace rtd {
 
 namespace {
 
+// ---------------------------------------------------------------------------
+// Wave-wide scans and reductions on DPP (data movement inside the VALU, no
+// LDS round trip): Hillis-Steele within each row of 16 lanes (row_shr 1, 2,
+// 4, 8), then the row totals carried across rows (row_bcast 15 and 31).
+// Lanes whose source is out of range or disabled read the identity.  Fixed
+// order of operations, so the results are deterministic.
+// ---------------------------------------------------------------------------
+template <int CTRL, int RM>
+__device__ inline int dpp_i(int v, int ident) {
+  return __builtin_amdgcn_update_dpp(ident, v, CTRL, RM, 0xf, false);
+}
+template <int CTRL, int RM>
+__device__ inline double dpp_d(double v, double ident) {
+  const long long b = __double_as_longlong(v), o = __double_as_longlong(ident);
+  const int lo = dpp_i<CTRL, RM>((int)b, (int)o);
+  const int hi = dpp_i<CTRL, RM>((int)(b >> 32), (int)(o >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int CTRL, int RM>
+__device__ inline int64_t dpp_l(int64_t v, int64_t ident) {
+  const int lo = dpp_i<CTRL, RM>((int)v, (int)ident);
+  const int hi = dpp_i<CTRL, RM>((int)(v >> 32), (int)(ident >> 32));
+  return ((int64_t)hi << 32) | (int64_t)(unsigned)lo;
+}
+
+// inclusive prefix sum over the wave's 64 lanes
+__device__ inline int wave_incl_sum(int x) {
+  x += dpp_i<0x111, 0xf>(x, 0);
+  x += dpp_i<0x112, 0xf>(x, 0);
+  x += dpp_i<0x114, 0xf>(x, 0);
+  x += dpp_i<0x118, 0xf>(x, 0);
+  x += dpp_i<0x142, 0xa>(x, 0);
+  x += dpp_i<0x143, 0xc>(x, 0);
+  return x;
+}
+__device__ inline double wave_incl_sum(double x) {
+  x += dpp_d<0x111, 0xf>(x, 0.0);
+  x += dpp_d<0x112, 0xf>(x, 0.0);
+  x += dpp_d<0x114, 0xf>(x, 0.0);
+  x += dpp_d<0x118, 0xf>(x, 0.0);
+  x += dpp_d<0x142, 0xa>(x, 0.0);
+  x += dpp_d<0x143, 0xc>(x, 0.0);
+  return x;
+}
+// sum over the wave, in every lane
+__device__ inline double wave_sum(double x) {
+  const double t = wave_incl_sum(x);
+  const long long b = __double_as_longlong(t);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// (value, index) with the smallest value, ties to the smallest index; index
+// -1 marks "none".  The result is valid in every lane.
+__device__ inline bool argmin_takes(double b2, int64_t j2, double b, int64_t j) {
+  return j2 >= 0 && (j < 0 || b2 < b || (b2 == b && j2 < j));
+}
+template <int CTRL, int RM>
+__device__ inline void argmin_step(double& b, int64_t& j) {
+  const double b2 = dpp_d<CTRL, RM>(b, INFINITY);
+  const int64_t j2 = dpp_l<CTRL, RM>(j, -1);
+  if (argmin_takes(b2, j2, b, j)) {
+    b = b2;
+    j = j2;
+  }
+}
+__device__ inline void wave_argmin(double& b, int64_t& j) {
+  argmin_step<0x111, 0xf>(b, j);
+  argmin_step<0x112, 0xf>(b, j);
+  argmin_step<0x114, 0xf>(b, j);
+  argmin_step<0x118, 0xf>(b, j);
+  argmin_step<0x142, 0xa>(b, j);
+  argmin_step<0x143, 0xc>(b, j);
+  const long long bb = __double_as_longlong(b);
+  const int blo = __builtin_amdgcn_readlane((int)bb, 63);
+  const int bhi = __builtin_amdgcn_readlane((int)(bb >> 32), 63);
+  b = __longlong_as_double(((long long)bhi << 32) | (long long)(unsigned)blo);
+  const int jlo = __builtin_amdgcn_readlane((int)j, 63);
+  const int jhi = __builtin_amdgcn_readlane((int)(j >> 32), 63);
+  j = ((int64_t)jhi << 32) | (int64_t)(unsigned)jlo;
+}
+
 constexpr int RS_NT = 256;           // threads per tile
 constexpr int RS_ITEMS = 16;         // keys per thread
 constexpr int RS_TILE = RS_NT * RS_ITEMS;
@@ -73,11 +156,7 @@ __global__ __launch_bounds__(SCAN_NT) void k_rs_scan(const int32_t* __restrict__
     const int g0 = gt[0][d], g1 = gt[1][d], g2 = gt[2][d], g3 = gt[3][d];
     const int T = g0 + g1 + g2 + g3;
     int x = T;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
-    }
+    x = wave_incl_sum(x);
     if (lane == 63) wsum[w] = x;
     const int ex = x - T;
     gt[0][d] = ex;
@@ -164,11 +243,7 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K* __restrict__ kin,
       acc += v;
     }
     int x = acc;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
-    }
+    x = wave_incl_sum(x);
     if (lane == 63) wtot[w] = x;
     __syncthreads();
     int ex = x - acc;
@@ -251,15 +326,9 @@ __device__ inline void block_excl_prefix(double (&v)[NV], double* __restrict__ r
   double ex[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    double x = v[k];
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const double y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
-    }
+    const double x = wave_incl_sum(v[k]);
     if (lane == 63) red[k * NW + w] = x;
-    const double e = __shfl_up(x, 1, 64);
-    ex[k] = lane == 0 ? 0.0 : e;
+    ex[k] = dpp_d<0x138, 0xf>(x, 0.0);   // wave_shr 1: the previous lane's, 0 in lane 0
   }
   __syncthreads();
 #pragma unroll
@@ -279,9 +348,7 @@ __device__ inline void block_sums(double (&v)[NV], double* __restrict__ red) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    double x = v[k];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    const double x = wave_sum(v[k]);
     if (lane == 0) red[k * NW + w] = x;
   }
   __syncthreads();
@@ -467,15 +534,7 @@ __device__ __forceinline__ SegStat segstat_body(const K* __restrict__ v, int64_t
   double* __restrict__ rb = red + 64;
   {
     const int64_t own = bj;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double c2 = __shfl_xor(best, o, 64);
-      const int64_t j2 = __shfl_xor(bj, o, 64);
-      if (j2 >= 0 && (bj < 0 || c2 < best || (c2 == best && j2 < bj))) {
-        best = c2;
-        bj = j2;
-      }
-    }
+    wave_argmin(best, bj);
     if (own >= 0 && own == bj) {
       rb[SS_WV + w] = (b2 - b1 * b1 / hd) / (hd - 1.0);
       rb[2 * SS_WV + w] = b1;
@@ -518,9 +577,7 @@ __device__ __forceinline__ SegStat segstat_body(const K* __restrict__ v, int64_t
   double* __restrict__ rs = red + 128;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    double x = cs[k];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    const double x = wave_sum(cs[k]);
     if (lane == 0) rs[k * SS_WV + w] = x;
   }
   __syncthreads();
@@ -660,11 +717,7 @@ __device__ inline void lds_radix_pass(K (&kv)[KPT], int shift, K* __restrict__ s
     const int t0 = gs[d], t1 = gs[256 + d], t2 = gs[512 + d], t3 = gs[768 + d];
     const int tot = t0 + t1 + t2 + t3;
     int x = tot;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
-    }
+    x = wave_incl_sum(x);
     if (lane == 63) wt[w] = x;
     const int ex = x - tot;   // exclusive within this wave's 64 digits
     gs[d] = ex;
@@ -991,15 +1044,7 @@ __global__ __launch_bounds__(MB_NT) void k_mb_window(const K* __restrict__ keys,
     }
   }
   // smallest criterion, ties to the lowest start (an exact min)
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double b2 = __shfl_xor(best, o, 64);
-    const int64_t j2 = __shfl_xor(bj, o, 64);
-    if (j2 >= 0 && (bj < 0 || b2 < best || (b2 == best && j2 < bj))) {
-      best = b2;
-      bj = j2;
-    }
-  }
+  wave_argmin(best, bj);
   if (lane == 0) {
     sb[w] = best;
     sj[w] = bj;
@@ -1053,12 +1098,7 @@ __global__ __launch_bounds__(MB_NT) void k_mb_mid(const K* __restrict__ keys,
       const double b2 = wbest[t];
       if (j2 >= 0 && (j < 0 || b2 < b || (b2 == b && j2 < j))) { b = b2; j = j2; }
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double b2 = __shfl_xor(b, o, 64);
-      const int64_t j2 = __shfl_xor(j, o, 64);
-      if (j2 >= 0 && (j < 0 || b2 < b || (b2 == b && j2 < j))) { b = b2; j = j2; }
-    }
+    wave_argmin(b, j);
     if ((threadIdx.x & 63) == 0) {
       red[threadIdx.x >> 6] = b;
       reinterpret_cast<int64_t*>(red)[MB_WV + (threadIdx.x >> 6)] = j;
