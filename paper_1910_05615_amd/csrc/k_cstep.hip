@@ -1,6 +1,7 @@
 // Per-item kernels of the C-step loop: exact h-subset selection, and the
 // float64 statistics / Cholesky / condition-monitor step.
 #include "common.h"
+#include "wave.h"
 
 namespace rtd {
 
@@ -19,11 +20,7 @@ __device__ inline int block_excl_scan(int v, int* wtot, int& total) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int x = v;
   // inclusive wave scan
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
+  x = wave_incl_sum(x);
   if (lane == 63) wtot[wv] = x;
   __syncthreads();
   int off = 0;
@@ -166,11 +163,7 @@ __device__ inline int scan256_excl(int* __restrict__ v, int n, int* __restrict__
   if (tid < 256) {
     own = tid < n ? v[tid] : 0;
     x = own;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
-    }
+    x = wave_incl_sum(x);
     if (lane == 63) wsum[w] = x;
   }
   __syncthreads();
@@ -411,8 +404,7 @@ __global__ __launch_bounds__(64) void k_finalize(const ItemDesc* __restrict__ it
         n1 += fabs(a[j]);
       }
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) n1 = fmax(n1, __shfl_xor(n1, o, 64));
+n1 = wave_max(n1);
   // Cholesky: column k of L from row k (lane k) and each lane's own row
   double diag = 1.0;   // L[lane][lane]
 #pragma unroll
@@ -450,8 +442,7 @@ __global__ __launch_bounds__(64) void k_finalize(const ItemDesc* __restrict__ it
     }
   }
   if (!in) n2 = 0.0;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) n2 = fmax(n2, __shfl_xor(n2, o, 64));
+n2 = wave_max(n2);
   double* __restrict__ linv = A.linv + (size_t)it * MSTRIDE;
   double* __restrict__ mt = A.mtri + (size_t)it * MSTRIDE;
 #pragma unroll

@@ -3,6 +3,7 @@
 // per-block float64 steps, robust aggregation and reweighting.
 #include "../../include/rtdetmcd.h"
 #include "fitk.h"
+#include "wave.h"
 
 namespace rtd {
 
@@ -238,11 +239,8 @@ __global__ __launch_bounds__(64) void k_eig(const ItemDesc* __restrict__ items, 
         if (j != lane) off = fma(x, x, off);
         else dia = fma(x, x, dia);
       }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      off += __shfl_xor(off, o, 64);
-      dia += __shfl_xor(dia, o, 64);
-    }
+    off = wave_sum(off);
+    dia = wave_sum(dia);
     // converged once the off-diagonal mass is about 1e-14 of the diagonal's
     // (the rounding floor of the rotations is near 1e-16 per entry, so a much
     // tighter bound may never be met); uniform: every lane holds the sums

@@ -5,6 +5,7 @@
 // contributes exact zeros).
 #include "common.h"
 #include "fitk.h"
+#include "wave.h"
 
 namespace rtd {
 
@@ -255,8 +256,7 @@ __global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items
       }
       if (MODE == SSCP_GSSCM) {
         // weight xi^2(||z||) of eq. (LR); the 16 lanes of a row add their parts
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) r2 += __shfl_xor(r2, o, 16);
+        r2 = row16_sum(r2);
         const double rr = sqrt(r2);
         double xi;
         if (gB <= gA) xi = (rr <= gA) ? 1.0 : 0.0;

@@ -6,6 +6,7 @@
 //   * the GSSCM cutoffs A, B of the linearly redescending weight (eq. LR).
 #include "common.h"
 #include "sortseg.h"
+#include "wave.h"
 
 #include <type_traits>
 
@@ -13,88 +14,6 @@ namespace rtd {
 
 namespace {
 
-// ---------------------------------------------------------------------------
-// Wave-wide scans and reductions on DPP (data movement inside the VALU, no
-// LDS round trip): Hillis-Steele within each row of 16 lanes (row_shr 1, 2,
-// 4, 8), then the row totals carried across rows (row_bcast 15 and 31).
-// Lanes whose source is out of range or disabled read the identity.  Fixed
-// order of operations, so the results are deterministic.
-// ---------------------------------------------------------------------------
-template <int CTRL, int RM>
-__device__ inline int dpp_i(int v, int ident) {
-  return __builtin_amdgcn_update_dpp(ident, v, CTRL, RM, 0xf, false);
-}
-template <int CTRL, int RM>
-__device__ inline double dpp_d(double v, double ident) {
-  const long long b = __double_as_longlong(v), o = __double_as_longlong(ident);
-  const int lo = dpp_i<CTRL, RM>((int)b, (int)o);
-  const int hi = dpp_i<CTRL, RM>((int)(b >> 32), (int)(o >> 32));
-  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-template <int CTRL, int RM>
-__device__ inline int64_t dpp_l(int64_t v, int64_t ident) {
-  const int lo = dpp_i<CTRL, RM>((int)v, (int)ident);
-  const int hi = dpp_i<CTRL, RM>((int)(v >> 32), (int)(ident >> 32));
-  return ((int64_t)hi << 32) | (int64_t)(unsigned)lo;
-}
-
-// inclusive prefix sum over the wave's 64 lanes
-__device__ inline int wave_incl_sum(int x) {
-  x += dpp_i<0x111, 0xf>(x, 0);
-  x += dpp_i<0x112, 0xf>(x, 0);
-  x += dpp_i<0x114, 0xf>(x, 0);
-  x += dpp_i<0x118, 0xf>(x, 0);
-  x += dpp_i<0x142, 0xa>(x, 0);
-  x += dpp_i<0x143, 0xc>(x, 0);
-  return x;
-}
-__device__ inline double wave_incl_sum(double x) {
-  x += dpp_d<0x111, 0xf>(x, 0.0);
-  x += dpp_d<0x112, 0xf>(x, 0.0);
-  x += dpp_d<0x114, 0xf>(x, 0.0);
-  x += dpp_d<0x118, 0xf>(x, 0.0);
-  x += dpp_d<0x142, 0xa>(x, 0.0);
-  x += dpp_d<0x143, 0xc>(x, 0.0);
-  return x;
-}
-// sum over the wave, in every lane
-__device__ inline double wave_sum(double x) {
-  const double t = wave_incl_sum(x);
-  const long long b = __double_as_longlong(t);
-  const int lo = __builtin_amdgcn_readlane((int)b, 63);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
-  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
-// (value, index) with the smallest value, ties to the smallest index; index
-// -1 marks "none".  The result is valid in every lane.
-__device__ inline bool argmin_takes(double b2, int64_t j2, double b, int64_t j) {
-  return j2 >= 0 && (j < 0 || b2 < b || (b2 == b && j2 < j));
-}
-template <int CTRL, int RM>
-__device__ inline void argmin_step(double& b, int64_t& j) {
-  const double b2 = dpp_d<CTRL, RM>(b, INFINITY);
-  const int64_t j2 = dpp_l<CTRL, RM>(j, -1);
-  if (argmin_takes(b2, j2, b, j)) {
-    b = b2;
-    j = j2;
-  }
-}
-__device__ inline void wave_argmin(double& b, int64_t& j) {
-  argmin_step<0x111, 0xf>(b, j);
-  argmin_step<0x112, 0xf>(b, j);
-  argmin_step<0x114, 0xf>(b, j);
-  argmin_step<0x118, 0xf>(b, j);
-  argmin_step<0x142, 0xa>(b, j);
-  argmin_step<0x143, 0xc>(b, j);
-  const long long bb = __double_as_longlong(b);
-  const int blo = __builtin_amdgcn_readlane((int)bb, 63);
-  const int bhi = __builtin_amdgcn_readlane((int)(bb >> 32), 63);
-  b = __longlong_as_double(((long long)bhi << 32) | (long long)(unsigned)blo);
-  const int jlo = __builtin_amdgcn_readlane((int)j, 63);
-  const int jhi = __builtin_amdgcn_readlane((int)(j >> 32), 63);
-  j = ((int64_t)jhi << 32) | (int64_t)(unsigned)jlo;
-}
 
 constexpr int RS_NT = 256;           // threads per tile
 constexpr int RS_ITEMS = 16;         // keys per thread
