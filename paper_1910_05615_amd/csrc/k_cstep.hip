@@ -368,14 +368,20 @@ __global__ __launch_bounds__(64) void k_finalize(const ItemDesc* __restrict__ it
     // tile partials already collapsed into the first tile's
     const double* __restrict__ P0 = A.part + (size_t)D.tile0 * PSTRIDE;
     const double dm = in ? P0[1 + lane] / h : 0.0;   // mu_new - c (pivot-centred sum / h)
+    // every load first (a loop without stores, so they all go out at once),
+    // then the update and the stores
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const int hi = lane >= j ? lane : j, lo = lane >= j ? j : lane;
+      const bool ok = in && j < p;
+      const double old = (ok && !full) ? lam[lane * PMAX + j] : 0.0;
+      a[j] = ok ? old + P0[1 + PMAX + hi * (hi + 1) / 2 + lo] : 0.0;
+    }
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       const double dmj = lane_bcast(dm, j), scj = lane_bcast(sc, j);
       if (in && j < p) {
-        const int hi = lane >= j ? lane : j, lo = lane >= j ? j : lane;
-        const double sj = P0[1 + PMAX + hi * (hi + 1) / 2 + lo];
-        const double old = full ? 0.0 : lam[lane * PMAX + j];
-        const double v = old + sj - h * (dm * dmj);
+        const double v = a[j] - h * (dm * dmj);
         lam[lane * PMAX + j] = v;
         a[j] = v / (sc * scj) / (h - 1.0);
       } else {

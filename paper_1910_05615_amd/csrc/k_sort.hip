@@ -23,8 +23,10 @@ constexpr int RS_WAVES = RS_NT / 64;
 template <typename K>
 __device__ inline int digit_of(K k, int shift) { return (int)((k >> shift) & (K)0xFF); }
 
-// Per-tile digit counts of the pass at `shift`.
-template <typename K>
+// Per-tile digit counts of the pass at `shift`.  PEEL (the top digit of
+// double keys: very few distinct values) adds one count per distinct digit
+// of a wave's 64 keys instead of one atomic per key on one or two counters.
+template <typename K, bool PEEL>
 __global__ __launch_bounds__(RS_NT) void k_rs_count(const K* __restrict__ keys,
                                                     const SegTile* __restrict__ tiles,
                                                     const int64_t* __restrict__ seg_off,
@@ -39,7 +41,20 @@ __global__ __launch_bounds__(RS_NT) void k_rs_count(const K* __restrict__ keys,
 #pragma unroll
   for (int i = 0; i < RS_ITEMS; ++i) {
     const int64_t k = base + i * RS_NT + threadIdx.x;
-    if (k < end) atomicAdd(&hist[digit_of(keys[k], shift)], 1);
+    if constexpr (PEEL) {
+      const bool valid = k < end;
+      const int d = valid ? digit_of(keys[k], shift) : 0;
+      uint64_t left = __ballot(valid);
+      while (left) {
+        const int lead = __ffsll((long long)left) - 1;
+        const int dl = __builtin_amdgcn_readlane(d, lead);
+        const uint64_t mm = __ballot(valid && d == dl);
+        if ((int)(threadIdx.x & 63) == lead) atomicAdd(&hist[dl], __popcll(mm));
+        left &= ~mm;
+      }
+    } else {
+      if (k < end) atomicAdd(&hist[digit_of(keys[k], shift)], 1);
+    }
   }
   __syncthreads();
   counts[(size_t)blockIdx.x * 256 + threadIdx.x] = hist[threadIdx.x];
@@ -102,9 +117,11 @@ __global__ __launch_bounds__(SCAN_NT) void k_rs_scan(const int32_t* __restrict__
 // tile, visited 64 at a time in index order.  Equal digits are ranked within
 // a wave by LDS atomics on per-(wave, digit) counters (their results follow
 // lane order on this hardware) or, with SAFE, by eight ballots (stable by
-// construction).  The tile is then ordered by digit in LDS, so that the
-// global writes of each digit run are contiguous.
-template <typename K, bool SAFE>
+// construction).  PEEL ranks the top digit (few distinct values, so atomics
+// would serialise) with one ballot per distinct digit.  The tile is then
+// ordered by digit in LDS, so that the global writes of each digit run are
+// contiguous.
+template <typename K, bool SAFE, bool PEEL>
 __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K* __restrict__ kin,
                                                       K* __restrict__ kout,
                                                       const SegTile* __restrict__ tiles,
@@ -146,6 +163,19 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K* __restrict__ kin,
       const int cur = wc[w][d];
       rk[i] = cur + before;
       if (valid && before == 0) wc[w][d] = cur + __popcll(match);
+    } else if constexpr (PEEL) {
+      uint64_t left = __ballot(valid);
+      int rank = 0;
+      while (left) {
+        const int lead = __ffsll((long long)left) - 1;
+        const int dl = __builtin_amdgcn_readlane(d, lead);
+        const uint64_t mm = __ballot(valid && d == dl);
+        const int cur = wc[w][dl];
+        if (valid && d == dl) rank = cur + __popcll(mm & below);
+        if (lane == lead) wc[w][dl] = cur + __popcll(mm);
+        left &= ~mm;
+      }
+      rk[i] = rank;
     } else {
       rk[i] = valid ? atomicAdd(&wc[w][d], 1) : 0;
     }
@@ -1122,16 +1152,27 @@ hipError_t sort_segments_t(SortPlan& P, hipStream_t s) {
   K* b = static_cast<K*>(P.tmp);
   for (int ps = 0; ps < (int)sizeof(K); ++ps) {
     const int shift = 8 * ps;
-    hipLaunchKernelGGL((k_rs_count<K>), dim3(P.ntiles), dim3(RS_NT), 0, s, a, P.tiles,
-                       P.seg_off, P.seg_len, shift, P.counts);
+    // the top byte of a double's key (sign and the high 7 of 11 exponent
+    // bits) takes one or two values in practice: peel it; a float's (high 7
+    // of 8 exponent bits) spreads enough for atomics
+    const bool top = sizeof(K) == 8 && ps == (int)sizeof(K) - 1;
+    if (top)
+      hipLaunchKernelGGL((k_rs_count<K, true>), dim3(P.ntiles), dim3(RS_NT), 0, s, a, P.tiles,
+                         P.seg_off, P.seg_len, shift, P.counts);
+    else
+      hipLaunchKernelGGL((k_rs_count<K, false>), dim3(P.ntiles), dim3(RS_NT), 0, s, a, P.tiles,
+                         P.seg_off, P.seg_len, shift, P.counts);
     hipLaunchKernelGGL(k_rs_scan, dim3(P.nseg), dim3(SCAN_NT), 0, s, P.counts, P.seg_tile0,
                        P.tile_first, P.offs);
     if (P.safe)
-      hipLaunchKernelGGL((k_rs_scatter<K, true>), dim3(P.ntiles), dim3(RS_NT), 0, s, a, b,
-                         P.tiles, P.seg_off, P.seg_len, shift, P.offs);
+      hipLaunchKernelGGL((k_rs_scatter<K, true, false>), dim3(P.ntiles), dim3(RS_NT), 0, s, a,
+                         b, P.tiles, P.seg_off, P.seg_len, shift, P.offs);
+    else if (top)
+      hipLaunchKernelGGL((k_rs_scatter<K, false, true>), dim3(P.ntiles), dim3(RS_NT), 0, s, a,
+                         b, P.tiles, P.seg_off, P.seg_len, shift, P.offs);
     else
-      hipLaunchKernelGGL((k_rs_scatter<K, false>), dim3(P.ntiles), dim3(RS_NT), 0, s, a, b,
-                         P.tiles, P.seg_off, P.seg_len, shift, P.offs);
+      hipLaunchKernelGGL((k_rs_scatter<K, false, false>), dim3(P.ntiles), dim3(RS_NT), 0, s, a,
+                         b, P.tiles, P.seg_off, P.seg_len, shift, P.offs);
     K* t = a;
     a = b;
     b = t;
