@@ -59,8 +59,8 @@ def _traffic_from_profile(kernel_src: str):
 
 def _roofline(R, torch, X, F, dev, reps):
     """The distance kernel (float64 arithmetic on float32 rows) over all n rows
-    against the fitted (mu, Sigma): the same row computation as every C-step
-    distance pass, launched alone through rtdetmcd_score and timed with HIP
+    against the fitted (mu, Sigma): the row code of the fit's single-factor
+    distance passes, launched alone through rtdetmcd_score and timed with HIP
     events on the stream it is launched on."""
     Lc = torch.linalg.cholesky(F.sigma.cpu())
     Linv = torch.linalg.inv(Lc).to(dev).contiguous()
@@ -74,7 +74,7 @@ def _roofline(R, torch, X, F, dev, reps):
     alg_bytes = N * bytes_per_row
     achieved = alg_bytes / t_k / 1e9
     flops = N * (P * (P + 1) + 3 * P)       # triangular product, squares, centring
-    return {"kernel": "k_score (distance + flag; same row code as the C-step distance pass)",
+    return {"kernel": "k_score_direct (distance + flag, one row per thread)",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": _traffic_from_profile("paper_1910_05615_amd/csrc/k_dist.hip"),

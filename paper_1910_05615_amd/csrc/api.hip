@@ -196,12 +196,13 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
     int64_t max_m = 0;
     for (int i = first; i < first + n; ++i) max_m = std::max(max_m, S.items[i].m);
     const int max_nt = S.max_ntiles(first, first + n);
+    const bool dense = S.rows_dense(first, first + n, bucket);
     RTD_HIP(launch_finalize(bucket, D.items, D.A, first, n, 1, maxs, o.kappa_max, st));
     const int R = std::max(1, o.rounds_per_sync);
     // one C-step of every active item
     // one C-step of every active item; the selection zeroes the active count
     auto step = [&](hipStream_t s) -> rtdetmcd_status {
-      RTD_HIP(launch_dist(bucket, dtype, pairs ? 2 : 1, D.items, dtl + dt0, dtn, DIST_TILE,
+      RTD_HIP(launch_dist(bucket, dtype, dense, pairs ? 2 : 1, D.items, dtl + dt0, dtn, DIST_TILE,
                           D.A.mtri, D.A.mux, D.A.status, D.A.d2, s));
       RTD_HIP(launch_select(D.items, D.A, first, n, max_m, o.cstep_mode, s, 1));
       RTD_HIP(launch_sscp(bucket, dtype, SSCP_CSTEP, D.items, D.A, D.stiles + st0, stn,
@@ -215,7 +216,8 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
       // whole rounds of R steps replayed from a captured graph on the
       // handle's replay stream, ordered after / before the caller's stream
       const int64_t key[16] = {(int64_t)(uintptr_t)ctx->ws, (int64_t)(uintptr_t)D.items,
-                               (int64_t)(uintptr_t)dtl, bucket, dtype, first, n, pairs ? 2 : 1,
+                               (int64_t)(uintptr_t)dtl, bucket, dtype, first, n,
+                               (pairs ? 2 : 1) + (dense ? 4 : 0),
                                dt0, dtn, st0, stn, max_nt, max_m,
                                (int64_t)o.cstep_mode * 1000000 + maxs,
                                (int64_t)R * 4096 + (int64_t)(o.kappa_max * 16.0)};
@@ -252,7 +254,8 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
     RTD_HIP(hipStreamSynchronize(st));
     if (*pin_flag != ACTIVE) continue;
     for (int t = 1; t <= maxs; ++t) {
-      RTD_HIP(launch_dist(bucket, dtype, 1, D.items, D.dtiles + S.dt_first[i], S.dt_count[i],
+      RTD_HIP(launch_dist(bucket, dtype, S.rows_dense(i, i + 1, bucket), 1, D.items,
+                          D.dtiles + S.dt_first[i], S.dt_count[i],
                           DIST_TILE, D.A.mtri, D.A.mux, D.A.status, D.A.d2, st));
       RTD_HIP(launch_select(D.items, D.A, i, 1, d.m, o.cstep_mode, st));
       RTD_HIP(launch_sscp(bucket, dtype, SSCP_CSTEP, D.items, D.A, D.stiles + d.tile0,
@@ -467,7 +470,8 @@ rtdetmcd_status rtdetmcd_distances(rtdetmcd_handle ctx, const void* X, int32_t d
   RTD_HIP(hipGetLastError());
   RTD_HIP(launch_chol_factor(L, p, D.A.mtri, ctx->stream));
   // the distance kernel writes d2 + roff with roff = 0
-  RTD_HIP(launch_dist(bucket_of(p), dtype, 1, D.items, D.dtiles, (int)S.dtiles.size(), DIST_TILE,
+  RTD_HIP(launch_dist(bucket_of(p), dtype, S.rows_dense(0, (int)S.items.size(), bucket_of(p)), 1,
+                      D.items, D.dtiles, (int)S.dtiles.size(), DIST_TILE,
                       D.A.mtri, D.A.mux, nullptr, d2, ctx->stream));
   return RTDETMCD_OK;
 }

@@ -92,7 +92,21 @@ inline int bucket_of(int p) {
 // Launch helpers implemented in the .hip files (all enqueue on `s`).
 // ipt = 2: every tile names the first of two items (the two starts of a
 // block) that share their rows; ipt = 1: one item per tile.
-hipError_t launch_dist(int bucket, int dtype, int ipt, const ItemDesc* items, const Tile* tiles,
+// Largest power-of-two load (16, 8 or the element size) that divides a row of
+// `bucket` elements: the distance kernels read whole rows with it.
+inline int dist_row_align(int bucket, int dtype) {
+  const int es = dtype == 0 ? 4 : 8;
+  const int bytes = bucket * es;
+  return bytes % 16 == 0 ? 16 : bytes % 8 == 0 ? 8 : es;
+}
+inline bool rows_dense_at(const void* X, int64_t ld, int p, int dtype, int bucket) {
+  return p == bucket && ld == p &&
+         reinterpret_cast<uintptr_t>(X) % (uintptr_t)dist_row_align(bucket, dtype) == 0;
+}
+// dense: every item of the launch satisfies rows_dense_at (the kernels then
+// skip the per-element path for narrower or strided rows).
+hipError_t launch_dist(int bucket, int dtype, int dense, int ipt, const ItemDesc* items,
+                       const Tile* tiles,
                        int ntiles, int tile_rows, const double* mtri, const double* mux,
                        const int32_t* status, double* d2, hipStream_t s);
 // max_m: largest m among the items (picks the register-resident variant).

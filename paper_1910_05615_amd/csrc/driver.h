@@ -94,6 +94,14 @@ struct ItemSet {
     for (int i = a; i < b; ++i) r = items[i].ntiles > r ? items[i].ntiles : r;
     return r;
   }
+  // Items [a, b) all hold dense rows of exactly `bucket` columns (ld == p ==
+  // bucket) at a base aligned for whole-row vector loads: the distance
+  // kernels then take their row-load path only.
+  bool rows_dense(int a, int b, int bucket) const {
+    for (int i = a; i < b; ++i)
+      if (!rows_dense_at(items[i].X, items[i].ld, items[i].p, items[i].dtype, bucket)) return false;
+    return true;
+  }
 };
 
 // Device copies of an ItemSet and its state arrays inside the workspace.

@@ -493,8 +493,9 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     const int a = g.ds0, b = g.ds1;
     const int dt0 = G.dt_first[a], dtn = G.dt_first[b - 1] + G.dt_count[b - 1] - dt0;
     const int st0 = G.items[a].tile0, stn = G.items[b - 1].tile0 + G.items[b - 1].ntiles - st0;
-    RTD_HIP(launch_dist(g.bucket, g.dtype, 1, GD.items, GD.dtiles + dt0, dtn, DIST_TILE, GD.A.mtri,
-                        GD.A.mux, nullptr, GD.A.d2, st));
+    RTD_HIP(launch_dist(g.bucket, g.dtype, G.rows_dense(a, b, g.bucket), 1, GD.items,
+                        GD.dtiles + dt0, dtn, DIST_TILE, GD.A.mtri, GD.A.mux, nullptr, GD.A.d2,
+                        st));
     RTD_HIP(launch_sscp(g.bucket, g.dtype, SSCP_D2CUT, GD.items, GD.A, GD.stiles + st0, stn,
                         SSCP_TILE, nullptr, dchi, st));
     RTD_HIP(launch_collapse(GD.items, GD.A, a, b - a, G.max_ntiles(a, b), 0, SSCP_TILE, st));
@@ -508,7 +509,8 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   for (const Group& g : groups) {
     const int a = ND + g.ds0, b = ND + g.ds1;
     const int dt0 = G.dt_first[a], dtn = G.dt_first[b - 1] + G.dt_count[b - 1] - dt0;
-    RTD_HIP(launch_final_dist(g.bucket, g.dtype, GD.items, GD.dtiles + dt0, dtn, DIST_TILE,
+    RTD_HIP(launch_final_dist(g.bucket, g.dtype, G.rows_dense(a, b, g.bucket), GD.items,
+                              GD.dtiles + dt0, dtn, DIST_TILE,
                               GD.A.mtri, GD.A.mux, GD.A.d2, dds, douts, st));
   }
   RTD_HIP(launch_hsub(CD.items, CD.A, F, dds, douts, 0, NB, st));

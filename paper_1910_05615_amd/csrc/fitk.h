@@ -72,7 +72,8 @@ hipError_t launch_pool(DsInfo* ds, ItemArrays G, FitArrays F, int first_ds, int 
                        hipStream_t s);
 hipError_t launch_rew(DsInfo* ds, const ItemDesc* gitems, ItemArrays G, FitArrays F, int first_ds,
                       int nds, hipStream_t s);
-hipError_t launch_final_dist(int bucket, int dtype, const ItemDesc* items, const Tile* tiles,
+hipError_t launch_final_dist(int bucket, int dtype, int dense, const ItemDesc* items,
+                             const Tile* tiles,
                              int ntiles, int tile_rows, const double* mtri, const double* mux,
                              const double* d2, const DsInfo* ds,
                              const struct rtdetmcd_out* outs, hipStream_t s);

@@ -2,14 +2,18 @@
 // d2 = ||M (x - mu)||^2 with M the inverse Cholesky factor (folded with the
 // standardisation scales inside the fit).
 //
-// Rows stream through LDS in chunks loaded with 16-byte coalesced loads, the
-// next chunk's loads in flight while the current one is evaluated in
-// float64.  With one factor per launch (scoring, final distances) M is read
-// from global memory at uniform offsets, so the loads go through the scalar
-// unit and each FMA takes its entry from SGPRs; the C-step variant, which
-// evaluates the two starts of a block from one read of each row, stages both
-// factors (packed, zero-padded to the p-bucket) in LDS and reads them as
-// broadcasts (two factors in SGPRs measured slower).  mu is staged in LDS.
+// Up to p = 40 every thread reads its own row straight into registers (16-
+// or 8-byte loads when the row size and base allow, else one load per
+// element), and each block takes one 256-row slice, so no LDS, no barrier
+// and a full chip of short blocks.  The factor and the centre are read at
+// uniform offsets: the loads go through the scalar unit and every FMA takes
+// its M entry from scalar registers.  One factor is evaluated column by
+// column (y_i += M_ij z_j over j, the p partial sums independent of one
+// another, each still summed in order of j); the C-step pair (both starts of
+// a block from one read of each row) evaluates each factor row by row, and
+// goes direct up to p = 24.  Wider pairs (p = 32, 40) and all of p = 48, 64
+// stream rows through LDS in chunks loaded with 16-byte coalesced loads, the
+// factors staged in LDS and read as broadcasts.
 #include <stdint.h>
 
 #include "common.h"
@@ -240,6 +244,198 @@ __device__ inline void dist_rows(const T* __restrict__ X, int64_t ld, int p, int
   }
 }
 
+// ---------------------------------------------------------------------------
+// Direct row evaluation (p <= 40).
+
+constexpr int DROWS = 256;     // rows per block of the direct kernels
+constexpr int DIRECT_MAX = 40; // widest bucket evaluated directly
+
+template <typename T, int P>
+struct RowVec {
+  static constexpr int BYTES = P * (int)sizeof(T);
+  static constexpr int VB = BYTES % 16 == 0 ? 16 : BYTES % 8 == 0 ? 8 : (int)sizeof(T);
+  static constexpr int E = VB / (int)sizeof(T);   // elements per load
+};
+
+// Row r of a dense, VB-aligned row-major matrix of P columns.
+template <typename T, int P>
+__device__ inline void load_row_vec(const T* __restrict__ xr, T (&v)[P]) {
+  constexpr int E = RowVec<T, P>::E;
+  if constexpr (E == 1) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) v[j] = xr[j];
+  } else {
+    typedef T V __attribute__((ext_vector_type(E)));
+    const V* __restrict__ s = reinterpret_cast<const V*>(xr);
+#pragma unroll
+    for (int u = 0; u < P / E; ++u) {
+      const V t = s[u];
+#pragma unroll
+      for (int c = 0; c < E; ++c) v[u * E + c] = t[c];
+    }
+  }
+}
+
+// ||M (v - mu)||^2 column by column: y_i accumulates M_ij z_j in order of j
+// (the same operations, in the same order per y_i, as the row-wise form).
+template <typename T, int P>
+__device__ inline double col_norm2_g(const double* __restrict__ Mg, int ldm, int p,
+                                     const double* __restrict__ mu, const T (&v)[P]) {
+  double y[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) y[i] = 0.0;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    if (j < p) {
+      const double zj = (double)v[j] - mu[j];
+#pragma unroll
+      for (int i = j; i < P; ++i)
+        if (i < p) y[i] = fma(Mg[i * ldm + j], zj, y[i]);
+    }
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < P; ++i)
+    if (i < p) acc = fma(y[i], y[i], acc);
+  return acc;
+}
+
+template <typename T, int P, int NI, typename Emit>
+__device__ inline void eval_row(const T (&v)[P], int p, int ldm, const double* const (&Mg)[NI],
+                                const double* const (&mug)[NI], const bool (&act)[NI],
+                                Emit emit) {
+  if constexpr (NI == 1) {
+    emit(0, col_norm2_g<T, P>(Mg[0], ldm, p, mug[0], v));
+  } else {
+#pragma unroll
+    for (int q = 0; q < NI; ++q) {
+      if (act[q]) {
+        double z[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) z[j] = j < p ? (double)v[j] - mug[q][j] : 0.0;
+        emit(q, tri_norm2_g<P>(Mg[q], ldm, p, z));
+      }
+    }
+  }
+}
+
+// Row r of X; emit(q, d2) for each active factor.  LDM_IS_P: the factor's row
+// stride is p (a p x p factor), which the fast path then knows to be P.
+// GEN: rows may be narrower than P, strided or unaligned (checked per item);
+// without it the launch guarantees dense, aligned rows of P columns.
+template <typename T, int P, int NI, bool LDM_IS_P, bool GEN, typename Emit>
+__device__ inline void dist_row_direct(const T* __restrict__ X, int64_t ld, int p, int ldm,
+                                       int64_t r, const double* const (&Mg)[NI],
+                                       const double* const (&mug)[NI], const bool (&act)[NI],
+                                       Emit emit) {
+  constexpr int VB = RowVec<T, P>::VB;
+  const bool fast = !GEN || (p == P && ld == P && ((reinterpret_cast<uintptr_t>(X) % VB) == 0));
+  T v[P];
+  if (fast) {
+    load_row_vec<T, P>(X + r * P, v);
+    eval_row<T, P, NI>(v, P, LDM_IS_P ? P : ldm, Mg, mug, act, emit);   // guards fold
+  } else if constexpr (GEN) {
+    const T* __restrict__ xr = X + r * ld;
+#pragma unroll
+    for (int j = 0; j < P; ++j) v[j] = j < p ? xr[j] : (T)0;
+    eval_row<T, P, NI>(v, p, ldm, Mg, mug, act, emit);
+  }
+}
+
+template <typename T, int P, int NI, bool GEN>
+__global__ __launch_bounds__(DROWS) void k_dist_direct(const ItemDesc* __restrict__ items,
+                                                       const Tile* __restrict__ tiles,
+                                                       int tile_rows,
+                                                       const double* __restrict__ mtri,
+                                                       const double* __restrict__ mux,
+                                                       const int32_t* __restrict__ status,
+                                                       double* __restrict__ d2) {
+  const int nsub = tile_rows / DROWS;
+  const Tile tl = tiles[blockIdx.x / nsub];
+  bool act[NI];
+  bool any = false;
+#pragma unroll
+  for (int q = 0; q < NI; ++q) {
+    act[q] = status == nullptr || status[tl.item + q] == ACTIVE;
+    any = any || act[q];
+  }
+  if (!any) return;
+  const ItemDesc D = items[tl.item];
+  const int64_t t0 = (int64_t)tl.t * tile_rows;
+  const int64_t r = t0 + (int64_t)(blockIdx.x % nsub) * DROWS + threadIdx.x;
+  if (r >= min(t0 + (int64_t)tile_rows, D.m)) return;
+  int64_t roff[NI];
+  const double* Mg[NI];
+  const double* mug[NI];
+#pragma unroll
+  for (int q = 0; q < NI; ++q) {
+    const int it = tl.item + q;
+    roff[q] = items[it].roff;
+    Mg[q] = mtri + (size_t)it * MSTRIDE;
+    mug[q] = mux + (size_t)it * PMAX;
+  }
+  const T* __restrict__ X = static_cast<const T*>(D.X) + D.row0 * D.ld;
+  dist_row_direct<T, P, NI, false, GEN>(X, D.ld, D.p, PMAX, r, Mg, mug, act,
+                            [&](int q, double v) { d2[roff[q] + r] = v; });
+}
+
+template <typename T, int P, bool GEN>
+__global__ __launch_bounds__(DROWS) void k_final_dist_direct(
+    const ItemDesc* __restrict__ items, const Tile* __restrict__ tiles, int tile_rows,
+    const double* __restrict__ mtri, const double* __restrict__ mux,
+    const double* __restrict__ d2, const DsInfo* __restrict__ ds,
+    const rtdetmcd_out* __restrict__ outs) {
+  const int nsub = tile_rows / DROWS;
+  const Tile tl = tiles[blockIdx.x / nsub];
+  const int it = tl.item;
+  const ItemDesc D = items[it];
+  const int64_t t0 = (int64_t)tl.t * tile_rows;
+  const int64_t r = t0 + (int64_t)(blockIdx.x % nsub) * DROWS + threadIdx.x;
+  if (r >= min(t0 + (int64_t)tile_rows, D.m)) return;
+  const DsInfo dd = ds[D.ds];
+  if (dd.err) return;
+  const double cut = dd.chi2p;
+  double* __restrict__ od = outs[D.ds].dist;
+  uint8_t* __restrict__ of = outs[D.ds].outlier;
+  uint8_t* __restrict__ ow = outs[D.ds].rew_mask;
+  // reweighting set: as in k_final_dist
+  const ItemDesc R = items[dd.glob0];
+  const double* __restrict__ d2r = d2 + R.roff;
+  const T* __restrict__ X = static_cast<const T*>(D.X) + D.row0 * D.ld;
+  const double* Mg[1] = {mtri + (size_t)it * MSTRIDE};
+  const double* mug[1] = {mux + (size_t)it * PMAX};
+  const bool act[1] = {true};
+  dist_row_direct<T, P, 1, false, GEN>(X, D.ld, D.p, PMAX, r, Mg, mug, act, [&](int, double v) {
+    if (od) od[D.row0 + r] = sqrt(v);
+    if (of) of[D.row0 + r] = v > cut ? 1 : 0;
+    if (ow) {
+      const int64_t rr = D.row0 + r - R.row0;
+      ow[D.row0 + r] = (rr >= 0 && rr < R.m && d2r[rr] <= cut) ? 1 : 0;
+    }
+  });
+}
+
+template <typename T, int P, bool GEN>
+__global__ __launch_bounds__(DROWS) void k_score_direct(const T* __restrict__ X, int64_t n,
+                                                        int64_t ld, int p,
+                                                        const double* __restrict__ mu,
+                                                        const double* __restrict__ M,
+                                                        double cut, double* __restrict__ dist,
+                                                        uint8_t* __restrict__ flag) {
+  const int64_t r = (int64_t)blockIdx.x * DROWS + threadIdx.x;
+  if (r >= n) return;
+  const double* Mg[1] = {M};
+  const double* mug[1] = {mu};
+  const bool act[1] = {true};
+  dist_row_direct<T, P, 1, true, GEN>(X, ld, p, p, r, Mg, mug, act, [&](int, double v) {
+    if (dist) dist[r] = sqrt(v);
+    if (flag) flag[r] = v > cut ? 1 : 0;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Staged evaluation (p = 48, 64).
+
 // C-step distances.  NI = 2: tile.item and tile.item + 1 are the two starts of
 // one block (same rows); an inactive start is skipped.
 template <typename T, int P, int NI>
@@ -345,80 +541,135 @@ __global__ __launch_bounds__(CH) void k_score(const T* __restrict__ X, int64_t n
 
 }  // namespace
 
-#define RTD_BUCKETS(X) X(4) X(5) X(8) X(10) X(16) X(20) X(24) X(32) X(40) X(48) X(64)
+#define RTD_DIRECT_BUCKETS(X) X(4) X(5) X(8) X(10) X(16) X(20) X(24) X(32) X(40)
+#define RTD_STAGED_BUCKETS(X) X(48) X(64)
+#define RTD_PAIR_DIRECT_BUCKETS(X) X(4) X(5) X(8) X(10) X(16) X(20) X(24)
+#define RTD_PAIR_STAGED_BUCKETS(X) X(32) X(40)
+static_assert(DIRECT_MAX == 40, "bucket lists");
 
-hipError_t launch_dist(int bucket, int dtype, int ipt, const ItemDesc* items, const Tile* tiles,
+hipError_t launch_dist(int bucket, int dtype, int dense, int ipt, const ItemDesc* items,
+                       const Tile* tiles,
                        int ntiles, int tile_rows, const double* mtri, const double* mux,
                        const int32_t* status, double* d2, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-#define LAUNCH(T, PB, NI)                                                                       \
-  hipLaunchKernelGGL((k_dist<T, PB, NI>), dim3(ntiles), dim3(CH), 0, s, items, tiles, tile_rows, \
-                     mtri, mux, status, d2)
-#define CASE(PB)                                                                                \
+  if (tile_rows <= 0 || tile_rows % DROWS != 0) return hipErrorInvalidValue;
+  const unsigned nbd = (unsigned)ntiles * (unsigned)(tile_rows / DROWS);
+#define LAUNCH(K, NB, NT)                                                                       \
+  hipLaunchKernelGGL(K, dim3(NB), dim3(NT), 0, s, items, tiles, tile_rows, mtri, mux, status, d2)
+#define DIRECT(T, PB, NI)                                                                       \
+  do {                                                                                          \
+    if (dense) LAUNCH((k_dist_direct<T, PB, NI, false>), nbd, DROWS);                           \
+    else LAUNCH((k_dist_direct<T, PB, NI, true>), nbd, DROWS);                                  \
+  } while (0)
+#define STAGED(T, PB, NI) LAUNCH((k_dist<T, PB, NI>), ntiles, CH)
+#define CASE(K1, K2, PB)                                                                        \
   case PB:                                                                                      \
     if (dtype == 0) {                                                                           \
-      if (ipt == 2) LAUNCH(float, PB, 2);                                                       \
-      else LAUNCH(float, PB, 1);                                                                \
+      if (ipt == 2) K2(float, PB, 2);                                                           \
+      else K1(float, PB, 1);                                                                    \
     } else {                                                                                    \
-      if (ipt == 2) LAUNCH(double, PB, 2);                                                      \
-      else LAUNCH(double, PB, 1);                                                               \
+      if (ipt == 2) K2(double, PB, 2);                                                          \
+      else K1(double, PB, 1);                                                                   \
     }                                                                                           \
     return hipGetLastError();
+  // the pair kernel holds two rows of partial sums: direct up to p = 24; at
+  // p = 32, 40 its register count leaves 3 waves per SIMD and the staged
+  // kernel is faster (10M x 40: 745 against 1,132 us per C-step pass)
+#define DCASE(PB) CASE(DIRECT, DIRECT, PB)
+#define DSCASE(PB) CASE(DIRECT, STAGED, PB)
+#define SCASE(PB) CASE(STAGED, STAGED, PB)
   switch (bucket) {
-    RTD_BUCKETS(CASE)
+    RTD_PAIR_DIRECT_BUCKETS(DCASE)
+    RTD_PAIR_STAGED_BUCKETS(DSCASE)
+    RTD_STAGED_BUCKETS(SCASE)
     default: return hipErrorInvalidValue;
   }
+#undef SCASE
+#undef DSCASE
+#undef DCASE
 #undef CASE
+#undef STAGED
+#undef DIRECT
 #undef LAUNCH
 }
 
-hipError_t launch_final_dist(int bucket, int dtype, const ItemDesc* items, const Tile* tiles,
+hipError_t launch_final_dist(int bucket, int dtype, int dense, const ItemDesc* items,
+                             const Tile* tiles,
                              int ntiles, int tile_rows, const double* mtri, const double* mux,
                              const double* d2, const DsInfo* ds, const rtdetmcd_out* outs,
                              hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-#define CASE(PB)                                                                                \
+  if (tile_rows <= 0 || tile_rows % DROWS != 0) return hipErrorInvalidValue;
+  const unsigned nbd = (unsigned)ntiles * (unsigned)(tile_rows / DROWS);
+#define LAUNCH(K, NB, NT)                                                                       \
+  hipLaunchKernelGGL(K, dim3(NB), dim3(NT), 0, s, items, tiles, tile_rows, mtri, mux, d2, ds, outs)
+#define DIRECT(T, PB)                                                                           \
+  do {                                                                                          \
+    if (dense) LAUNCH((k_final_dist_direct<T, PB, false>), nbd, DROWS);                         \
+    else LAUNCH((k_final_dist_direct<T, PB, true>), nbd, DROWS);                                \
+  } while (0)
+#define STAGED(T, PB) LAUNCH((k_final_dist<T, PB>), ntiles, CH)
+#define CASE(K, PB)                                                                             \
   case PB:                                                                                      \
-    if (dtype == 0)                                                                             \
-      hipLaunchKernelGGL((k_final_dist<float, PB>), dim3(ntiles), dim3(CH), 0, s, items, tiles, \
-                         tile_rows, mtri, mux, d2, ds, outs);                                   \
-    else                                                                                        \
-      hipLaunchKernelGGL((k_final_dist<double, PB>), dim3(ntiles), dim3(CH), 0, s, items,       \
-                         tiles, tile_rows, mtri, mux, d2, ds, outs);                            \
+    if (dtype == 0) K(float, PB);                                                               \
+    else K(double, PB);                                                                         \
     return hipGetLastError();
+#define DCASE(PB) CASE(DIRECT, PB)
+#define SCASE(PB) CASE(STAGED, PB)
   switch (bucket) {
-    RTD_BUCKETS(CASE)
+    RTD_DIRECT_BUCKETS(DCASE)
+    RTD_STAGED_BUCKETS(SCASE)
     default: return hipErrorInvalidValue;
   }
+#undef SCASE
+#undef DCASE
 #undef CASE
+#undef STAGED
+#undef DIRECT
+#undef LAUNCH
 }
 
 hipError_t launch_score(int bucket, int dtype, const void* X, int64_t n, int64_t ld, int p,
                         const double* mu, const double* M, int ldm, double cut, double* dist,
                         uint8_t* flag, hipStream_t s) {
   if (ldm != p) return hipErrorInvalidValue;   // the factor is p x p, row stride p
-  // one 256-row chunk per block keeps the most loads in flight for narrow
-  // rows (1M x 20: 21 us against 29 us with 2,048-row tiles); wide factors
-  // are cheaper to stage in fewer, longer blocks (10M x 40: 675 against 760)
-  const int tile_rows = bucket <= 24 ? 256 : 2048;
-  const int64_t nb = (n + tile_rows - 1) / tile_rows;
-  if (nb <= 0) return hipSuccess;
+  if (n <= 0) return hipSuccess;
+  // direct buckets: one row per thread, 256 rows per block; the staged
+  // buckets take 2,048-row tiles (fewer stagings of the wide factor)
+  const int64_t nbd = (n + DROWS - 1) / DROWS;
+  const int64_t nbs = (n + 2047) / 2048;
+  const bool dense = rows_dense_at(X, ld, p, dtype, bucket);
+#define LAUNCH(T, PB, GEN)                                                                      \
+  hipLaunchKernelGGL((k_score_direct<T, PB, GEN>), dim3((unsigned)nbd), dim3(DROWS), 0, s,      \
+                     static_cast<const T*>(X), n, ld, p, mu, M, cut, dist, flag)
 #define CASE(PB)                                                                                \
   case PB:                                                                                      \
+    if (dtype == 0) {                                                                           \
+      if (dense) LAUNCH(float, PB, false);                                                      \
+      else LAUNCH(float, PB, true);                                                             \
+    } else {                                                                                    \
+      if (dense) LAUNCH(double, PB, false);                                                     \
+      else LAUNCH(double, PB, true);                                                            \
+    }                                                                                           \
+    return hipGetLastError();
+#define SCASE(PB)                                                                               \
+  case PB:                                                                                      \
     if (dtype == 0)                                                                             \
-      hipLaunchKernelGGL((k_score<float, PB>), dim3((unsigned)nb), dim3(CH), 0, s,              \
-                         static_cast<const float*>(X), n, ld, p, mu, M, cut, tile_rows, dist,   \
-                         flag);                                                                 \
+      hipLaunchKernelGGL((k_score<float, PB>), dim3((unsigned)nbs), dim3(CH), 0, s,             \
+                         static_cast<const float*>(X), n, ld, p, mu, M, cut, 2048, dist, flag); \
     else                                                                                        \
-      hipLaunchKernelGGL((k_score<double, PB>), dim3((unsigned)nb), dim3(CH), 0, s,             \
-                         static_cast<const double*>(X), n, ld, p, mu, M, cut, tile_rows, dist,  \
+      hipLaunchKernelGGL((k_score<double, PB>), dim3((unsigned)nbs), dim3(CH), 0, s,            \
+                         static_cast<const double*>(X), n, ld, p, mu, M, cut, 2048, dist,       \
                          flag);                                                                 \
     return hipGetLastError();
   switch (bucket) {
-    RTD_BUCKETS(CASE)
+    RTD_DIRECT_BUCKETS(CASE)
+    RTD_STAGED_BUCKETS(SCASE)
     default: return hipErrorInvalidValue;
   }
+#undef SCASE
 #undef CASE
+#undef LAUNCH
 }
 
 }  // namespace rtd

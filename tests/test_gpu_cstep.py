@@ -177,3 +177,33 @@ def test_score_matches_oracle(p, dtype):
     # flags decided on float64 d2; compare away from the threshold
     far = np.abs(d2 - cut) > 1e-9 * cut
     assert np.array_equal(flag.cpu().numpy()[far], (d2 > cut).astype(np.uint8)[far])
+
+
+@pytest.mark.parametrize("p,dtype", [(20, "f32"), (10, "f32"), (10, "f64"), (40, "f32"), (16, "f64")])
+def test_dense_and_generic_row_paths_agree(p, dtype):
+    """Dense, aligned rows take the whole-row vector loads; the same rows one
+    element past an aligned base take the per-element path.  Both evaluate
+    the same float64 operations in the same order: bitwise equal outputs."""
+    P = _P()
+    rng = np.random.default_rng(300 + p)
+    n = 4096 + 77
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    X = (rng.standard_normal((n, p)) * 2 + 1).astype(np.float32 if dtype == "f32" else np.float64)
+    S = _spd(p, rng)
+    mu = rng.standard_normal(p)
+    L = np.linalg.cholesky(S)
+    Linv = np.linalg.inv(L)
+    Xa = torch.from_numpy(X).to(_dev())
+    buf = torch.empty(n * p + 1, dtype=tdt, device=_dev())
+    Xu = buf[1:].view(n, p)
+    Xu.copy_(Xa)
+    assert Xu.data_ptr() % 16 != 0 and Xa.data_ptr() % 16 == 0
+    da, fa = P.score(Xa, torch.from_numpy(mu), torch.from_numpy(Linv))
+    du, fu = P.score(Xu, torch.from_numpy(mu), torch.from_numpy(Linv))
+    assert torch.equal(da, du) and torch.equal(fa, fu)
+    ga = P.distances(Xa, torch.from_numpy(mu), torch.from_numpy(L))
+    gu = P.distances(Xu, torch.from_numpy(mu), torch.from_numpy(L))
+    assert torch.equal(ga, gu)
+    ref = oracle.mahalanobis2(X.astype(np.float64), mu, L)
+    np.testing.assert_allclose(ga.cpu().numpy(), ref, rtol=1e-11, atol=0)
+    np.testing.assert_allclose(da.cpu().numpy(), np.sqrt(ref), rtol=1e-11)
