@@ -142,10 +142,23 @@ rtdetmcd_status rtdetmcd_fit(rtdetmcd_handle h, const void* X, int32_t dtype, in
 
 /* Many independent datasets fitted in the same launches.  `sets` is a HOST
  * array of n_datasets descriptors; each descriptor's X and out are device
- * buffers as for rtdetmcd_fit.  status[i] (host) receives each dataset's code. */
+ * buffers as for rtdetmcd_fit.  status[i] (host) receives each dataset's code.
+ *
+ * perm (device, int32 [n], or NULL): the random partition of Sec. 4 — block l
+ * is rows perm[l m], ..., perm[(l+1) m - 1] of X, and rows perm[q m .. n) are
+ * the unfitted remainder (still scored and flagged).  The caller draws the
+ * permutation (the library draws no random numbers); NULL means contiguous
+ * blocks [l m, (l+1) m).  The library copies the q m fitted rows into its
+ * workspace in block order.  A perm that is not a permutation of 0 .. n-1
+ * (an entry out of range or repeated) gives that dataset RTDETMCD_EINVAL;
+ * out-of-range entries are never used as row indices.  With a perm, hsubset
+ * lists each block's subset as rows of X in order of their position within
+ * the block (ascending only for contiguous blocks), and rew_mask and the
+ * final distances stay in the row order of X. */
 typedef struct rtdetmcd_dataset {
   const void* X; int32_t dtype; int64_t n; int32_t p; int64_t ld;
   int64_t h_sub; int32_t n_chunks; rtdetmcd_out out;
+  const int32_t* perm;
 } rtdetmcd_dataset;
 rtdetmcd_status rtdetmcd_fit_batched(rtdetmcd_handle h, int32_t n_datasets,
                                      const rtdetmcd_dataset* sets, const rtdetmcd_opts* o,

@@ -40,7 +40,7 @@ class Out(C.Structure):
 
 class DatasetDesc(C.Structure):
     _fields_ = [("X", c_vp), ("dtype", c_i32), ("n", c_i64), ("p", c_i32), ("ld", c_i64),
-                ("h_sub", c_i64), ("n_chunks", c_i32), ("out", Out)]
+                ("h_sub", c_i64), ("n_chunks", c_i32), ("out", Out), ("perm", c_vp)]
 
 
 _lib = None

@@ -223,8 +223,28 @@ def _alloc_fit(X: torch.Tensor, q: int, m: int, h: int):
     return F, out
 
 
-def fit(X: torch.Tensor, h_sub: int = 0, n_chunks: int = 0, **opts) -> Fit:
-    """RT-DetMCD fit of X (n x p) on the GPU; all outputs stay on the device."""
+def random_partition(n: int, seed: int, device=None) -> torch.Tensor:
+    """A random permutation of the n rows (int32, on `device`) for the random
+    partition of Sec. 4: block l of a fit given ``perm`` is rows
+    perm[l m : (l+1) m].  Drawn on the host from a seeded torch generator, so
+    that the same rows can be handed to any other implementation."""
+    g = torch.Generator().manual_seed(int(seed))
+    return torch.randperm(n, generator=g, dtype=torch.int64).to(torch.int32).to(device)
+
+
+def fit(X: torch.Tensor, h_sub: int = 0, n_chunks: int = 0,
+        perm: Optional[torch.Tensor] = None, **opts) -> Fit:
+    """RT-DetMCD fit of X (n x p) on the GPU; all outputs stay on the device.
+
+    perm: optional int32 device tensor of n row indices, the random partition
+    of Sec. 4 (see random_partition); None gives contiguous blocks."""
+    if perm is not None:
+        fits, status = fit_batched([X], h_subs=[h_sub], n_chunks=[n_chunks], perms=[perm],
+                                   **opts)
+        if status[0] != 0:
+            lib, hd = _handle(X.device)
+            _check(lib, hd, status[0], "rtdetmcd_fit_batched")
+        return fits[0]
     _check_X(X)
     n, p = X.shape
     q, m, h = plan(n, p, h_sub, n_chunks, **opts)
@@ -287,15 +307,19 @@ class RobustMCD(torch.autograd.Function):
 
 
 def fit_batched(Xs: Sequence[torch.Tensor], h_subs: Optional[Sequence[int]] = None,
-                n_chunks: Optional[Sequence[int]] = None, **opts):
+                n_chunks: Optional[Sequence[int]] = None,
+                perms: Optional[Sequence[Optional[torch.Tensor]]] = None, **opts):
     """Fit many independent datasets in the same launches.
 
-    Returns (list of Fit, list of per-dataset status codes)."""
+    perms: optional per-dataset random partitions (int32 device tensors of n
+    row indices, or None).  Returns (list of Fit, list of per-dataset status
+    codes)."""
     lib, hd = _handle(Xs[0].device)
     o = make_opts(**opts)
     k = len(Xs)
     h_subs = list(h_subs) if h_subs is not None else [0] * k
     n_chunks = list(n_chunks) if n_chunks is not None else [0] * k
+    perms = list(perms) if perms is not None else [None] * k
     arr = (_lib.DatasetDesc * k)()
     fits = []
     for i, X in enumerate(Xs):
@@ -305,8 +329,14 @@ def fit_batched(Xs: Sequence[torch.Tensor], h_subs: Optional[Sequence[int]] = No
         F, out = _alloc_fit(X, q, m, h)
         F.c_rew = lib.rtdetmcd_consistency(o.cutoff_q, p) if o.rew_consistency else 1.0
         fits.append(F)
+        pm = perms[i]
+        if pm is not None:
+            if (pm.dtype != torch.int32 or pm.device != X.device or pm.dim() != 1
+                    or pm.shape[0] != n or not pm.is_contiguous()):
+                raise ValueError("perm must be a contiguous int32 tensor of n rows on X's device")
         arr[i] = _lib.DatasetDesc(X=X.data_ptr(), dtype=_dtype_code(X), n=n, p=p, ld=X.stride(0),
-                                  h_sub=h_subs[i], n_chunks=n_chunks[i], out=out)
+                                  h_sub=h_subs[i], n_chunks=n_chunks[i], out=out,
+                                  perm=pm.data_ptr() if pm is not None else None)
     status = (C.c_int32 * k)()
     st = lib.rtdetmcd_fit_batched(hd, k, arr, C.byref(o), status)
     _check(lib, hd, st, "rtdetmcd_fit_batched")

@@ -15,6 +15,7 @@ namespace {
 
 struct DsHost {
   const rtdetmcd_dataset* in;
+  const int32_t* perm;   // random partition (Sec. 4), or null for contiguous blocks
   int p, dtype, bucket, q;
   int64_t n, m, h, ld;
   double chi2p, calpha, crew;
@@ -136,6 +137,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     }
     DsHost d{};
     d.in = &s;
+    d.perm = s.perm;
     d.p = s.p;
     d.dtype = s.dtype;
     d.bucket = bucket_of(s.p);
@@ -277,6 +279,14 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   for (int k = 0; k < 7; ++k) o_mb[k] = L.add(maxtiles * 8);
   o_mb[7] = L.add(maxseg * 2 * 8);
   o_mb[8] = L.add(maxseg * 5 * 8);
+  // random partitions: the fitted rows in block order (dense, row stride p)
+  // and the inverse permutation
+  std::vector<size_t> o_xp(ND, 0), o_inv(ND, 0);
+  for (int k = 0; k < ND; ++k)
+    if (D[k].perm) {
+      o_xp[k] = L.add((size_t)D[k].q * D[k].m * D[k].p * (D[k].dtype == 0 ? 4 : 8));
+      o_inv[k] = L.add((size_t)D[k].n * 4);
+    }
   RTD_TRY(ensure_ws(ctx, L.off));
   char* base = static_cast<char*>(ctx->ws);
 
@@ -343,12 +353,23 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   bind_items(base, C, offC, CD);
   bind_items(base, B, offB, BD);
   bind_items(base, G, offG, GD);
-  // loc/scale pointers of every item
+  // loc/scale pointers of every item; the blocks, starts and reweighting
+  // rows of a randomly partitioned dataset read its gathered copy
   for (auto* set : {&C, &B, &G})
     for (ItemDesc& e : set->items) {
       e.loc = F.loc + (size_t)e.ds * PMAX;
       e.scale = F.scale + (size_t)e.ds * PMAX;
     }
+  for (int k = 0; k < ND; ++k) {
+    if (!D[k].perm) continue;
+    auto repoint = [&](ItemDesc& e) {
+      e.X = base + o_xp[k];
+      e.ld = D[k].p;
+    };
+    for (int i = D[k].item0; i < D[k].item0 + 2 * D[k].q; ++i) repoint(C.items[i]);
+    for (int i = D[k].blk0; i < D[k].blk0 + D[k].q; ++i) repoint(B.items[i]);
+    repoint(G.items[D[k].glob0]);
+  }
   std::vector<DsInfo> dinfo(ND);
   std::vector<rtdetmcd_out> houts(ND);
   std::vector<double> hchi(ND);
@@ -360,6 +381,8 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     x.chi2p = D[k].chi2p; x.calpha = D[k].calpha; x.crew = D[k].crew;
     x.item0 = D[k].item0; x.blk0 = D[k].blk0; x.glob0 = D[k].glob0; x.glob1 = ND + k;
     x.err = 0;
+    x.perm = D[k].perm;
+    x.inv = D[k].perm ? reinterpret_cast<int32_t*>(base + o_inv[k]) : nullptr;
     houts[k] = D[k].in->out;
     hchi[k] = D[k].chi2p;
   }
@@ -394,6 +417,15 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   const double crew1 = consistency_memo(o.cutoff_q, 1);
   const int smode = o.standardize == RTDETMCD_STD_MEDMAD ? SEGSTAT_MEDMAD : SEGSTAT_UNIMCD;
 
+  // ---------------------------------------------------------------- random partitions
+  for (int k = 0; k < ND; ++k) {
+    if (!D[k].perm) continue;
+    int32_t* inv = reinterpret_cast<int32_t*>(base + o_inv[k]);
+    RTD_HIP(launch_fill_i32(inv, -1, D[k].n, st));
+    RTD_HIP(launch_perm_check(D[k].perm, D[k].n, inv, dds, k, st));
+    RTD_HIP(launch_perm_gather(D[k].dtype, D[k].in->X, D[k].n, D[k].ld, D[k].p, D[k].perm,
+                               (int64_t)D[k].q * D[k].m, base + o_xp[k], st));
+  }
   // ---------------------------------------------------------------- step 0: standardisation
   RTD_HIP(launch_fill_i32(sflag, 0, 1, st));
   for (int k = 0; k < ND; ++k) {
@@ -534,7 +566,9 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     if (status) status[orig] = s;
     if (s != RTDETMCD_OK) {
       ret = s;
-      ctx->err = "dataset " + std::to_string(orig) + ": no valid fit (degenerate data)";
+      ctx->err = "dataset " + std::to_string(orig) +
+                 (s == RTDETMCD_EINVAL ? ": perm is not a permutation of the rows"
+                                       : ": no valid fit (degenerate data)");
     }
   }
   return nd == 1 ? ret : RTDETMCD_OK;

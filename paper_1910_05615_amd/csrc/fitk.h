@@ -19,6 +19,8 @@ struct DsInfo {
   int32_t blk0;      // first block item
   int32_t glob0;     // first of the two global items
   int32_t err;       // 0 ok, else a status code
+  const int32_t* perm;  // random partition: dataset row of block position k, or null
+  int32_t* inv;         // its inverse: block position of dataset row i (valid perm only)
 };
 
 // Per-dataset and per-block result arrays.
@@ -77,6 +79,14 @@ hipError_t launch_final_dist(int bucket, int dtype, int dense, const ItemDesc* i
                              int ntiles, int tile_rows, const double* mtri, const double* mux,
                              const double* d2, const DsInfo* ds,
                              const struct rtdetmcd_out* outs, hipStream_t s);
+// Random partition (Sec. 4) of dataset d: check that perm is a permutation
+// of 0..n-1 (inv prefilled with -1 receives its inverse; a bad entry sets
+// ds[d].err = RTDETMCD_EINVAL), and copy the q m fitted rows into Xp
+// (row-major, row stride p) in block order; a bad entry copies zeros.
+hipError_t launch_perm_check(const int32_t* perm, int64_t n, int32_t* inv, DsInfo* ds, int d,
+                             hipStream_t s);
+hipError_t launch_perm_gather(int dtype, const void* X, int64_t n, int64_t ld, int p,
+                              const int32_t* perm, int64_t rows, void* Xp, hipStream_t s);
 hipError_t launch_hsub(const ItemDesc* citems, ItemArrays A, FitArrays F, const DsInfo* ds,
                        const struct rtdetmcd_out* outs, int first, int n, hipStream_t s);
 hipError_t launch_outputs(const DsInfo* ds, ItemArrays G, FitArrays F,

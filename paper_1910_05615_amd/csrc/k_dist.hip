@@ -409,7 +409,9 @@ __global__ __launch_bounds__(DROWS) void k_final_dist_direct(
     if (od) od[D.row0 + r] = sqrt(v);
     if (of) of[D.row0 + r] = v > cut ? 1 : 0;
     if (ow) {
-      const int64_t rr = D.row0 + r - R.row0;
+      // position of the row among the fitted rows (through the inverse
+      // permutation for a random partition)
+      const int64_t rr = dd.inv ? (int64_t)dd.inv[D.row0 + r] : D.row0 + r - R.row0;
       ow[D.row0 + r] = (rr >= 0 && rr < R.m && d2r[rr] <= cut) ? 1 : 0;
     }
   });
@@ -512,7 +514,9 @@ __global__ __launch_bounds__(CH) void k_final_dist(const ItemDesc* __restrict__ 
                              if (od) od[D.row0 + r] = sqrt(v);
                              if (of) of[D.row0 + r] = v > cut ? 1 : 0;
                              if (ow) {
-                               const int64_t rr = D.row0 + r - R.row0;
+                               // position of the row among the fitted rows (through the inverse
+      // permutation for a random partition)
+      const int64_t rr = dd.inv ? (int64_t)dd.inv[D.row0 + r] : D.row0 + r - R.row0;
                                ow[D.row0 + r] = (rr >= 0 && rr < R.m && d2r[rr] <= cut) ? 1 : 0;
                              }
                            });

@@ -687,7 +687,34 @@ __global__ __launch_bounds__(256) void k_rew(DsInfo* __restrict__ ds,
   if (threadIdx.x == 0) F.nw[dd] = (int64_t)nw;
 }
 
-// Subset indices of each block's chosen start, ascending dataset rows.
+// Random partition (Sec. 4): validate the permutation and build its inverse.
+__global__ __launch_bounds__(256) void k_perm_check(const int32_t* __restrict__ perm, int64_t n,
+                                                    int32_t* __restrict__ inv,
+                                                    DsInfo* __restrict__ ds, int d) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int32_t i = perm[k];
+  bool bad = i < 0 || (int64_t)i >= n;
+  if (!bad) bad = atomicExch(&inv[i], (int32_t)k) != -1;   // a repeated row
+  if (bad) ds[d].err = RTDETMCD_EINVAL;
+}
+
+// The fitted rows of a randomly partitioned dataset, in block order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_perm_gather(const T* __restrict__ X, int64_t n,
+                                                     int64_t ld, int p,
+                                                     const int32_t* __restrict__ perm,
+                                                     int64_t rows, T* __restrict__ Xp) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * p) return;
+  const int64_t k = e / p;
+  const int j = (int)(e - k * p);
+  const int32_t i = perm[k];
+  Xp[e] = (i >= 0 && (int64_t)i < n) ? X[(int64_t)i * ld + j] : (T)0;
+}
+
+// Subset indices of each block's chosen start: rows of X in order of their
+// position within the block (ascending rows for contiguous blocks).
 __global__ __launch_bounds__(1024) void k_hsub(const ItemDesc* __restrict__ citems, ItemArrays A,
                                                FitArrays F, const DsInfo* __restrict__ ds,
                                                const rtdetmcd_out* __restrict__ outs, int first) {
@@ -719,7 +746,8 @@ __global__ __launch_bounds__(1024) void k_hsub(const ItemDesc* __restrict__ cite
       if (k < wv) off += wtot[k];
       tot += wtot[k];
     }
-    if (f && n + off + pos < d.h) o[n + off + pos] = (int32_t)(C.row0 + i);
+    if (f && n + off + pos < d.h)   // block position -> row of X
+      o[n + off + pos] = d.perm ? d.perm[C.row0 + i] : (int32_t)(C.row0 + i);
     n += tot;
     __syncthreads();
   }
@@ -991,6 +1019,28 @@ hipError_t launch_rew(DsInfo* ds, const ItemDesc* gitems, ItemArrays G, FitArray
                       int nds, hipStream_t s) {
   if (nds <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_rew, dim3(nds), dim3(256), 0, s, ds, gitems, G, F, first_ds);
+  return hipGetLastError();
+}
+
+hipError_t launch_perm_check(const int32_t* perm, int64_t n, int32_t* inv, DsInfo* ds, int d,
+                             hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_perm_check, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, perm, n,
+                     inv, ds, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_perm_gather(int dtype, const void* X, int64_t n, int64_t ld, int p,
+                              const int32_t* perm, int64_t rows, void* Xp, hipStream_t s) {
+  const int64_t ne = rows * p;
+  if (ne <= 0) return hipSuccess;
+  const dim3 g((unsigned)((ne + 255) / 256));
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_perm_gather<float>, g, dim3(256), 0, s, static_cast<const float*>(X), n,
+                       ld, p, perm, rows, static_cast<float*>(Xp));
+  else
+    hipLaunchKernelGGL(k_perm_gather<double>, g, dim3(256), 0, s, static_cast<const double*>(X),
+                       n, ld, p, perm, rows, static_cast<double*>(Xp));
   return hipGetLastError();
 }
 

@@ -167,3 +167,37 @@ def test_fit_chunked_p20_full_size():
     ds = synthdata.workload_chunked_p20()                # n=1,000,000, p=20, 64 blocks
     ref = oracle.fit(ds.X, n_chunks=64)
     check_fit(_run(ds.X, n_chunks=64), ref, "full size p20")
+
+
+@pytest.mark.parametrize("dtype,n,p,q", [(np.float32, 40_009, 20, 4), (np.float64, 12_345, 5, 3)])
+def test_random_partition_matches_oracle(dtype, n, p, q):
+    """Blocks drawn by a row permutation (Sec. 4), with a ragged remainder of
+    unfitted rows; the permutation is the same input to both sides."""
+    P = _P()
+    ds = synthdata.small_gaussian(n, p, seed=41, dtype=dtype, rho=0.5, eps=0.1, kind="shift",
+                                  gamma=8)
+    perm = P.random_partition(n, seed=5, device=_dev())
+    F = P.fit(torch.from_numpy(ds.X).to(_dev()), n_chunks=q, perm=perm)
+    ref = oracle.fit(ds.X, n_chunks=q, perm=perm.cpu().numpy().astype(np.int64))
+    check_fit(F, ref, f"perm n={n} p={p}")
+    assert np.array_equal(F.rew_mask.cpu().numpy(), ref.rew_mask)
+
+
+def test_random_partition_rejects_bad_permutations():
+    P = _P()
+    ds = synthdata.small_gaussian(5000, 4, seed=3, dtype=np.float32)
+    X = torch.from_numpy(ds.X).to(_dev())
+    good = P.random_partition(5000, seed=1, device=_dev())
+    out_of_range = good.clone()
+    out_of_range[17] = 5000
+    repeated = good.clone()
+    repeated[3] = repeated[4]
+    negative = good.clone()
+    negative[0] = -1
+    fits, status = P.fit_batched([X, X, X, X], n_chunks=[2] * 4,
+                                 perms=[good, out_of_range, repeated, negative])
+    assert status == [0, -1, -1, -1]          # RTDETMCD_EINVAL for each bad perm
+    ref = oracle.fit(ds.X, n_chunks=2, perm=good.cpu().numpy().astype(np.int64))
+    check_fit(fits[0], ref, "good perm next to bad ones")
+    with pytest.raises(P.RTDetMCDError):
+        P.fit(X, n_chunks=2, perm=repeated)

@@ -534,3 +534,32 @@ def test_condition_check_in_standardised_units():
     assert np.array_equal(r_scaled.H, r_plain.H)
     r_raw = oracle.csteps(Xs, 400, mu0 * s, S0 * np.outer(s, s))
     assert r_raw.status == oracle.ST_DROP_FIRST
+
+
+def test_random_partition_is_the_fit_of_the_permuted_rows():
+    """Sec. 4 partitions the rows at random: fitting X with blocks
+    X[perm[l m : (l+1) m]] is fitting X[perm] with contiguous blocks.  The
+    global standardisation depends only on the columns' values (up to the
+    rounding of its sums, which run in row order), so the two fits make the
+    same discrete choices and agree to rounding once rows are mapped back
+    through perm."""
+    rng = np.random.default_rng(77)
+    n, p, q = 1203, 3, 3
+    X = rng.standard_normal((n, p)) @ np.array([[1.0, 0.4, 0.0], [0.0, 1.0, 0.3], [0.0, 0.0, 1.0]])
+    X[rng.choice(n, 120, replace=False)] += 6.0
+    perm = rng.permutation(n)
+    fp = oracle.fit(X, n_chunks=q, perm=perm)
+    fc = oracle.fit(X[perm], n_chunks=q)
+    close = lambda a, b: np.allclose(a, b, rtol=1e-12, atol=1e-14)
+    assert close(fp.loc, fc.loc) and close(fp.scale, fc.scale)
+    assert close(fp.mu, fc.mu) and close(fp.sigma, fc.sigma)
+    assert np.array_equal(fp.chunk_status, fc.chunk_status)
+    assert np.array_equal(fp.hsubset, perm[fc.hsubset])
+    assert close(fp.dist[perm], fc.dist)
+    assert np.array_equal(fp.outlier[perm], fc.outlier)
+    assert np.array_equal(fp.rew_mask[perm], fc.rew_mask)
+    assert fp.n_w == fc.n_w
+    # the identity permutation is the contiguous partition
+    fi = oracle.fit(X, n_chunks=q, perm=np.arange(n))
+    f0 = oracle.fit(X, n_chunks=q)
+    assert np.array_equal(fi.hsubset, f0.hsubset) and np.array_equal(fi.sigma, f0.sigma)
