@@ -186,7 +186,8 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
   if (o.launch == RTDETMCD_LAUNCH_BATCHED) {
     // tiles of the items [first, first+n) are contiguous in all tables; when
     // the range is made of whole start pairs, one distance pass serves both
-    const bool pairs = (n % 2 == 0) && S.pt_first[first] >= 0 && S.pt_first[first + n - 2] >= 0;
+    const bool pairs = dist_pairs_pay(bucket) && (n % 2 == 0) && S.pt_first[first] >= 0 &&
+                       S.pt_first[first + n - 2] >= 0;
     const Tile* dtl = pairs ? D.ptiles : D.dtiles;
     const int dt0 = pairs ? S.pt_first[first] : S.dt_first[first];
     const int dtn = pairs ? S.pt_first[first + n - 2] + S.pt_count[first + n - 2] - dt0

@@ -7,13 +7,13 @@
 // element), and each block takes one 256-row slice, so no LDS, no barrier
 // and a full chip of short blocks.  The factor and the centre are read at
 // uniform offsets: the loads go through the scalar unit and every FMA takes
-// its M entry from scalar registers.  One factor is evaluated column by
+// its M entry from scalar registers.  The factor is evaluated column by
 // column (y_i += M_ij z_j over j, the p partial sums independent of one
-// another, each still summed in order of j); the C-step pair (both starts of
-// a block from one read of each row) evaluates each factor row by row, and
-// goes direct up to p = 24.  Wider pairs (p = 32, 40) and all of p = 48, 64
-// stream rows through LDS in chunks loaded with 16-byte coalesced loads, the
-// factors staged in LDS and read as broadcasts.
+// another, each still summed in order of j).  The C-step runs it over both
+// starts' items of a block (each row read twice: still faster than one read
+// feeding two factors).  Rows of p = 48, 64 stream through LDS in chunks
+// loaded with 16-byte coalesced loads, the factors staged in LDS and read as
+// broadcasts, both starts of a block from one read of each row.
 #include <stdint.h>
 
 #include "common.h"
@@ -312,25 +312,6 @@ __device__ inline double col_norm2_g(const double* __restrict__ Mg, int ldm, int
   return acc;
 }
 
-template <typename T, int P, int NI, typename Emit>
-__device__ inline void eval_row(const T (&v)[P], int p, int ldm, const double* const (&Mg)[NI],
-                                const double* const (&mug)[NI], const bool (&act)[NI],
-                                Emit emit) {
-  if constexpr (NI == 1) {
-    emit(0, col_norm2_g<T, P>(Mg[0], ldm, p, mug[0], v));
-  } else {
-#pragma unroll
-    for (int q = 0; q < NI; ++q) {
-      if (act[q]) {
-        double z[P];
-#pragma unroll
-        for (int j = 0; j < P; ++j) z[j] = j < p ? (double)v[j] - mug[q][j] : 0.0;
-        emit(q, tri_norm2_g<P>(Mg[q], ldm, p, z));
-      }
-    }
-  }
-}
-
 // Every element of the row in a register at this point: all of the row's
 // loads are in flight together.  Without it the compiler issues the later
 // columns' loads after the first columns' FMAs (they are not needed before),
@@ -340,6 +321,21 @@ template <typename T, int P>
 __device__ inline void all_loaded(T (&v)[P]) {
 #pragma unroll
   for (int j = 0; j < P; ++j) asm volatile("" : "+v"(v[j]));
+}
+
+template <typename T, int P, int NI, typename Emit>
+__device__ inline void eval_row(T (&v)[P], int p, int ldm, const double* const (&Mg)[NI],
+                                const double* const (&mug)[NI], const bool (&act)[NI],
+                                Emit emit) {
+  // the factors one after the other on the same row, each column by column;
+  // between them the row goes through all_loaded again, so that its float64
+  // conversions are not kept live from the first factor to the second (the
+  // launches use one factor: see dist_pairs_pay)
+#pragma unroll
+  for (int q = 0; q < NI; ++q) {
+    if (q > 0) all_loaded(v);
+    if (act[q]) emit(q, col_norm2_g<T, P>(Mg[q], ldm, p, mug[q], v));
+  }
 }
 
 // Row r of X; emit(q, d2) for each active factor.  LDM_IS_P: the factor's row
@@ -572,8 +568,6 @@ __global__ __launch_bounds__(CH) void k_score(const T* __restrict__ X, int64_t n
 
 #define RTD_DIRECT_BUCKETS(X) X(4) X(5) X(8) X(10) X(16) X(20) X(24) X(32) X(40)
 #define RTD_STAGED_BUCKETS(X) X(48) X(64)
-#define RTD_PAIR_DIRECT_BUCKETS(X) X(4) X(5) X(8) X(10) X(16) X(20) X(24)
-#define RTD_PAIR_STAGED_BUCKETS(X) X(32) X(40)
 static_assert(DIRECT_MAX == 40, "bucket lists");
 
 hipError_t launch_dist(int bucket, int dtype, int dense, int ipt, const ItemDesc* items,
@@ -601,20 +595,17 @@ hipError_t launch_dist(int bucket, int dtype, int dense, int ipt, const ItemDesc
       else K1(double, PB, 1);                                                                   \
     }                                                                                           \
     return hipGetLastError();
-  // the pair kernel holds two rows of partial sums: direct up to p = 24; at
-  // p = 32, 40 its register count leaves 3 waves per SIMD and the staged
-  // kernel is faster (10M x 40: 745 against 1,132 us per C-step pass)
-#define DCASE(PB) CASE(DIRECT, DIRECT, PB)
-#define DSCASE(PB) CASE(DIRECT, STAGED, PB)
+  // pairs (ipt = 2) are only worth it for the staged buckets (the C-step
+  // loop asks for them there only, see dist_pairs_pay); a pair launch of a
+  // direct bucket takes the staged pair kernel
+#define DCASE(PB) CASE(DIRECT, STAGED, PB)
 #define SCASE(PB) CASE(STAGED, STAGED, PB)
   switch (bucket) {
-    RTD_PAIR_DIRECT_BUCKETS(DCASE)
-    RTD_PAIR_STAGED_BUCKETS(DSCASE)
+    RTD_DIRECT_BUCKETS(DCASE)
     RTD_STAGED_BUCKETS(SCASE)
     default: return hipErrorInvalidValue;
   }
 #undef SCASE
-#undef DSCASE
 #undef DCASE
 #undef CASE
 #undef STAGED
