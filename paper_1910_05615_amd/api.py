@@ -7,6 +7,7 @@ paper_1910_05615_amd.build``); nothing here falls back to a CPU path.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import dataclasses
 from typing import List, Optional, Sequence
 
@@ -200,26 +201,28 @@ class Fit:
 
 
 def _alloc_fit(X: torch.Tensor, q: int, m: int, h: int):
+    """The outputs of one fit, carved out of a single device allocation (one
+    allocator call per fit instead of fifteen)."""
     n, p = X.shape
     dev = X.device
-    f64 = dict(dtype=torch.float64, device=dev)
-    i32 = dict(dtype=torch.int32, device=dev)
-    F = Fit(mu=torch.empty(p, **f64), sigma=torch.empty(p, p, **f64),
-            mu_raw=torch.empty(p, **f64), sigma_raw=torch.empty(p, p, **f64),
-            logdet=torch.empty(2, **f64), dist=torch.empty(n, **f64),
-            outlier=torch.empty(n, dtype=torch.uint8, device=dev),
-            hsubset=torch.empty(q, h, **i32), block_status=torch.empty(q, **i32),
-            block_start=torch.empty(q, **i32), block_iters=torch.empty(q, **i32),
-            loc=torch.empty(p, **f64), scale=torch.empty(p, **f64),
-            n_w=torch.empty(1, dtype=torch.int64, device=dev),
-            rew_mask=torch.empty(n, dtype=torch.uint8, device=dev), q=q, m=m, h=h)
-    out = _lib.Out(mu=F.mu.data_ptr(), sigma=F.sigma.data_ptr(), mu_raw=F.mu_raw.data_ptr(),
-                   sigma_raw=F.sigma_raw.data_ptr(), logdet=F.logdet.data_ptr(),
-                   dist=F.dist.data_ptr(), outlier=F.outlier.data_ptr(),
-                   hsubset=F.hsubset.data_ptr(), block_status=F.block_status.data_ptr(),
-                   block_start=F.block_start.data_ptr(), block_iters=F.block_iters.data_ptr(),
-                   loc=F.loc.data_ptr(), scale=F.scale.data_ptr(), n_w=F.n_w.data_ptr(),
-                   rew_mask=F.rew_mask.data_ptr())
+    f64, i32, i64, u8 = torch.float64, torch.int32, torch.int64, torch.uint8
+    parts = [("mu", f64, (p,)), ("sigma", f64, (p, p)), ("mu_raw", f64, (p,)),
+             ("sigma_raw", f64, (p, p)), ("logdet", f64, (2,)), ("dist", f64, (n,)),
+             ("loc", f64, (p,)), ("scale", f64, (p,)), ("n_w", i64, (1,)),
+             ("hsubset", i32, (q, h)), ("block_status", i32, (q,)), ("block_start", i32, (q,)),
+             ("block_iters", i32, (q,)), ("outlier", u8, (n,)), ("rew_mask", u8, (n,))]
+    offs, total = [], 0
+    for _, dt, shape in parts:
+        total = (total + 255) // 256 * 256
+        offs.append(total)
+        total += math.prod(shape) * torch.empty((), dtype=dt).element_size()
+    buf = torch.empty(max(total, 1), dtype=u8, device=dev)
+    t = {}
+    for (name, dt, shape), off in zip(parts, offs):
+        nb = math.prod(shape) * torch.empty((), dtype=dt).element_size()
+        t[name] = buf[off:off + nb].view(dt).view(shape)
+    F = Fit(q=q, m=m, h=h, **t)
+    out = _lib.Out(**{name: t[name].data_ptr() for name, _, _ in parts})
     return F, out
 
 

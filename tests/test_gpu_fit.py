@@ -201,3 +201,28 @@ def test_random_partition_rejects_bad_permutations():
     check_fit(fits[0], ref, "good perm next to bad ones")
     with pytest.raises(P.RTDetMCDError):
         P.fit(X, n_chunks=2, perm=repeated)
+
+
+@pytest.mark.parametrize("p", [48, 64])
+def test_fit_wide_p_pair_tiles(p):
+    """p = 48, 64: the C-step distances take the staged kernel with both
+    starts of a block from one read of each row (pair tiles)."""
+    ds = synthdata.small_gaussian(7001, p, seed=p, dtype=np.float32, rho=0.4, eps=0.1,
+                                  kind="shift", gamma=8)
+    ref = oracle.fit(ds.X, n_chunks=2)
+    check_fit(_run(ds.X, n_chunks=2), ref, f"p={p}")
+
+
+def test_fit_strided_rows():
+    """Rows with a stride larger than p (a column slice of a wider array) take
+    the per-element load paths; same fit as the oracle on the same values."""
+    P = _P()
+    ds = synthdata.small_gaussian(30_007, 20, seed=12, dtype=np.float32, rho=0.5, eps=0.1,
+                                  kind="shift", gamma=8)
+    wide = np.zeros((ds.X.shape[0], 24), np.float32)
+    wide[:, :20] = ds.X
+    Xw = torch.from_numpy(wide).to(_dev())[:, :20]
+    assert Xw.stride(0) == 24
+    F = P.fit(Xw, n_chunks=3)
+    check_fit(F, oracle.fit(ds.X, n_chunks=3), "strided")
+    assert np.array_equal(F.rew_mask.cpu().numpy(), oracle.fit(ds.X, n_chunks=3).rew_mask)
