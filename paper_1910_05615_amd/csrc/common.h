@@ -109,7 +109,9 @@ inline bool rows_dense_at(const void* X, int64_t ld, int p, int dtype, int bucke
 // reads the rows twice (10^6 x 20: 35 against 37 us; x 40: 130 against 154).
 inline bool dist_pairs_pay(int bucket) { return bucket > 40; }
 // dense: every item of the launch satisfies rows_dense_at (the kernels then
-// skip the per-element path for narrower or strided rows).
+// skip the per-element path for narrower or strided rows).  ipt: 1, or 2 for
+// pair tiles (both starts of a block per tile), valid only where
+// dist_pairs_pay(bucket); otherwise hipErrorInvalidValue.
 hipError_t launch_dist(int bucket, int dtype, int dense, int ipt, const ItemDesc* items,
                        const Tile* tiles,
                        int ntiles, int tile_rows, const double* mtri, const double* mux,

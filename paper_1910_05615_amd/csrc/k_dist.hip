@@ -595,10 +595,11 @@ hipError_t launch_dist(int bucket, int dtype, int dense, int ipt, const ItemDesc
       else K1(double, PB, 1);                                                                   \
     }                                                                                           \
     return hipGetLastError();
-  // pairs (ipt = 2) are only worth it for the staged buckets (the C-step
-  // loop asks for them there only, see dist_pairs_pay); a pair launch of a
-  // direct bucket takes the staged pair kernel
-#define DCASE(PB) CASE(DIRECT, STAGED, PB)
+  // pairs (ipt = 2) exist for the staged buckets only (dist_pairs_pay): the
+  // direct buckets run one factor per launch, and a pair launch of one of
+  // them is an invalid request
+#define NOPAIR(T, PB, NI) return hipErrorInvalidValue
+#define DCASE(PB) CASE(DIRECT, NOPAIR, PB)
 #define SCASE(PB) CASE(STAGED, STAGED, PB)
   switch (bucket) {
     RTD_DIRECT_BUCKETS(DCASE)
@@ -607,6 +608,7 @@ hipError_t launch_dist(int bucket, int dtype, int dense, int ipt, const ItemDesc
   }
 #undef SCASE
 #undef DCASE
+#undef NOPAIR
 #undef CASE
 #undef STAGED
 #undef DIRECT
