@@ -179,7 +179,8 @@ double rtdetmcd_consistency(double alpha, int32_t p);
 
 /* Squared statistical distances d2[i] = ||L^{-1}(x_i - mu)||^2 of the n rows
  * of X, with L the lower Cholesky factor of Sigma (eq. statdist via Sec. 3.4).
- * mu [p] and L [p*p, lower triangle read] are device float64. */
+ * mu [p] and L [p*p, lower triangle read] are device float64.  n = 0 returns
+ * RTDETMCD_OK without reading or writing anything (pointers may be NULL). */
 rtdetmcd_status rtdetmcd_distances(rtdetmcd_handle h, const void* X, int32_t dtype, int64_t n,
                                    int32_t p, int64_t ld, const double* mu, const double* L,
                                    double* d2);
@@ -190,7 +191,8 @@ rtdetmcd_status rtdetmcd_distances(rtdetmcd_handle h, const void* X, int32_t dty
  * inverse of the lower Cholesky factor of Sigma, row-major (lower triangle
  * read), so that d2_i = ||Linv (x_i - mu)||^2.  dist [n] (float64, nullable)
  * receives sqrt(d2_i); outlier [n] (nullable) receives d2_i > cut, with
- * cut <= 0 meaning chi2_{p,0.975}.  One kernel launch. */
+ * cut <= 0 meaning chi2_{p,0.975}.  One kernel launch; n = 0 returns
+ * RTDETMCD_OK without reading or writing anything (pointers may be NULL). */
 rtdetmcd_status rtdetmcd_score(rtdetmcd_handle h, const void* X, int32_t dtype, int64_t n,
                                int32_t p, int64_t ld, const double* mu, const double* Linv,
                                double cut, double* dist, uint8_t* outlier);

@@ -64,7 +64,7 @@ def _dtype_code(X: torch.Tensor) -> int:
 def _check_X(X: torch.Tensor):
     if not X.is_cuda:
         raise ValueError("X must be a CUDA (HIP) tensor")
-    if X.dim() != 2 or X.stride(1) != 1:
+    if X.dim() != 2 or (X.numel() > 0 and X.stride(1) != 1):   # empty: any strides
         raise ValueError("X must be 2-D with unit column stride")
 
 

@@ -445,12 +445,13 @@ rtdetmcd_status rtdetmcd_distances(rtdetmcd_handle ctx, const void* X, int32_t d
                                    int32_t p, int64_t ld, const double* mu, const double* L,
                                    double* d2) {
   if (!ctx) return RTDETMCD_EINVAL;
+  if (n == 0 && p >= 1 && p <= RTDETMCD_MAX_P && (dtype == 0 || dtype == 1))
+    return RTDETMCD_OK;   // no rows: nothing is read or written
   if (!X || !mu || !L || !d2 || n < 0 || p < 1 || ld < p || (dtype != 0 && dtype != 1)) {
     ctx->err = "rtdetmcd_distances: bad argument";
     return RTDETMCD_EINVAL;
   }
   if (p > RTDETMCD_MAX_P) return RTDETMCD_EUNSUPPORTED;
-  if (n == 0) return RTDETMCD_OK;
   RTD_HIP(hipSetDevice(ctx->device));
   ItemSet S;
   ItemDesc d{};
@@ -481,12 +482,13 @@ rtdetmcd_status rtdetmcd_score(rtdetmcd_handle ctx, const void* X, int32_t dtype
                                int32_t p, int64_t ld, const double* mu, const double* Linv,
                                double cut, double* dist, uint8_t* outlier) {
   if (!ctx) return RTDETMCD_EINVAL;
+  if (n == 0 && p >= 1 && p <= RTDETMCD_MAX_P && (dtype == 0 || dtype == 1))
+    return RTDETMCD_OK;   // no rows: nothing is read or written
   if (!X || !mu || !Linv || n < 0 || p < 1 || ld < p || (dtype != 0 && dtype != 1)) {
     ctx->err = "rtdetmcd_score: bad argument";
     return RTDETMCD_EINVAL;
   }
   if (p > RTDETMCD_MAX_P) return RTDETMCD_EUNSUPPORTED;
-  if (n == 0) return RTDETMCD_OK;
   RTD_HIP(hipSetDevice(ctx->device));
   const double c = cut > 0.0 ? cut : chi2_quantile(0.975, p);
   RTD_HIP(launch_score(bucket_of(p), dtype, X, n, ld, p, mu, Linv, p, c, dist, outlier,

@@ -207,3 +207,26 @@ def test_dense_and_generic_row_paths_agree(p, dtype):
     ref = oracle.mahalanobis2(X.astype(np.float64), mu, L)
     np.testing.assert_allclose(ga.cpu().numpy(), ref, rtol=1e-11, atol=0)
     np.testing.assert_allclose(da.cpu().numpy(), np.sqrt(ref), rtol=1e-11)
+
+
+@pytest.mark.parametrize("p,dtype", [(20, "f32"), (1, "f64"), (3, "f32")])
+def test_score_and_distances_empty_and_tiny(p, dtype):
+    """n = 0 (nothing read or written), a single row, two rows and a ragged
+    257; p = 1 and 3 take the per-element row path of their bucket."""
+    P = _P()
+    rng = np.random.default_rng(500 + p)
+    S = _spd(p, rng)
+    mu = rng.standard_normal(p)
+    L = np.linalg.cholesky(S)
+    Linv = np.linalg.inv(L)
+    npdt = np.float32 if dtype == "f32" else np.float64
+    for n in (0, 1, 2, 257):
+        X = (rng.standard_normal((n, p)) * 2).astype(npdt)
+        Xt = torch.from_numpy(X).to(_dev())
+        d2 = P.distances(Xt, torch.from_numpy(mu), torch.from_numpy(L))
+        dist, flag = P.score(Xt, torch.from_numpy(mu), torch.from_numpy(Linv))
+        assert d2.shape == (n,) and dist.shape == (n,) and flag.shape == (n,)
+        if n:
+            ref = oracle.mahalanobis2(X.astype(np.float64), mu, L)
+            np.testing.assert_allclose(d2.cpu().numpy(), ref, rtol=1e-11, atol=1e-300)
+            np.testing.assert_allclose(dist.cpu().numpy(), np.sqrt(ref), rtol=1e-11)

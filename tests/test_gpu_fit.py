@@ -226,3 +226,12 @@ def test_fit_strided_rows():
     F = P.fit(Xw, n_chunks=3)
     check_fit(F, oracle.fit(ds.X, n_chunks=3), "strided")
     assert np.array_equal(F.rew_mask.cpu().numpy(), oracle.fit(ds.X, n_chunks=3).rew_mask)
+
+
+@pytest.mark.parametrize("n,p,dtype", [(12, 2, np.float64), (40, 1, np.float32),
+                                       (101, 5, np.float32)])
+def test_fit_smallest_sizes(n, p, dtype):
+    """The smallest fits the method admits (n > 2p, p < h < m): one block far
+    below every tile size."""
+    ds = synthdata.small_gaussian(n, p, seed=n + p, dtype=dtype, rho=0.3)
+    check_fit(_run(ds.X), oracle.fit(ds.X), f"n={n} p={p}")
