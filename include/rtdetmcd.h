@@ -37,7 +37,7 @@ typedef int32_t rtdetmcd_status;
 #define RTDETMCD_ENOMEM       -2   /* device allocation of the workspace failed */
 #define RTDETMCD_EDEVICE      -3   /* HIP runtime error (message in last_error) */
 #define RTDETMCD_ESINGULAR    -4   /* no block produced a valid fit */
-#define RTDETMCD_EUNSUPPORTED -6   /* p > RTDETMCD_MAX_P, unknown dtype, POOL_UNION */
+#define RTDETMCD_EUNSUPPORTED -6   /* p > RTDETMCD_MAX_P, too many blocks */
 
 #define RTDETMCD_MAX_P 64
 
@@ -63,8 +63,9 @@ typedef int32_t rtdetmcd_status;
 #define RTDETMCD_CSTEP_UPDATE 1 /* update from the swapped rows only (Sec. 3.5) */
 #define RTDETMCD_CSTEP_AUTO   2 /* update, with a full recompute when many rows swap */
 #define RTDETMCD_POOL_PRINTED 0 /* Sec. 4 step 7 formulas with block counts m */
-#define RTDETMCD_POOL_UNION   1 /* covariance of the union of the kept h-subsets;
-                                  not implemented: fits return EUNSUPPORTED */
+#define RTDETMCD_POOL_UNION   1 /* the text of Sec. 4 step 7: classical mean and
+                                  covariance of the union of the kept blocks'
+                                  h-subsets, times c(h/m) */
 #define RTDETMCD_LAUNCH_BATCHED 0 /* every block and start in the same launches */
 #define RTDETMCD_LAUNCH_PLAIN   1 /* one block, one start at a time, host-driven */
 

@@ -287,10 +287,6 @@ rtdetmcd_status check_opts(rtdetmcd_ctx* ctx, const rtdetmcd_opts* in, rtdetmcd_
     ctx->err = "invalid option value";
     return RTDETMCD_EINVAL;
   }
-  if (o.pool_mode == RTDETMCD_POOL_UNION) {
-    ctx->err = "pool_mode UNION is not available on the GPU path (PRINTED only)";
-    return RTDETMCD_EUNSUPPORTED;
-  }
   return RTDETMCD_OK;
 }
 

@@ -573,7 +573,7 @@ __global__ __launch_bounds__(256) void k_kl(const DsInfo* __restrict__ ds, ItemA
 // (block counts m, Lambda_l = (m-1) S_l).  The result is the start of the
 // first global item (reweighting).
 __global__ __launch_bounds__(256) void k_pool(DsInfo* __restrict__ ds, ItemArrays G, FitArrays F,
-                                              int first_ds) {
+                                              int first_ds, int union_mode) {
   __shared__ int order[4096];   // ceil(q/2) <= 4096 (q <= 8192 is enforced by the planner)
   __shared__ double mu[PMAX];
   __shared__ double dmu[PMAX];
@@ -606,13 +606,19 @@ __global__ __launch_bounds__(256) void k_pool(DsInfo* __restrict__ ds, ItemArray
     if (r < keep && r < 4096) order[r] = b;
   }
   __syncthreads();
-  const double m = (double)d.m;
+  // PRINTED: each kept block counts m rows with Lambda_l = (m - 1) Sigma_raw^(l)
+  // (c(alpha) included).  UNION: the kept blocks' h-subsets, disjoint, so
+  // pooling their (h, mean, Lambda_l = (h - 1) S_l) gives the classical mean
+  // and covariance of the union; S_l is Sigma_raw^(l) without c(alpha), which
+  // multiplies the pooled covariance once at the end.
+  const double m = union_mode ? (double)d.h : (double)d.m;
+  const double lf = union_mode ? ((double)d.h - 1.0) / d.calpha : (double)d.m - 1.0;
   const int g0 = d.glob0;
   double* Lam = G.sigz + (size_t)g0 * MSTRIDE;   // accumulates Lambda_pooled
   const int b0 = order[0];
   for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
     const int i = e / p, j = e % p;
-    Lam[i * PMAX + j] = (m - 1.0) * F.bsig[(size_t)b0 * MSTRIDE + i * PMAX + j];
+    Lam[i * PMAX + j] = lf * F.bsig[(size_t)b0 * MSTRIDE + i * PMAX + j];
   }
   for (int j = threadIdx.x; j < p; j += blockDim.x) mu[j] = F.bmu[(size_t)b0 * PMAX + j];
   double np = m;
@@ -624,7 +630,7 @@ __global__ __launch_bounds__(256) void k_pool(DsInfo* __restrict__ ds, ItemArray
     const double f = np * m / (np + m);
     for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
       const int i = e / p, j = e % p;
-      Lam[i * PMAX + j] += (m - 1.0) * F.bsig[(size_t)b * MSTRIDE + i * PMAX + j] +
+      Lam[i * PMAX + j] += lf * F.bsig[(size_t)b * MSTRIDE + i * PMAX + j] +
                            dmu[i] * dmu[j] * f;
     }
     for (int j = threadIdx.x; j < p; j += blockDim.x)
@@ -634,7 +640,8 @@ __global__ __launch_bounds__(256) void k_pool(DsInfo* __restrict__ ds, ItemArray
   }
   for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
     const int i = e / p, j = e % p;
-    const double v = 0.5 * (Lam[i * PMAX + j] + Lam[j * PMAX + i]) / (np - 1.0);
+    double v = 0.5 * (Lam[i * PMAX + j] + Lam[j * PMAX + i]) / (np - 1.0);
+    if (union_mode) v *= d.calpha;
     F.sigraw[(size_t)dd * MSTRIDE + i * PMAX + j] = v;
   }
   __syncthreads();
@@ -1008,10 +1015,11 @@ hipError_t launch_kl(const DsInfo* ds, ItemArrays A, FitArrays F, int first_blk,
   return hipGetLastError();
 }
 
-hipError_t launch_pool(DsInfo* ds, ItemArrays G, FitArrays F, int first_ds, int nds, int,
+hipError_t launch_pool(DsInfo* ds, ItemArrays G, FitArrays F, int first_ds, int nds, int pool_mode,
                        hipStream_t s) {
   if (nds <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pool, dim3(nds), dim3(256), 0, s, ds, G, F, first_ds);
+  hipLaunchKernelGGL(k_pool, dim3(nds), dim3(256), 0, s, ds, G, F, first_ds,
+                     pool_mode == RTDETMCD_POOL_UNION ? 1 : 0);
   return hipGetLastError();
 }
 

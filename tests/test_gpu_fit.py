@@ -235,3 +235,18 @@ def test_fit_smallest_sizes(n, p, dtype):
     below every tile size."""
     ds = synthdata.small_gaussian(n, p, seed=n + p, dtype=dtype, rho=0.3)
     check_fit(_run(ds.X), oracle.fit(ds.X), f"n={n} p={p}")
+
+
+@pytest.mark.parametrize("n,p,q,dtype", [(60_011, 10, 8, np.float32), (20_000, 5, 3, np.float64)])
+def test_fit_union_pooling(n, p, q, dtype):
+    """POOL_UNION (the text of Sec. 4 step 7): the GPU pools the kept blocks'
+    subset statistics; the oracle takes the covariance of the union of the
+    kept h-subsets directly."""
+    ds = synthdata.small_gaussian(n, p, seed=q + p, dtype=dtype, rho=0.5, eps=0.1,
+                                  kind="shift", gamma=8)
+    ref = oracle.fit(ds.X, n_chunks=q, pool="union")
+    F = _run(ds.X, n_chunks=q, pool="union")
+    check_fit(F, ref, f"union n={n} p={p} q={q}")
+    # the two readings differ (block counts m against h): the option is live
+    printed = oracle.fit(ds.X, n_chunks=q)
+    assert _relF(printed.sigma_raw, ref.sigma_raw) > 1e-6
