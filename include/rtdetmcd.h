@@ -37,6 +37,8 @@ typedef int32_t rtdetmcd_status;
 #define RTDETMCD_ENOMEM       -2   /* device allocation of the workspace failed */
 #define RTDETMCD_EDEVICE      -3   /* HIP runtime error (message in last_error) */
 #define RTDETMCD_ESINGULAR    -4   /* no block produced a valid fit */
+#define RTDETMCD_ENONFINITE   -5   /* X holds NaN or Inf (fits: that dataset; its outputs are
+                                      not meaningful) */
 #define RTDETMCD_EUNSUPPORTED -6   /* p > RTDETMCD_MAX_P, too many blocks */
 
 #define RTDETMCD_MAX_P 64

@@ -432,7 +432,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     const SortHost& Hs = D[k].dtype == 0 ? S32 : S64;
     SortDev& Ds = D[k].dtype == 0 ? D32 : D64;
     char* kb = static_cast<char*>(Ds.plan.keys) + Hs.off[std_seg0[k]] * Hs.key_bytes;
-    RTD_HIP(launch_colkeys(D[k].dtype, D[k].in->X, D[k].n, D[k].ld, D[k].p, kb, st));
+    RTD_HIP(launch_colkeys(D[k].dtype, D[k].in->X, D[k].n, D[k].ld, D[k].p, kb, &dds[k].err, st));
   }
   RTD_TRY(sort_stats(ctx, S32, D32, 0, S32.nseg(), smode, q1, crew1));
   RTD_TRY(sort_stats(ctx, S64, D64, 0, S64.nseg(), smode, q1, crew1));
@@ -567,8 +567,9 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     if (s != RTDETMCD_OK) {
       ret = s;
       ctx->err = "dataset " + std::to_string(orig) +
-                 (s == RTDETMCD_EINVAL ? ": perm is not a permutation of the rows"
-                                       : ": no valid fit (degenerate data)");
+                 (s == RTDETMCD_EINVAL       ? ": perm is not a permutation of the rows"
+                  : s == RTDETMCD_ENONFINITE ? ": X holds NaN or Inf values"
+                                             : ": no valid fit (degenerate data)");
     }
   }
   return nd == 1 ? ret : RTDETMCD_OK;

@@ -48,8 +48,10 @@ struct FitArrays {
   double* rS;        // [I*MSTRIDE]
 };
 
+// Column-major order keys of X for the standardisation sort; a NaN or Inf
+// anywhere in X sets *err = RTDETMCD_ENONFINITE.
 hipError_t launch_colkeys(int dtype, const void* X, int64_t n, int64_t ld, int p, void* keys,
-                          hipStream_t s);
+                          int32_t* err, hipStream_t s);
 hipError_t launch_std_finish(const SegStat* st32, const SegStat* st64, const int32_t* seg0,
                              const int32_t* in64, int D, DsInfo* ds, FitArrays F, hipStream_t s);
 hipError_t launch_project(int bucket, int dtype, int mode, const ItemDesc* items,

@@ -31,7 +31,8 @@ constexpr int CK_NT = 256;
 
 template <typename T, typename K>
 __global__ __launch_bounds__(CK_NT) void k_colkeys(const T* __restrict__ X, int64_t n, int64_t ld,
-                                                   int p, K* __restrict__ keys) {
+                                                   int p, K* __restrict__ keys,
+                                                   int32_t* __restrict__ err) {
   __shared__ K tile[CK_ROWS * (PMAX + 1)];   // row-major, row stride p + 1
   const int64_t r0 = (int64_t)blockIdx.x * CK_ROWS;
   const int nr = (int)min((int64_t)CK_ROWS, n - r0);
@@ -40,8 +41,10 @@ __global__ __launch_bounds__(CK_NT) void k_colkeys(const T* __restrict__ X, int6
     int i = tid / p, j = tid - (tid / p) * p;
     const int di = CK_NT / p, dj = CK_NT - (CK_NT / p) * p;
     const T* __restrict__ xb = X + r0 * ld;
+    bool finite = true;   // every value of X passes through here once
     for (int e = tid; e < nr * p; e += CK_NT) {
       const T x = xb[(int64_t)i * ld + j];
+      finite = finite && isfinite(x);
       if constexpr (sizeof(K) == 4) tile[i * pp + j] = fkey32((float)x);
       else tile[i * pp + j] = fkey64((double)x);
       i += di;
@@ -51,6 +54,7 @@ __global__ __launch_bounds__(CK_NT) void k_colkeys(const T* __restrict__ X, int6
         ++i;
       }
     }
+    if (!finite) *err = RTDETMCD_ENONFINITE;
   }
   __syncthreads();
   for (int e = tid; e < p * CK_ROWS; e += CK_NT) {
@@ -73,7 +77,7 @@ __global__ void k_std_finish(const SegStat* __restrict__ st32, const SegStat* __
       loc = s.mu;
       sc = sqrt(s.var);
       if (!(sc > 0.0) || !(sc < 1e300) || !(fabs(loc) < 1e300)) {
-        ds[d].err = RTDETMCD_ESINGULAR;
+        if (ds[d].err == 0) ds[d].err = RTDETMCD_ESINGULAR;   // keep an earlier ENONFINITE
         loc = 0.0;
         sc = 1.0;
       }
@@ -914,16 +918,16 @@ hipError_t project_t(const ItemDesc* items, const Tile* tiles, int ntiles, int t
 }  // namespace
 
 hipError_t launch_colkeys(int dtype, const void* X, int64_t n, int64_t ld, int p, void* keys,
-                          hipStream_t s) {
+                          int32_t* err, hipStream_t s) {
   const int64_t nb = (n + CK_ROWS - 1) / CK_ROWS;
   if (nb < 1 || p < 1) return hipSuccess;
   if (nb > 0x7fffffff || p > PMAX) return hipErrorInvalidValue;
   if (dtype == 0)
     hipLaunchKernelGGL((k_colkeys<float, uint32_t>), dim3((unsigned)nb), dim3(CK_NT), 0, s,
-                       static_cast<const float*>(X), n, ld, p, static_cast<uint32_t*>(keys));
+                       static_cast<const float*>(X), n, ld, p, static_cast<uint32_t*>(keys), err);
   else
     hipLaunchKernelGGL((k_colkeys<double, uint64_t>), dim3((unsigned)nb), dim3(CK_NT), 0, s,
-                       static_cast<const double*>(X), n, ld, p, static_cast<uint64_t*>(keys));
+                       static_cast<const double*>(X), n, ld, p, static_cast<uint64_t*>(keys), err);
   return hipGetLastError();
 }
 

@@ -250,3 +250,20 @@ def test_fit_union_pooling(n, p, q, dtype):
     # the two readings differ (block counts m against h): the option is live
     printed = oracle.fit(ds.X, n_chunks=q)
     assert _relF(printed.sigma_raw, ref.sigma_raw) > 1e-6
+
+
+def test_fit_nonfinite_input_is_an_error():
+    """NaN or Inf anywhere in X: that dataset reports RTDETMCD_ENONFINITE
+    (-5); the other datasets of the batch are fitted as usual."""
+    P = _P()
+    ds = synthdata.small_gaussian(5000, 4, seed=9, dtype=np.float32, rho=0.3)
+    good = torch.from_numpy(ds.X).to(_dev())
+    nan = good.clone()
+    nan[123, 2] = float("nan")
+    inf = good.clone()
+    inf[4999, 0] = float("-inf")
+    fits, status = P.fit_batched([nan, good, inf], n_chunks=[2, 2, 2])
+    assert status == [-5, 0, -5]
+    check_fit(fits[1], oracle.fit(ds.X, n_chunks=2), "finite next to non-finite")
+    with pytest.raises(P.RTDetMCDError):
+        P.fit(nan, n_chunks=2)
