@@ -565,8 +565,8 @@ __global__ __launch_bounds__(SS_NT) void k_segstats(const K* __restrict__ keys,
 // Sort one segment of at most LDS_KEYS keys entirely in LDS (LSD radix on
 // 8-bit digits), then run the estimator on the sorted LDS copy.  With KPT
 // keys per thread, wave w holds the keys at positions w*KPT*64 + i*64 + lane,
-// i < KPT, so ranks follow position order; KPT is the smallest of 4, 8, 12, 16
-// that holds the segment, so short segments sort no padding.
+// i < KPT, so ranks follow position order; KPT is the smallest even number
+// from 4 to 16 that holds the segment, so little padding is sorted.
 //
 // The passes run on a 32-bit key: the key itself for float data, and for
 // double data the high half of the order key (sign, exponent and 20 mantissa
@@ -1193,23 +1193,32 @@ hipError_t sort_segments(SortPlan& P, hipStream_t s) {
 hipError_t launch_seg_lds(const SortPlan& P, const double* seg_craw, double q1, double crew,
                           int mode, SegStat* out, int64_t max_len, hipStream_t s) {
   if (P.nseg <= 0) return hipSuccess;
-  // keys per thread: the smallest of 4, 8, 12, 16 that holds the longest segment
-  const int kpt = max_len <= 4 * SS_NT ? 4 : max_len <= 8 * SS_NT ? 8 : max_len <= 12 * SS_NT ? 12 : 16;
+  // keys per thread: the smallest of 4, 6, ..., 16 that holds the longest
+  // segment (the passes work on every slot, padding included: 9,765-row
+  // blocks take 10,240 slots, not 12,288)
+  int kpt = 16;
+  for (const int k : {4, 6, 8, 10, 12, 14})
+    if (max_len <= (int64_t)k * SS_NT) { kpt = k; break; }
 #define SEG_LDS(K, KPT)                                                                        \
   hipLaunchKernelGGL((k_seg_lds<K, KPT>), dim3(P.nseg), dim3(SS_NT), 0, s,                     \
                      static_cast<const K*>(P.keys), P.seg_off, P.seg_len, seg_craw, P.seg_first, \
                      q1, crew, mode, out)
-  if (P.key_bytes == 4) {
-    if (kpt == 4) SEG_LDS(uint32_t, 4);
-    else if (kpt == 8) SEG_LDS(uint32_t, 8);
-    else if (kpt == 12) SEG_LDS(uint32_t, 12);
-    else SEG_LDS(uint32_t, 16);
-  } else {
-    if (kpt == 4) SEG_LDS(uint64_t, 4);
-    else if (kpt == 8) SEG_LDS(uint64_t, 8);
-    else if (kpt == 12) SEG_LDS(uint64_t, 12);
-    else SEG_LDS(uint64_t, 16);
+#define BY_KPT(K)                        \
+  switch (kpt) {                         \
+    case 4: SEG_LDS(K, 4); break;        \
+    case 6: SEG_LDS(K, 6); break;        \
+    case 8: SEG_LDS(K, 8); break;        \
+    case 10: SEG_LDS(K, 10); break;      \
+    case 12: SEG_LDS(K, 12); break;      \
+    case 14: SEG_LDS(K, 14); break;      \
+    default: SEG_LDS(K, 16); break;      \
   }
+  if (P.key_bytes == 4) {
+    BY_KPT(uint32_t)
+  } else {
+    BY_KPT(uint64_t)
+  }
+#undef BY_KPT
 #undef SEG_LDS
   return hipGetLastError();
 }
