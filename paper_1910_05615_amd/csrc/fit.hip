@@ -263,6 +263,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   const size_t o_nkb = L.add((size_t)NB * 8), o_rkb = L.add((size_t)NC * 8);
   const size_t o_rseg0 = L.add((size_t)NC * 4);
   const size_t o_sflag = L.add(8);
+  const size_t o_cjobs = L.add((size_t)ND * sizeof(ColJob));
   SortDev D32, D64, DN, DR;
   layout_sort(L, S32, D32);
   layout_sort(L, S64, D64);
@@ -386,7 +387,30 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     houts[k] = D[k].in->out;
     hchi[k] = D[k].chi2p;
   }
+  // column-key jobs of the standardisation: float datasets, then double ones
+  std::vector<ColJob> cjobs;
+  int64_t ctiles[2] = {0, 0};
+  int ncjobs[2] = {0, 0};
+  for (int t = 0; t < 2; ++t)
+    for (int k = 0; k < ND; ++k) {
+      if (D[k].dtype != t) continue;
+      const SortHost& Hs = t == 0 ? S32 : S64;
+      const SortDev& Ds = t == 0 ? D32 : D64;
+      ColJob j{};
+      j.X = D[k].in->X;
+      j.keys = static_cast<char*>(Ds.plan.keys) + Hs.off[std_seg0[k]] * Hs.key_bytes;
+      j.err = &dds[k].err;
+      j.n = D[k].n;
+      j.ld = D[k].ld;
+      j.p = D[k].p;
+      j.tile0 = ctiles[t];
+      ctiles[t] += (D[k].n + COLKEY_ROWS - 1) / COLKEY_ROWS;
+      ++ncjobs[t];
+      cjobs.push_back(j);
+    }
+  ColJob* dcjobs = reinterpret_cast<ColJob*>(base + o_cjobs);
   Uploader up;
+  up.add(dcjobs, cjobs.data(), cjobs.size());
   up.add(CD.items, C.items.data(), C.items.size());
   up.add(CD.dtiles, C.dtiles.data(), C.dtiles.size());
   up.add(CD.stiles, C.stiles.data(), C.stiles.size());
@@ -428,12 +452,8 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   }
   // ---------------------------------------------------------------- step 0: standardisation
   RTD_HIP(launch_fill_i32(sflag, 0, 1, st));
-  for (int k = 0; k < ND; ++k) {
-    const SortHost& Hs = D[k].dtype == 0 ? S32 : S64;
-    SortDev& Ds = D[k].dtype == 0 ? D32 : D64;
-    char* kb = static_cast<char*>(Ds.plan.keys) + Hs.off[std_seg0[k]] * Hs.key_bytes;
-    RTD_HIP(launch_colkeys(D[k].dtype, D[k].in->X, D[k].n, D[k].ld, D[k].p, kb, &dds[k].err, st));
-  }
+  RTD_HIP(launch_colkeys(0, dcjobs, ncjobs[0], ctiles[0], st));
+  RTD_HIP(launch_colkeys(1, dcjobs + ncjobs[0], ncjobs[1], ctiles[1], st));
   RTD_TRY(sort_stats(ctx, S32, D32, 0, S32.nseg(), smode, q1, crew1));
   RTD_TRY(sort_stats(ctx, S64, D64, 0, S64.nseg(), smode, q1, crew1));
   RTD_HIP(launch_std_finish(D32.st, D64.st, dstd_seg0, din64, ND, dds, F, st));

@@ -48,10 +48,23 @@ struct FitArrays {
   double* rS;        // [I*MSTRIDE]
 };
 
-// Column-major order keys of X for the standardisation sort; a NaN or Inf
-// anywhere in X sets *err = RTDETMCD_ENONFINITE.
-hipError_t launch_colkeys(int dtype, const void* X, int64_t n, int64_t ld, int p, void* keys,
-                          int32_t* err, hipStream_t s);
+// One dataset of a column-key launch: its n x p rows (stride ld) become p
+// columns of order keys at `keys` (column j at keys + j n); a NaN or Inf
+// sets *err = RTDETMCD_ENONFINITE.  tile0: its first block in the launch
+// (CK tiles of 128 rows; jobs in increasing tile0).
+struct ColJob {
+  const void* X;
+  void* keys;
+  int32_t* err;
+  int64_t n, ld;
+  int64_t tile0;
+  int32_t p, pad;
+};
+constexpr int COLKEY_ROWS = 128;   // rows per block of the column-key kernel
+// Column-major order keys of the datasets of one element type (0 = f32 with
+// 32-bit keys, 1 = f64 with 64-bit keys) for the standardisation sort.
+hipError_t launch_colkeys(int dtype, const ColJob* jobs, int njobs, int64_t ntiles,
+                          hipStream_t s);
 hipError_t launch_std_finish(const SegStat* st32, const SegStat* st64, const int32_t* seg0,
                              const int32_t* in64, int D, DsInfo* ds, FitArrays F, hipStream_t s);
 hipError_t launch_project(int bucket, int dtype, int mode, const ItemDesc* items,

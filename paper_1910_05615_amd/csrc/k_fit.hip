@@ -26,15 +26,25 @@ __device__ inline double ldx(const T* __restrict__ p, int64_t i) { return (doubl
 // Column-major order keys of the columns of X: a tile of CK_ROWS rows is read
 // row by row (contiguous when ld == p), turned into keys in LDS and written
 // column by column, so that both sides are coalesced.
-constexpr int CK_ROWS = 128;
+constexpr int CK_ROWS = COLKEY_ROWS;
 constexpr int CK_NT = 256;
 
 template <typename T, typename K>
-__global__ __launch_bounds__(CK_NT) void k_colkeys(const T* __restrict__ X, int64_t n, int64_t ld,
-                                                   int p, K* __restrict__ keys,
-                                                   int32_t* __restrict__ err) {
+__global__ __launch_bounds__(CK_NT) void k_colkeys(const ColJob* __restrict__ jobs, int njobs) {
   __shared__ K tile[CK_ROWS * (PMAX + 1)];   // row-major, row stride p + 1
-  const int64_t r0 = (int64_t)blockIdx.x * CK_ROWS;
+  // this block's dataset: the last job whose first tile is <= blockIdx.x
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (jobs[mid].tile0 <= (int64_t)blockIdx.x) lo = mid;
+    else hi = mid - 1;
+  }
+  const ColJob J = jobs[lo];
+  const T* __restrict__ X = static_cast<const T*>(J.X);
+  K* __restrict__ keys = static_cast<K*>(J.keys);
+  const int64_t n = J.n, ld = J.ld;
+  const int p = J.p;
+  const int64_t r0 = ((int64_t)blockIdx.x - J.tile0) * CK_ROWS;
   const int nr = (int)min((int64_t)CK_ROWS, n - r0);
   const int pp = p + 1, tid = threadIdx.x;
   {
@@ -54,7 +64,7 @@ __global__ __launch_bounds__(CK_NT) void k_colkeys(const T* __restrict__ X, int6
         ++i;
       }
     }
-    if (!finite) *err = RTDETMCD_ENONFINITE;
+    if (!finite) *J.err = RTDETMCD_ENONFINITE;
   }
   __syncthreads();
   for (int e = tid; e < p * CK_ROWS; e += CK_NT) {
@@ -917,17 +927,16 @@ hipError_t project_t(const ItemDesc* items, const Tile* tiles, int ntiles, int t
 
 }  // namespace
 
-hipError_t launch_colkeys(int dtype, const void* X, int64_t n, int64_t ld, int p, void* keys,
-                          int32_t* err, hipStream_t s) {
-  const int64_t nb = (n + CK_ROWS - 1) / CK_ROWS;
-  if (nb < 1 || p < 1) return hipSuccess;
-  if (nb > 0x7fffffff || p > PMAX) return hipErrorInvalidValue;
+hipError_t launch_colkeys(int dtype, const ColJob* jobs, int njobs, int64_t ntiles,
+                          hipStream_t s) {
+  if (njobs <= 0 || ntiles <= 0) return hipSuccess;
+  if (ntiles > 0x7fffffff) return hipErrorInvalidValue;
   if (dtype == 0)
-    hipLaunchKernelGGL((k_colkeys<float, uint32_t>), dim3((unsigned)nb), dim3(CK_NT), 0, s,
-                       static_cast<const float*>(X), n, ld, p, static_cast<uint32_t*>(keys), err);
+    hipLaunchKernelGGL((k_colkeys<float, uint32_t>), dim3((unsigned)ntiles), dim3(CK_NT), 0, s,
+                       jobs, njobs);
   else
-    hipLaunchKernelGGL((k_colkeys<double, uint64_t>), dim3((unsigned)nb), dim3(CK_NT), 0, s,
-                       static_cast<const double*>(X), n, ld, p, static_cast<uint64_t*>(keys), err);
+    hipLaunchKernelGGL((k_colkeys<double, uint64_t>), dim3((unsigned)ntiles), dim3(CK_NT), 0, s,
+                       jobs, njobs);
   return hipGetLastError();
 }
 
