@@ -18,6 +18,7 @@
 
 #include "common.h"
 #include "fitk.h"
+#include "rowload.h"
 
 namespace rtd {
 
@@ -257,16 +258,6 @@ struct RowVec {
   static constexpr int E = VB / (int)sizeof(T);   // elements per load
 };
 
-// X as a global-memory pointer: rows reached through the item table would
-// otherwise be read with flat loads (the compiler cannot tell the address
-// space of a pointer loaded from memory).
-template <typename T>
-using gptr_t = const T __attribute__((address_space(1)))*;
-template <typename T>
-__device__ inline gptr_t<T> as_global(const T* p) {
-  return (gptr_t<T>)p;
-}
-
 // Row r of a dense, VB-aligned row-major matrix of P columns.
 template <typename T, int P>
 __device__ inline void load_row_vec(const T* xr_, T (&v)[P]) {
@@ -310,17 +301,6 @@ __device__ inline double col_norm2_g(const double* __restrict__ Mg, int ldm, int
   for (int i = 0; i < P; ++i)
     if (i < p) acc = fma(y[i], y[i], acc);
   return acc;
-}
-
-// Every element of the row in a register at this point: all of the row's
-// loads are in flight together.  Without it the compiler issues the later
-// columns' loads after the first columns' FMAs (they are not needed before),
-// and a wave waits for memory up to three times (1M x 20 scoring: 20.0
-// against 17.7 us).  The empty statements emit no instructions.
-template <typename T, int P>
-__device__ inline void all_loaded(T (&v)[P]) {
-#pragma unroll
-  for (int j = 0; j < P; ++j) asm volatile("" : "+v"(v[j]));
 }
 
 template <typename T, int P, int NI, typename Emit>

@@ -3,6 +3,7 @@
 // per-block float64 steps, robust aggregation and reweighting.
 #include "../../include/rtdetmcd.h"
 #include "fitk.h"
+#include "rowload.h"
 #include "wave.h"
 
 namespace rtd {
@@ -18,8 +19,6 @@ __device__ inline uint64_t fkey64(double f) {
   return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
 }
 
-template <typename T>
-__device__ inline double ldx(const T* __restrict__ p, int64_t i) { return (double)p[i]; }
 
 // ------------------------------------------------------------ standardisation
 
@@ -102,48 +101,52 @@ __global__ void k_std_finish(const SegStat* __restrict__ st32, const SegStat* __
 //         W = V^T gives the scores T = Z V, W = Sigma^{-1/2} the sphered data).
 // MODE 1: v = ||z|| (GSSCM norms), one segment.
 // z = (x - loc) / scale, the standardised row (Sec. 3.1, Sec. 4 eq. standardization).
+// One row per thread, 256 rows per block (tile_rows / 256 blocks per tile):
+// the row's loads all issued before its arithmetic, loc and scale read at
+// uniform offsets (scalar unit).
+constexpr int PROJ_ROWS = 256;
 template <typename T, int P, int MODE>
-__global__ __launch_bounds__(256) void k_project(const ItemDesc* __restrict__ items,
-                                                 const Tile* __restrict__ tiles, int tile_rows,
-                                                 const int32_t* __restrict__ status,
-                                                 const double* __restrict__ W,
-                                                 const int64_t* __restrict__ kbase,
-                                                 uint64_t* __restrict__ keys) {
-  const Tile tl = tiles[blockIdx.x];
+__global__ __launch_bounds__(PROJ_ROWS) void k_project(const ItemDesc* __restrict__ items,
+                                                       const Tile* __restrict__ tiles,
+                                                       int tile_rows,
+                                                       const int32_t* __restrict__ status,
+                                                       const double* __restrict__ W,
+                                                       const int64_t* __restrict__ kbase,
+                                                       uint64_t* __restrict__ keys) {
+  const int nsub = tile_rows / PROJ_ROWS;
+  const Tile tl = tiles[blockIdx.x / nsub];
   const int it = tl.item;
   if (status != nullptr && status[it] != ACTIVE) return;
   const ItemDesc D = items[it];
+  const int64_t t0 = (int64_t)tl.t * tile_rows;
+  const int64_t r = t0 + (int64_t)(blockIdx.x % nsub) * PROJ_ROWS + threadIdx.x;
+  if (r >= min(t0 + (int64_t)tile_rows, D.m)) return;
   const int p = D.p;
-  const T* __restrict__ X = static_cast<const T*>(D.X) + D.row0 * D.ld;
+  const double* __restrict__ loc = D.loc;
+  const double* __restrict__ sc = D.scale;
   const double* __restrict__ Wi = W + (size_t)it * MSTRIDE;
   uint64_t* __restrict__ ko = keys + kbase[it];
-  double loc[P], isc[P];
+  const gptr_t<T> xr = as_global(static_cast<const T*>(D.X) + (D.row0 + r) * D.ld);
+  T x[P];
 #pragma unroll
-  for (int k = 0; k < P; ++k) {
-    loc[k] = k < p ? D.loc[k] : 0.0;
-    isc[k] = k < p ? D.scale[k] : 1.0;
-  }
-  const int64_t r0 = (int64_t)tl.t * tile_rows;
-  const int64_t r1 = min(r0 + (int64_t)tile_rows, D.m);
-  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-    const T* __restrict__ xr = X + r * D.ld;
-    double z[P];
+  for (int k = 0; k < P; ++k) x[k] = k < p ? xr[k] : (T)0;
+  all_loaded(x);
+  double z[P];
 #pragma unroll
-    for (int k = 0; k < P; ++k) z[k] = (k < p) ? (ldx(xr, k) - loc[k]) / isc[k] : 0.0;
-    if (MODE == 1) {
-      double s = 0.0;
+  for (int k = 0; k < P; ++k) z[k] = (k < p) ? ((double)x[k] - loc[k]) / sc[k] : 0.0;
+  if (MODE == 1) {
+    double s = 0.0;
 #pragma unroll
-      for (int k = 0; k < P; ++k) s = fma(z[k], z[k], s);
-      ko[r] = fkey64(sqrt(s));
-    } else {
+    for (int k = 0; k < P; ++k) s = fma(z[k], z[k], s);
+    ko[r] = fkey64(sqrt(s));
+  } else {
 #pragma unroll
-      for (int j = 0; j < P; ++j) {
-        if (j < p) {
-          double v = 0.0;
+    for (int j = 0; j < P; ++j) {
+      if (j < p) {
+        double v = 0.0;
 #pragma unroll
-          for (int k = 0; k < P; ++k) v = fma(Wi[j * PMAX + k], z[k], v);
-          ko[(size_t)j * D.m + r] = fkey64(v);
-        }
+        for (int k = 0; k < P; ++k) v = fma(Wi[j * PMAX + k], z[k], v);
+        ko[(size_t)j * D.m + r] = fkey64(v);
       }
     }
   }
@@ -919,9 +922,11 @@ hipError_t project_t(const ItemDesc* items, const Tile* tiles, int ntiles, int t
   if constexpr (MODE == 0 && P >= 16)
     hipLaunchKernelGGL((k_project_mfma<T, P>), dim3(ntiles), dim3(256), 0, s, items, tiles,
                        tile_rows, status, W, kbase, keys);
-  else
-    hipLaunchKernelGGL((k_project<T, P, MODE>), dim3(ntiles), dim3(256), 0, s, items, tiles,
-                       tile_rows, status, W, kbase, keys);
+  else {
+    if (tile_rows % PROJ_ROWS != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_project<T, P, MODE>), dim3(ntiles * (tile_rows / PROJ_ROWS)),
+                       dim3(PROJ_ROWS), 0, s, items, tiles, tile_rows, status, W, kbase, keys);
+  }
   return hipGetLastError();
 }
 
