@@ -593,7 +593,6 @@ __global__ __launch_bounds__(256) void k_pool(DsInfo* __restrict__ ds, ItemArray
                                               int first_ds, int union_mode) {
   __shared__ int order[4096];   // ceil(q/2) <= 4096 (q <= 8192 is enforced by the planner)
   __shared__ double mu[PMAX];
-  __shared__ double dmu[PMAX];
   __shared__ int nvs;
   const int dd = first_ds + blockIdx.x;
   DsInfo d = ds[dd];
@@ -628,33 +627,33 @@ __global__ __launch_bounds__(256) void k_pool(DsInfo* __restrict__ ds, ItemArray
   // pooling their (h, mean, Lambda_l = (h - 1) S_l) gives the classical mean
   // and covariance of the union; S_l is Sigma_raw^(l) without c(alpha), which
   // multiplies the pooled covariance once at the end.
+  // The pooled pair in closed form (what merging the blocks one after the
+  // other gives, up to rounding): mu = sum_l m mu_l / N and Lambda =
+  // sum_l [Lambda_l + m (mu_l - mu)(mu_l - mu)^T]; every entry is its own sum
+  // over the kept blocks, taken in KL order.
   const double m = union_mode ? (double)d.h : (double)d.m;
   const double lf = union_mode ? ((double)d.h - 1.0) / d.calpha : (double)d.m - 1.0;
   const int g0 = d.glob0;
-  double* Lam = G.sigz + (size_t)g0 * MSTRIDE;   // accumulates Lambda_pooled
-  const int b0 = order[0];
+  double* Lam = G.sigz + (size_t)g0 * MSTRIDE;   // Lambda_pooled
+  const int nk = keep < 4096 ? keep : 4096;
+  const double np = m * nk;
+  for (int j = threadIdx.x; j < p; j += blockDim.x) {
+    double s = 0.0;
+    for (int r = 0; r < nk; ++r) s += F.bmu[(size_t)order[r] * PMAX + j];
+    mu[j] = s / nk;
+  }
+  __syncthreads();
   for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
     const int i = e / p, j = e % p;
-    Lam[i * PMAX + j] = lf * F.bsig[(size_t)b0 * MSTRIDE + i * PMAX + j];
-  }
-  for (int j = threadIdx.x; j < p; j += blockDim.x) mu[j] = F.bmu[(size_t)b0 * PMAX + j];
-  double np = m;
-  __syncthreads();
-  for (int r = 1; r < keep && r < 4096; ++r) {
-    const int b = order[r];
-    for (int j = threadIdx.x; j < p; j += blockDim.x) dmu[j] = F.bmu[(size_t)b * PMAX + j] - mu[j];
-    __syncthreads();
-    const double f = np * m / (np + m);
-    for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
-      const int i = e / p, j = e % p;
-      Lam[i * PMAX + j] += lf * F.bsig[(size_t)b * MSTRIDE + i * PMAX + j] +
-                           dmu[i] * dmu[j] * f;
+    double a = 0.0, c = 0.0;
+    for (int r = 0; r < nk; ++r) {
+      const int b = order[r];
+      a += F.bsig[(size_t)b * MSTRIDE + i * PMAX + j];
+      c = fma(F.bmu[(size_t)b * PMAX + i] - mu[i], F.bmu[(size_t)b * PMAX + j] - mu[j], c);
     }
-    for (int j = threadIdx.x; j < p; j += blockDim.x)
-      mu[j] = (np * mu[j] + m * F.bmu[(size_t)b * PMAX + j]) / (np + m);
-    np += m;
-    __syncthreads();
+    Lam[i * PMAX + j] = lf * a + m * c;
   }
+  __syncthreads();
   for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
     const int i = e / p, j = e % p;
     double v = 0.5 * (Lam[i * PMAX + j] + Lam[j * PMAX + i]) / (np - 1.0);
