@@ -494,6 +494,7 @@ __global__ __launch_bounds__(256) void k_choose(const ItemDesc* __restrict__ bit
 // is mu_e, otherwise a lower-triangle entry of Sigma.
 __global__ __launch_bounds__(256) void k_median(const DsInfo* __restrict__ ds, FitArrays F,
                                                 const int2* __restrict__ ent) {
+  __shared__ double vs[8192];   // the entry of every valid block (q <= 8192), any order
   __shared__ double lo_v, hi_v;
   __shared__ int nvs;
   const int2 de = ent[blockIdx.x];
@@ -509,22 +510,20 @@ __global__ __launch_bounds__(256) void k_median(const DsInfo* __restrict__ ds, F
   auto val = [&](int b) -> double {
     return i < 0 ? F.bmu[(size_t)b * PMAX + de.y] : F.bsig[(size_t)b * MSTRIDE + i * PMAX + j];
   };
-  if (threadIdx.x == 0) {
-    int c = 0;
-    for (int b = d.blk0; b < d.blk0 + d.q; ++b) c += F.bitem[b] >= 0;
-    nvs = c;
-  }
+  if (threadIdx.x == 0) nvs = 0;
+  __syncthreads();
+  // the valid blocks' values, gathered in LDS once (ranks depend on values only)
+  for (int b = d.blk0 + threadIdx.x; b < d.blk0 + d.q; b += blockDim.x)
+    if (F.bitem[b] >= 0) vs[atomicAdd(&nvs, 1)] = val(b);
   __syncthreads();
   const int nv = nvs;
   if (nv == 0) return;
   const int k1 = (nv - 1) / 2, k2 = nv / 2;
-  for (int b = d.blk0 + threadIdx.x; b < d.blk0 + d.q; b += blockDim.x) {
-    if (F.bitem[b] < 0) continue;
-    const double x = val(b);
+  for (int t = threadIdx.x; t < nv; t += blockDim.x) {
+    const double x = vs[t];
     int less = 0, eq = 0;
-    for (int c = d.blk0; c < d.blk0 + d.q; ++c) {
-      if (F.bitem[c] < 0) continue;
-      const double y = val(c);
+    for (int c = 0; c < nv; ++c) {
+      const double y = vs[c];
       less += y < x;
       eq += y == x;
     }
