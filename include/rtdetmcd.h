@@ -220,6 +220,12 @@ rtdetmcd_status rtdetmcd_cstep(rtdetmcd_handle h, const void* X, int32_t dtype, 
                                int32_t* hsubset, int32_t* status, int32_t* iters,
                                double* logdet);
 
+/* Number of fits on this handle that were run a second time with ballot
+ * ranking because a global sort's order check failed (see rtdetmcd_create).
+ * Such a fit takes about twice its usual time; its results are those of the
+ * ballot-ranked run.  Host-only; -1 for a null handle. */
+int64_t rtdetmcd_sort_reruns(rtdetmcd_handle h);
+
 /* ---- adjoint -------------------------------------------------------------- */
 
 /* Gradient with respect to X of <g_dist, dist> + <g_mu, mu> + <g_sigma, sigma>

@@ -11,7 +11,7 @@ c_i32, c_i64, c_f64, c_vp = C.c_int32, C.c_int64, C.c_double, C.c_void_p
 
 RTDETMCD_OK = 0
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESINGULAR",
-                -6: "EUNSUPPORTED"}
+                -5: "ENONFINITE", -6: "EUNSUPPORTED"}
 
 # exported symbols, in the header's order
 SYMBOLS = [
@@ -19,7 +19,7 @@ SYMBOLS = [
     "rtdetmcd_default_opts", "rtdetmcd_plan", "rtdetmcd_fit", "rtdetmcd_fit_batched",
     "rtdetmcd_chi2_quantile", "rtdetmcd_chi2_cdf", "rtdetmcd_consistency",
     "rtdetmcd_distances", "rtdetmcd_score", "rtdetmcd_select", "rtdetmcd_cstep",
-    "rtdetmcd_backward",
+    "rtdetmcd_sort_reruns", "rtdetmcd_backward",
 ]
 
 
@@ -73,6 +73,7 @@ def load() -> C.CDLL:
         "rtdetmcd_select": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_vp, c_vp]),
         "rtdetmcd_cstep": (c_i32, [c_vp, c_vp, c_i32, c_i64, c_i32, c_i64, c_i64, c_vp, c_vp,
                                    c_vp, P(Opts), c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+        "rtdetmcd_sort_reruns": (c_i64, [c_vp]),
         "rtdetmcd_backward": (c_i32, [c_vp, c_vp, c_i32, c_i64, c_i32, c_i64, c_vp, c_vp, c_vp,
                                       c_vp, c_vp, c_f64, c_vp, c_vp, c_vp, c_vp]),
     }

@@ -174,6 +174,14 @@ def cstep(X: torch.Tensor, h_sub: int, mu0: torch.Tensor, sigma0: torch.Tensor,
     return CStepResult(mu, sig, hs, int(stt.item()), int(its.item()), float(ld.item()))
 
 
+def sort_reruns(device=None) -> int:
+    """Fits on this device's handle that were run again with ballot ranking
+    after a sort's order check failed (rtdetmcd_sort_reruns)."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    lib, h = _handle(dev)
+    return int(lib.rtdetmcd_sort_reruns(h))
+
+
 # ----------------------------------------------------------------- full fit
 
 @dataclasses.dataclass

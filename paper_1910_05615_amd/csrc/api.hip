@@ -137,10 +137,10 @@ void bind_items(char* base, const ItemSet& S, const size_t off[20], ItemDev& D) 
 // now on the handle's replay stream (no memset nodes: counters are cleared by
 // a fill kernel).
 template <typename Step>
-rtdetmcd_status graph_for(rtdetmcd_ctx* ctx, const int64_t (&key)[16], int R, Step& step,
+rtdetmcd_status graph_for(rtdetmcd_ctx* ctx, const std::vector<int64_t>& key, int R, Step& step,
                           hipGraphExec_t* out) {
   for (rtd_graph& g : ctx->graphs) {
-    if (std::equal(key, key + 16, g.key)) {
+    if (g.key == key) {
       *out = g.exec;
       return RTDETMCD_OK;
     }
@@ -171,7 +171,7 @@ rtdetmcd_status graph_for(rtdetmcd_ctx* ctx, const int64_t (&key)[16], int R, St
   (void)hipGraphDestroy(g);
   RTD_HIP(ei);
   rtd_graph e;
-  std::copy(key, key + 16, e.key);
+  e.key = key;
   e.exec = ge;
   ctx->graphs.push_back(e);
   *out = ge;
@@ -216,12 +216,23 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
     if (o.graph && maxs >= R) {
       // whole rounds of R steps replayed from a captured graph on the
       // handle's replay stream, ordered after / before the caller's stream
-      const int64_t key[16] = {(int64_t)(uintptr_t)ctx->ws, (int64_t)(uintptr_t)D.items,
-                               (int64_t)(uintptr_t)dtl, bucket, dtype, first, n,
-                               (pairs ? 2 : 1) + (dense ? 4 : 0),
-                               dt0, dtn, st0, stn, max_nt, max_m,
-                               (int64_t)o.cstep_mode * 1000000 + maxs,
-                               (int64_t)R * 4096 + (int64_t)(o.kappa_max * 16.0)};
+      // every argument of every captured launch: the tables and the per-item
+      // and per-row state arrays (their offsets in the workspace depend on
+      // the item count and the total row count of the set), the grid sizes
+      // and the options
+      const ItemArrays& A = D.A;
+      const void* ptrs[] = {ctx->ws,   D.items,  dtl,      D.stiles, A.status, A.iter,
+                            A.kswap,   A.full,   A.logdet, A.mux,    A.lamx,   A.muz,
+                            A.sigz,    A.linv,   A.mtri,   A.d2,     A.mask,   A.swap,
+                            A.part,    A.nactive};
+      std::vector<int64_t> key;
+      for (const void* q : ptrs) key.push_back((int64_t)(uintptr_t)q);
+      int64_t kbits;
+      std::memcpy(&kbits, &o.kappa_max, 8);
+      const int64_t scal[] = {bucket, dtype, first, n, (pairs ? 2 : 1) + (dense ? 4 : 0),
+                              dt0, dtn, st0, stn, max_nt, max_m, (int64_t)S.items.size(),
+                              S.rows, o.cstep_mode, maxs, R, kbits};
+      key.insert(key.end(), std::begin(scal), std::end(scal));
       hipGraphExec_t ge = nullptr;
       RTD_TRY(graph_for(ctx, key, R, step, &ge));
       RTD_HIP(hipEventRecord(ctx->gev[0], st));
@@ -578,5 +589,7 @@ rtdetmcd_status rtdetmcd_cstep(rtdetmcd_handle ctx, const void* X, int32_t dtype
   if (hsubset) RTD_HIP(launch_extract_subset(D.items, D.A, 0, 1, hsubset, h_sub, 0, st));
   return RTDETMCD_OK;
 }
+
+int64_t rtdetmcd_sort_reruns(rtdetmcd_handle ctx) { return ctx ? ctx->sort_reruns : -1; }
 
 }  // extern "C"

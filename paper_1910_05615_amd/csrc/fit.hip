@@ -575,6 +575,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     // a sort whose atomic ranks came out of lane order: fit again with
     // ballot ranking throughout
     ctx->sort_safe = 1;
+    ++ctx->sort_reruns;
     const rtdetmcd_status again = fit_many(ctx, nd, sets, o, status);
     ctx->sort_safe = 0;
     return again;

@@ -107,10 +107,11 @@ inline double consistency_memo(double alpha, int p) {
 
 }  // namespace rtd
 
-// A captured round of C-steps and what its kernel arguments were made of:
-// a replay is valid only for the same workspace, item tables and options.
+// A captured round of C-steps and every kernel argument it was captured
+// with (pointers, grid sizes, options): a replay is valid only when all of
+// them are the same again.
 struct rtd_graph {
-  int64_t key[16];
+  std::vector<int64_t> key;
   hipGraphExec_t exec = nullptr;
 };
 
@@ -128,6 +129,7 @@ struct rtdetmcd_ctx {
   bool pin_pending = false;
   int32_t* flag = nullptr;     // pinned readback word
   int sort_safe = 0;           // 1: global sorts rank with ballots (no order check)
+  int64_t sort_reruns = 0;     // fits run again with ballot ranking (an order check failed)
   hipStream_t gstream = nullptr;          // capture / replay stream (created on first use)
   hipEvent_t gev[2] = {nullptr, nullptr}; // ordering with `stream`
   std::vector<rtd_graph> graphs;          // captured C-step rounds, most recent last

@@ -143,6 +143,28 @@ def test_graph_replays_equal_eager(rounds):
     check_fit(ga, oracle.fit(a.X, n_chunks=4), "graph")
 
 
+def test_graph_cache_tells_batches_of_other_total_rows_apart():
+    # two batches that share the block count, p bucket, tile counts and the
+    # longest block but not the total row count: the per-row state arrays sit
+    # at other workspace offsets, so the second batch must not replay the
+    # graphs captured for the first
+    P = _P()
+    mk = lambda n, k: synthdata.small_gaussian(n, 5, seed=90 + k, dtype=np.float32, rho=0.5,
+                                               eps=0.1, kind="shift", gamma=8)
+    first = [mk(5000, 0), mk(2000, 1)]
+    second = [mk(5000, 0), mk(2040, 2)]
+    for batch in (first, second, first, second):
+        Xs = [torch.from_numpy(d.X).to(_dev()) for d in batch]
+        g, sg = P.fit_batched(Xs, graph=True, rounds_per_sync=2)
+        e, se = P.fit_batched(Xs, rounds_per_sync=2)
+        assert sg == se == [0, 0]
+        for a, b in zip(g, e):
+            for name in _ALL:
+                assert torch.equal(getattr(a, name), getattr(b, name)), name
+    for d, F in zip(second, g):
+        check_fit(F, oracle.fit(d.X), d.name)
+
+
 def test_fit_heavy_ties_in_one_column():
     # one column on 12 integer levels: runs of equal keys far longer than the
     # sorter's insertion-sort fix-up accepts, so those segments take the

@@ -308,6 +308,87 @@ def test_determinant_update_identity():
         assert lhs == pytest.approx((1 + d * v @ np.linalg.solve(Lam, u)) * np.linalg.det(Lam), rel=1e-10)
 
 
+def _brute_cond1(S):
+    # ||S||_1 ||S^-1||_1 from column sums of |S| and of |inverse|, the inverse
+    # by Gauss-Jordan elimination written out here (no Cholesky, no LAPACK)
+    n = S.shape[0]
+    A = np.hstack([S.astype(float), np.eye(n)])
+    for c in range(n):
+        r = c + int(np.argmax(np.abs(A[c:, c])))
+        A[[c, r]] = A[[r, c]]
+        A[c] /= A[c, c]
+        for k in range(n):
+            if k != c:
+                A[k] -= A[k, c] * A[c]
+    Si = A[:, n:]
+    norm1 = lambda M: max(sum(abs(M[i, j]) for i in range(n)) for j in range(n))
+    return norm1(S) * norm1(Si)
+
+
+@pytest.mark.parametrize("seed", [0, 3, 7])
+def test_kappa1_is_the_one_norm_condition_number(seed):
+    # eq. (choleskymonitor) uses the 1-norm: on a dense SPD matrix whose
+    # 2-norm condition is 700 the 1-norm condition exceeds 1000, so a 2-norm
+    # (eigenvalue ratio) reading would pass the check and the 1-norm one fails it
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((6, 6)))
+    S = (Q * np.geomspace(1.0, 1.0 / 700.0, 6)) @ Q.T
+    S = 0.5 * (S + S.T)
+    k1 = _brute_cond1(S)
+    assert np.linalg.cond(S, 2) < 1000.0 < k1
+    L = np.linalg.cholesky(S)
+    assert oracle.kappa1(S, L) == pytest.approx(k1, rel=1e-9)
+    # and the C-step refuses a start with that scatter (Sec. 3.4)
+    X = _contaminated(400, 6, 2)
+    r = oracle.csteps(X, 300, X.mean(0), S)
+    assert r.status == oracle.ST_DROP_FIRST
+    # the same matrix scaled into the accepted range is taken
+    S2 = (Q * np.geomspace(1.0, 1.0 / 20.0, 6)) @ Q.T
+    S2 = 0.5 * (S2 + S2.T)
+    assert oracle.kappa1(S2, np.linalg.cholesky(S2)) == pytest.approx(_brute_cond1(S2), rel=1e-9)
+    assert oracle.csteps(X, 300, X.mean(0), S2).status == oracle.ST_CONVERGED
+
+
+def _brute_median(v):
+    # the middle order statistic, or the mean of the two middle ones, found by
+    # counting how many values lie below and above each candidate
+    v = [float(x) for x in v]
+    n = len(v)
+    def kth(k):   # k-th smallest, 0-based
+        for x in v:
+            below = sum(1 for y in v if y < x)
+            equal = sum(1 for y in v if y == x)
+            if below <= k < below + equal:
+                return x
+    return kth(n // 2) if n % 2 else 0.5 * (kth(n // 2 - 1) + kth(n // 2))
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 8, 31, 64])
+def test_medmad_matches_brute_force(n):
+    # median and 1.4826 * median absolute deviation (odd and even counts,
+    # with repeated values)
+    rng = np.random.default_rng(n)
+    x = np.round(rng.standard_normal(n) * 3.0, 1)
+    med = _brute_median(x)
+    mad = _brute_median([abs(a - med) for a in x])
+    got_med, got_scale = oracle.medmad(x)
+    assert got_med == med
+    assert got_scale == pytest.approx(1.4826 * mad, rel=1e-15)
+
+
+def test_medmad_consistent_at_the_normal():
+    # 1.4826 MAD is consistent for the standard deviation at the normal
+    # (1 / Phi^-1(3/4) = 1.482602...), and the median for its centre
+    x = np.random.default_rng(12).standard_normal(1_000_000) * 2.5 + 4.0
+    med, s = oracle.medmad(x)
+    assert abs(med - 4.0) < 0.01
+    assert abs(s / 2.5 - 1.0) < 0.005
+    # location / scale equivariance
+    med2, s2 = oracle.medmad(-3.0 * x + 1.0)
+    assert med2 == pytest.approx(-3.0 * med + 1.0, rel=1e-12)
+    assert s2 == pytest.approx(3.0 * s, rel=1e-12)
+
+
 def test_kappa_threshold_stops_cstep():
     X = _contaminated(400, 3, 1)
     mu0 = X.mean(0)
