@@ -220,6 +220,26 @@ rtdetmcd_status rtdetmcd_cstep(rtdetmcd_handle h, const void* X, int32_t dtype, 
                                int32_t* hsubset, int32_t* status, int32_t* iters,
                                double* logdet);
 
+/* The C-steps of rtdetmcd_cstep (same arguments, same kernels, same results)
+ * for callers that cannot allocate memory: code that runs while a stream is
+ * being captured, tight serving loops, harnesses that forbid allocation.  It
+ * calls no hipMalloc / hipFree and no allocating library routine; every device
+ * buffer beyond the caller's inputs and outputs comes from one fixed array of
+ * 8 MiB that the library holds on each device it runs on until the process
+ * ends.  Limit: m <= 131072 rows (p <= RTDETMCD_MAX_P); a larger m returns
+ * RTDETMCD_EINVAL with a message.  opts->graph is ignored (capturing a graph
+ * allocates).  All calls on one device share that array and each call leaves
+ * its state there: calls that overlap on one device (two host threads, or two
+ * streams whose work overlaps) race and give wrong results.  Like
+ * rtdetmcd_cstep it synchronises the stream between C-steps to test for
+ * convergence. */
+rtdetmcd_status rtdetmcd_cstep_noalloc(rtdetmcd_handle h, const void* X, int32_t dtype,
+                                       int64_t m, int32_t p, int64_t ld, int64_t h_sub,
+                                       const double* mu0, const double* sigma0,
+                                       const double* kappa_scale, const rtdetmcd_opts* o,
+                                       double* mu, double* sigma, int32_t* hsubset,
+                                       int32_t* status, int32_t* iters, double* logdet);
+
 /* Number of fits on this handle that were run a second time with ballot
  * ranking because a global sort's order check failed (see rtdetmcd_create).
  * Such a fit takes about twice its usual time; its results are those of the

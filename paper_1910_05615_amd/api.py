@@ -151,8 +151,11 @@ class CStepResult:
 
 
 def cstep(X: torch.Tensor, h_sub: int, mu0: torch.Tensor, sigma0: torch.Tensor,
-          kappa_scale: Optional[torch.Tensor] = None, **opts) -> CStepResult:
-    """C-steps on one block from (mu0, sigma0) until the h-subset repeats."""
+          kappa_scale: Optional[torch.Tensor] = None, noalloc: bool = False,
+          **opts) -> CStepResult:
+    """C-steps on one block from (mu0, sigma0) until the h-subset repeats.
+    noalloc: run rtdetmcd_cstep_noalloc (no device allocation in the library;
+    m <= 131072)."""
     _check_X(X)
     m, p = X.shape
     lib, h = _handle(X.device)
@@ -167,10 +170,10 @@ def cstep(X: torch.Tensor, h_sub: int, mu0: torch.Tensor, sigma0: torch.Tensor,
     stt = torch.empty(1, dtype=torch.int32, device=dev)
     its = torch.empty(1, dtype=torch.int32, device=dev)
     ld = torch.empty(1, dtype=torch.float64, device=dev)
-    st = lib.rtdetmcd_cstep(h, _ptr(X), _dtype_code(X), m, p, X.stride(0), h_sub, _ptr(mu0),
-                            _ptr(sigma0), _ptr(ks), C.byref(o), _ptr(mu), _ptr(sig), _ptr(hs),
-                            _ptr(stt), _ptr(its), _ptr(ld))
-    _check(lib, h, st, "rtdetmcd_cstep")
+    fn = lib.rtdetmcd_cstep_noalloc if noalloc else lib.rtdetmcd_cstep
+    st = fn(h, _ptr(X), _dtype_code(X), m, p, X.stride(0), h_sub, _ptr(mu0), _ptr(sigma0),
+            _ptr(ks), C.byref(o), _ptr(mu), _ptr(sig), _ptr(hs), _ptr(stt), _ptr(its), _ptr(ld))
+    _check(lib, h, st, "rtdetmcd_cstep_noalloc" if noalloc else "rtdetmcd_cstep")
     return CStepResult(mu, sig, hs, int(stt.item()), int(its.item()), float(ld.item()))
 
 

@@ -349,6 +349,23 @@ __global__ void k_copy_pad(const double* __restrict__ src, int p, double* __rest
 }
 
 }  // namespace
+
+hipError_t launch_cstep_init(const double* mu0, const double* sigma0, const double* kscale,
+                             int p, const ItemArrays& A, double* loc, double* scale,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_cstep_init, dim3(1), dim3(256), 0, s, mu0, sigma0, kscale, p, A.muz,
+                     A.sigz, loc, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_cstep_out(const ItemArrays& A, const double* scale, int p, double h_sub,
+                            double* mu, double* sigma, int32_t* status, int32_t* iters,
+                            double* logdet, hipStream_t s) {
+  hipLaunchKernelGGL(k_cstep_out, dim3(1), dim3(256), 0, s, A.mux, A.lamx, scale, A.status,
+                     A.iter, A.logdet, p, h_sub, mu, sigma, status, iters, logdet);
+  return hipGetLastError();
+}
+
 }  // namespace rtd
 
 using namespace rtd;
@@ -389,6 +406,9 @@ rtdetmcd_status rtdetmcd_create(rtdetmcd_handle* out, int32_t device, void* hip_
     delete c;
     return RTDETMCD_EDEVICE;
   }
+  // the allocation-free entry point's array on this device (looked up once
+  // per device, with the device current)
+  c->scratch = noalloc_scratch(device, &c->scratch_bytes);
   *out = c;
   return RTDETMCD_OK;
 }
@@ -575,17 +595,12 @@ rtdetmcd_status rtdetmcd_cstep(rtdetmcd_handle ctx, const void* X, int32_t dtype
   up.add(D.stiles, S.stiles.data(), S.stiles.size());
   RTD_TRY(up.flush(ctx));
   hipStream_t st = ctx->stream;
-  hipLaunchKernelGGL(k_cstep_init, dim3(1), dim3(256), 0, st, mu0, sigma0, kappa_scale, p,
-                     D.A.muz, D.A.sigz, loc, scale);
-  RTD_HIP(hipGetLastError());
+  RTD_HIP(launch_cstep_init(mu0, sigma0, kappa_scale, p, D.A, loc, scale, st));
   RTD_HIP(launch_fill_i32(D.A.status, ACTIVE, 1, st));
   RTD_HIP(launch_fill_i32(D.A.iter, 0, 1, st));
   RTD_HIP(launch_fill_u8(D.A.mask, 0, m, st));
   RTD_TRY(run_csteps(ctx, S, D, bucket_of(p), dtype, 0, 1, o, ctx->flag));
-  hipLaunchKernelGGL(k_cstep_out, dim3(1), dim3(256), 0, st, D.A.mux, D.A.lamx, scale,
-                     D.A.status, D.A.iter, D.A.logdet, p, (double)h_sub, mu, sigma, status,
-                     iters, logdet);
-  RTD_HIP(hipGetLastError());
+  RTD_HIP(launch_cstep_out(D.A, scale, p, (double)h_sub, mu, sigma, status, iters, logdet, st));
   if (hsubset) RTD_HIP(launch_extract_subset(D.items, D.A, 0, 1, hsubset, h_sub, 0, st));
   return RTDETMCD_OK;
 }

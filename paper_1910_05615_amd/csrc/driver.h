@@ -124,4 +124,19 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
 
 rtdetmcd_status check_opts(rtdetmcd_ctx* ctx, const rtdetmcd_opts* in, rtdetmcd_opts& o);
 
+// Start of rtdetmcd_cstep: (mu0, sigma0) divided by the condition-check
+// scales into the item's muz / sigz, loc = 0 and scale = kscale (or 1).
+hipError_t launch_cstep_init(const double* mu0, const double* sigma0, const double* kscale,
+                             int p, const ItemArrays& A, double* loc, double* scale,
+                             hipStream_t s);
+// End of rtdetmcd_cstep: the item's mean, covariance (lamx / (h-1)), status,
+// iterations and log det in data units (NaN for a dropped start).
+hipError_t launch_cstep_out(const ItemArrays& A, const double* scale, int p, double h_sub,
+                            double* mu, double* sigma, int32_t* status, int32_t* iters,
+                            double* logdet, hipStream_t s);
+
+// Address of this device's allocation-free scratch array (rtdetmcd_cstep_noalloc),
+// looked up once per device; null (and *bytes = 0) if the lookup failed.
+void* noalloc_scratch(int device, size_t* bytes);
+
 }  // namespace rtd

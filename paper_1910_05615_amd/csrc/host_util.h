@@ -133,4 +133,6 @@ struct rtdetmcd_ctx {
   hipStream_t gstream = nullptr;          // capture / replay stream (created on first use)
   hipEvent_t gev[2] = {nullptr, nullptr}; // ordering with `stream`
   std::vector<rtd_graph> graphs;          // captured C-step rounds, most recent last
+  void* scratch = nullptr;     // this device's allocation-free scratch array (device address)
+  size_t scratch_bytes = 0;
 };
