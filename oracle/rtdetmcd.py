@@ -229,6 +229,14 @@ def mahalanobis2(X: np.ndarray, mu: np.ndarray, L: np.ndarray) -> np.ndarray:
     return np.sum(Y * Y, axis=0)
 
 
+def mahalanobis2_inverse(X: np.ndarray, mu: np.ndarray, P: np.ndarray) -> np.ndarray:
+    """Squared distances (x_i - mu)^T P (x_i - mu) with an explicit inverse P
+    of the scatter: the distance computation that Sec. 3.4 replaces by the
+    Cholesky form (the ID versus I rows of Table 1 in Sec. 5)."""
+    R = X - mu
+    return np.sum((R @ P) * R, axis=1)
+
+
 def chol_or_none(S: np.ndarray):
     try:
         L = np.linalg.cholesky(S)
@@ -294,6 +302,29 @@ def update_stats(X, H_old, H_new, mu_old, Lam_old):
     return mu, 0.5 * (Lam + Lam.T)
 
 
+def smw_swap(x: np.ndarray, delta: int, h: int, mu: np.ndarray, Lam: np.ndarray,
+             Lam_inv: np.ndarray, logdet_lam: float):
+    """One case entering (delta = +1) or leaving (delta = -1) the subset, with
+    the inverse and the determinant of the sscp matrix carried along (Sec. 3.5:
+    the sequential update eq. propcstep1, muUpdate, propcstep2; the
+    Sherman-Morrison-Woodbury identity eq. woodbury; the determinant identity
+    eq. scaleddetUpdate).  Returns (h, mu, Lam, Lam_inv, logdet_lam), or None
+    when Delta_i <= 0 (the updated sscp matrix would not be positive
+    definite)."""
+    h = h + delta
+    u = x - mu
+    mu = mu + (delta / h) * u
+    v = x - mu
+    a = Lam_inv @ u                       # Lam^{-1} u
+    b = Lam_inv @ v                       # (v^T Lam^{-1})^T, Lam symmetric
+    Delta = 1.0 + delta * float(v @ a)
+    if not (Delta > 0.0):
+        return None
+    Lam_inv = Lam_inv - (delta / Delta) * np.outer(a, b)
+    Lam = Lam + delta * np.outer(u, v)
+    return h, mu, Lam, Lam_inv, logdet_lam + math.log(Delta)
+
+
 @dataclasses.dataclass
 class CStepResult:
     status: int
@@ -303,11 +334,13 @@ class CStepResult:
     logdet: float
     iters: int
     logdets: List[float]             # logdet of Sigma_old at each evaluated step
+    smw_steps: int = 0               # steps taken by the single-swap update (mode "smw")
 
 
 def csteps(X: np.ndarray, h: int, mu0: np.ndarray, sigma0: np.ndarray,
            max_steps: int = MAX_CSTEPS, kappa_max: float = KAPPA_MAX,
-           kappa_scale: Optional[np.ndarray] = None) -> CStepResult:
+           kappa_scale: Optional[np.ndarray] = None, distance: str = "cholesky",
+           mode: str = "full") -> CStepResult:
     """Iterate C-steps from (mu0, sigma0) until the h-subset repeats (Sec. 2.2 step 4).
 
     Each step: Cholesky of Sigma_old and its condition monitor (Sec. 3.4); if
@@ -323,39 +356,94 @@ def csteps(X: np.ndarray, h: int, mu0: np.ndarray, sigma0: np.ndarray,
     ``kappa_scale``: the condition check is made in standardised units; when X
     is in raw units pass the column scales so that Sigma_old is divided by
     scale_j scale_k before the check.
+
+    ``distance="inverse"``: distances by the explicit inverse of Sigma_old
+    (mahalanobis2_inverse) instead of forward substitution (Sec. 3.4).
+
+    ``mode="smw"``: a step whose new subset differs from the old one by one
+    case out and one case in (sum |delta_i| = 2) updates the mean and sscp
+    matrix case by case (leaving case first) and carries the inverse and the
+    determinant of the sscp matrix by eq. (woodbury) and eq. (scaleddetUpdate)
+    (smw_swap); the next step's distances then use that inverse and its
+    condition check uses it too.  Other steps recompute in full.
     """
+    p = len(mu0)
     mu, S = np.asarray(mu0, float), np.asarray(sigma0, float)
     H_prev = None
     logdets: List[float] = []
+    smw = None            # (Sigma^{-1}, log det Sigma) after a single-swap update
+    nsmw = 0
     for t in range(1, max_steps + 1):
-        L = chol_or_none(S)
-        if L is None:
-            # Sigma_old is not positive definite: no step can be taken and the
-            # subset (if any) has a singular covariance, so the start is dropped.
-            return CStepResult(ST_DROP_FIRST if H_prev is None else ST_SINGULAR,
-                               None, None, None, math.nan, t - 1, logdets)
-        Sk, Lk = S, L
-        if kappa_scale is not None:
-            Sk = S / np.outer(kappa_scale, kappa_scale)
-            Lk = chol_or_none(Sk)
-        kap = kappa1(Sk, Lk) if Lk is not None else math.inf
-        ld = 2.0 * float(np.sum(np.log(np.diag(L))))
+        if smw is None:
+            L = chol_or_none(S)
+            if L is None:
+                # Sigma_old is not positive definite: no step can be taken and the
+                # subset (if any) has a singular covariance, so the start is dropped.
+                return CStepResult(ST_DROP_FIRST if H_prev is None else ST_SINGULAR,
+                                   None, None, None, math.nan, t - 1, logdets, nsmw)
+            Sk, Lk = S, L
+            if kappa_scale is not None:
+                Sk = S / np.outer(kappa_scale, kappa_scale)
+                Lk = chol_or_none(Sk)
+            kap = kappa1(Sk, Lk) if Lk is not None else math.inf
+            ld = 2.0 * float(np.sum(np.log(np.diag(L))))
+        else:
+            Si, ld = smw
+            Sk, Ski = S, Si
+            if kappa_scale is not None:
+                Sk = S / np.outer(kappa_scale, kappa_scale)
+                Ski = Si * np.outer(kappa_scale, kappa_scale)
+            kap = float(np.max(np.sum(np.abs(Sk), axis=0)) *
+                        np.max(np.sum(np.abs(Ski), axis=0)))
         if not (kap < kappa_max):
             if H_prev is None:
-                return CStepResult(ST_DROP_FIRST, None, None, None, math.nan, t - 1, logdets)
-            return CStepResult(ST_ILLCOND, H_prev, mu, S, ld, t - 1, logdets)
+                return CStepResult(ST_DROP_FIRST, None, None, None, math.nan, t - 1, logdets,
+                                   nsmw)
+            return CStepResult(ST_ILLCOND, H_prev, mu, S, ld, t - 1, logdets, nsmw)
         logdets.append(ld)
-        d2 = mahalanobis2(X, mu, L)
+        if smw is not None:
+            d2 = mahalanobis2_inverse(X, mu, smw[0])
+        elif distance == "inverse":
+            d2 = mahalanobis2_inverse(X, mu, np.linalg.inv(S))
+        else:
+            d2 = mahalanobis2(X, mu, L)
         H = select_h(d2, h)
         if H_prev is not None and np.array_equal(H, H_prev):
-            return CStepResult(ST_CONVERGED, H, mu, S, ld, t, logdets)
-        mu, S = subset_stats(X, H)
+            return CStepResult(ST_CONVERGED, H, mu, S, ld, t, logdets, nsmw)
+        smw_next = None
+        if mode == "smw" and H_prev is not None:
+            out_ = np.setdiff1d(H_prev, H)
+            in_ = np.setdiff1d(H, H_prev)
+            if len(out_) == 1 and len(in_) == 1:
+                Lam = (h - 1) * S
+                if smw is not None:
+                    Lam_inv = smw[0] / (h - 1)
+                else:
+                    Li = sla.solve_triangular(L, np.eye(p), lower=True)
+                    Lam_inv = (Li.T @ Li) / (h - 1)
+                st = (h, mu, Lam, Lam_inv, ld + p * math.log(h - 1))
+                for i, dlt in ((int(out_[0]), -1), (int(in_[0]), +1)):
+                    st = smw_swap(X[i], dlt, st[0], st[1], st[2], st[3], st[4])
+                    if st is None:
+                        break
+                if st is None:
+                    return CStepResult(ST_SINGULAR, None, None, None, math.nan, t, logdets,
+                                       nsmw)
+                _, mu, Lam, Lam_inv, ldl = st
+                S = 0.5 * (Lam + Lam.T) / (h - 1)
+                smw_next = ((h - 1) * Lam_inv, ldl - p * math.log(h - 1))
+                nsmw += 1
+        if smw_next is None:
+            mu, S = subset_stats(X, H)
+        smw = smw_next
         H_prev = H
+    if smw is not None:
+        return CStepResult(ST_NOTCONV, H_prev, mu, S, smw[1], max_steps, logdets, nsmw)
     L = chol_or_none(S)
     if L is None:
-        return CStepResult(ST_SINGULAR, None, None, None, math.nan, max_steps, logdets)
+        return CStepResult(ST_SINGULAR, None, None, None, math.nan, max_steps, logdets, nsmw)
     return CStepResult(ST_NOTCONV, H_prev, mu, S, 2.0 * float(np.sum(np.log(np.diag(L)))),
-                       max_steps, logdets)
+                       max_steps, logdets, nsmw)
 
 
 # --------------------------------------------------------------------------
@@ -469,16 +557,33 @@ class Fit:
     diag: dict
 
 
+START_WARM = 2             # chunk_start of a block fitted from a warm start
+
+
 def fit(X: np.ndarray, alpha: float = 0.75, h_sub: int = 0, n_chunks: int = 0,
         standardize: str = "unimcd", pool: str = "printed",
         rew_consistency: bool = False, max_csteps: int = MAX_CSTEPS,
         kappa_max: float = KAPPA_MAX, cutoff_q: float = CUTOFF_Q,
-        omega: int = OMEGA, perm: Optional[np.ndarray] = None) -> Fit:
+        omega: int = OMEGA, perm: Optional[np.ndarray] = None,
+        distance: str = "cholesky", cstep_mode: str = "full",
+        warm: Optional[tuple] = None) -> Fit:
     """RT-DetMCD fit of one dataset X (n x p), every step in float64.
 
     Reading of the partition (Sec. 4): contiguous blocks of m = floor(n/q)
     rows in the given order (``perm`` re-orders the rows first); the n - q m
     remainder rows are not fitted but are scored and flagged in step 10.
+
+    ``distance="inverse"`` computes every distance of the fit (C-steps,
+    reweighting, final) with the explicit inverse of the scatter instead of
+    the Cholesky form of Sec. 3.4 (Table 1: version I against ID);
+    ``cstep_mode="smw"`` takes single-swap C-steps by the inverse and
+    determinant updates of Sec. 3.5 (csteps).
+
+    ``warm=(mu, sigma)`` (units of X): the warm start of the last paragraph of
+    Sec. 4.  Reading: a previous fit's reweighted estimate is the one start of
+    every block's C-steps (step 3); the initial estimators and their
+    refinement (steps 1-2) are skipped, the standardisation of this data and
+    steps 4-10 are as usual (chunk_start = START_WARM).
     """
     X = np.asarray(X, dtype=np.float64)
     n, p = X.shape
@@ -512,18 +617,27 @@ def fit(X: np.ndarray, alpha: float = 0.75, h_sub: int = 0, n_chunks: int = 0,
     chunk_iters = np.zeros(q, np.int32)
     hsub = np.full((q, h), -1, np.int64)
     starts_diag = []
+    if warm is not None:
+        mu_w = (np.asarray(warm[0], float) - loc) / scale
+        S_w = np.asarray(warm[1], float) / np.outer(scale, scale)
+        S_w = 0.5 * (S_w + S_w.T)
     for l in range(q):
         rows = order[l * m:(l + 1) * m]
         Zl = Z[rows]
         res = []
-        for S0 in (init_wrap_cov(Zl), init_gsscm(Zl)):      # Sec. 4 step 1
-            st = refine(S0, Zl, kappa_max)                  # step 2
-            if not st.ok:
-                res.append(CStepResult(ST_DROP_REFINE, None, None, None, math.nan, 0, []))
-                continue
-            res.append(csteps(Zl, h, st.mu, st.sigma, max_csteps, kappa_max))  # step 3
+        if warm is not None:                                # step 3 from the warm start
+            res.append(csteps(Zl, h, mu_w, S_w, max_csteps, kappa_max,
+                              distance=distance, mode=cstep_mode))
+        else:
+            for S0 in (init_wrap_cov(Zl), init_gsscm(Zl)):  # Sec. 4 step 1
+                st = refine(S0, Zl, kappa_max)              # step 2
+                if not st.ok:
+                    res.append(CStepResult(ST_DROP_REFINE, None, None, None, math.nan, 0, []))
+                    continue
+                res.append(csteps(Zl, h, st.mu, st.sigma, max_csteps, kappa_max,
+                                  distance=distance, mode=cstep_mode))   # step 3
         starts_diag.append(res)
-        ok = [k for k in range(2) if res[k].H is not None]
+        ok = [k for k in range(len(res)) if res[k].H is not None]
         if not ok:
             chunk_status[l] = CHUNK_INVALID
             continue
@@ -534,7 +648,7 @@ def fit(X: np.ndarray, alpha: float = 0.75, h_sub: int = 0, n_chunks: int = 0,
                 best = k
         r = res[best]
         chunk_status[l] = r.status
-        chunk_start[l] = best
+        chunk_start[l] = START_WARM if warm is not None else best
         chunk_iters[l] = r.iters
         hsub[l] = rows[r.H]
         fits_mu.append(r.mu)
@@ -550,16 +664,19 @@ def fit(X: np.ndarray, alpha: float = 0.75, h_sub: int = 0, n_chunks: int = 0,
         alpha_factor=c_alpha)
 
     # Steps 8-9: reweighting over the fitted rows.
-    Lr = np.linalg.cholesky(sig_raw)
-    d2 = mahalanobis2(Zfit, mu_raw, Lr)
+    def dist2(Zr, mu_, S_):
+        if distance == "inverse":
+            return mahalanobis2_inverse(Zr, mu_, np.linalg.inv(S_))
+        return mahalanobis2(Zr, mu_, np.linalg.cholesky(S_))
+
+    d2 = dist2(Zfit, mu_raw, sig_raw)
     W = d2 <= chi2
     n_w = int(W.sum())
     mu_rew, sig_rew = subset_stats(Zfit, np.nonzero(W)[0])
     if rew_consistency:
         sig_rew = sig_rew * consistency_factor(cutoff_q, p)
     # Step 10: final distances and flags for every row.
-    Lw = np.linalg.cholesky(sig_rew)
-    d2all = mahalanobis2(Z, mu_rew, Lw)
+    d2all = dist2(Z, mu_rew, sig_rew)
     rew_mask = np.zeros(n, np.uint8)
     rew_mask[order[: q * m][W]] = 1
 

@@ -644,3 +644,140 @@ def test_random_partition_is_the_fit_of_the_permuted_rows():
     fi = oracle.fit(X, n_chunks=q, perm=np.arange(n))
     f0 = oracle.fit(X, n_chunks=q)
     assert np.array_equal(fi.hsubset, f0.hsubset) and np.array_equal(fi.sigma, f0.sigma)
+
+
+# ---------------------------------------------------------------- explicit-inverse distances (Table 1, I vs ID)
+
+def test_inverse_distances_equal_forward_substitution():
+    # Sec. 3.4: ||L^{-1} r||^2 = r^T Sigma^{-1} r; the two are computed by
+    # different routines (triangular solve against a general inverse)
+    rng = np.random.default_rng(31)
+    p = 7
+    A = rng.standard_normal((p, p))
+    S = A @ A.T + p * np.eye(p)
+    X = rng.standard_normal((500, p)) * 3.0
+    mu = rng.standard_normal(p)
+    d_inv = oracle.mahalanobis2_inverse(X, mu, np.linalg.inv(S))
+    d_chol = oracle.mahalanobis2(X, mu, np.linalg.cholesky(S))
+    assert np.allclose(d_inv, d_chol, rtol=1e-12, atol=0.0)
+
+
+def test_inverse_distances_diagonal_closed_form():
+    rng = np.random.default_rng(32)
+    s = rng.uniform(0.5, 4.0, 5)
+    X = rng.standard_normal((100, 5))
+    d = oracle.mahalanobis2_inverse(X, np.zeros(5), np.diag(1.0 / s ** 2))
+    assert np.allclose(d, np.sum((X / s) ** 2, axis=1), rtol=1e-14)
+
+
+# ---------------------------------------------------------------- single-swap updates (Sec. 3.5)
+
+def _sscp(X, H):
+    mu = X[H].mean(axis=0)
+    D = X[H] - mu
+    return mu, D.T @ D
+
+
+def test_smw_swap_matches_recomputation():
+    # eq. (woodbury) and eq. (scaleddetUpdate): after one case leaves and one
+    # enters, the carried inverse and log determinant equal those of the sscp
+    # matrix recomputed from the new subset, and the mean is its mean
+    rng = np.random.default_rng(33)
+    m, p, h = 200, 4, 150
+    X = rng.standard_normal((m, p)) @ rng.standard_normal((p, p))
+    H = np.sort(rng.choice(m, h, replace=False))
+    out_i = int(H[17])
+    in_i = int(np.setdiff1d(np.arange(m), H)[5])
+    mu, Lam = _sscp(X, H)
+    st = (h, mu, Lam, np.linalg.inv(Lam), float(np.linalg.slogdet(Lam)[1]))
+    for i, dlt in ((out_i, -1), (in_i, +1)):
+        st = oracle.smw_swap(X[i], dlt, *st)
+    hh, mu2, Lam2, Li2, ld2 = st
+    H2 = np.sort(np.concatenate([H[H != out_i], [in_i]]))
+    mu_r, Lam_r = _sscp(X, H2)
+    assert hh == h
+    assert np.allclose(mu2, mu_r, rtol=1e-12, atol=1e-13)
+    assert np.allclose(Lam2, Lam_r, rtol=1e-11, atol=1e-10)
+    assert np.allclose(Li2, np.linalg.inv(Lam_r), rtol=1e-9, atol=1e-13)
+    assert ld2 == pytest.approx(np.linalg.slogdet(Lam_r)[1], abs=1e-10)
+
+
+def test_smw_swap_singular_update_is_refused():
+    # p = 1, subset {0, 2}: removing 2 leaves one point, whose sscp is 0:
+    # Delta = 1 - (x - mu_new) Lam^{-1} (x - mu_old) = 1 - 2 * 0.5 * 1 = 0
+    X = np.array([[0.0], [2.0]])
+    Lam = np.array([[2.0]])
+    assert oracle.smw_swap(X[1], -1, 2, np.array([1.0]), Lam, np.linalg.inv(Lam),
+                           math.log(2.0)) is None
+
+
+@pytest.mark.parametrize("seed,m,p", [(0, 400, 2), (5, 1000, 3), (10, 3000, 5)])
+def test_csteps_smw_mode_follows_full_mode(seed, m, p):
+    # the single-swap update is exact: the same subsets, iterations and
+    # determinants as full recomputation, with at least one swap step taken
+    ds = synthdata.small_gaussian(m, p, seed=seed, rho=0.6, eps=0.1, kind="shift", gamma=3)
+    X = ds.X.astype(float)
+    h = oracle.subset_size(m, p, 0.75)
+    rng = np.random.default_rng(seed)
+    mu0, S0 = oracle.subset_stats(X, np.sort(rng.choice(m, h, replace=False)))
+    a = oracle.csteps(X, h, mu0, S0)
+    b = oracle.csteps(X, h, mu0, S0, mode="smw")
+    assert b.smw_steps > 0
+    assert (a.status, a.iters) == (b.status, b.iters)
+    assert np.array_equal(a.H, b.H)
+    assert b.logdet == pytest.approx(a.logdet, abs=1e-10)
+    assert np.allclose(b.sigma, a.sigma, rtol=1e-10, atol=1e-12)
+    assert np.allclose(a.logdets, b.logdets, atol=1e-10)
+    c = oracle.csteps(X, h, mu0, S0, distance="inverse")
+    assert np.array_equal(a.H, c.H) and a.iters == c.iters
+
+
+def test_fit_distance_and_update_switches_leave_the_fit_unchanged():
+    # Sec. 5: versions I, ID and IDC agree up to rounding (the paper's
+    # "equivalent if numerical precision were perfect")
+    ds = synthdata.small_gaussian(6000, 4, seed=12, rho=0.5, eps=0.15, kind="shift", gamma=5)
+    a = oracle.fit(ds.X, n_chunks=3)
+    b = oracle.fit(ds.X, n_chunks=3, distance="inverse")
+    c = oracle.fit(ds.X, n_chunks=3, cstep_mode="smw")
+    for f in (b, c):
+        assert np.array_equal(a.hsubset, f.hsubset)
+        assert np.array_equal(a.outlier, f.outlier)
+        assert np.allclose(a.sigma, f.sigma, rtol=1e-10)
+    assert sum(r.smw_steps for st in c.diag["starts"] for r in st) > 0
+
+
+# ---------------------------------------------------------------- warm start (end of Sec. 4)
+
+def test_warm_start_from_a_fixed_point_reproduces_the_fit():
+    # a block's converged h-subset is a C-step fixed point: started from that
+    # subset's mean and covariance (given in data units), the C-steps select
+    # it again at once (two steps: select, then confirm), so the whole fit is
+    # reproduced; the data are far from standardised, so the units matter
+    ds = synthdata.small_gaussian(3000, 3, seed=4, rho=0.5, eps=0.1, kind="shift", gamma=6)
+    X = ds.X * np.array([50.0, 0.01, 3.0]) + np.array([1e3, -2.0, 7.0])
+    a = oracle.fit(X)
+    assert a.chunk_status[0] == oracle.ST_CONVERGED
+    H = a.hsubset[0]
+    mu_h = X[H].mean(axis=0)
+    S_h = np.cov(X[H], rowvar=False, ddof=1)
+    b = oracle.fit(X, warm=(mu_h, S_h))
+    assert b.chunk_start[0] == oracle.START_WARM
+    assert b.chunk_iters[0] == 2 and b.chunk_status[0] == oracle.ST_CONVERGED
+    assert np.array_equal(a.hsubset, b.hsubset)
+    assert np.array_equal(a.outlier, b.outlier)
+    assert np.allclose(a.sigma, b.sigma, rtol=1e-12)
+    assert np.allclose(a.mu, b.mu, rtol=1e-12)
+
+
+def test_warm_start_on_new_data_lowers_no_determinant():
+    # the C-step monotonicity (Prop. 1) holds from a warm start too: each
+    # block's determinant sequence from step 2 on does not increase
+    old = synthdata.small_gaussian(8000, 4, seed=21, rho=0.6, eps=0.1, kind="shift", gamma=6)
+    new = synthdata.small_gaussian(8000, 4, seed=22, rho=0.6, eps=0.1, kind="shift", gamma=6)
+    f0 = oracle.fit(old.X, n_chunks=2)
+    f1 = oracle.fit(new.X, n_chunks=2, warm=(f0.mu, f0.sigma))
+    for st in f1.diag["starts"]:
+        assert len(st) == 1
+        ld = st[0].logdets
+        assert all(b <= a + 1e-9 for a, b in zip(ld[1:], ld[2:]))
+    assert np.all(f1.chunk_start == oracle.START_WARM)
