@@ -64,6 +64,17 @@ typedef int32_t rtdetmcd_status;
 #define RTDETMCD_CSTEP_FULL   0 /* recompute the subset mean / covariance (eq. cstep4a, cstep4b) */
 #define RTDETMCD_CSTEP_UPDATE 1 /* update from the swapped rows only (Sec. 3.5) */
 #define RTDETMCD_CSTEP_AUTO   2 /* update, with a full recompute when many rows swap */
+#define RTDETMCD_CSTEP_SMW    3 /* AUTO, and a step whose subset changed by one row out and one
+                                  in updates the inverse of the sscp matrix by the
+                                  Sherman-Morrison-Woodbury identity and its determinant by
+                                  the ratio Delta_i (Sec. 3.5, eq. woodbury, scaleddetUpdate);
+                                  the next step's distances use that inverse */
+#define RTDETMCD_DIST_CHOLESKY 0 /* distances by forward substitution with the Cholesky
+                                   factor (Sec. 3.4) */
+#define RTDETMCD_DIST_INVERSE  1 /* distances (x-mu)^T Sigma^{-1} (x-mu) with the explicit
+                                   inverse, every distance of the fit (the I versus ID rows
+                                   of Table 1, Sec. 5) */
+#define RTDETMCD_START_WARM    2 /* block_start of a block fitted from a warm start */
 #define RTDETMCD_POOL_PRINTED 0 /* Sec. 4 step 7 formulas with block counts m */
 #define RTDETMCD_POOL_UNION   1 /* the text of Sec. 4 step 7: classical mean and
                                   covariance of the union of the kept blocks'
@@ -85,6 +96,7 @@ typedef struct rtdetmcd_opts {
   int32_t launch;           /* RTDETMCD_LAUNCH_* (default BATCHED) */
   int32_t graph;            /* 1: replay the C-step rounds from a captured hipGraph */
   int32_t rounds_per_sync;  /* C-steps enqueued between host checks of convergence (default 4) */
+  int32_t distance;         /* RTDETMCD_DIST_* (default CHOLESKY) */
 } rtdetmcd_opts;
 
 /* Output buffers of a fit.  Every field is a caller-allocated device buffer or
@@ -100,7 +112,8 @@ typedef struct rtdetmcd_out {
   uint8_t* outlier;       /* [n]   1 iff squared distance > chi2_{p,cutoff_q} */
   int32_t* hsubset;       /* [q*h] chosen h-subset of each block, ascending row indices of X */
   int32_t* block_status;  /* [q]   RTDETMCD_ST_* of the chosen start, or BLOCK_INVALID */
-  int32_t* block_start;   /* [q]   0 = wrapping start, 1 = GSSCM start, -1 none */
+  int32_t* block_start;   /* [q]   0 = wrapping start, 1 = GSSCM start, RTDETMCD_START_WARM
+                           *       for a warm start, -1 none */
   int32_t* block_iters;   /* [q]   C-steps taken by the chosen start */
   double*  loc;           /* [p]   standardisation location (Sec. 3.1) */
   double*  scale;         /* [p]   standardisation scale */
@@ -157,11 +170,22 @@ rtdetmcd_status rtdetmcd_fit(rtdetmcd_handle h, const void* X, int32_t dtype, in
  * out-of-range entries are never used as row indices.  With a perm, hsubset
  * lists each block's subset as rows of X in order of their position within
  * the block (ascending only for contiguous blocks), and rew_mask and the
- * final distances stay in the row order of X. */
+ * final distances stay in the row order of X.
+ *
+ * warm_mu (device, float64 [p]) and warm_sigma (device, float64 [p*p],
+ * row-major), both non-NULL: the warm start of the last paragraph of Sec. 4.
+ * A previous fit's reweighted location and scatter (units of X) become the
+ * one start of every block's C-steps (Sec. 4 step 3); the initial estimators
+ * and their refinement (steps 1-2) are not computed for that dataset.  The
+ * standardisation of the new data and steps 4-10 run as usual.  A warm start
+ * that is not positive definite or too ill-conditioned leaves the blocks
+ * invalid (RTDETMCD_ESINGULAR).  Both NULL: the usual two starts. */
 typedef struct rtdetmcd_dataset {
   const void* X; int32_t dtype; int64_t n; int32_t p; int64_t ld;
   int64_t h_sub; int32_t n_chunks; rtdetmcd_out out;
   const int32_t* perm;
+  const double* warm_mu;
+  const double* warm_sigma;
 } rtdetmcd_dataset;
 rtdetmcd_status rtdetmcd_fit_batched(rtdetmcd_handle h, int32_t n_datasets,
                                      const rtdetmcd_dataset* sets, const rtdetmcd_opts* o,

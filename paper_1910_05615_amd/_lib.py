@@ -28,7 +28,7 @@ class Opts(C.Structure):
                 ("cstep_mode", c_i32), ("max_csteps", c_i32), ("kappa_max", c_f64),
                 ("cutoff_q", c_f64), ("pool_mode", c_i32), ("rew_consistency", c_i32),
                 ("omega", c_i32), ("launch", c_i32), ("graph", c_i32),
-                ("rounds_per_sync", c_i32)]
+                ("rounds_per_sync", c_i32), ("distance", c_i32)]
 
 
 class Out(C.Structure):
@@ -40,7 +40,8 @@ class Out(C.Structure):
 
 class DatasetDesc(C.Structure):
     _fields_ = [("X", c_vp), ("dtype", c_i32), ("n", c_i64), ("p", c_i32), ("ld", c_i64),
-                ("h_sub", c_i64), ("n_chunks", c_i32), ("out", Out), ("perm", c_vp)]
+                ("h_sub", c_i64), ("n_chunks", c_i32), ("out", Out), ("perm", c_vp),
+                ("warm_mu", c_vp), ("warm_sigma", c_vp)]
 
 
 _lib = None

@@ -17,7 +17,9 @@ from . import _lib
 _handles = {}
 
 STD = {"unimcd": 0, "medmad": 1}
-CSTEP = {"full": 0, "update": 1, "auto": 2}
+CSTEP = {"full": 0, "update": 1, "auto": 2, "smw": 3}
+DIST = {"cholesky": 0, "inverse": 1}
+START_WARM = 2   # block_start of a block fitted from a warm start (RTDETMCD_START_WARM)
 POOL = {"printed": 0, "union": 1}
 LAUNCH = {"batched": 0, "plain": 1}
 
@@ -71,7 +73,8 @@ def _check_X(X: torch.Tensor):
 def make_opts(alpha: float = 0.75, standardize: str = "unimcd", cstep_mode: str = "auto",
               max_csteps: int = 100, kappa_max: float = 1000.0, cutoff_q: float = 0.975,
               pool: str = "printed", rew_consistency: bool = False, omega: int = 4096,
-              launch: str = "batched", graph: bool = False, rounds_per_sync: int = 4) -> _lib.Opts:
+              launch: str = "batched", graph: bool = False, rounds_per_sync: int = 4,
+              distance: str = "cholesky") -> _lib.Opts:
     lib = _lib.load()
     o = _lib.Opts()
     lib.rtdetmcd_default_opts(C.byref(o))
@@ -87,6 +90,7 @@ def make_opts(alpha: float = 0.75, standardize: str = "unimcd", cstep_mode: str 
     o.launch = LAUNCH[launch]
     o.graph = int(graph)
     o.rounds_per_sync = rounds_per_sync
+    o.distance = DIST[distance]
     return o
 
 
@@ -248,14 +252,16 @@ def random_partition(n: int, seed: int, device=None) -> torch.Tensor:
 
 
 def fit(X: torch.Tensor, h_sub: int = 0, n_chunks: int = 0,
-        perm: Optional[torch.Tensor] = None, **opts) -> Fit:
+        perm: Optional[torch.Tensor] = None, warm=None, **opts) -> Fit:
     """RT-DetMCD fit of X (n x p) on the GPU; all outputs stay on the device.
 
     perm: optional int32 device tensor of n row indices, the random partition
-    of Sec. 4 (see random_partition); None gives contiguous blocks."""
-    if perm is not None:
+    of Sec. 4 (see random_partition); None gives contiguous blocks.
+    warm: optional (mu, sigma) of a previous fit (units of X), the warm start
+    of the last paragraph of Sec. 4."""
+    if perm is not None or warm is not None:
         fits, status = fit_batched([X], h_subs=[h_sub], n_chunks=[n_chunks], perms=[perm],
-                                   **opts)
+                                   warms=[warm], **opts)
         if status[0] != 0:
             lib, hd = _handle(X.device)
             _check(lib, hd, status[0], "rtdetmcd_fit_batched")
@@ -323,20 +329,24 @@ class RobustMCD(torch.autograd.Function):
 
 def fit_batched(Xs: Sequence[torch.Tensor], h_subs: Optional[Sequence[int]] = None,
                 n_chunks: Optional[Sequence[int]] = None,
-                perms: Optional[Sequence[Optional[torch.Tensor]]] = None, **opts):
+                perms: Optional[Sequence[Optional[torch.Tensor]]] = None,
+                warms: Optional[Sequence] = None, **opts):
     """Fit many independent datasets in the same launches.
 
     perms: optional per-dataset random partitions (int32 device tensors of n
-    row indices, or None).  Returns (list of Fit, list of per-dataset status
-    codes)."""
+    row indices, or None).  warms: optional per-dataset warm starts ((mu,
+    sigma) in the units of X, or None).  Returns (list of Fit, list of
+    per-dataset status codes)."""
     lib, hd = _handle(Xs[0].device)
     o = make_opts(**opts)
     k = len(Xs)
     h_subs = list(h_subs) if h_subs is not None else [0] * k
     n_chunks = list(n_chunks) if n_chunks is not None else [0] * k
     perms = list(perms) if perms is not None else [None] * k
+    warms = list(warms) if warms is not None else [None] * k
     arr = (_lib.DatasetDesc * k)()
     fits = []
+    keep = []   # warm-start tensors stay alive until the call returns
     for i, X in enumerate(Xs):
         _check_X(X)
         n, p = X.shape
@@ -349,9 +359,18 @@ def fit_batched(Xs: Sequence[torch.Tensor], h_subs: Optional[Sequence[int]] = No
             if (pm.dtype != torch.int32 or pm.device != X.device or pm.dim() != 1
                     or pm.shape[0] != n or not pm.is_contiguous()):
                 raise ValueError("perm must be a contiguous int32 tensor of n rows on X's device")
+        wm = ws = None
+        if warms[i] is not None:
+            wm = warms[i][0].to(device=X.device, dtype=torch.float64).contiguous()
+            ws = warms[i][1].to(device=X.device, dtype=torch.float64).contiguous()
+            if tuple(wm.shape) != (p,) or tuple(ws.shape) != (p, p):
+                raise ValueError("warm start must be (mu [p], sigma [p, p])")
+            keep += [wm, ws]
         arr[i] = _lib.DatasetDesc(X=X.data_ptr(), dtype=_dtype_code(X), n=n, p=p, ld=X.stride(0),
                                   h_sub=h_subs[i], n_chunks=n_chunks[i], out=out,
-                                  perm=pm.data_ptr() if pm is not None else None)
+                                  perm=pm.data_ptr() if pm is not None else None,
+                                  warm_mu=wm.data_ptr() if wm is not None else None,
+                                  warm_sigma=ws.data_ptr() if ws is not None else None)
     status = (C.c_int32 * k)()
     st = lib.rtdetmcd_fit_batched(hd, k, arr, C.byref(o), status)
     _check(lib, hd, st, "rtdetmcd_fit_batched")

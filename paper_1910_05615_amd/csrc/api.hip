@@ -84,7 +84,7 @@ rtdetmcd_status Uploader::flush(rtdetmcd_ctx* ctx) {
   return RTDETMCD_OK;
 }
 
-void layout_items(Layout& L, const ItemSet& S, size_t off[20]) {
+void layout_items(Layout& L, const ItemSet& S, size_t off[NOFF]) {
   const size_t I = S.items.size();
   off[0] = L.add(I * sizeof(ItemDesc));
   off[1] = L.add(S.dtiles.size() * sizeof(Tile));
@@ -106,9 +106,11 @@ void layout_items(Layout& L, const ItemSet& S, size_t off[20]) {
   off[17] = L.add(S.stiles.size() * PSTRIDE * 8);  // partials
   off[18] = L.add(64);                   // nactive
   off[19] = L.add(S.ptiles.size() * sizeof(Tile));
+  off[20] = L.add(I * 4);             // form
+  off[21] = L.add(I * MSTRIDE * 8);   // sinv
 }
 
-void bind_items(char* base, const ItemSet& S, const size_t off[20], ItemDev& D) {
+void bind_items(char* base, const ItemSet& S, const size_t off[NOFF], ItemDev& D) {
   D.items = reinterpret_cast<ItemDesc*>(base + off[0]);
   D.dtiles = reinterpret_cast<Tile*>(base + off[1]);
   D.stiles = reinterpret_cast<Tile*>(base + off[2]);
@@ -130,6 +132,8 @@ void bind_items(char* base, const ItemSet& S, const size_t off[20], ItemDev& D) 
   A.part = reinterpret_cast<double*>(base + off[17]);
   A.nactive = reinterpret_cast<int32_t*>(base + off[18]);
   D.ptiles = reinterpret_cast<Tile*>(base + off[19]);
+  A.form = reinterpret_cast<int32_t*>(base + off[20]);
+  A.sinv = reinterpret_cast<double*>(base + off[21]);
   (void)S;
 }
 
@@ -198,18 +202,24 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
     for (int i = first; i < first + n; ++i) max_m = std::max(max_m, S.items[i].m);
     const int max_nt = S.max_ntiles(first, first + n);
     const bool dense = S.rows_dense(first, first + n, bucket);
-    RTD_HIP(launch_finalize(bucket, D.items, D.A, first, n, 1, maxs, o.kappa_max, st));
+    RTD_HIP(launch_finalize(bucket, D.items, D.A, first, n, 1, maxs, o.kappa_max, o.cstep_mode,
+                            o.distance, st));
     const int R = std::max(1, o.rounds_per_sync);
+    // items may hold the explicit-inverse form only with the distance switch
+    // or the single-swap mode
+    const int32_t* form =
+        (o.distance || o.cstep_mode == RTDETMCD_CSTEP_SMW) ? D.A.form : nullptr;
     // one C-step of every active item
     // one C-step of every active item; the selection zeroes the active count
     auto step = [&](hipStream_t s) -> rtdetmcd_status {
       RTD_HIP(launch_dist(bucket, dtype, dense, pairs ? 2 : 1, D.items, dtl + dt0, dtn, DIST_TILE,
-                          D.A.mtri, D.A.mux, D.A.status, D.A.d2, s));
+                          D.A.mtri, D.A.mux, D.A.status, form, D.A.d2, s));
       RTD_HIP(launch_select(D.items, D.A, first, n, max_m, o.cstep_mode, s, 1));
       RTD_HIP(launch_sscp(bucket, dtype, SSCP_CSTEP, D.items, D.A, D.stiles + st0, stn,
                           SSCP_TILE, nullptr, nullptr, s));
       RTD_HIP(launch_collapse(D.items, D.A, first, n, max_nt, 1, SSCP_TILE, s));
-      RTD_HIP(launch_finalize(bucket, D.items, D.A, first, n, 0, maxs, o.kappa_max, s));
+      RTD_HIP(launch_finalize(bucket, D.items, D.A, first, n, 0, maxs, o.kappa_max,
+                              o.cstep_mode, o.distance, s));
       return RTDETMCD_OK;
     };
     int t = 1;
@@ -224,14 +234,14 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
       const void* ptrs[] = {ctx->ws,   D.items,  dtl,      D.stiles, A.status, A.iter,
                             A.kswap,   A.full,   A.logdet, A.mux,    A.lamx,   A.muz,
                             A.sigz,    A.linv,   A.mtri,   A.d2,     A.mask,   A.swap,
-                            A.part,    A.nactive};
+                            A.part,    A.nactive, A.form,  A.sinv};
       std::vector<int64_t> key;
       for (const void* q : ptrs) key.push_back((int64_t)(uintptr_t)q);
       int64_t kbits;
       std::memcpy(&kbits, &o.kappa_max, 8);
       const int64_t scal[] = {bucket, dtype, first, n, (pairs ? 2 : 1) + (dense ? 4 : 0),
                               dt0, dtn, st0, stn, max_nt, max_m, (int64_t)S.items.size(),
-                              S.rows, o.cstep_mode, maxs, R, kbits};
+                              S.rows, o.cstep_mode, maxs, R, kbits, o.distance};
       key.insert(key.end(), std::begin(scal), std::end(scal));
       hipGraphExec_t ge = nullptr;
       RTD_TRY(graph_for(ctx, key, R, step, &ge));
@@ -261,19 +271,23 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
   // plain: one item at a time, host-driven, one host check per step
   for (int i = first; i < first + n; ++i) {
     const ItemDesc& d = S.items[i];
-    RTD_HIP(launch_finalize(bucket, D.items, D.A, i, 1, 1, maxs, o.kappa_max, st));
+    RTD_HIP(launch_finalize(bucket, D.items, D.A, i, 1, 1, maxs, o.kappa_max, o.cstep_mode,
+                            o.distance, st));
     RTD_HIP(hipMemcpyAsync(pin_flag, D.A.status + i, 4, hipMemcpyDeviceToHost, st));
     RTD_HIP(hipStreamSynchronize(st));
     if (*pin_flag != ACTIVE) continue;
     for (int t = 1; t <= maxs; ++t) {
       RTD_HIP(launch_dist(bucket, dtype, S.rows_dense(i, i + 1, bucket), 1, D.items,
                           D.dtiles + S.dt_first[i], S.dt_count[i],
-                          DIST_TILE, D.A.mtri, D.A.mux, D.A.status, D.A.d2, st));
+                          DIST_TILE, D.A.mtri, D.A.mux, D.A.status,
+                          (o.distance || o.cstep_mode == RTDETMCD_CSTEP_SMW) ? D.A.form : nullptr,
+                          D.A.d2, st));
       RTD_HIP(launch_select(D.items, D.A, i, 1, d.m, o.cstep_mode, st));
       RTD_HIP(launch_sscp(bucket, dtype, SSCP_CSTEP, D.items, D.A, D.stiles + d.tile0,
                           d.ntiles, SSCP_TILE, nullptr, nullptr, st));
       RTD_HIP(launch_collapse(D.items, D.A, i, 1, d.ntiles, 1, SSCP_TILE, st));
-      RTD_HIP(launch_finalize(bucket, D.items, D.A, i, 1, 0, maxs, o.kappa_max, st));
+      RTD_HIP(launch_finalize(bucket, D.items, D.A, i, 1, 0, maxs, o.kappa_max, o.cstep_mode,
+                              o.distance, st));
       RTD_HIP(hipMemcpyAsync(pin_flag, D.A.status + i, 4, hipMemcpyDeviceToHost, st));
       RTD_HIP(hipStreamSynchronize(st));
       if (*pin_flag != ACTIVE) break;
@@ -293,8 +307,8 @@ rtdetmcd_status check_opts(rtdetmcd_ctx* ctx, const rtdetmcd_opts* in, rtdetmcd_
   }
   if (!(o.alpha > 0.5 && o.alpha <= 1.0) || o.max_csteps < 1 || !(o.kappa_max > 1.0) ||
       !(o.cutoff_q > 0.0 && o.cutoff_q < 1.0) || o.omega < 1 || o.standardize < 0 ||
-      o.standardize > 1 || o.cstep_mode < 0 || o.cstep_mode > 2 || o.pool_mode < 0 ||
-      o.pool_mode > 1 || o.launch < 0 || o.launch > 1) {
+      o.standardize > 1 || o.cstep_mode < 0 || o.cstep_mode > 3 || o.pool_mode < 0 ||
+      o.pool_mode > 1 || o.launch < 0 || o.launch > 1 || o.distance < 0 || o.distance > 1) {
     ctx->err = "invalid option value";
     return RTDETMCD_EINVAL;
   }
@@ -388,6 +402,7 @@ void rtdetmcd_default_opts(rtdetmcd_opts* o) {
   o->launch = RTDETMCD_LAUNCH_BATCHED;
   o->graph = 0;
   o->rounds_per_sync = 4;
+  o->distance = RTDETMCD_DIST_CHOLESKY;
 }
 
 rtdetmcd_status rtdetmcd_create(rtdetmcd_handle* out, int32_t device, void* hip_stream) {
@@ -485,7 +500,7 @@ rtdetmcd_status rtdetmcd_distances(rtdetmcd_handle ctx, const void* X, int32_t d
   d.X = X; d.ld = ld; d.row0 = 0; d.m = n; d.h = 0; d.p = p; d.dtype = dtype; d.start = -1;
   S.add(d);
   Layout L0;
-  size_t off[20];
+  size_t off[NOFF];
   layout_items(L0, S, off);
   // only items, tiles, mux and mtri are used
   RTD_TRY(ensure_ws(ctx, L0.off));
@@ -501,7 +516,7 @@ rtdetmcd_status rtdetmcd_distances(rtdetmcd_handle ctx, const void* X, int32_t d
   // the distance kernel writes d2 + roff with roff = 0
   RTD_HIP(launch_dist(bucket_of(p), dtype, S.rows_dense(0, (int)S.items.size(), bucket_of(p)), 1,
                       D.items, D.dtiles, (int)S.dtiles.size(), DIST_TILE,
-                      D.A.mtri, D.A.mux, nullptr, d2, ctx->stream));
+                      D.A.mtri, D.A.mux, nullptr, nullptr, d2, ctx->stream));
   return RTDETMCD_OK;
 }
 
@@ -536,7 +551,7 @@ rtdetmcd_status rtdetmcd_select(rtdetmcd_handle ctx, const double* d2, int64_t m
   d.m = m; d.h = h_sub; d.p = 1; d.start = -1;
   S.add(d);
   Layout L0;
-  size_t off[20];
+  size_t off[NOFF];
   layout_items(L0, S, off);
   RTD_TRY(ensure_ws(ctx, L0.off));
   ItemDev D;
@@ -577,7 +592,7 @@ rtdetmcd_status rtdetmcd_cstep(rtdetmcd_handle ctx, const void* X, int32_t dtype
   d.X = X; d.ld = ld; d.row0 = 0; d.m = m; d.h = h_sub; d.p = p; d.dtype = dtype; d.start = -1;
   S.add(d);
   Layout L0;
-  size_t off[20];
+  size_t off[NOFF];
   layout_items(L0, S, off);
   const size_t o_loc = L0.add(PMAX * 8), o_scale = L0.add(PMAX * 8), o_flag = L0.add(64);
   RTD_TRY(ensure_ws(ctx, L0.off));

@@ -57,6 +57,8 @@ struct ItemArrays {
   int32_t* swap;     // [rows] entering rows from 0, leaving rows from m/2
   double* part;      // [tiles * PSTRIDE] SSCP tile partials
   int32_t* nactive;  // [1] items still active after the last finalize
+  int32_t* form;     // [I] 0: mtri holds L^{-1} D^{-1}; 1: the packed explicit inverse P~
+  double* sinv;      // [I*MSTRIDE] inverse of lamx (data units), kept by the single-swap mode
 };
 
 constexpr int PSTRIDE = 1 + PMAX + TRI;  // count, sum, packed sscp
@@ -112,10 +114,13 @@ inline bool dist_pairs_pay(int bucket) { return bucket > 40; }
 // skip the per-element path for narrower or strided rows).  ipt: 1, or 2 for
 // pair tiles (both starts of a block per tile), valid only where
 // dist_pairs_pay(bucket); otherwise hipErrorInvalidValue.
+// form: per-item distance form (ItemArrays::form), or null when every item
+// holds L^{-1} D^{-1} (the launch then takes the kernels without the
+// explicit-inverse evaluation).
 hipError_t launch_dist(int bucket, int dtype, int dense, int ipt, const ItemDesc* items,
                        const Tile* tiles,
                        int ntiles, int tile_rows, const double* mtri, const double* mux,
-                       const int32_t* status, double* d2, hipStream_t s);
+                       const int32_t* status, const int32_t* form, double* d2, hipStream_t s);
 // max_m: largest m among the items (picks the register-resident variant).
 // reset_nactive: the first block zeroes *A.nactive before anything else (the
 // C-step loop counts the items left active by the step's finalize).
@@ -132,9 +137,13 @@ hipError_t launch_sscp(int bucket, int dtype, int mode, const ItemDesc* items, I
 hipError_t launch_collapse(const ItemDesc* items, ItemArrays A, int first, int nitems,
                            int max_ntiles, int cstep, int tile_rows, hipStream_t s);
 // bucket: a p bucket (bucket_of) no smaller than any item's p.
+// cstep_mode: RTDETMCD_CSTEP_*; with RTDETMCD_CSTEP_SMW a step that swapped
+// one row in and one out takes the single-swap update (Sec. 3.5) and the
+// inverse form.  dist_form: 1 writes the explicit-inverse form P~ for every
+// other step too (the distance switch), 0 the Cholesky form.
 hipError_t launch_finalize(int bucket, const ItemDesc* items, ItemArrays A, int first_item,
                            int nitems, int from_start, int max_csteps, double kappa_max,
-                           hipStream_t s);
+                           int cstep_mode, int dist_form, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 // stage: n records (dst, offset, bytes) of 3 uint64 each, then the payload at
 // those offsets from stage; copies every record's bytes to its dst.

@@ -113,8 +113,9 @@ struct ItemDev {
   ItemArrays A{};
 };
 
-void layout_items(Layout& L, const ItemSet& S, size_t off[20]);  // uses off[0..19]
-void bind_items(char* base, const ItemSet& S, const size_t off[20], ItemDev& D);
+constexpr int NOFF = 22;   // workspace offsets of one item set
+void layout_items(Layout& L, const ItemSet& S, size_t off[NOFF]);
+void bind_items(char* base, const ItemSet& S, const size_t off[NOFF], ItemDev& D);
 
 // Enqueue the C-step loop for items [first, first+n) of a bucket/dtype class.
 // Batched: all items in each launch, host checks convergence every

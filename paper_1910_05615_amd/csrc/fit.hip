@@ -16,6 +16,7 @@ namespace {
 struct DsHost {
   const rtdetmcd_dataset* in;
   const int32_t* perm;   // random partition (Sec. 4), or null for contiguous blocks
+  bool warm;             // warm start (last paragraph of Sec. 4)
   int p, dtype, bucket, q;
   int64_t n, m, h, ld;
   double chi2p, calpha, crew;
@@ -110,6 +111,7 @@ struct Group {   // datasets sharing a kernel instantiation (p bucket, dtype)
   int ds0, ds1;          // dataset range (in fit order)
   int c0, c1;            // C-step items
   int b0, b1;            // block items
+  bool all_warm;         // every dataset warm-started: no starts to compute
 };
 
 }  // namespace
@@ -127,7 +129,8 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     int32_t q;
     int64_t m, h;
     rtdetmcd_status ps = rtdetmcd_plan(s.n, s.p, s.h_sub, s.n_chunks, &o, &q, &m, &h);
-    if (ps == RTDETMCD_OK && (!s.X || s.ld < s.p || (s.dtype != 0 && s.dtype != 1)))
+    if (ps == RTDETMCD_OK && (!s.X || s.ld < s.p || (s.dtype != 0 && s.dtype != 1) ||
+                              (!s.warm_mu) != (!s.warm_sigma)))
       ps = RTDETMCD_EINVAL;
     if (ps != RTDETMCD_OK) {
       if (status) status[i] = ps;
@@ -138,6 +141,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     DsHost d{};
     d.in = &s;
     d.perm = s.perm;
+    d.warm = s.warm_mu != nullptr;
     d.p = s.p;
     d.dtype = s.dtype;
     d.bucket = bucket_of(s.p);
@@ -167,7 +171,8 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     DsHost& d = D[k];
     if (groups.empty() || groups.back().bucket != d.bucket || groups.back().dtype != d.dtype)
       groups.push_back({d.bucket, d.dtype, k, k, (int)C.items.size(), (int)C.items.size(),
-                        (int)B.items.size(), (int)B.items.size()});
+                        (int)B.items.size(), (int)B.items.size(), true});
+    groups.back().all_warm = groups.back().all_warm && d.warm;
     d.item0 = (int)C.items.size();
     d.blk0 = (int)B.items.size();
     for (int l = 0; l < d.q; ++l) {
@@ -237,7 +242,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
 
   // ---------------------------------------------------------------- workspace
   Layout L;
-  size_t offC[20], offB[20], offG[20];
+  size_t offC[NOFF], offB[NOFF], offG[NOFF];
   layout_items(L, C, offC);
   layout_items(L, B, offB);
   layout_items(L, G, offG);
@@ -384,6 +389,8 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     x.err = 0;
     x.perm = D[k].perm;
     x.inv = D[k].perm ? reinterpret_cast<int32_t*>(base + o_inv[k]) : nullptr;
+    x.warm_mu = D[k].warm ? D[k].in->warm_mu : nullptr;
+    x.warm_sigma = D[k].warm ? D[k].in->warm_sigma : nullptr;
     houts[k] = D[k].in->out;
     hchi[k] = D[k].chi2p;
   }
@@ -513,9 +520,12 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   RTD_HIP(launch_fill_u8(CD.A.mask, 0, C.rows, st));
   if (!plain) {
     for (const Group& g : groups) {
+      if (g.all_warm) continue;   // steps 1-2 are not needed
       if (g.b1 > g.b0) RTD_TRY(blocks_phase(g.b0, g.b1));
       if (g.c1 > g.c0) RTD_TRY(refine_phase(g.c0, g.c1));
     }
+    for (int k = 0; k < ND; ++k)
+      if (D[k].warm) RTD_HIP(launch_warm_start(dds, k, D[k].q, CD.A, F, st));
     // ---------------------------------------------------------------- step 3: C-steps
     for (const Group& g : groups)
       if (g.c1 > g.c0)
@@ -523,9 +533,15 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     RTD_HIP(launch_choose(BD.items, CD.items, CD.A, F, dds, 0, NB, st));
   } else {
     for (int b = 0; b < NB; ++b) {
-      RTD_TRY(blocks_phase(b, b + 1));
+      const int k = B.items[b].ds;
+      if (D[k].warm) {
+        // the dataset's blocks in one go, at its first block
+        if (b == D[k].blk0) RTD_HIP(launch_warm_start(dds, k, D[k].q, CD.A, F, st));
+      } else {
+        RTD_TRY(blocks_phase(b, b + 1));
+      }
       for (int c = 2 * b; c < 2 * b + 2; ++c) {
-        RTD_TRY(refine_phase(c, c + 1));
+        if (!D[k].warm) RTD_TRY(refine_phase(c, c + 1));
         const Group& g = group_of_item(c);
         RTD_TRY(run_csteps(ctx, C, CD, g.bucket, g.dtype, c, 1, o, ctx->flag));
       }
@@ -535,19 +551,20 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
 
   // ---------------------------------------------------------------- steps 5-7: aggregation
   RTD_HIP(launch_median(dds, F, dent, (int)ent.size(), st));
-  RTD_HIP(launch_kl(dds, CD.A, F, 0, NB, st));
+  RTD_HIP(launch_kl(dds, CD.A, F, 0, NB, o.cstep_mode == RTDETMCD_CSTEP_SMW, st));
   RTD_HIP(launch_fill_i32(GD.A.status, ACTIVE, NG, st));
   RTD_HIP(launch_pool(dds, GD.A, F, 0, ND, o.pool_mode, st));
   for (const Group& g : groups)
-    RTD_HIP(launch_finalize(g.bucket, GD.items, GD.A, g.ds0, g.ds1 - g.ds0, 1, 1, 1e300, st));
+    RTD_HIP(launch_finalize(g.bucket, GD.items, GD.A, g.ds0, g.ds1 - g.ds0, 1, 1, 1e300,
+                            RTDETMCD_CSTEP_FULL, o.distance, st));
   // ---------------------------------------------------------------- steps 8-9: reweighting
   for (const Group& g : groups) {
     const int a = g.ds0, b = g.ds1;
     const int dt0 = G.dt_first[a], dtn = G.dt_first[b - 1] + G.dt_count[b - 1] - dt0;
     const int st0 = G.items[a].tile0, stn = G.items[b - 1].tile0 + G.items[b - 1].ntiles - st0;
     RTD_HIP(launch_dist(g.bucket, g.dtype, G.rows_dense(a, b, g.bucket), 1, GD.items,
-                        GD.dtiles + dt0, dtn, DIST_TILE, GD.A.mtri, GD.A.mux, nullptr, GD.A.d2,
-                        st));
+                        GD.dtiles + dt0, dtn, DIST_TILE, GD.A.mtri, GD.A.mux, nullptr,
+                        o.distance ? GD.A.form : nullptr, GD.A.d2, st));
     RTD_HIP(launch_sscp(g.bucket, g.dtype, SSCP_D2CUT, GD.items, GD.A, GD.stiles + st0, stn,
                         SSCP_TILE, nullptr, dchi, st));
     RTD_HIP(launch_collapse(GD.items, GD.A, a, b - a, G.max_ntiles(a, b), 0, SSCP_TILE, st));
@@ -556,14 +573,15 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   RTD_HIP(launch_fill_i32(GD.A.status + ND, ACTIVE, ND, st));
   for (const Group& g : groups)
     RTD_HIP(launch_finalize(g.bucket, GD.items, GD.A, ND + g.ds0, g.ds1 - g.ds0, 1, 1, 1e300,
-                            st));
+                            RTDETMCD_CSTEP_FULL, o.distance, st));
   // ---------------------------------------------------------------- step 10: distances, flags
   for (const Group& g : groups) {
     const int a = ND + g.ds0, b = ND + g.ds1;
     const int dt0 = G.dt_first[a], dtn = G.dt_first[b - 1] + G.dt_count[b - 1] - dt0;
     RTD_HIP(launch_final_dist(g.bucket, g.dtype, G.rows_dense(a, b, g.bucket), GD.items,
                               GD.dtiles + dt0, dtn, DIST_TILE,
-                              GD.A.mtri, GD.A.mux, GD.A.d2, dds, douts, st));
+                              GD.A.mtri, GD.A.mux, o.distance ? GD.A.form : nullptr, GD.A.d2,
+                              dds, douts, st));
   }
   RTD_HIP(launch_hsub(CD.items, CD.A, F, dds, douts, 0, NB, st));
   RTD_HIP(launch_outputs(dds, GD.A, F, douts, 0, ND, st));

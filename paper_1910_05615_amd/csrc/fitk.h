@@ -21,6 +21,8 @@ struct DsInfo {
   int32_t err;       // 0 ok, else a status code
   const int32_t* perm;  // random partition: dataset row of block position k, or null
   int32_t* inv;         // its inverse: block position of dataset row i (valid perm only)
+  const double* warm_mu;     // warm start (units of X), or null
+  const double* warm_sigma;
 };
 
 // Per-dataset and per-block result arrays.
@@ -84,15 +86,16 @@ hipError_t launch_choose(const ItemDesc* bitems, const ItemDesc* citems, ItemArr
 hipError_t launch_median(const DsInfo* ds, FitArrays F, const int2* ent, int nent,
                          hipStream_t s);
 hipError_t launch_kl(const DsInfo* ds, ItemArrays A, FitArrays F, int first_blk, int nblk,
-                     hipStream_t s);
+                     int use_sinv, hipStream_t s);
 hipError_t launch_pool(DsInfo* ds, ItemArrays G, FitArrays F, int first_ds, int nds, int pool_mode,
                        hipStream_t s);
 hipError_t launch_rew(DsInfo* ds, const ItemDesc* gitems, ItemArrays G, FitArrays F, int first_ds,
                       int nds, hipStream_t s);
+// form: per-item distance form of the items (ItemArrays::form), or null.
 hipError_t launch_final_dist(int bucket, int dtype, int dense, const ItemDesc* items,
                              const Tile* tiles,
                              int ntiles, int tile_rows, const double* mtri, const double* mux,
-                             const double* d2, const DsInfo* ds,
+                             const int32_t* form, const double* d2, const DsInfo* ds,
                              const struct rtdetmcd_out* outs, hipStream_t s);
 // Random partition (Sec. 4) of dataset d: check that perm is a permutation
 // of 0..n-1 (inv prefilled with -1 receives its inverse; a bad entry sets
@@ -102,6 +105,11 @@ hipError_t launch_perm_check(const int32_t* perm, int64_t n, int32_t* inv, DsInf
                              hipStream_t s);
 hipError_t launch_perm_gather(int dtype, const void* X, int64_t n, int64_t ld, int p,
                               const int32_t* perm, int64_t rows, void* Xp, hipStream_t s);
+// Warm start (last paragraph of Sec. 4) of dataset d's q blocks: the first
+// item of each block starts from (warm_mu, warm_sigma) in standardised units,
+// the second is dropped.
+hipError_t launch_warm_start(const DsInfo* ds, int d, int q, ItemArrays C, FitArrays F,
+                             hipStream_t s);
 hipError_t launch_hsub(const ItemDesc* citems, ItemArrays A, FitArrays F, const DsInfo* ds,
                        const struct rtdetmcd_out* outs, int first, int n, hipStream_t s);
 hipError_t launch_outputs(const DsInfo* ds, ItemArrays G, FitArrays F,

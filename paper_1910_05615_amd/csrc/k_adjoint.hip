@@ -232,7 +232,7 @@ extern "C" rtdetmcd_status rtdetmcd_backward(rtdetmcd_handle ctx, const void* X,
   d.X = X; d.ld = ld; d.row0 = 0; d.m = n; d.h = n - 1; d.p = p; d.dtype = dtype; d.start = -1;
   S.add(d);
   Layout L0;
-  size_t off[20];
+  size_t off[NOFF];
   layout_items(L0, S, off);
   const size_t o_P = L0.add(PMAX * PMAX * 8);
   const size_t o_K = L0.add(PMAX * PMAX * 8);

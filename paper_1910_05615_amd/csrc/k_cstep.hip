@@ -346,10 +346,59 @@ __device__ inline double lane_bcast(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// Single-swap step of an item (Sec. 3.5): the leaving row, then the entering
+// row, update the mean and the sscp matrix case by case (eq. propcstep1,
+// muUpdate, propcstep2), and the inverse of the sscp matrix by the
+// Sherman-Morrison-Woodbury identity (eq. woodbury), with the determinant
+// ratio Delta_i of eq. (scaleddetUpdate).  Lane i holds row i of the sscp
+// matrix (lr) and of its inverse (li), in data units.  Returns false when a
+// Delta_i is not positive (the new sscp matrix would be singular).
+template <int P>
+__device__ inline bool smw_swaps(const ItemDesc& D, const int32_t* __restrict__ swp, double h,
+                                 double& mu, double (&lr)[P], double (&li)[P], double& ldsum) {
+  const int lane = threadIdx.x;
+  const bool in = lane < D.p;
+  const int64_t rows[2] = {swp[D.m / 2], swp[0]};   // leaving, entering
+  const double dl[2] = {-1.0, 1.0};
+  double hc = h;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int64_t r = D.row0 + rows[c];
+    double x = 0.0;
+    if (in) {
+      x = D.dtype == 0 ? (double)static_cast<const float*>(D.X)[r * D.ld + lane]
+                       : static_cast<const double*>(D.X)[r * D.ld + lane];
+    }
+    const double dlt = dl[c];
+    hc += dlt;
+    const double u = in ? x - mu : 0.0;
+    mu = mu + (dlt / hc) * u;
+    const double v = in ? x - mu : 0.0;
+    double av = 0.0, bv = 0.0;   // (Lam^{-1} u)_i, (Lam^{-1} v)_i
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      av = fma(li[j], lane_bcast(u, j), av);
+      bv = fma(li[j], lane_bcast(v, j), bv);
+    }
+    const double dot = wave_sum(in ? v * av : 0.0);
+    const double Delta = 1.0 + dlt * dot;
+    if (!(Delta > 0.0)) return false;
+    const double f = dlt / Delta;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      li[j] = fma(-f * av, lane_bcast(bv, j), li[j]);
+      lr[j] = fma(dlt * u, lane_bcast(v, j), lr[j]);
+    }
+    ldsum += log(Delta);
+  }
+  return true;
+}
+
 template <int P>
 __global__ __launch_bounds__(64) void k_finalize(const ItemDesc* __restrict__ items,
                                                  ItemArrays A, int first_item, int from_start,
-                                                 int max_csteps, double kappa_max) {
+                                                 int max_csteps, double kappa_max,
+                                                 int cstep_mode, int dist_form) {
   const int it = first_item + blockIdx.x;
   if (A.status[it] != ACTIVE) return;
   const ItemDesc D = items[it];
@@ -361,7 +410,60 @@ __global__ __launch_bounds__(64) void k_finalize(const ItemDesc* __restrict__ it
   double* __restrict__ lam = A.lamx + (size_t)it * MSTRIDE;
   double* __restrict__ muz = A.muz + (size_t)it * PMAX;
   double* __restrict__ sigz = A.sigz + (size_t)it * MSTRIDE;
+  double* __restrict__ sinv = A.sinv + (size_t)it * MSTRIDE;
+  double* __restrict__ mt = A.mtri + (size_t)it * MSTRIDE;
   const double sc = in ? D.scale[lane] : 1.0;
+  const bool smw_mode = cstep_mode == 3;   // RTDETMCD_CSTEP_SMW
+  // a step whose subset changed by one row out and one in, in the single-swap
+  // mode: the inverse and the determinant are carried, no Cholesky
+  if (!from_start && smw_mode && !A.full[it] && A.kswap[it] == 1) {
+    double lr[P], li[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const bool ok = in && j < p;
+      lr[j] = ok ? lam[lane * PMAX + j] : 0.0;
+      li[j] = ok ? sinv[lane * PMAX + j] : 0.0;
+    }
+    double mu = in ? mux[lane] : 0.0;
+    double ldsum = 0.0;
+    if (!smw_swaps<P>(D, A.swap + D.roff, h, mu, lr, li, ldsum)) {
+      if (lane == 0) A.status[it] = ST_SINGULAR;
+      return;
+    }
+    // Sigma_z = D^{-1} Lam D^{-1} / (h-1), Sigma_z^{-1} = (h-1) D Lam^{-1} D;
+    // the distance factor is the packed inverse in data units
+    double n1 = 0.0, n2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const double scj = lane_bcast(sc, j);
+      if (in && j < p) {
+        lam[lane * PMAX + j] = lr[j];
+        sinv[lane * PMAX + j] = li[j];
+        const double sz = lr[j] / (sc * scj) / (h - 1.0);
+        sigz[lane * PMAX + j] = sz;
+        n1 += fabs(sz);
+        n2 += fabs((h - 1.0) * li[j] * (sc * scj));
+        if (j <= lane) mt[lane * PMAX + j] = (j < lane ? 2.0 : 1.0) * (h - 1.0) * li[j];
+      }
+    }
+    if (in) {
+      mux[lane] = mu;
+      muz[lane] = (mu - D.loc[lane]) / sc;
+    }
+    n1 = wave_max(n1);
+    n2 = wave_max(n2);
+    if (lane == 0) {
+      A.form[it] = 1;
+      A.logdet[it] += ldsum;
+      const double kap = n1 * n2;
+      int st = ACTIVE;
+      if (A.iter[it] >= max_csteps) st = ST_NOTCONV;
+      else if (!(kap < kappa_max)) st = ST_ILLCOND;
+      A.status[it] = st;
+      if (st == ACTIVE && A.nactive) atomicAdd(A.nactive, 1);
+    }
+    return;
+  }
   double a[P];
   if (!from_start) {
     const int full = A.full[it];
@@ -436,7 +538,10 @@ n1 = wave_max(n1);
     for (int k = 0; k < i; ++k) si = fma(-lane_bcast(a[k], i), x[k], si);
     x[i] = si / lane_bcast(diag, i);
   }
-  // 1-norm of Sigma^{-1} = X^T X: column `lane`, entries b in order
+  // 1-norm of Sigma^{-1} = X^T X: column `lane`, entries b in order.  The
+  // single-swap mode keeps Lam^{-1} = D^{-1} Sigma^{-1} D^{-1} / (h-1); the
+  // distance switch takes the packed inverse P~ (data units) as the factor.
+  const bool keep_inv = smw_mode || dist_form;
   double n2 = 0.0;
 #pragma unroll
   for (int b = 0; b < P; ++b) {
@@ -445,16 +550,21 @@ n1 = wave_max(n1);
 #pragma unroll
       for (int k = b; k < P; ++k) v = fma(x[k], lane_bcast(x[k], b), v);
       n2 += fabs(v);
+      if (keep_inv) {
+        const double scb = lane_bcast(sc, b);
+        const double vx = v / (sc * scb);             // (Sigma^{-1} in data units)_{lane, b}
+        if (in && smw_mode) sinv[lane * PMAX + b] = vx / (h - 1.0);
+        if (in && dist_form && b <= lane) mt[lane * PMAX + b] = (b < lane ? 2.0 : 1.0) * vx;
+      }
     }
   }
   if (!in) n2 = 0.0;
 n2 = wave_max(n2);
   double* __restrict__ linv = A.linv + (size_t)it * MSTRIDE;
-  double* __restrict__ mt = A.mtri + (size_t)it * MSTRIDE;
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     if (i < p) {
-      mt[i * PMAX + lane] = lane <= i ? x[i] / sc : 0.0;
+      if (!dist_form) mt[i * PMAX + lane] = lane <= i ? x[i] / sc : 0.0;
       if (in) linv[i * PMAX + lane] = x[i];
     }
   }
@@ -464,6 +574,7 @@ n2 = wave_max(n2);
   for (int j = 0; j < P; ++j)
     if (j < p) ld += lane_bcast(lg, j);
   if (lane == 0) {
+    A.form[it] = dist_form ? 1 : 0;
     A.logdet[it] = 2.0 * ld;
     const double kap = n1 * n2;
     int st = ACTIVE;
@@ -563,12 +674,12 @@ hipError_t launch_select(const ItemDesc* items, ItemArrays A, int first_item, in
 
 hipError_t launch_finalize(int bucket, const ItemDesc* items, ItemArrays A, int first_item,
                            int nitems, int from_start, int max_csteps, double kappa_max,
-                           hipStream_t s) {
+                           int cstep_mode, int dist_form, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
 #define CASE(PB)                                                                              \
   case PB:                                                                                    \
     hipLaunchKernelGGL((k_finalize<PB>), dim3(nitems), dim3(64), 0, s, items, A, first_item, \
-                       from_start, max_csteps, kappa_max);                                    \
+                       from_start, max_csteps, kappa_max, cstep_mode, dist_form);             \
     break;
   switch (bucket) {
     CASE(4) CASE(5) CASE(8) CASE(10) CASE(16) CASE(20) CASE(24) CASE(32) CASE(40) CASE(48)

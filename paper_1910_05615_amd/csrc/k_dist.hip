@@ -1,6 +1,11 @@
 // Statistical distances (Sec. 2.1 eq. statdist computed as in Sec. 3.4):
 // d2 = ||M (x - mu)||^2 with M the inverse Cholesky factor (folded with the
-// standardisation scales inside the fit).
+// standardisation scales inside the fit).  An item whose form word is 1
+// holds instead the explicit inverse P of its scatter, packed like M as a
+// lower triangle with doubled off-diagonal entries (P~), and
+// d2 = sum_i r_i (P~ r)_i = r^T P r: the distance computation that Sec. 3.4
+// replaces (Table 1, version I), and the form the single-swap update of
+// Sec. 3.5 produces.  Both forms cost p(p+1)/2 multiply-adds per row.
 //
 // Up to p = 40 every thread reads its own row straight into registers (16-
 // or 8-byte loads when the row size and base allow, else one load per
@@ -75,9 +80,9 @@ __device__ inline void stage_factor(const double* __restrict__ M, int ldm,
   for (int j = threadIdx.x; j < P; j += CH) mul[j] = j < p ? mu[j] : 0.0;
 }
 
-// ||M z||^2 for R rows at once, M packed lower triangular in LDS (one LDS
-// read of an entry feeds R FMAs).
-template <int P, int R>
+// ||M z||^2 (INV: z^T (M z), M = P~) for R rows at once, M packed lower
+// triangular in LDS (one LDS read of an entry feeds R FMAs).
+template <int P, int R, bool INV>
 __device__ inline void tri_norm2_r(const double* __restrict__ Ml, const double (&z)[R][P],
                                    double (&acc)[R]) {
 #pragma unroll
@@ -94,14 +99,14 @@ __device__ inline void tri_norm2_r(const double* __restrict__ Ml, const double (
       for (int r = 0; r < R; ++r) y[r] = fma(mij, z[r][j], y[r]);
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] = fma(y[r], y[r], acc[r]);
+    for (int r = 0; r < R; ++r) acc[r] = fma(y[r], INV ? z[r][i] : y[r], acc[r]);
   }
 }
 
-// ||M z||^2 with M read from global memory at uniform, compile-time offsets
-// (row stride LDM): the loads go through the scalar unit and every FMA takes
-// its M entry from SGPRs.
-template <int P>
+// ||M z||^2 (INV: z^T (M z)) with M read from global memory at uniform,
+// compile-time offsets (row stride LDM): the loads go through the scalar unit
+// and every FMA takes its M entry from SGPRs.
+template <int P, bool INV>
 __device__ inline double tri_norm2_g(const double* __restrict__ Mg, int ldm, int p,
                                      const double (&z)[P]) {
   double acc = 0.0;
@@ -112,13 +117,13 @@ __device__ inline double tri_norm2_g(const double* __restrict__ Mg, int ldm, int
       double y = 0.0;
 #pragma unroll
       for (int j = 0; j <= i; ++j) y = fma(mr[j], z[j], y);
-      acc = fma(y, y, acc);
+      acc = fma(y, INV ? z[i] : y, acc);
     }
   }
   return acc;
 }
 
-template <int P>
+template <int P, bool INV>
 __device__ inline double tri_norm2_l(const double* __restrict__ Ml, const double (&z)[P]) {
   double acc = 0.0;
 #pragma unroll
@@ -126,18 +131,19 @@ __device__ inline double tri_norm2_l(const double* __restrict__ Ml, const double
     double y = 0.0;
 #pragma unroll
     for (int j = 0; j <= i; ++j) y = fma(Ml[i * (i + 1) / 2 + j], z[j], y);
-    acc = fma(y, y, acc);
+    acc = fma(y, INV ? z[i] : y, acc);
   }
   return acc;
 }
 
 // Evaluate rows [r0, r1) of X against NI factors; emit(q, row, d2).
-// Mg[q], mug[q]: factor (row stride ldm) and centre in global memory.
+// Mg[q], mug[q]: factor (row stride ldm) and centre in global memory;
+// inv[q]: the factor is P~ (explicit inverse) rather than L^{-1}.
 template <typename T, int P, int NI, typename Emit>
 __device__ inline void dist_rows(const T* __restrict__ X, int64_t ld, int p, int ldm, int64_t r0,
                                  int64_t r1, const double* const (&Mg)[NI],
-                                 const double* const (&mug)[NI], double* Ml, double* mul,
-                                 T* xs, Emit emit) {
+                                 const double* const (&mug)[NI], const bool (&inv)[NI],
+                                 double* Ml, double* mul, T* xs, Emit emit) {
   using S = Shape<T, P>;
   const int tid = threadIdx.x;
   const bool fast = p == P && ld == P && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
@@ -198,8 +204,14 @@ __device__ inline void dist_rows(const T* __restrict__ X, int64_t ld, int p, int
               for (int j = 0; j < P; ++j)
                 z[r][j] = (double)xs[(tid + r * CH) * S::PP + j] - mul[q * P + j];
             double acc[S::R];
-            if constexpr (NI == 1 && S::R == 1) acc[0] = tri_norm2_g<P>(Mg[q], ldm, p, z[0]);
-            else tri_norm2_r<P, S::R>(Ml + q * (P * (P + 1) / 2), z, acc);
+            if constexpr (NI == 1 && S::R == 1) {
+              acc[0] = inv[q] ? tri_norm2_g<P, true>(Mg[q], ldm, p, z[0])
+                              : tri_norm2_g<P, false>(Mg[q], ldm, p, z[0]);
+            } else if (inv[q]) {
+              tri_norm2_r<P, S::R, true>(Ml + q * (P * (P + 1) / 2), z, acc);
+            } else {
+              tri_norm2_r<P, S::R, false>(Ml + q * (P * (P + 1) / 2), z, acc);
+            }
 #pragma unroll
             for (int r = 0; r < S::R; ++r)
               if (tid + r * CH < n) emit(q, rc + tid + r * CH, acc[r]);
@@ -225,7 +237,8 @@ __device__ inline void dist_rows(const T* __restrict__ X, int64_t ld, int p, int
           double z[P];
 #pragma unroll
           for (int j = 0; j < P; ++j) z[j] = (double)xs[tid * S::PP + j] - mul[q * P + j];
-          emit(q, rc + tid, tri_norm2_l<P>(Ml + q * (P * (P + 1) / 2), z));
+          const double* Mq = Ml + q * (P * (P + 1) / 2);
+          emit(q, rc + tid, inv[q] ? tri_norm2_l<P, true>(Mq, z) : tri_norm2_l<P, false>(Mq, z));
         }
       }
       __syncthreads();
@@ -239,7 +252,8 @@ __device__ inline void dist_rows(const T* __restrict__ X, int64_t ld, int p, int
         double z[P];
 #pragma unroll
         for (int j = 0; j < P; ++j) z[j] = (j < p ? (double)xr[j] : 0.0) - mul[q * P + j];
-        emit(q, r, tri_norm2_l<P>(Ml + q * (P * (P + 1) / 2), z));
+        const double* Mq = Ml + q * (P * (P + 1) / 2);
+        emit(q, r, inv[q] ? tri_norm2_l<P, true>(Mq, z) : tri_norm2_l<P, false>(Mq, z));
       }
     }
   }
@@ -281,7 +295,8 @@ __device__ inline void load_row_vec(const T* xr_, T (&v)[P]) {
 
 // ||M (v - mu)||^2 column by column: y_i accumulates M_ij z_j in order of j
 // (the same operations, in the same order per y_i, as the row-wise form).
-template <typename T, int P>
+// INV: z^T (M z) with M = P~ (explicit inverse).
+template <typename T, int P, bool INV>
 __device__ inline double col_norm2_g(const double* __restrict__ Mg, int ldm, int p,
                                      const double* __restrict__ mu, const T (&v)[P]) {
   double y[P];
@@ -299,11 +314,11 @@ __device__ inline double col_norm2_g(const double* __restrict__ Mg, int ldm, int
   double acc = 0.0;
 #pragma unroll
   for (int i = 0; i < P; ++i)
-    if (i < p) acc = fma(y[i], y[i], acc);
+    if (i < p) acc = fma(y[i], INV ? (double)v[i] - mu[i] : y[i], acc);
   return acc;
 }
 
-template <typename T, int P, int NI, typename Emit>
+template <typename T, int P, int NI, bool INV, typename Emit>
 __device__ inline void eval_row(T (&v)[P], int p, int ldm, const double* const (&Mg)[NI],
                                 const double* const (&mug)[NI], const bool (&act)[NI],
                                 Emit emit) {
@@ -314,7 +329,7 @@ __device__ inline void eval_row(T (&v)[P], int p, int ldm, const double* const (
 #pragma unroll
   for (int q = 0; q < NI; ++q) {
     if (q > 0) all_loaded(v);
-    if (act[q]) emit(q, col_norm2_g<T, P>(Mg[q], ldm, p, mug[q], v));
+    if (act[q]) emit(q, col_norm2_g<T, P, INV>(Mg[q], ldm, p, mug[q], v));
   }
 }
 
@@ -322,7 +337,8 @@ __device__ inline void eval_row(T (&v)[P], int p, int ldm, const double* const (
 // stride is p (a p x p factor), which the fast path then knows to be P.
 // GEN: rows may be narrower than P, strided or unaligned (checked per item);
 // without it the launch guarantees dense, aligned rows of P columns.
-template <typename T, int P, int NI, bool LDM_IS_P, bool GEN, typename Emit>
+// INV: the factors are P~ (explicit inverse).
+template <typename T, int P, int NI, bool LDM_IS_P, bool GEN, bool INV, typename Emit>
 __device__ inline void dist_row_direct(const T* __restrict__ X, int64_t ld, int p, int ldm,
                                        int64_t r, const double* const (&Mg)[NI],
                                        const double* const (&mug)[NI], const bool (&act)[NI],
@@ -333,23 +349,27 @@ __device__ inline void dist_row_direct(const T* __restrict__ X, int64_t ld, int 
   if (fast) {
     load_row_vec<T, P>(X + r * P, v);
     all_loaded(v);
-    eval_row<T, P, NI>(v, P, LDM_IS_P ? P : ldm, Mg, mug, act, emit);   // guards fold
+    eval_row<T, P, NI, INV>(v, P, LDM_IS_P ? P : ldm, Mg, mug, act, emit);   // guards fold
   } else if constexpr (GEN) {
     const gptr_t<T> xr = as_global(X + r * ld);
 #pragma unroll
     for (int j = 0; j < P; ++j) v[j] = j < p ? xr[j] : (T)0;
     all_loaded(v);
-    eval_row<T, P, NI>(v, p, ldm, Mg, mug, act, emit);
+    eval_row<T, P, NI, INV>(v, p, ldm, Mg, mug, act, emit);
   }
 }
 
-template <typename T, int P, int NI, bool GEN>
+// PER_ITEM: read each tile's distance form (form may then be null: all
+// Cholesky); without it every factor of the launch is L^{-1} D^{-1} (the
+// default path carries no second evaluation).
+template <typename T, int P, int NI, bool GEN, bool PER_ITEM>
 __global__ __launch_bounds__(DROWS) void k_dist_direct(const ItemDesc* __restrict__ items,
                                                        const Tile* __restrict__ tiles,
                                                        int tile_rows,
                                                        const double* __restrict__ mtri,
                                                        const double* __restrict__ mux,
                                                        const int32_t* __restrict__ status,
+                                                       const int32_t* __restrict__ form,
                                                        double* __restrict__ d2) {
   const int nsub = tile_rows / DROWS;
   const Tile tl = tiles[blockIdx.x / nsub];
@@ -376,16 +396,21 @@ __global__ __launch_bounds__(DROWS) void k_dist_direct(const ItemDesc* __restric
     mug[q] = mux + (size_t)it * PMAX;
   }
   const T* __restrict__ X = static_cast<const T*>(D.X) + D.row0 * D.ld;
-  dist_row_direct<T, P, NI, false, GEN>(X, D.ld, D.p, PMAX, r, Mg, mug, act,
-                            [&](int q, double v) { d2[roff[q] + r] = v; });
+  auto emit = [&](int q, double v) { d2[roff[q] + r] = v; };
+  // the form of the tile's factor (uniform over the block; one factor per
+  // tile in the direct launches)
+  if (PER_ITEM && form != nullptr && form[tl.item] != 0)
+    dist_row_direct<T, P, NI, false, GEN, true>(X, D.ld, D.p, PMAX, r, Mg, mug, act, emit);
+  else
+    dist_row_direct<T, P, NI, false, GEN, false>(X, D.ld, D.p, PMAX, r, Mg, mug, act, emit);
 }
 
-template <typename T, int P, bool GEN>
+template <typename T, int P, bool GEN, bool PER_ITEM>
 __global__ __launch_bounds__(DROWS) void k_final_dist_direct(
     const ItemDesc* __restrict__ items, const Tile* __restrict__ tiles, int tile_rows,
     const double* __restrict__ mtri, const double* __restrict__ mux,
-    const double* __restrict__ d2, const DsInfo* __restrict__ ds,
-    const rtdetmcd_out* __restrict__ outs) {
+    const int32_t* __restrict__ form, const double* __restrict__ d2,
+    const DsInfo* __restrict__ ds, const rtdetmcd_out* __restrict__ outs) {
   const int nsub = tile_rows / DROWS;
   const Tile tl = tiles[blockIdx.x / nsub];
   const int it = tl.item;
@@ -406,7 +431,7 @@ __global__ __launch_bounds__(DROWS) void k_final_dist_direct(
   const double* Mg[1] = {mtri + (size_t)it * MSTRIDE};
   const double* mug[1] = {mux + (size_t)it * PMAX};
   const bool act[1] = {true};
-  dist_row_direct<T, P, 1, false, GEN>(X, D.ld, D.p, PMAX, r, Mg, mug, act, [&](int, double v) {
+  auto emit = [&](int, double v) {
     if (od) od[D.row0 + r] = sqrt(v);
     if (of) of[D.row0 + r] = v > cut ? 1 : 0;
     if (ow) {
@@ -415,7 +440,11 @@ __global__ __launch_bounds__(DROWS) void k_final_dist_direct(
       const int64_t rr = dd.inv ? (int64_t)dd.inv[D.row0 + r] : D.row0 + r - R.row0;
       ow[D.row0 + r] = (rr >= 0 && rr < R.m && d2r[rr] <= cut) ? 1 : 0;
     }
-  });
+  };
+  if (PER_ITEM && form != nullptr && form[it] != 0)
+    dist_row_direct<T, P, 1, false, GEN, true>(X, D.ld, D.p, PMAX, r, Mg, mug, act, emit);
+  else
+    dist_row_direct<T, P, 1, false, GEN, false>(X, D.ld, D.p, PMAX, r, Mg, mug, act, emit);
 }
 
 template <typename T, int P, bool GEN>
@@ -430,7 +459,7 @@ __global__ __launch_bounds__(DROWS) void k_score_direct(const T* __restrict__ X,
   const double* Mg[1] = {M};
   const double* mug[1] = {mu};
   const bool act[1] = {true};
-  dist_row_direct<T, P, 1, true, GEN>(X, ld, p, p, r, Mg, mug, act, [&](int, double v) {
+  dist_row_direct<T, P, 1, true, GEN, false>(X, ld, p, p, r, Mg, mug, act, [&](int, double v) {
     if (dist) dist[r] = sqrt(v);
     if (flag) flag[r] = v > cut ? 1 : 0;
   });
@@ -447,6 +476,7 @@ __global__ __launch_bounds__(CH) void k_dist(const ItemDesc* __restrict__ items,
                                              const double* __restrict__ mtri,
                                              const double* __restrict__ mux,
                                              const int32_t* __restrict__ status,
+                                             const int32_t* __restrict__ form,
                                              double* __restrict__ d2) {
   __shared__ double Ml[NI * P * (P + 1) / 2];
   __shared__ double mul[NI * P];
@@ -464,17 +494,19 @@ __global__ __launch_bounds__(CH) void k_dist(const ItemDesc* __restrict__ items,
   int64_t roff[NI];
   const double* Mg[NI];
   const double* mug[NI];
+  bool inv[NI];
 #pragma unroll
   for (int q = 0; q < NI; ++q) {
     const int it = tl.item + q;
     roff[q] = items[it].roff;
     Mg[q] = mtri + (size_t)it * MSTRIDE;
     mug[q] = mux + (size_t)it * PMAX;
+    inv[q] = form != nullptr && form[it] != 0;
   }
   const int64_t r0 = (int64_t)tl.t * tile_rows;
   const int64_t r1 = min(r0 + (int64_t)tile_rows, D.m);
   const T* __restrict__ X = static_cast<const T*>(D.X) + D.row0 * D.ld;
-  dist_rows<T, P, NI>(X, D.ld, D.p, PMAX, r0, r1, Mg, mug, Ml, mul, xs,
+  dist_rows<T, P, NI>(X, D.ld, D.p, PMAX, r0, r1, Mg, mug, inv, Ml, mul, xs,
                             [&](int q, int64_t r, double v) {
                               if (act[q]) d2[roff[q] + r] = v;
                             });
@@ -486,6 +518,7 @@ __global__ __launch_bounds__(CH) void k_final_dist(const ItemDesc* __restrict__ 
                                                    const Tile* __restrict__ tiles, int tile_rows,
                                                    const double* __restrict__ mtri,
                                                    const double* __restrict__ mux,
+                                                   const int32_t* __restrict__ form,
                                                    const double* __restrict__ d2,
                                                    const DsInfo* __restrict__ ds,
                                                    const rtdetmcd_out* __restrict__ outs) {
@@ -510,7 +543,8 @@ __global__ __launch_bounds__(CH) void k_final_dist(const ItemDesc* __restrict__ 
   const T* __restrict__ X = static_cast<const T*>(D.X) + D.row0 * D.ld;
   const double* Mg[1] = {mtri + (size_t)it * MSTRIDE};
   const double* mug[1] = {mux + (size_t)it * PMAX};
-  dist_rows<T, P, 1>(X, D.ld, D.p, PMAX, r0, r1, Mg, mug, Ml, mul, xs,
+  const bool inv[1] = {form != nullptr && form[it] != 0};
+  dist_rows<T, P, 1>(X, D.ld, D.p, PMAX, r0, r1, Mg, mug, inv, Ml, mul, xs,
                            [&](int, int64_t r, double v) {
                              if (od) od[D.row0 + r] = sqrt(v);
                              if (of) of[D.row0 + r] = v > cut ? 1 : 0;
@@ -537,7 +571,8 @@ __global__ __launch_bounds__(CH) void k_score(const T* __restrict__ X, int64_t n
   const int64_t r1 = min(r0 + (int64_t)tile_rows, n);
   const double* Mg[1] = {M};
   const double* mug[1] = {mu};
-  dist_rows<T, P, 1>(X, ld, p, p, r0, r1, Mg, mug, Ml, mul, xs,
+  const bool inv[1] = {false};
+  dist_rows<T, P, 1>(X, ld, p, p, r0, r1, Mg, mug, inv, Ml, mul, xs,
                         [&](int, int64_t r, double v) {
                           if (dist) dist[r] = sqrt(v);
                           if (flag) flag[r] = v > cut ? 1 : 0;
@@ -553,16 +588,18 @@ static_assert(DIRECT_MAX == 40, "bucket lists");
 hipError_t launch_dist(int bucket, int dtype, int dense, int ipt, const ItemDesc* items,
                        const Tile* tiles,
                        int ntiles, int tile_rows, const double* mtri, const double* mux,
-                       const int32_t* status, double* d2, hipStream_t s) {
+                       const int32_t* status, const int32_t* form, double* d2, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (tile_rows <= 0 || tile_rows % DROWS != 0) return hipErrorInvalidValue;
   const unsigned nbd = (unsigned)ntiles * (unsigned)(tile_rows / DROWS);
 #define LAUNCH(K, NB, NT)                                                                       \
-  hipLaunchKernelGGL(K, dim3(NB), dim3(NT), 0, s, items, tiles, tile_rows, mtri, mux, status, d2)
+  hipLaunchKernelGGL(K, dim3(NB), dim3(NT), 0, s, items, tiles, tile_rows, mtri, mux, status, \
+                     form, d2)
 #define DIRECT(T, PB, NI)                                                                       \
   do {                                                                                          \
-    if (dense) LAUNCH((k_dist_direct<T, PB, NI, false>), nbd, DROWS);                           \
-    else LAUNCH((k_dist_direct<T, PB, NI, true>), nbd, DROWS);                                  \
+    if (dense && !form) LAUNCH((k_dist_direct<T, PB, NI, false, false>), nbd, DROWS);           \
+    else if (dense) LAUNCH((k_dist_direct<T, PB, NI, false, true>), nbd, DROWS);                \
+    else LAUNCH((k_dist_direct<T, PB, NI, true, true>), nbd, DROWS);                            \
   } while (0)
 #define STAGED(T, PB, NI) LAUNCH((k_dist<T, PB, NI>), ntiles, CH)
 #define CASE(K1, K2, PB)                                                                        \
@@ -598,17 +635,19 @@ hipError_t launch_dist(int bucket, int dtype, int dense, int ipt, const ItemDesc
 hipError_t launch_final_dist(int bucket, int dtype, int dense, const ItemDesc* items,
                              const Tile* tiles,
                              int ntiles, int tile_rows, const double* mtri, const double* mux,
-                             const double* d2, const DsInfo* ds, const rtdetmcd_out* outs,
-                             hipStream_t s) {
+                             const int32_t* form, const double* d2, const DsInfo* ds,
+                             const rtdetmcd_out* outs, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
   if (tile_rows <= 0 || tile_rows % DROWS != 0) return hipErrorInvalidValue;
   const unsigned nbd = (unsigned)ntiles * (unsigned)(tile_rows / DROWS);
 #define LAUNCH(K, NB, NT)                                                                       \
-  hipLaunchKernelGGL(K, dim3(NB), dim3(NT), 0, s, items, tiles, tile_rows, mtri, mux, d2, ds, outs)
+  hipLaunchKernelGGL(K, dim3(NB), dim3(NT), 0, s, items, tiles, tile_rows, mtri, mux, form, d2, \
+                     ds, outs)
 #define DIRECT(T, PB)                                                                           \
   do {                                                                                          \
-    if (dense) LAUNCH((k_final_dist_direct<T, PB, false>), nbd, DROWS);                         \
-    else LAUNCH((k_final_dist_direct<T, PB, true>), nbd, DROWS);                                \
+    if (dense && !form) LAUNCH((k_final_dist_direct<T, PB, false, false>), nbd, DROWS);         \
+    else if (dense) LAUNCH((k_final_dist_direct<T, PB, false, true>), nbd, DROWS);              \
+    else LAUNCH((k_final_dist_direct<T, PB, true, true>), nbd, DROWS);                          \
   } while (0)
 #define STAGED(T, PB) LAUNCH((k_final_dist<T, PB>), ntiles, CH)
 #define CASE(K, PB)                                                                             \

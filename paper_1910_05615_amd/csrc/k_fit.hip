@@ -481,9 +481,32 @@ __global__ __launch_bounds__(256) void k_choose(const ItemDesc* __restrict__ bit
     F.bitem[b] = ch;
     F.bds[b] = B.ds;
     F.bstat[b] = ch >= 0 ? A.status[ch] : RTDETMCD_BLOCK_INVALID;
-    F.bstart[b] = ch >= 0 ? ch - i0 : -1;
+    F.bstart[b] = ch < 0 ? -1 : d.warm_mu ? RTDETMCD_START_WARM : ch - i0;
     F.biters[b] = ch >= 0 ? A.iter[ch] : 0;
     F.bld[b] = ch >= 0 ? A.logdet[ch] + p * lc : NAN;
+  }
+}
+
+// Warm start: block l of dataset d starts its C-steps from the given
+// location and scatter, taken into the dataset's standardised units
+// (z = (x - loc) / scale); its second start is not used.
+__global__ __launch_bounds__(256) void k_warm_start(const DsInfo* __restrict__ ds, int dd,
+                                                    ItemArrays C, FitArrays F) {
+  const DsInfo d = ds[dd];
+  const int p = d.p;
+  const int i0 = d.item0 + 2 * blockIdx.x;
+  const double* __restrict__ loc = F.loc + (size_t)dd * PMAX;
+  const double* __restrict__ sc = F.scale + (size_t)dd * PMAX;
+  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+    const int i = e / p, j = e % p;
+    C.sigz[(size_t)i0 * MSTRIDE + i * PMAX + j] =
+        0.5 * (d.warm_sigma[i * p + j] + d.warm_sigma[j * p + i]) / (sc[i] * sc[j]);
+  }
+  for (int j = threadIdx.x; j < p; j += blockDim.x)
+    C.muz[(size_t)i0 * PMAX + j] = (d.warm_mu[j] - loc[j]) / sc[j];
+  if (threadIdx.x == 0) {
+    C.status[i0] = ACTIVE;
+    C.status[i0 + 1] = ST_DROP_REFINE;
   }
 }
 
@@ -545,8 +568,10 @@ __global__ __launch_bounds__(256) void k_median(const DsInfo* __restrict__ ds, F
 // KL'_l = tr(S_med S_l^{-1}) + log det S_l + (mu_med - mu_l)' S_l^{-1} (mu_med - mu_l)
 // for the raw block fit S_l = c(alpha) Sigma_l; eq. (KL) without its
 // l-independent terms, so that a non-positive-definite S_med is allowed.
+// use_sinv: the chosen item's inverse comes from its kept inverse sscp matrix
+// (single-swap mode: its last step may not have had a Cholesky factor).
 __global__ __launch_bounds__(256) void k_kl(const DsInfo* __restrict__ ds, ItemArrays A,
-                                            FitArrays F, int first) {
+                                            FitArrays F, int first, int use_sinv) {
   __shared__ double Si[PMAX * PMAX];
   __shared__ double dv[PMAX];
   __shared__ double red[256];
@@ -561,12 +586,22 @@ __global__ __launch_bounds__(256) void k_kl(const DsInfo* __restrict__ ds, ItemA
   const double* Li = A.linv + (size_t)ch * MSTRIDE;
   const double* M = F.med + (size_t)F.bds[b] * (PMAX + MSTRIDE);
   const double ic = 1.0 / d.calpha;
-  for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
-    const int i = e / p, j = e % p;
-    const int k0 = i > j ? i : j;
-    double s = 0.0;
-    for (int k = k0; k < p; ++k) s = fma(Li[k * PMAX + i], Li[k * PMAX + j], s);
-    Si[i * PMAX + j] = s * ic;
+  if (use_sinv) {
+    // Sigma^{-1} = (h-1) D Lam^{-1} D (standardised units)
+    const double* Lv = A.sinv + (size_t)ch * MSTRIDE;
+    const double* sc = F.scale + (size_t)F.bds[b] * PMAX;
+    for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+      const int i = e / p, j = e % p;
+      Si[i * PMAX + j] = (double)(d.h - 1) * Lv[i * PMAX + j] * (sc[i] * sc[j]) * ic;
+    }
+  } else {
+    for (int e = threadIdx.x; e < p * p; e += blockDim.x) {
+      const int i = e / p, j = e % p;
+      const int k0 = i > j ? i : j;
+      double s = 0.0;
+      for (int k = k0; k < p; ++k) s = fma(Li[k * PMAX + i], Li[k * PMAX + j], s);
+      Si[i * PMAX + j] = s * ic;
+    }
   }
   for (int j = threadIdx.x; j < p; j += blockDim.x) dv[j] = M[j] - F.bmu[(size_t)b * PMAX + j];
   __syncthreads();
@@ -1017,6 +1052,13 @@ hipError_t launch_choose(const ItemDesc* bitems, const ItemDesc* citems, ItemArr
   return hipGetLastError();
 }
 
+hipError_t launch_warm_start(const DsInfo* ds, int d, int q, ItemArrays C, FitArrays F,
+                             hipStream_t s) {
+  if (q <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_warm_start, dim3(q), dim3(256), 0, s, ds, d, C, F);
+  return hipGetLastError();
+}
+
 hipError_t launch_median(const DsInfo* ds, FitArrays F, const int2* ent, int nent,
                          hipStream_t s) {
   if (nent <= 0) return hipSuccess;
@@ -1025,9 +1067,9 @@ hipError_t launch_median(const DsInfo* ds, FitArrays F, const int2* ent, int nen
 }
 
 hipError_t launch_kl(const DsInfo* ds, ItemArrays A, FitArrays F, int first_blk, int nblk,
-                     hipStream_t s) {
+                     int use_sinv, hipStream_t s) {
   if (nblk <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_kl, dim3(nblk), dim3(256), 0, s, ds, A, F, first_blk);
+  hipLaunchKernelGGL(k_kl, dim3(nblk), dim3(256), 0, s, ds, A, F, first_blk, use_sinv);
   return hipGetLastError();
 }
 

@@ -89,7 +89,7 @@ extern "C" rtdetmcd_status rtdetmcd_cstep_noalloc(
   d.X = X; d.ld = ld; d.row0 = 0; d.m = m; d.h = h_sub; d.p = p; d.dtype = dtype; d.start = -1;
   S.add(d);
   Layout L0;
-  size_t off[20];
+  size_t off[NOFF];
   layout_items(L0, S, off);
   const size_t o_loc = L0.add(PMAX * 8), o_scale = L0.add(PMAX * 8);
   if (L0.off > ctx->scratch_bytes) {   // cannot happen for m <= NOALLOC_MAX_M
