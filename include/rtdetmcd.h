@@ -264,6 +264,45 @@ rtdetmcd_status rtdetmcd_cstep_noalloc(rtdetmcd_handle h, const void* X, int32_t
                                        double* mu, double* sigma, int32_t* hsubset,
                                        int32_t* status, int32_t* iters, double* logdet);
 
+/* ---- kernel timing -------------------------------------------------------- */
+
+/* Kernel classes timed by rtdetmcd_profile_read. */
+#define RTDETMCD_PROF_SEGSORT    0 /* LDS segment sort + univariate MCD / order statistics
+                                      (standardisation of short columns, GSSCM norms, the
+                                      refinement's score columns); bytes: keys read + results */
+#define RTDETMCD_PROF_CSTEP_DIST 1 /* distance pass of the first C-step (every start active);
+                                      bytes: rows read + float64 d2 written; flops: p(p+1)+3p
+                                      per row and start */
+#define RTDETMCD_PROF_SELECT     2 /* h-subset selection of the first C-step; bytes: d2 read,
+                                      mask written */
+#define RTDETMCD_PROF_SSCP       3 /* subset sums of the first (full) C-step on the matrix
+                                      cores; bytes: rows and mask read; flops useful: h (p+1)
+                                      (p+2) per start (lower triangle with sums and count),
+                                      executed: the 16 x 16 x 4 blocks over every row */
+#define RTDETMCD_PROF_FINALIZE   4 /* Cholesky / inverse / condition step of the first C-step */
+#define RTDETMCD_PROF_FINAL_DIST 5 /* final distances and flags of every row (Sec. 4 step 10);
+                                      bytes: rows read, distance, flag and weight written,
+                                      the reweighting distances read */
+#define RTDETMCD_PROF_FIT        6 /* a whole fit, first launch to last */
+#define RTDETMCD_PROF_DISTANCES  7 /* the distance kernel of rtdetmcd_distances / the scoring
+                                      kernel of rtdetmcd_score; bytes: rows read, results
+                                      written; flops: p(p+1)+3p per row */
+#define RTDETMCD_PROF_KINDS      8
+
+/* Kernel timing of the fits that follow on this handle: enable = 1 clears the
+ * records and starts recording a HIP event on the handle's stream before and
+ * after each launch of the classes above (eager launches only: the C-step
+ * rounds replayed from a graph are not timed, the first C-step always runs
+ * eagerly while timing is on); 0 stops.  Host-side bookkeeping only. */
+rtdetmcd_status rtdetmcd_profile(rtdetmcd_handle h, int32_t enable);
+/* Totals over the recorded launches of one class (synchronises the stream):
+ * milliseconds between the events, launches, algorithmic bytes and flops
+ * (useful, and executed by the matrix cores where that differs).  Every
+ * pointer may be NULL. */
+rtdetmcd_status rtdetmcd_profile_read(rtdetmcd_handle h, int32_t kind, double* ms,
+                                      int64_t* launches, double* bytes, double* flops_useful,
+                                      double* flops_exec);
+
 /* Number of fits on this handle that were run a second time with ballot
  * ranking because a global sort's order check failed (see rtdetmcd_create).
  * Such a fit takes about twice its usual time; its results are those of the

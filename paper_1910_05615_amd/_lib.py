@@ -19,7 +19,8 @@ SYMBOLS = [
     "rtdetmcd_default_opts", "rtdetmcd_plan", "rtdetmcd_fit", "rtdetmcd_fit_batched",
     "rtdetmcd_chi2_quantile", "rtdetmcd_chi2_cdf", "rtdetmcd_consistency",
     "rtdetmcd_distances", "rtdetmcd_score", "rtdetmcd_select", "rtdetmcd_cstep",
-    "rtdetmcd_cstep_noalloc", "rtdetmcd_sort_reruns", "rtdetmcd_backward",
+    "rtdetmcd_cstep_noalloc", "rtdetmcd_profile", "rtdetmcd_profile_read",
+    "rtdetmcd_sort_reruns", "rtdetmcd_backward",
 ]
 
 
@@ -77,6 +78,9 @@ def load() -> C.CDLL:
         "rtdetmcd_cstep_noalloc": (c_i32, [c_vp, c_vp, c_i32, c_i64, c_i32, c_i64, c_i64, c_vp,
                                            c_vp, c_vp, P(Opts), c_vp, c_vp, c_vp, c_vp, c_vp,
                                            c_vp]),
+        "rtdetmcd_profile": (c_i32, [c_vp, c_i32]),
+        "rtdetmcd_profile_read": (c_i32, [c_vp, c_i32, P(c_f64), P(c_i64), P(c_f64), P(c_f64),
+                                          P(c_f64)]),
         "rtdetmcd_sort_reruns": (c_i64, [c_vp]),
         "rtdetmcd_backward": (c_i32, [c_vp, c_vp, c_i32, c_i64, c_i32, c_i64, c_vp, c_vp, c_vp,
                                       c_vp, c_vp, c_f64, c_vp, c_vp, c_vp, c_vp]),

@@ -132,6 +132,16 @@ def distances(X: torch.Tensor, mu: torch.Tensor, L: torch.Tensor) -> torch.Tenso
     return d2
 
 
+def distances_into(X: torch.Tensor, mu: torch.Tensor, L: torch.Tensor, d2: torch.Tensor) -> None:
+    """distances() into a preallocated float64 output; mu and L float64,
+    contiguous, on X's device (no allocation; for timing loops)."""
+    n, p = X.shape
+    lib, h = _handle(X.device)
+    st = lib.rtdetmcd_distances(h, _ptr(X), _dtype_code(X), n, p, X.stride(0), _ptr(mu),
+                                _ptr(L), _ptr(d2))
+    _check(lib, h, st, "rtdetmcd_distances")
+
+
 def select(d2: torch.Tensor, h_sub: int):
     """(ascending indices of the h_sub smallest d2, 0/1 mask); ties by index."""
     d2 = d2.to(torch.float64).contiguous()
@@ -179,6 +189,34 @@ def cstep(X: torch.Tensor, h_sub: int, mu0: torch.Tensor, sigma0: torch.Tensor,
             _ptr(ks), C.byref(o), _ptr(mu), _ptr(sig), _ptr(hs), _ptr(stt), _ptr(its), _ptr(ld))
     _check(lib, h, st, "rtdetmcd_cstep_noalloc" if noalloc else "rtdetmcd_cstep")
     return CStepResult(mu, sig, hs, int(stt.item()), int(its.item()), float(ld.item()))
+
+
+PROF_KINDS = {"segsort": 0, "cstep_dist": 1, "select": 2, "sscp": 3, "finalize": 4,
+              "final_dist": 5, "fit": 6, "distances": 7}
+
+
+def profile(enable: bool, device=None) -> None:
+    """Start (clearing earlier records) or stop the library's kernel timing
+    on this device's handle (rtdetmcd_profile)."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    lib, h = _handle(dev)
+    _check(lib, h, lib.rtdetmcd_profile(h, int(bool(enable))), "rtdetmcd_profile")
+
+
+def profile_read(device=None) -> dict:
+    """Totals per kernel class since profile(True): {name: {ms, launches,
+    bytes, flops_useful, flops_exec}} (rtdetmcd_profile_read)."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    lib, h = _handle(dev)
+    out = {}
+    for name, k in PROF_KINDS.items():
+        ms, n, b, fu, fe = C.c_double(), C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+        _check(lib, h, lib.rtdetmcd_profile_read(h, k, C.byref(ms), C.byref(n), C.byref(b),
+                                                 C.byref(fu), C.byref(fe)),
+               "rtdetmcd_profile_read")
+        out[name] = {"ms": ms.value, "launches": n.value, "bytes": b.value,
+                     "flops_useful": fu.value, "flops_exec": fe.value}
+    return out
 
 
 def sort_reruns(device=None) -> int:

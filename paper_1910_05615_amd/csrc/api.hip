@@ -9,6 +9,31 @@
 
 namespace rtd {
 
+static hipEvent_t prof_event(rtdetmcd_ctx* ctx) {
+  if (ctx->prof_next < ctx->prof_events.size()) return ctx->prof_events[ctx->prof_next++];
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  ctx->prof_events.push_back(e);
+  ctx->prof_next = ctx->prof_events.size();
+  return e;
+}
+
+ProfMark::ProfMark(rtdetmcd_ctx* c, int kind, hipStream_t s, double bytes, double flops_useful,
+                   double flops_exec) {
+  if (!c || !c->prof_on) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+  hipEvent_t e0 = prof_event(c), e1 = prof_event(c);
+  if (!e0 || !e1 || hipEventRecord(e0, s) != hipSuccess) return;
+  ctx = c;
+  idx = (int)c->prof.size();
+  c->prof.push_back({kind, e0, e1, bytes, flops_useful, flops_exec});
+}
+
+void ProfMark::end(hipStream_t s) {
+  if (idx >= 0 && hipEventRecord(ctx->prof[idx].e1, s) != hipSuccess) ctx->prof[idx].e1 = nullptr;
+}
+
 void drop_graphs(rtdetmcd_ctx* ctx) {
   for (rtd_graph& g : ctx->graphs)
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
@@ -222,7 +247,61 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
                               o.cstep_mode, o.distance, s));
       return RTDETMCD_OK;
     };
+    // kernel timing of the first C-step (every start still active): the
+    // distance pass, the selection and the full sscp
+    auto step1 = [&](hipStream_t s) -> rtdetmcd_status {
+      double rows = 0.0, byt_d = 0.0, fl_d = 0.0, fl_su = 0.0, fl_se = 0.0;
+      for (int i = first; i < first + n; ++i) {
+        const ItemDesc& e = S.items[i];
+        const double m = (double)e.m, p = (double)e.p, es = e.dtype == 0 ? 4.0 : 8.0;
+        rows += m;
+        byt_d += m * (es * p + 8.0);
+        fl_d += m * (p * (p + 1.0) + 3.0 * p);
+        // useful: h rows of the lower triangle of the sscp (with the sum and
+        // count); executed: the matrix-core blocks over every candidate row
+        const double g = std::ceil((p + 1.0) / 16.0);
+        fl_su += (double)e.h * (p + 1.0) * (p + 2.0);
+        fl_se += std::ceil(m / 4.0) * g * (g + 1.0) / 2.0 * 2048.0;
+      }
+      {
+        ProfMark pm(ctx, RTDETMCD_PROF_CSTEP_DIST, s, byt_d, fl_d, fl_d);
+        RTD_HIP(launch_dist(bucket, dtype, dense, pairs ? 2 : 1, D.items, dtl + dt0, dtn,
+                            DIST_TILE, D.A.mtri, D.A.mux, D.A.status, form, D.A.d2, s));
+        pm.end(s);
+      }
+      {
+        ProfMark pm(ctx, RTDETMCD_PROF_SELECT, s, rows * 9.0);
+        RTD_HIP(launch_select(D.items, D.A, first, n, max_m, o.cstep_mode, s, 1));
+        pm.end(s);
+      }
+      double byt_s = 0.0;
+      for (int i = first; i < first + n; ++i)
+        byt_s += (double)S.items[i].m * ((S.items[i].dtype == 0 ? 4.0 : 8.0) * S.items[i].p + 1.0);
+      {
+        ProfMark pm(ctx, RTDETMCD_PROF_SSCP, s, byt_s, fl_su, fl_se);
+        RTD_HIP(launch_sscp(bucket, dtype, SSCP_CSTEP, D.items, D.A, D.stiles + st0, stn,
+                            SSCP_TILE, nullptr, nullptr, s));
+        pm.end(s);
+      }
+      RTD_HIP(launch_collapse(D.items, D.A, first, n, max_nt, 1, SSCP_TILE, s));
+      {
+        ProfMark pm(ctx, RTDETMCD_PROF_FINALIZE, s, 0.0);
+        RTD_HIP(launch_finalize(bucket, D.items, D.A, first, n, 0, maxs, o.kappa_max,
+                                o.cstep_mode, o.distance, s));
+        pm.end(s);
+      }
+      return RTDETMCD_OK;
+    };
     int t = 1;
+    if (ctx->prof_on) {
+      RTD_TRY(step1(st));
+      if (maxs == 1) {
+        RTD_HIP(hipMemcpyAsync(pin_flag, D.A.nactive, 4, hipMemcpyDeviceToHost, st));
+        RTD_HIP(hipStreamSynchronize(st));
+        return RTDETMCD_OK;
+      }
+      t = 2;
+    }
     if (o.graph && maxs >= R) {
       // whole rounds of R steps replayed from a captured graph on the
       // handle's replay stream, ordered after / before the caller's stream
@@ -248,7 +327,7 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
       RTD_HIP(hipEventRecord(ctx->gev[0], st));
       RTD_HIP(hipStreamWaitEvent(ctx->gstream, ctx->gev[0], 0));
       bool done = false;
-      for (; t + R - 1 <= maxs; t += R) {
+      for (; t + R - 1 <= maxs; t += R) {   // (t = 2 after a profiled first step)
         RTD_HIP(hipGraphLaunch(ge, ctx->gstream));
         RTD_HIP(hipMemcpyAsync(pin_flag, D.A.nactive, 4, hipMemcpyDeviceToHost, ctx->gstream));
         RTD_HIP(hipStreamSynchronize(ctx->gstream));
@@ -442,6 +521,7 @@ rtdetmcd_status rtdetmcd_destroy(rtdetmcd_handle ctx) {
   if (ctx->pin_ev) (void)hipEventDestroy(ctx->pin_ev);
   if (ctx->flag) (void)hipHostFree(ctx->flag);
   if (ctx->stage) (void)hipFree(ctx->stage);
+  for (hipEvent_t e : ctx->prof_events) (void)hipEventDestroy(e);
   delete ctx;
   return RTDETMCD_OK;
 }
@@ -514,9 +594,13 @@ rtdetmcd_status rtdetmcd_distances(rtdetmcd_handle ctx, const void* X, int32_t d
   RTD_HIP(hipGetLastError());
   RTD_HIP(launch_chol_factor(L, p, D.A.mtri, ctx->stream));
   // the distance kernel writes d2 + roff with roff = 0
+  const double es = dtype == 0 ? 4.0 : 8.0;
+  ProfMark pm(ctx, RTDETMCD_PROF_DISTANCES, ctx->stream, (double)n * (es * p + 8.0),
+              (double)n * (p * (p + 1.0) + 3.0 * p));
   RTD_HIP(launch_dist(bucket_of(p), dtype, S.rows_dense(0, (int)S.items.size(), bucket_of(p)), 1,
                       D.items, D.dtiles, (int)S.dtiles.size(), DIST_TILE,
                       D.A.mtri, D.A.mux, nullptr, nullptr, d2, ctx->stream));
+  pm.end(ctx->stream);
   return RTDETMCD_OK;
 }
 
@@ -533,8 +617,13 @@ rtdetmcd_status rtdetmcd_score(rtdetmcd_handle ctx, const void* X, int32_t dtype
   if (p > RTDETMCD_MAX_P) return RTDETMCD_EUNSUPPORTED;
   RTD_HIP(hipSetDevice(ctx->device));
   const double c = cut > 0.0 ? cut : chi2_quantile(0.975, p);
+  const double es = dtype == 0 ? 4.0 : 8.0;
+  ProfMark pm(ctx, RTDETMCD_PROF_DISTANCES, ctx->stream,
+              (double)n * (es * p + (dist ? 8.0 : 0.0) + (outlier ? 1.0 : 0.0)),
+              (double)n * (p * (p + 1.0) + 3.0 * p));
   RTD_HIP(launch_score(bucket_of(p), dtype, X, n, ld, p, mu, Linv, p, c, dist, outlier,
                        ctx->stream));
+  pm.end(ctx->stream);
   return RTDETMCD_OK;
 }
 
@@ -621,5 +710,43 @@ rtdetmcd_status rtdetmcd_cstep(rtdetmcd_handle ctx, const void* X, int32_t dtype
 }
 
 int64_t rtdetmcd_sort_reruns(rtdetmcd_handle ctx) { return ctx ? ctx->sort_reruns : -1; }
+
+rtdetmcd_status rtdetmcd_profile(rtdetmcd_handle ctx, int32_t enable) {
+  if (!ctx) return RTDETMCD_EINVAL;
+  ctx->prof_on = enable != 0;
+  if (ctx->prof_on) {
+    RTD_HIP(hipSetDevice(ctx->device));
+    RTD_HIP(hipStreamSynchronize(ctx->stream));   // every recorded event has completed
+    ctx->prof.clear();
+    ctx->prof_next = 0;
+  }
+  return RTDETMCD_OK;
+}
+
+rtdetmcd_status rtdetmcd_profile_read(rtdetmcd_handle ctx, int32_t kind, double* ms,
+                                      int64_t* launches, double* bytes, double* flops_useful,
+                                      double* flops_exec) {
+  if (!ctx || kind < 0 || kind >= RTDETMCD_PROF_KINDS) return RTDETMCD_EINVAL;
+  RTD_HIP(hipSetDevice(ctx->device));
+  RTD_HIP(hipStreamSynchronize(ctx->stream));
+  double t = 0.0, b = 0.0, fu = 0.0, fe = 0.0;
+  int64_t k = 0;
+  for (const auto& r : ctx->prof) {
+    if (r.kind != kind || !r.e1) continue;
+    float x = 0.0f;
+    RTD_HIP(hipEventElapsedTime(&x, r.e0, r.e1));
+    t += x;
+    b += r.bytes;
+    fu += r.flops_useful;
+    fe += r.flops_exec;
+    ++k;
+  }
+  if (ms) *ms = t;
+  if (launches) *launches = k;
+  if (bytes) *bytes = b;
+  if (flops_useful) *flops_useful = fu;
+  if (flops_exec) *flops_exec = fe;
+  return RTDETMCD_OK;
+}
 
 }  // extern "C"

@@ -125,6 +125,18 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
 
 rtdetmcd_status check_opts(rtdetmcd_ctx* ctx, const rtdetmcd_opts* in, rtdetmcd_opts& o);
 
+// Kernel timing: while rtdetmcd_profile is on (and no graph is being
+// captured), a ProfMark records a HIP event on the launching stream before
+// a launch and another after it (end), with the launch's algorithmic bytes
+// and flops.  Off, it does nothing.
+struct ProfMark {
+  rtdetmcd_ctx* ctx = nullptr;
+  int idx = -1;
+  ProfMark(rtdetmcd_ctx* c, int kind, hipStream_t s, double bytes, double flops_useful = 0.0,
+           double flops_exec = 0.0);
+  void end(hipStream_t s);
+};
+
 // Start of rtdetmcd_cstep: (mu0, sigma0) divided by the condition-check
 // scales into the item's muz / sigz, loc = 0 and scale = kscale (or 1).
 hipError_t launch_cstep_init(const double* mu0, const double* sigma0, const double* kscale,

@@ -95,7 +95,12 @@ rtdetmcd_status sort_stats(rtdetmcd_ctx* ctx, const SortHost& H, SortDev& D, int
   SortPlan P = D.plan.sub(a, b, H.tile0.data());
   const int64_t maxlen = *std::max_element(H.len.begin() + a, H.len.begin() + b);
   if (maxlen <= lds_sort_capacity()) {
+    double keys = 0.0;
+    for (int k = a; k < b; ++k) keys += (double)H.len[k];
+    ProfMark pm(ctx, RTDETMCD_PROF_SEGSORT, ctx->stream,
+                keys * H.key_bytes + (double)(b - a) * sizeof(SegStat));
     RTD_HIP(launch_seg_lds(P, D.craw + a, q1, crew1, mode, D.st + a, maxlen, ctx->stream));
+    pm.end(ctx->stream);
     return RTDETMCD_OK;
   }
   RTD_HIP(sort_segments(P, ctx->stream));
@@ -448,6 +453,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   const double crew1 = consistency_memo(o.cutoff_q, 1);
   const int smode = o.standardize == RTDETMCD_STD_MEDMAD ? SEGSTAT_MEDMAD : SEGSTAT_UNIMCD;
 
+  ProfMark pm_fit(ctx, RTDETMCD_PROF_FIT, st, 0.0);
   // ---------------------------------------------------------------- random partitions
   for (int k = 0; k < ND; ++k) {
     if (!D[k].perm) continue;
@@ -578,13 +584,20 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   for (const Group& g : groups) {
     const int a = ND + g.ds0, b = ND + g.ds1;
     const int dt0 = G.dt_first[a], dtn = G.dt_first[b - 1] + G.dt_count[b - 1] - dt0;
+    double byt = 0.0;
+    for (int k = g.ds0; k < g.ds1; ++k)
+      byt += (double)D[k].n * ((D[k].dtype == 0 ? 4.0 : 8.0) * D[k].p + 10.0) +
+             (double)D[k].q * D[k].m * 8.0;
+    ProfMark pm(ctx, RTDETMCD_PROF_FINAL_DIST, st, byt);
     RTD_HIP(launch_final_dist(g.bucket, g.dtype, G.rows_dense(a, b, g.bucket), GD.items,
                               GD.dtiles + dt0, dtn, DIST_TILE,
                               GD.A.mtri, GD.A.mux, o.distance ? GD.A.form : nullptr, GD.A.d2,
                               dds, douts, st));
+    pm.end(st);
   }
   RTD_HIP(launch_hsub(CD.items, CD.A, F, dds, douts, 0, NB, st));
   RTD_HIP(launch_outputs(dds, GD.A, F, douts, 0, ND, st));
+  pm_fit.end(st);
   // ---------------------------------------------------------------- status
   RTD_HIP(hipMemcpyAsync(dinfo.data(), dds, ND * sizeof(DsInfo), hipMemcpyDeviceToHost, st));
   RTD_HIP(hipMemcpyAsync(ctx->flag, sflag, 4, hipMemcpyDeviceToHost, st));

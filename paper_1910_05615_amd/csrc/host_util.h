@@ -135,4 +135,14 @@ struct rtdetmcd_ctx {
   std::vector<rtd_graph> graphs;          // captured C-step rounds, most recent last
   void* scratch = nullptr;     // this device's allocation-free scratch array (device address)
   size_t scratch_bytes = 0;
+  // kernel timing (rtdetmcd_profile): HIP events around chosen launches
+  struct ProfRec {
+    int kind;
+    hipEvent_t e0, e1;
+    double bytes, flops_useful, flops_exec;
+  };
+  bool prof_on = false;
+  std::vector<ProfRec> prof;
+  std::vector<hipEvent_t> prof_events;   // every event created for profiling (reused)
+  size_t prof_next = 0;                  // next free event of prof_events
 };
