@@ -5,8 +5,9 @@ against the oracle, and every dataset checked for the identities that hold at
 any size.  10,000,000 x 40 in 1,024 blocks: the standardisation of sampled
 columns against the oracle's estimator, each sampled block's h-subset a
 C-step fixed point of its own mean and covariance, the reweighted fit equal
-to the classical estimates of the kept rows, and flags consistent with the
-distances of every row (the 640 rows past the last block included)."""
+to the classical estimates of the kept rows, flags consistent with the
+distances of every row (the 640 rows past the last block included), and the
+whole fit equal to the oracle's fit of the same data (a stored digest)."""
 import math
 
 import numpy as np
@@ -120,3 +121,43 @@ def test_large_p40_full_size():
     # the rows past the last block are scored too
     tail = F.dist.cpu().numpy()[q * m:]
     assert tail.size == n - q * m == 640 and np.all(np.isfinite(tail))
+    _check_large_digest(F)
+
+
+def _check_large_digest(F):
+    """The whole fit against the oracle's fit of the same seeded data, stored
+    as a digest by tests/golden/make_large_p40_digest.py (oracle only): every
+    block's status, start, iterations and h-subset (CRC32 and sum of its
+    row indices), standardisation, raw and reweighted fits, the reweighting
+    set and the flagged rows exactly, distances on sampled rows."""
+    import json
+    import os
+    import zlib
+    path = os.path.join(os.path.dirname(__file__), "golden", "large_p40_oracle_digest.json")
+    with open(path) as f:
+        g = json.load(f)
+    crc = lambda a: int(zlib.crc32(np.ascontiguousarray(a).tobytes()))
+    assert (F.q, F.m, F.h) == (g["q"], g["m"], g["h"])
+    np.testing.assert_allclose(F.loc.cpu().numpy(), g["loc"], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(F.scale.cpu().numpy(), g["scale"], rtol=1e-12)
+    assert F.block_status.cpu().numpy().tolist() == g["block_status"]
+    assert F.block_start.cpu().numpy().tolist() == g["block_start"]
+    assert F.block_iters.cpu().numpy().tolist() == g["block_iters"]
+    H = F.hsubset.cpu().numpy().astype(np.int32)
+    bad = [b for b in range(F.q) if crc(H[b]) != g["hsubset_crc32"][b] or
+           int(H[b].astype(np.int64).sum()) != g["hsubset_sum"][b]]
+    assert not bad, f"blocks whose h-subset differs from the oracle's: {bad[:10]}"
+    assert int(F.n_w.cpu()[0]) == g["n_w"]
+    assert crc(F.rew_mask.cpu().numpy().astype(np.uint8)) == g["rew_mask_crc32"]
+    flagged = np.nonzero(F.outlier.cpu().numpy())[0].astype(np.int64)
+    assert flagged.size == g["n_flagged"] and crc(flagged) == g["flagged_crc32"]
+    for name in ("sigma_raw", "sigma"):
+        a, b = getattr(F, name).cpu().numpy(), np.array(g[name])
+        assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-8, name
+    for mname, sname in (("mu_raw", "sigma_raw"), ("mu", "sigma")):
+        d = getattr(F, mname).cpu().numpy() - np.array(g[mname])
+        assert math.sqrt(float(d @ np.linalg.solve(np.array(g[sname]), d))) < 1e-8, mname
+    ld = F.logdet.cpu().numpy()
+    assert abs(ld[0] - g["logdet_raw"]) < 1e-8 and abs(ld[1] - g["logdet_rew"]) < 1e-8
+    rows = np.array(g["dist_rows"])
+    np.testing.assert_allclose(F.dist.cpu().numpy()[rows], g["dist_at_rows"], rtol=1e-9)
