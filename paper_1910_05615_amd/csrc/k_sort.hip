@@ -568,55 +568,122 @@ __global__ __launch_bounds__(SS_NT) void k_segstats(const K* __restrict__ keys,
 // i < KPT, so ranks follow position order; KPT is the smallest even number
 // from 4 to 16 that holds the segment, so little padding is sorted.
 //
-// The passes run on a 32-bit key: the key itself for float data, and for
-// double data the high half of the order key (sign, exponent and 20 mantissa
-// bits: a monotone function of the key, so its order never contradicts the
-// order of the values).  Runs of equal sort keys are then ordered by
-// insertion sort on the full key; they are short for continuous data.
+// The three passes run on a 24-bit key normalised to the segment's value
+// range (DigitNorm): a monotone function of the value, so its order never
+// contradicts the order of the values, and all of its digits spread over the
+// values (the high bits of the order key hold the sign and exponent, which
+// take few distinct values).  The last pass scatters the values themselves,
+// so the buffer then holds the values ordered on the key.
 //
-// Ranks within a wave come from LDS atomics on per-(wave, digit) counters in
-// the passes whose digits spread well; those ranks follow lane order on this
-// hardware, which keeps each pass stable.  The top digit (sign and the high
-// exponent bits: few distinct values in a wave, so atomics would serialise)
-// is ranked by peeling: one wave ballot per distinct digit present, stable
-// by construction.  Nothing is taken on trust: every
-// adjacent pair of 32-bit keys is checked in the same sweep that finds the
-// runs, and a segment that is out of order, or has a run that is too long or
-// too costly for the fix-up, goes through the full-width sort with ballot
-// ranking only.
+// Ranks within a wave come from LDS atomics on per-(wave, digit) counters;
+// those ranks follow lane order on this hardware, which keeps each pass
+// stable.  Nothing is taken on trust: the estimator's threads load their
+// contiguous ranges of the result and compare every adjacent pair
+// (check_fix).  A descent between equal keys (values closer than the key's
+// resolution: a few pairs per segment of continuous data) puts its run on a
+// list, found from the run's first descent; each listed run is then put in
+// order by insertion sort by one thread.  Runs of equal values hold no
+// descent and are never walked.  A descent between unequal keys or a padding
+// value inside the segment fails the check; so do too many descents, or a
+// run too long or too costly for the fix-up (values crowded into a few keys:
+// heavy tails, far outliers).  Such a segment is left to k_seg_lds_slow:
+// passes on the high 32 bits of the order key (resolution relative to each
+// value) with the same check, and failing that the full-width sort with
+// ballot ranking only.
 constexpr int LDS_KEYS = SS_NT * 16;
 constexpr int FIXUP_RUN = 256;      // longest run finished by insertion sort
 constexpr int FIXUP_MOVES = 2048;   // insertion-sort budget per run
-
-// 32-bit sort key of a double's order key: its high half.
-__device__ inline uint32_t key32_of(uint64_t k) { return (uint32_t)(k >> 32); }
+constexpr int FIXUP_LIST = 1024;    // runs fixed per segment
+constexpr int NORM_MAX_DESC = 512;  // descents fixed after the normalised-key passes
+constexpr int64_t SEG_REDO = -2;    // SegStat.start of a segment left to k_seg_lds_slow
 
 // How a pass ranks keys within a wave (all three follow lane order).
 constexpr int RK_ATOM = 0;     // LDS atomics on per-(wave, digit) counters
 constexpr int RK_BALLOT = 1;   // match by eight bit ballots: any digit mix
 constexpr int RK_PEEL = 2;     // one ballot per distinct digit in the wave
 
-template <typename K, bool K32>
-__device__ inline int digit_at(K k, int shift) {
-  if constexpr (K32 && sizeof(K) == 8) return (int)((key32_of(k) >> shift) & 0xFFu);
-  else return (int)((k >> shift) & (K)0xFF);
-}
+// Digits of a pass: 8 bits at `shift` of the item's sort key.
+struct DigitFull {   // the key itself
+  template <typename K>
+  __device__ int operator()(K k, int shift) const { return (int)((k >> shift) & (K)0xFF); }
+};
+struct DigitKey32 {   // the high 32 bits of the key (all of a float key)
+  template <typename K>
+  __device__ int operator()(K k, int shift) const {
+    return (int)(((uint32_t)(k >> (8 * sizeof(K) - 32)) >> shift) & 0xFFu);
+  }
+};
+// The segment-normalised 24-bit key floor((x - lo) 2^24 / (hi - lo)) of the
+// item's value x, clamped to [0, 2^24 - 1] (padding: 2^24 - 1).  Each step
+// (fma with a positive scale, clamps, truncation) is monotone in x, so its
+// order never contradicts the order of the values; unlike the high bits of
+// the order key, all three digits spread over the segment's values.
+struct DigitNorm {
+  double sc, off;   // 2^24 / (hi - lo), -lo sc
+  // From per-wave bounds of the high 32 bits of the order keys, rr[0..16)
+  // (minima) and rr[16..32) (maxima), read after a barrier: 16 lanes of
+  // every wave reduce them, so every lane gets the same values, kept in
+  // scalar registers.  lo and hi are the smallest and largest values with
+  // those high halves, so lo <= every value <= hi.  A range that is empty or
+  // too narrow to scale gives one key to all values (a single run of equal
+  // keys).
+  template <typename K>
+  __device__ void finish(const uint32_t* rr) {
+    const int l = threadIdx.x & 15;
+    uint32_t mn = rr[l], mx = rr[16 + l];
+    mn = min(mn, (uint32_t)dpp_i<0x111, 0xf>((int)mn, -1));   // row_shr 1, 2, 4, 8
+    mx = max(mx, (uint32_t)dpp_i<0x111, 0xf>((int)mx, 0));
+    mn = min(mn, (uint32_t)dpp_i<0x112, 0xf>((int)mn, -1));
+    mx = max(mx, (uint32_t)dpp_i<0x112, 0xf>((int)mx, 0));
+    mn = min(mn, (uint32_t)dpp_i<0x114, 0xf>((int)mn, -1));
+    mx = max(mx, (uint32_t)dpp_i<0x114, 0xf>((int)mx, 0));
+    mn = min(mn, (uint32_t)dpp_i<0x118, 0xf>((int)mn, -1));
+    mx = max(mx, (uint32_t)dpp_i<0x118, 0xf>((int)mx, 0));
+    mn = (uint32_t)__builtin_amdgcn_readlane((int)mn, 15);
+    mx = (uint32_t)__builtin_amdgcn_readlane((int)mx, 15);
+    double lo, hi;
+    if constexpr (sizeof(K) == 8) {
+      lo = val_of<K>((K)mn << 32);
+      hi = val_of<K>(((K)mx << 32) | 0xFFFFFFFFull);
+    } else {
+      lo = val_of<K>((K)mn);
+      hi = val_of<K>((K)mx);
+    }
+    const double s = 16777216.0 / (hi - lo);
+    sc = uniform_d((hi > lo && s < 1e300) ? s : 0.0);
+    off = uniform_d(-lo * sc);
+  }
+  __device__ uint32_t of_val(double x) const {
+    const double t = fmin(fmax(fma(x, sc, off), 0.0), 16777215.0);
+    return (uint32_t)t;
+  }
+  template <typename K>
+  __device__ uint32_t of_key(K k) const {
+    return k == ~(K)0 ? 16777215u : of_val(val_of<K>(k));
+  }
+  template <typename K>
+  __device__ int operator()(K k, int shift) const { return (int)((of_key<K>(k) >> shift) & 0xFFu); }
+};
 
 // One LSD pass over the block's keys (kv in position order on entry and on
-// exit).  RK: how ranks are found (RK_*).  K32: digits of the 32-bit sort
-// key.  wc: [16][256] ints, gs: [4][256] ints, wt: [4].
-template <typename K, int RK, bool K32, int KPT>
-__device__ inline void lds_radix_pass(K (&kv)[KPT], int shift, K* __restrict__ sk,
+// exit).  RK: how ranks are found (RK_*).  dg: the digit of an item; with
+// PREP, dg.finish(prep) runs after the pass's first barrier (it may read
+// what the block wrote to prep before the pass).  wc: [16][256] ints, gs: [4][256] ints, wt: [4].  TOVAL (the last
+// pass): the values of the keys are scattered instead (double for double
+// keys, float for float keys, in the same buffer) and kv is left as it was.
+template <typename K, int RK, typename DG, int KPT, bool TOVAL = false, bool PREP = false>
+__device__ inline void lds_radix_pass(K (&kv)[KPT], int shift, DG& dg, K* __restrict__ sk,
                                       int* __restrict__ wc, int* __restrict__ gs,
-                                      int* __restrict__ wt) {
+                                      int* __restrict__ wt, const uint32_t* prep = nullptr) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint64_t below = (1ull << lane) - 1ull;
   for (int e = tid; e < 16 * 256; e += SS_NT) wc[e] = 0;
   __syncthreads();
+  if constexpr (PREP) dg.template finish<K>(prep);
   int dr[KPT];   // digit << 16 | rank within (wave, digit)
 #pragma unroll
   for (int i = 0; i < KPT; ++i) {
-    const int d = digit_at<K, K32>(kv[i], shift);
+    const int d = dg(kv[i], shift);
     if constexpr (RK == RK_ATOM) {
       dr[i] = (d << 16) | atomicAdd(&wc[w * 256 + d], 1);
     } else if constexpr (RK == RK_PEEL) {
@@ -682,6 +749,17 @@ __device__ inline void lds_radix_pass(K (&kv)[KPT], int shift, K* __restrict__ s
     for (int k = 0; k < 4; ++k) wc[(g * 4 + k) * 256 + d] = base + c[k];
   }
   __syncthreads();
+  if constexpr (TOVAL) {
+    using V = typename std::conditional<sizeof(K) == 8, double, float>::type;
+    V* __restrict__ sv = reinterpret_cast<V*>(sk);
+#pragma unroll
+    for (int i = 0; i < KPT; ++i) {
+      const int di = dr[i] >> 16;
+      sv[wc[w * 256 + di] + (dr[i] & 0xFFFF)] = (V)val_of<K>(kv[i]);
+    }
+    __syncthreads();
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < KPT; ++i) {
     const int di = dr[i] >> 16;
@@ -692,68 +770,305 @@ __device__ inline void lds_radix_pass(K (&kv)[KPT], int shift, K* __restrict__ s
   for (int i = 0; i < KPT; ++i) kv[i] = sk[w * KPT * 64 + i * 64 + lane];
 }
 
-// 32-bit sort key of a key: the key itself (float data) or the high half of
-// a double's order key.
-template <typename K>
-__device__ inline uint32_t skey_of(K k) {
-  if constexpr (sizeof(K) == 8) return key32_of(k);
-  else return k;
-}
+// Sort key of a value under the order-key passes: the high half of a double's
+// order key, or a float's order key (for float data it is the whole key).
+struct Key32 {
+  __device__ uint32_t of_val(double x) const {
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    return (uint32_t)(((b >> 63) ? ~b : (b | 0x8000000000000000ull)) >> 32);
+  }
+  __device__ uint32_t of_val(float x) const {
+    const uint32_t b = __float_as_uint(x);
+    return (b >> 31) ? ~b : (b | 0x80000000u);
+  }
+};
+struct KeyNormV {   // the normalised key of a value (see DigitNorm)
+  DigitNorm dn;
+  __device__ uint32_t of_val(double x) const { return dn.of_val(x); }
+  __device__ uint32_t of_val(float x) const { return dn.of_val((double)x); }
+};
 
-// After passes that ordered the block's keys on skey (kv holds each thread's
-// keys in position order): one look at every adjacent pair checks that order
-// (it is not assumed), and runs of equal skey of double data are then put in
-// order on the full key by insertion sort, each by the thread that holds its
-// first position.  Sets *redo when the order is wrong or a run is too long or
-// too costly.  Ends with a barrier.
-template <typename K, int KPT>
-__device__ inline void check_and_fix(const K (&kv)[KPT], K* __restrict__ sk, int L,
-                                     int* __restrict__ redo) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  uint32_t starts = 0;
-  bool bad = false;
+// Check of sv[0..L) after passes that ordered it on the key kf (a monotone
+// function of the value), and the fix-up of runs of equal keys.  Thread t
+// reads its range [a0, a0 + n) into x and compares every adjacent pair.  A
+// descent between unequal keys, or a padding value (NaN) inside the segment,
+// fails the check; a descent between equal keys marks its run.  When there
+// are at most max_desc descents, each run that holds one is listed from its
+// first descent (the walks only read) and then put in order by insertion
+// sort by one thread; runs longer than FIXUP_RUN or costlier than
+// FIXUP_MOVES fail.  Returns true (the same in every thread) on failure;
+// otherwise x holds the sorted range.  flg[0..3) must be zero on entry and
+// no thread may still read them from an earlier use.
+template <typename V, int RN, typename KF>
+__device__ bool check_fix(V* __restrict__ sv, int L, int a0, int n, V (&x)[RN], KF kf,
+                          int max_desc, int* flg, int* runs) {
 #pragma unroll
-  for (int i = 0; i < KPT; ++i) {
-    const int pos = w * KPT * 64 + i * 64 + lane;
-    if (pos + 1 < L) {
-      const uint32_t a = skey_of<K>(kv[i]), b = skey_of<K>(sk[pos + 1]);
-      bad = bad || a > b;
-      if constexpr (sizeof(K) == 8) {   // equal sort keys, possibly unequal full keys
-        const bool prev_eq = pos > 0 && skey_of<K>(sk[pos - 1]) == a;
-        if (a == b && !prev_eq) starts |= 1u << i;
+  for (int k = 0; k < RN; ++k) {   // a0 + RN <= CAP + RN: no branches
+    const V t = sv[a0 + k];
+    x[k] = k < n ? t : (V)0;
+  }
+  uint32_t desc = 0;
+  bool bad = false;
+  {
+    const V nxt = sv[a0 + n];   // a0 + n <= L
+#pragma unroll
+    for (int k = 0; k < RN; ++k) {
+      if (k < n) {
+        const V a = x[k];
+        const V b2 = (k + 1 < n) ? x[k + 1] : nxt;
+        bad = bad || !(a == a);
+        if (a0 + k + 1 < L && a > b2) {
+          if (kf.of_val(a) != kf.of_val(b2)) bad = true;
+          else desc |= 1u << k;
+        }
       }
     }
   }
-  if (bad) *redo = 1;
+  if (bad) atomicOr(&flg[1], 1);
+  if (desc) atomicAdd(&flg[0], __popc(desc));
   __syncthreads();
-  while (starts) {
-    const int i = __ffs(starts) - 1;
-    starts &= starts - 1;
-    const int s0 = w * KPT * 64 + i * 64 + lane;
-    const uint32_t k0 = skey_of<K>(sk[s0]);
-    int e = s0 + 1;
-    while (e < L && e - s0 <= FIXUP_RUN && skey_of<K>(sk[e]) == k0) ++e;
-    if (e - s0 > FIXUP_RUN) {
-      *redo = 1;
-      break;
+  if (flg[1] || flg[0] > max_desc) return true;
+  if (!flg[0]) return false;
+  for (uint32_t dm = desc; dm; dm &= dm - 1u) {
+    const int q = a0 + __ffs(dm) - 1;
+    const V vq = sv[q];
+    const uint32_t kq = kf.of_val(vq);
+    int s0 = q;
+    bool first = true, over = false;
+    V right = vq;
+    while (s0 > 0) {
+      if (q - s0 >= FIXUP_RUN) { over = true; break; }
+      const V left = sv[s0 - 1];
+      if (kf.of_val(left) != kq) break;
+      if (left > right) { first = false; break; }   // an earlier descent takes the run
+      right = left;
+      --s0;
     }
+    if (!first) continue;
+    int e = q + 2;
+    while (!over && e < L && kf.of_val(sv[e]) == kq) {
+      if (e - s0 >= FIXUP_RUN) over = true;
+      ++e;
+    }
+    if (over) {
+      atomicOr(&flg[1], 1);
+      continue;
+    }
+    const int slot = atomicAdd(&flg[2], 1);
+    if (slot < FIXUP_LIST) {
+      runs[2 * slot] = s0;
+      runs[2 * slot + 1] = e;
+    } else {
+      atomicOr(&flg[1], 1);
+    }
+  }
+  __syncthreads();
+  const int nr = min(flg[2], FIXUP_LIST);
+  for (int t = threadIdx.x; t < nr && !flg[1]; t += SS_NT) {
+    const int s0 = runs[2 * t], e = runs[2 * t + 1];
     int moves = 0;
     for (int a = s0 + 1; a < e && moves <= FIXUP_MOVES; ++a) {
-      const K x = sk[a];
+      const V xa = sv[a];
       int b = a;
-      while (b > s0 && sk[b - 1] > x && moves <= FIXUP_MOVES) {
-        sk[b] = sk[b - 1];
+      while (b > s0 && sv[b - 1] > xa && moves <= FIXUP_MOVES) {
+        sv[b] = sv[b - 1];
         --b;
         ++moves;
       }
-      sk[b] = x;
+      sv[b] = xa;
     }
-    if (moves > FIXUP_MOVES) {
-      *redo = 1;
-      break;
+    if (moves > FIXUP_MOVES) atomicOr(&flg[1], 1);
+  }
+  __syncthreads();
+  if (flg[1]) return true;
+#pragma unroll
+  for (int k = 0; k < RN; ++k) {
+    const V t = sv[a0 + k];
+    x[k] = k < n ? t : (V)0;
+  }
+  return false;
+}
+
+// Univariate reweighted MCD (Sec. 3.1) of a sorted LDS segment v[0..L), with
+// RN readable slots past L.  Thread t takes the positions [t S, t S + S) of
+// the segment (clipped to L), S odd (so that the threads of a wave start
+// their ranges in different LDS banks) and S <= RN, so every loop is unrolled
+// over RN with its reads issued together; no value is held across a
+// barrier.  The operations are those of segstat_body (prefix sums of the
+// values centred at the middle order statistic, windows ranked by
+// hd s2 - s1^2, reweighting of the raw fit), in order within each range.  Scratch: red, pfa, pfb hold SS_NT doubles each; the result is
+// valid in thread 0.
+template <typename V, int RN>
+__device__ __forceinline__ SegStat segstat_regs(const V* __restrict__ v, int L, int S, int a0, int a1,
+                                                double craw, double q1,
+                                                double crew, double* red, double* pfa,
+                                                double* pfb) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  SegStat r{};
+  const int n = a1 - a0;
+  const int hh = L / 2 + 1;
+  const double hd = (double)hh;
+  const double c = (double)v[L / 2];
+  // window ends j + hh: position hh mod S of a range (the end L aside)
+  const int r0 = hh % S;
+  // centred sums over the range, and over its first r0 positions
+  double pa[2] = {0.0, 0.0}, pr[2] = {0.0, 0.0};
+  V xin[RN];
+#pragma unroll
+  for (int k = 0; k < RN; ++k) xin[k] = v[a0 + k];
+#pragma unroll
+  for (int k = 0; k < RN; ++k) {
+    if (k == r0) {
+      pr[0] = pa[0];
+      pr[1] = pa[1];
+    }
+    if (k < n) {
+      const double d = (double)xin[k] - c;
+      pa[0] += d;
+      pa[1] = fma(d, d, pa[1]);
+    }
+  }
+  if (r0 >= RN) {
+    pr[0] = pa[0];
+    pr[1] = pa[1];
+  }
+  // exclusive prefix over the block: wave scans, then the wave totals
+  // scanned by 16 lanes of every wave (fixed order, so deterministic)
+  double ex[2], tot[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const double inc = wave_incl_sum(pa[q]);
+    if (lane == 63) red[q * SS_WV + w] = inc;
+    ex[q] = dpp_d<0x138, 0xf>(inc, 0.0);   // wave_shr 1: the previous lane's
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    double t = red[q * SS_WV + (lane & 15)];
+    t += dpp_d<0x111, 0xf>(t, 0.0);   // row_shr 1, 2, 4, 8: inclusive within each 16 lanes
+    t += dpp_d<0x112, 0xf>(t, 0.0);
+    t += dpp_d<0x114, 0xf>(t, 0.0);
+    t += dpp_d<0x118, 0xf>(t, 0.0);
+    const double before = w > 0 ? lane_bcast_d(t, w - 1) : 0.0;
+    tot[q] = lane_bcast_d(t, SS_WV - 1);
+    ex[q] += before;
+  }
+  const double P1a = ex[0], P2a = ex[1];
+  // publish the prefix at a0 + r0
+  pfa[tid] = P1a + pr[0];
+  pfb[tid] = P2a + pr[1];
+  const int nw = L - hh + 1;                 // number of windows
+  const int j0 = a0, j1 = a1 < nw ? a1 : nw;
+  __syncthreads();
+  double best = INFINITY, b1 = 0.0, b2 = 0.0;
+  int64_t bj = -1;
+  if (j0 < j1) {
+    // prefix at j0 + hh <= L: the owner's published prefix, or the total
+    const int pos = j0 + hh;
+    double q1h = tot[0], q2h = tot[1];
+    if (pos < L) {
+      const int ow = pos / S;                // pos = ow S + r0
+      q1h = pfa[ow];
+      q2h = pfb[ow];
+    }
+    // (v holds RN readable slots past L: j0 + hh <= L)
+    V x[RN], y[RN];
+#pragma unroll
+    for (int k = 0; k < RN; ++k) {
+      x[k] = v[a0 + k];
+      y[k] = v[j0 + hh + k];
+    }
+    // windows are ranked by hd * s2 - s1^2 = hd (hd - 1) var (no division
+    // in the loop); the variance itself is formed from the best window's sums
+    double q1l = P1a, q2l = P2a;
+#pragma unroll
+    for (int k = 0; k < RN; ++k) {
+      const int j = j0 + k;
+      if (j < j1) {
+        const double s1 = q1h - q1l, s2 = q2h - q2l;
+        const double cr = fma(s2, hd, -(s1 * s1));
+        if (cr < best) { best = cr; bj = j; b1 = s1; b2 = s2; }
+        const double dl = (double)x[k] - c;
+        q1l += dl;
+        q2l = fma(dl, dl, q2l);
+        if (j + hh < L) {
+          const double dh = (double)y[k] - c;
+          q1h += dh;
+          q2h = fma(dh, dh, q2h);
+        }
+      }
+    }
+  }
+  // smallest criterion, ties to the lowest start; the lane that owns the
+  // winning wave's window publishes its variance and window sum; the 16
+  // wave results are reduced by 16 lanes of every wave
+  double* __restrict__ rb = red + 64;
+  {
+    const int64_t own = bj;
+    wave_argmin(best, bj);
+    if (own >= 0 && own == bj) {
+      rb[SS_WV + w] = (b2 - b1 * b1 / hd) / (hd - 1.0);
+      rb[2 * SS_WV + w] = b1;
+    }
+    if (lane == 0) {
+      rb[w] = best;
+      reinterpret_cast<int64_t*>(rb)[3 * SS_WV + w] = bj;
     }
   }
   __syncthreads();
+  double cb = rb[lane & 15];
+  int64_t jb = reinterpret_cast<const int64_t*>(rb)[3 * SS_WV + (lane & 15)];
+  argmin_step<0x111, 0xf>(cb, jb);   // within each row of 16 lanes
+  argmin_step<0x112, 0xf>(cb, jb);
+  argmin_step<0x114, 0xf>(cb, jb);
+  argmin_step<0x118, 0xf>(cb, jb);
+  const int64_t js = lane_bcast_l(jb, 15);
+  const int qw = min((int)(js / (64 * S)), SS_WV - 1);   // the wave that holds start js
+  const double wmin = rb[SS_WV + qw], s1w = rb[2 * SS_WV + qw];
+  const double mu_raw = c + s1w / hd;
+  const double var_raw = wmin * craw;
+  // reweighting: keep (v - mu_raw)^2 <= q1 var_raw
+  const double lim = q1 * var_raw;
+  double cs[3] = {0.0, 0.0, 0.0};
+  {
+    V x[RN];
+#pragma unroll
+    for (int k = 0; k < RN; ++k) x[k] = v[a0 + k];
+#pragma unroll
+    for (int k = 0; k < RN; ++k)
+      if (k < n) {
+        const double xv = (double)x[k];
+        const double e = xv - mu_raw;
+        if (e * e <= lim) {
+          const double d = xv - c;
+          cs[0] += 1.0;
+          cs[1] += d;
+          cs[2] = fma(d, d, cs[2]);
+        }
+      }
+  }
+  double* __restrict__ rs = red + 128;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double t = wave_sum(cs[k]);
+    if (lane == 0) rs[k * SS_WV + w] = t;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double N = 0.0, S1 = 0.0, S2 = 0.0;
+    for (int q = 0; q < SS_WV; ++q) {
+      N += rs[q];
+      S1 += rs[SS_WV + q];
+      S2 += rs[2 * SS_WV + q];
+    }
+    r.mu_raw = mu_raw;
+    r.var_raw = var_raw;
+    r.start = js;
+    r.n_kept = (int64_t)N;
+    r.mu = N > 0 ? c + S1 / N : NAN;
+    r.var = N > 1 ? (S2 - S1 * S1 / N) / (N - 1.0) * crew : 0.0;
+  }
+  return r;
 }
 
 template <typename K, int KPT>
@@ -763,18 +1078,28 @@ __global__ __launch_bounds__(SS_NT) void k_seg_lds(const K* __restrict__ keys,
                                                    const double* __restrict__ seg_craw,
                                                    int seg_first, double q1, double crew, int mode,
                                                    SegStat* __restrict__ out) {
+  using V = typename std::conditional<sizeof(K) == 8, double, float>::type;
   constexpr int CAP = SS_NT * KPT;             // keys per block
-  __shared__ K sk[CAP];
-  __shared__ double scratch[3 * SS_NT];        // estimator scratch / wave digit counters
+  constexpr int RN = KPT + 1;                  // longest estimator range
+  __shared__ K sk[CAP + RN + 1];               // keys, then values (sv); spare
+                                               // slots for the range reads
+  __shared__ double scratch[3 * SS_NT];        // digit counters / fix-up list / estimator
   int* wc = reinterpret_cast<int*>(scratch);   // [16][256] during the sort
-  __shared__ int gs[4 * 256 + 8];              // group sums, wave totals, flag
+  int* runs = reinterpret_cast<int*>(scratch);   // [FIXUP_LIST][2] after it
+  static_assert(2 * FIXUP_LIST <= 6 * SS_NT, "fix-up list exceeds the scratch");
+  __shared__ int gs[4 * 256 + 8];              // group sums, wave totals, flags
   int* wt = gs + 4 * 256;
-  int* redo = gs + 4 * 256 + 4;
+  int* flg = gs + 4 * 256 + 4;                 // [0] descents, [1] redo, [2] runs listed
+  V* sv = reinterpret_cast<V*>(sk);
   const int sb = blockIdx.x;                   // index into seg_craw / out
   const int sg = seg_first + sb;               // absolute segment
   const K* __restrict__ src = keys + seg_off[sg];
   const int L = (int)seg_len[sg];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (L <= 0) {   // uniform
+    if (tid == 0) out[sb] = SegStat{};
+    return;
+  }
   const K pad = ~(K)0;
   K kv[KPT];
   auto load = [&]() {
@@ -784,30 +1109,130 @@ __global__ __launch_bounds__(SS_NT) void k_seg_lds(const K* __restrict__ keys,
       kv[i] = pos < L ? src[pos] : pad;
     }
   };
-  auto sort32 = [&]() {   // the four digits of the 32-bit sort key
-    lds_radix_pass<K, RK_ATOM, true, KPT>(kv, 0, sk, wc, gs, wt);
-    lds_radix_pass<K, RK_ATOM, true, KPT>(kv, 8, sk, wc, gs, wt);
-    lds_radix_pass<K, RK_ATOM, true, KPT>(kv, 16, sk, wc, gs, wt);
-    lds_radix_pass<K, RK_PEEL, true, KPT>(kv, 24, sk, wc, gs, wt);
+  // this thread's contiguous range of sorted positions: S (odd) from t S
+  const int S = ((L + SS_NT - 1) / SS_NT) | 1;   // <= KPT + 1
+  const int a0 = min(tid * S, L), a1 = min(a0 + S, L);
+  const int n = a1 - a0;
+  V x[RN];
+  auto load_range = [&]() {
+#pragma unroll
+    for (int k = 0; k < RN; ++k) {   // a0 + RN <= CAP + RN: no branches
+      const V t = sv[a0 + k];
+      x[k] = k < n ? t : (V)0;
+    }
   };
   load();
-  if (tid == 0) *redo = 0;
-  sort32();
-  check_and_fix<K, KPT>(kv, sk, L, redo);
-  if (*redo) {   // uniform: every thread reads the flag after the barrier
-    __syncthreads();
-    load();
-    for (int shift = 0; shift < 8 * (int)sizeof(K); shift += 8)
-      lds_radix_pass<K, RK_BALLOT, false, KPT>(kv, shift, sk, wc, gs, wt);
+  // bounds of the segment's values for the normalised key: the smallest and
+  // largest high halves of the order keys (one 32-bit comparison per key);
+  // the reduction over the waves happens in the first pass
+  DigitNorm dn;
+  {
+    uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+#pragma unroll
+    for (int i = 0; i < KPT; ++i) {
+      const uint32_t hk = (uint32_t)(kv[i] >> (8 * sizeof(K) - 32));
+      mn = min(mn, hk);   // padding is the largest key
+      if (w * KPT * 64 + i * 64 + lane < L) mx = max(mx, hk);
+    }
+    mn = wave_min_u32(mn);
+    mx = wave_max_u32(mx);
+    uint32_t* rr = reinterpret_cast<uint32_t*>(scratch + 2 * SS_NT);   // clear of the counters
+    if (lane == 0) {
+      rr[w] = mn;
+      rr[SS_WV + w] = mx;
+    }
+    if (tid < 3) flg[tid] = 0;   // first read after the passes' barriers
   }
-  // the estimator reads values: turn the order keys back into them in place
-  using V = typename std::conditional<sizeof(K) == 8, double, float>::type;
-  V* sv = reinterpret_cast<V*>(sk);
-  for (int pos = tid; pos < L; pos += SS_NT) sv[pos] = (V)val_of<K>(sk[pos]);
-  __syncthreads();
-  const SegStat r = segstat_body<V>(sv, L, seg_craw[sb], q1, crew, mode, scratch,
-                                    scratch + SS_NT, scratch + 2 * SS_NT);
+  lds_radix_pass<K, RK_ATOM, DigitNorm, KPT, false, true>(
+      kv, 0, dn, sk, wc, gs, wt, reinterpret_cast<const uint32_t*>(scratch + 2 * SS_NT));
+  lds_radix_pass<K, RK_ATOM, DigitNorm, KPT>(kv, 8, dn, sk, wc, gs, wt);
+  lds_radix_pass<K, RK_ATOM, DigitNorm, KPT, true>(kv, 16, dn, sk, wc, gs, wt);
+  if (check_fix<V, RN>(sv, L, a0, n, x, KeyNormV{dn}, NORM_MAX_DESC, flg, runs)) {
+    // uniform.  Values crowded into few keys (heavy tails, far outliers):
+    // left to k_seg_lds_slow, marked by start = SEG_REDO
+    if (tid == 0) {
+      SegStat r{};
+      r.start = SEG_REDO;
+      out[sb] = r;
+    }
+    return;
+  }
+  if (mode != SEGSTAT_UNIMCD) {
+    if (tid == 0) out[sb] = segstat_order<V>(sv, L, mode);
+    return;
+  }
+  const SegStat r = segstat_regs<V, RN>(sv, L, S, a0, a1, seg_craw[sb], q1, crew, scratch,
+                                         scratch + SS_NT, scratch + 2 * SS_NT);
   if (tid == 0) out[sb] = r;
+}
+
+// The segments k_seg_lds left (start = SEG_REDO), each by one block of a
+// small grid: LSD passes on the high 32 bits of the order key (resolution
+// relative to each value), checked and fixed up the same way; failing that,
+// the full-width sort with ballot ranking only.  Then the same estimator.
+template <typename K, int KPT>
+__global__ __launch_bounds__(SS_NT) void k_seg_lds_slow(const K* __restrict__ keys,
+                                                        const int64_t* __restrict__ seg_off,
+                                                        const int64_t* __restrict__ seg_len,
+                                                        const double* __restrict__ seg_craw,
+                                                        int seg_first, int nseg, double q1,
+                                                        double crew, int mode,
+                                                        SegStat* __restrict__ out) {
+  using V = typename std::conditional<sizeof(K) == 8, double, float>::type;
+  constexpr int CAP = SS_NT * KPT;
+  constexpr int RN = KPT + 1;
+  __shared__ K sk[CAP + RN + 1];
+  __shared__ double scratch[3 * SS_NT];
+  int* wc = reinterpret_cast<int*>(scratch);
+  int* runs = reinterpret_cast<int*>(scratch);
+  __shared__ int gs[4 * 256 + 8];
+  int* wt = gs + 4 * 256;
+  int* flg = gs + 4 * 256 + 4;
+  V* sv = reinterpret_cast<V*>(sk);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int sb = blockIdx.x; sb < nseg; sb += gridDim.x) {
+    if (out[sb].start != SEG_REDO) continue;   // uniform
+    const int sg = seg_first + sb;
+    const K* __restrict__ src = keys + seg_off[sg];
+    const int L = (int)seg_len[sg];
+    K kv[KPT];
+    auto load = [&]() {
+#pragma unroll
+      for (int i = 0; i < KPT; ++i) {
+        const int pos = w * KPT * 64 + i * 64 + lane;
+        kv[i] = pos < L ? src[pos] : ~(K)0;
+      }
+    };
+    const int S = ((L + SS_NT - 1) / SS_NT) | 1;
+    const int a0 = min(tid * S, L), a1 = min(a0 + S, L), n = a1 - a0;
+    __syncthreads();   // the previous segment is done with the shared arrays
+    if (tid < 3) flg[tid] = 0;
+    load();
+    DigitKey32 d32;
+    lds_radix_pass<K, RK_ATOM, DigitKey32, KPT>(kv, 0, d32, sk, wc, gs, wt);
+    lds_radix_pass<K, RK_ATOM, DigitKey32, KPT>(kv, 8, d32, sk, wc, gs, wt);
+    lds_radix_pass<K, RK_ATOM, DigitKey32, KPT>(kv, 16, d32, sk, wc, gs, wt);
+    lds_radix_pass<K, RK_PEEL, DigitKey32, KPT, true>(kv, 24, d32, sk, wc, gs, wt);
+    V x[RN];
+    if (check_fix<V, RN>(sv, L, a0, n, x, Key32{}, CAP, flg, runs)) {
+      __syncthreads();
+      load();
+      DigitFull df;
+#pragma unroll 1
+      for (int shift = 0; shift < 8 * (int)sizeof(K) - 8; shift += 8)
+        lds_radix_pass<K, RK_BALLOT, DigitFull, KPT>(kv, shift, df, sk, wc, gs, wt);
+      lds_radix_pass<K, RK_BALLOT, DigitFull, KPT, true>(kv, 8 * (int)sizeof(K) - 8, df, sk, wc,
+                                                         gs, wt);
+    }
+    SegStat r{};
+    if (mode != SEGSTAT_UNIMCD) {
+      if (tid == 0) r = segstat_order<V>(sv, L, mode);
+    } else {
+      r = segstat_regs<V, RN>(sv, L, S, a0, a1, seg_craw[sb], q1, crew, scratch, scratch + SS_NT,
+                              scratch + 2 * SS_NT);
+    }
+    if (tid == 0) out[sb] = r;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1193,6 +1618,10 @@ hipError_t sort_segments(SortPlan& P, hipStream_t s) {
 hipError_t launch_seg_lds(const SortPlan& P, const double* seg_craw, double q1, double crew,
                           int mode, SegStat* out, int64_t max_len, hipStream_t s) {
   if (P.nseg <= 0) return hipSuccess;
+  // k_seg_lds sorts and estimates every segment but those whose values
+  // crowd into few normalised keys, which k_seg_lds_slow then takes up
+  // (a small grid that skips the rest)
+  constexpr int SLOW_GRID = 256;
   // keys per thread: the smallest of 4, 6, ..., 16 that holds the longest
   // segment (the passes work on every slot, padding included: 9,765-row
   // blocks take 10,240 slots, not 12,288)
@@ -1202,7 +1631,10 @@ hipError_t launch_seg_lds(const SortPlan& P, const double* seg_craw, double q1, 
 #define SEG_LDS(K, KPT)                                                                        \
   hipLaunchKernelGGL((k_seg_lds<K, KPT>), dim3(P.nseg), dim3(SS_NT), 0, s,                     \
                      static_cast<const K*>(P.keys), P.seg_off, P.seg_len, seg_craw, P.seg_first, \
-                     q1, crew, mode, out)
+                     q1, crew, mode, out);                                                     \
+  hipLaunchKernelGGL((k_seg_lds_slow<K, KPT>), dim3(std::min(P.nseg, SLOW_GRID)), dim3(SS_NT), \
+                     0, s, static_cast<const K*>(P.keys), P.seg_off, P.seg_len, seg_craw,       \
+                     P.seg_first, P.nseg, q1, crew, mode, out)
 #define BY_KPT(K)                        \
   switch (kpt) {                         \
     case 4: SEG_LDS(K, 4); break;        \

@@ -59,6 +59,29 @@ __device__ inline double wave_sum(double x) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// a value that is the same in every lane, as a wave-uniform (scalar) value
+__device__ inline double uniform_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)b);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// lane l's value in every lane (l uniform over the wave)
+__device__ inline double lane_bcast_d(double v, int l) {
+  const int sl = __builtin_amdgcn_readfirstlane(l);
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, sl);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), sl);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ inline int64_t lane_bcast_l(int64_t v, int l) {
+  const int sl = __builtin_amdgcn_readfirstlane(l);
+  const int lo = __builtin_amdgcn_readlane((int)v, sl);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), sl);
+  return ((int64_t)hi << 32) | (int64_t)(unsigned)lo;
+}
+
 // (value, index) with the smallest value, ties to the smallest index; index
 // -1 marks "none".  The result is valid in every lane.
 __device__ inline bool argmin_takes(double b2, int64_t j2, double b, int64_t j) {
@@ -87,6 +110,26 @@ __device__ inline void wave_argmin(double& b, int64_t& j) {
   const int jlo = __builtin_amdgcn_readlane((int)j, 63);
   const int jhi = __builtin_amdgcn_readlane((int)(j >> 32), 63);
   j = ((int64_t)jhi << 32) | (int64_t)(unsigned)jlo;
+}
+
+// unsigned minimum / maximum over the wave, in every lane
+__device__ inline uint32_t wave_min_u32(uint32_t x) {
+  x = min(x, (uint32_t)dpp_i<0x111, 0xf>((int)x, -1));
+  x = min(x, (uint32_t)dpp_i<0x112, 0xf>((int)x, -1));
+  x = min(x, (uint32_t)dpp_i<0x114, 0xf>((int)x, -1));
+  x = min(x, (uint32_t)dpp_i<0x118, 0xf>((int)x, -1));
+  x = min(x, (uint32_t)dpp_i<0x142, 0xa>((int)x, -1));
+  x = min(x, (uint32_t)dpp_i<0x143, 0xc>((int)x, -1));
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+__device__ inline uint32_t wave_max_u32(uint32_t x) {
+  x = max(x, (uint32_t)dpp_i<0x111, 0xf>((int)x, 0));
+  x = max(x, (uint32_t)dpp_i<0x112, 0xf>((int)x, 0));
+  x = max(x, (uint32_t)dpp_i<0x114, 0xf>((int)x, 0));
+  x = max(x, (uint32_t)dpp_i<0x118, 0xf>((int)x, 0));
+  x = max(x, (uint32_t)dpp_i<0x142, 0xa>((int)x, 0));
+  x = max(x, (uint32_t)dpp_i<0x143, 0xc>((int)x, 0));
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
 // maximum over the wave, in every lane
