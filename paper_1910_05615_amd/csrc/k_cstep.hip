@@ -154,6 +154,25 @@ __global__ __launch_bounds__(SEL_NT) void k_select(const ItemDesc* __restrict__ 
 // Row order is slot-major, then wave, then lane, i.e. plain index order.
 constexpr int SEL_KR = 16;
 constexpr int SEL_WV = SEL_NT / 64;
+constexpr int SEL_NBB = 13;               // bins of the one-pass histogram: 2^13
+constexpr int SEL_NB = 1 << SEL_NBB;
+constexpr int SEL_CMAX = 512;             // keys ranked exactly in the threshold bin
+
+// unsigned 64-bit minimum / maximum over the wave, in every lane
+__device__ inline uint64_t wave_min_u64(uint64_t x) {
+#define RTD_MIN_STEP(C, R) { const uint64_t y = (uint64_t)dpp_l<C, R>((int64_t)x, -1); x = y < x ? y : x; }
+  RTD_MIN_STEP(0x111, 0xf) RTD_MIN_STEP(0x112, 0xf) RTD_MIN_STEP(0x114, 0xf)
+  RTD_MIN_STEP(0x118, 0xf) RTD_MIN_STEP(0x142, 0xa) RTD_MIN_STEP(0x143, 0xc)
+#undef RTD_MIN_STEP
+  return (uint64_t)lane_bcast_l((int64_t)x, 63);
+}
+__device__ inline uint64_t wave_max_u64(uint64_t x) {
+#define RTD_MAX_STEP(C, R) { const uint64_t y = (uint64_t)dpp_l<C, R>((int64_t)x, 0); x = y > x ? y : x; }
+  RTD_MAX_STEP(0x111, 0xf) RTD_MAX_STEP(0x112, 0xf) RTD_MAX_STEP(0x114, 0xf)
+  RTD_MAX_STEP(0x118, 0xf) RTD_MAX_STEP(0x142, 0xa) RTD_MAX_STEP(0x143, 0xc)
+#undef RTD_MAX_STEP
+  return (uint64_t)lane_bcast_l((int64_t)x, 63);
+}
 
 // Exclusive scan, in place, of n <= 256 ints laid out in order, by the first
 // four waves; returns the total to every thread.  wsum: 4 ints.
@@ -179,16 +198,45 @@ __device__ inline int scan256_excl(int* __restrict__ v, int n, int* __restrict__
   return tot;
 }
 
+// Two such scans at once: waves 0-3 scan v1, waves 4-7 scan v2; returns
+// both totals.  wsum: 8 ints.
+__device__ inline int2 scan256_excl2(int* __restrict__ v1, int* __restrict__ v2, int n,
+                                     int* __restrict__ wsum) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int* __restrict__ v = tid < 256 ? v1 : v2;
+  const int t = tid & 255;
+  int x = 0, own = 0;
+  if (tid < 512) {
+    own = t < n ? v[t] : 0;
+    x = wave_incl_sum(own);
+    if (lane == 63) wsum[w] = x;
+  }
+  __syncthreads();
+  const int wb = w & 4;
+  int off = 0, tot1 = 0, tot2 = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    tot1 += wsum[k];
+    tot2 += wsum[4 + k];
+    if (wb + k < w) off += wsum[wb + k];
+  }
+  if (tid < 512 && t < n) v[t] = off + x - own;
+  __syncthreads();
+  return make_int2(tot1, tot2);
+}
+
 __global__ __launch_bounds__(SEL_NT) void k_select_reg(const ItemDesc* __restrict__ items,
                                                        ItemArrays A, int first_item,
                                                        int cstep_mode, int reset_nactive) {
   if (reset_nactive && blockIdx.x == 0 && threadIdx.x == 0) *A.nactive = 0;
-  __shared__ unsigned hist[8192];
+  __shared__ __align__(16) unsigned hist[8192];
   __shared__ int wtot[SEL_WV];
   __shared__ int tab[3][SEL_KR * SEL_WV];   // eq, entering, leaving per (slot, wave)
-  __shared__ int wsum[4];
-  __shared__ int s_bin, s_cnt;
-  __shared__ long long s_below;
+  __shared__ int wsum[8];
+  __shared__ int s_bin, s_cnt, s_nc, s_all;
+  __shared__ long long s_below, s_rank;
+  __shared__ uint64_t s_prefix;
+  __shared__ uint64_t s_bound[2 * SEL_WV];
   const int it = first_item + blockIdx.x;
   if (A.status[it] != ACTIVE) return;
   const ItemDesc D = items[it];
@@ -201,31 +249,61 @@ __global__ __launch_bounds__(SEL_NT) void k_select_reg(const ItemDesc* __restric
   const uint64_t below = (1ull << lane) - 1ull;
 
   uint64_t key[SEL_KR];
+  uint32_t oldb = 0;   // the previous subset's membership of this thread's rows
 #pragma unroll
   for (int i = 0; i < SEL_KR; ++i) {
     const int r = i * SEL_NT + tid;
     key[i] = r < m ? key_of(d2[r]) : 0ull;
+    if (r < m && mask[r] != 0) oldb |= 1u << i;
   }
-  const int shifts[5] = {52, 39, 26, 13, 0};
-  const int bitsv[5] = {12, 13, 13, 13, 13};
-  uint64_t prefix = 0, pmask = 0;
+  const int it0 = A.iter[it];
+  uint64_t prefix = 0, pmask = ~0ull;
   int64_t rank = h;
   bool take_all = false;
-#pragma unroll
-  for (int ps = 0; ps < 5; ++ps) {
-    const int shift = shifts[ps], bits = bitsv[ps];
-    const int nbins = 1 << bits;
-    for (int b = tid; b < nbins; b += SEL_NT) hist[b] = 0u;
-    __syncthreads();
+  // One histogram of the keys over 8192 bins of the segment's key range
+  // (bin = (key - kmin) >> sh: monotone, and logarithmic in the value, so
+  // far outliers do not crowd the bulk into a few bins), then the keys of the
+  // bin that holds rank h, ranked among themselves exactly.
+  {
+    uint64_t kmn = ~0ull, kmx = 0ull;
 #pragma unroll
     for (int i = 0; i < SEL_KR; ++i) {
-      const int r = i * SEL_NT + tid;
-      if (r < m && (key[i] & pmask) == prefix)
-        atomicAdd(&hist[(key[i] >> shift) & (uint64_t)(nbins - 1)], 1u);
+      if (i * SEL_NT + tid < m) {
+        kmn = key[i] < kmn ? key[i] : kmn;
+        if (key[i] != ~0ull && key[i] > kmx) kmx = key[i];   // NaN keys: the last bin
+      }
     }
+    kmn = wave_min_u64(kmn);
+    kmx = wave_max_u64(kmx);
+    if (lane == 0) {
+      s_bound[w] = kmn;
+      s_bound[SEL_WV + w] = kmx;
+    }
+    for (int b = tid; b < SEL_NB; b += SEL_NT) hist[b] = 0u;
+    if (tid == 0) s_nc = 0;
     __syncthreads();
-    const int per = nbins / SEL_NT;
+    kmn = ~0ull;
+    kmx = 0ull;
+#pragma unroll
+    for (int q = 0; q < SEL_WV; ++q) {
+      kmn = s_bound[q] < kmn ? s_bound[q] : kmn;
+      kmx = s_bound[SEL_WV + q] > kmx ? s_bound[SEL_WV + q] : kmx;
+    }
+    const uint64_t span = kmx > kmn ? kmx - kmn : 0ull;
+    const int bl = span ? 64 - __clzll((long long)span) : 0;
+    const int sh = bl > SEL_NBB ? bl - SEL_NBB : 0;
+    auto bin_of = [&](uint64_t k) -> int {
+      if (k == ~0ull) return SEL_NB - 1;
+      const uint64_t b = (k - kmn) >> sh;
+      return b < (uint64_t)SEL_NB ? (int)b : SEL_NB - 1;
+    };
+#pragma unroll
+    for (int i = 0; i < SEL_KR; ++i)
+      if (i * SEL_NT + tid < m) atomicAdd(&hist[bin_of(key[i])], 1u);
+    __syncthreads();
+    constexpr int per = SEL_NB / SEL_NT;
     int loc = 0;
+#pragma unroll
     for (int b = 0; b < per; ++b) loc += (int)hist[tid * per + b];
     int tot;
     const int before = block_excl_scan<SEL_NT>(loc, wtot, tot);
@@ -238,12 +316,74 @@ __global__ __launch_bounds__(SEL_NT) void k_select_reg(const ItemDesc* __restric
       }
     }
     __syncthreads();
-    prefix |= (uint64_t)s_bin << shift;
-    pmask |= (uint64_t)(nbins - 1) << shift;
-    rank -= s_below;
-    const int cnt = s_cnt;
-    __syncthreads();
-    if ((int64_t)cnt == rank) { take_all = true; break; }
+    const int bstar = s_bin, cnt = s_cnt;
+    const int64_t k1 = rank - s_below;   // 1-based rank within the bin
+    if (cnt <= SEL_CMAX) {   // uniform
+      uint64_t* ck = reinterpret_cast<uint64_t*>(hist);   // the counts are read
+#pragma unroll
+      for (int i = 0; i < SEL_KR; ++i)
+        if (i * SEL_NT + tid < m && bin_of(key[i]) == bstar) ck[atomicAdd(&s_nc, 1)] = key[i];
+      __syncthreads();
+      if (tid < cnt) {
+        const uint64_t x = ck[tid];
+        int nless = 0, nleq = 0;
+        for (int j = 0; j < cnt; ++j) {
+          const uint64_t y = ck[j];
+          nless += y < x ? 1 : 0;
+          nleq += y <= x ? 1 : 0;
+        }
+        if (nless < k1 && k1 <= nleq) {   // x is the h-th smallest key (equal keys agree)
+          s_prefix = x;
+          s_rank = k1 - nless;
+          s_all = k1 == nleq ? 1 : 0;
+        }
+      }
+      __syncthreads();
+      prefix = s_prefix;
+      rank = s_rank;
+      take_all = s_all != 0;
+    } else {
+      // a bin crowded with equal or nearly equal keys: radix select on the
+      // float64 bit patterns, digits 12/13/13/13/13 bits from the top
+      __syncthreads();   // every thread has read s_bin / s_cnt
+      pmask = 0;
+      const int shifts[5] = {52, 39, 26, 13, 0};
+      const int bitsv[5] = {12, 13, 13, 13, 13};
+#pragma unroll
+      for (int ps = 0; ps < 5; ++ps) {
+        const int shift = shifts[ps], bits = bitsv[ps];
+        const int nbins = 1 << bits;
+        for (int b = tid; b < nbins; b += SEL_NT) hist[b] = 0u;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < SEL_KR; ++i) {
+          const int r = i * SEL_NT + tid;
+          if (r < m && (key[i] & pmask) == prefix)
+            atomicAdd(&hist[(key[i] >> shift) & (uint64_t)(nbins - 1)], 1u);
+        }
+        __syncthreads();
+        const int per = nbins / SEL_NT;
+        int loc = 0;
+        for (int b = 0; b < per; ++b) loc += (int)hist[tid * per + b];
+        int tot;
+        const int before = block_excl_scan<SEL_NT>(loc, wtot, tot);
+        if ((int64_t)before < rank && rank <= (int64_t)(before + loc)) {
+          int64_t run = before;
+          for (int b = 0; b < per; ++b) {
+            const int c = (int)hist[tid * per + b];
+            if (rank <= run + c) { s_bin = tid * per + b; s_cnt = c; s_below = run; break; }
+            run += c;
+          }
+        }
+        __syncthreads();
+        prefix |= (uint64_t)s_bin << shift;
+        pmask |= (uint64_t)(nbins - 1) << shift;
+        rank -= s_below;
+        const int cnt = s_cnt;
+        __syncthreads();
+        if ((int64_t)cnt == rank) { take_all = true; break; }
+      }
+    }
   }
 
   // membership; ties at the threshold key go to the lowest row indices
@@ -274,7 +414,6 @@ __global__ __launch_bounds__(SEL_NT) void k_select_reg(const ItemDesc* __restric
       if (eq && er < rank) selb |= 1u << i;
     }
   }
-  const int it0 = A.iter[it];
   const bool first = (it0 == 0);
   uint32_t entb = 0, lftb = 0;
 #pragma unroll
@@ -282,7 +421,7 @@ __global__ __launch_bounds__(SEL_NT) void k_select_reg(const ItemDesc* __restric
     const int r = i * SEL_NT + tid;
     const bool valid = r < m;
     const bool sel = (selb >> i) & 1u;
-    const bool old = valid && mask[r] != 0;
+    const bool old = (oldb >> i) & 1u;
     const bool ent = sel && !old, lft = valid && !sel && old;
     if (ent) entb |= 1u << i;
     if (lft) lftb |= 1u << i;
@@ -294,8 +433,8 @@ __global__ __launch_bounds__(SEL_NT) void k_select_reg(const ItemDesc* __restric
     if (valid) mask[r] = sel ? 1 : 0;
   }
   __syncthreads();
-  const int nin = scan256_excl(tab[1], SEL_KR * SEL_WV, wsum);
-  const int nout = scan256_excl(tab[2], SEL_KR * SEL_WV, wsum);
+  const int2 nio = scan256_excl2(tab[1], tab[2], SEL_KR * SEL_WV, wsum);
+  const int nin = nio.x;
   if (!first) {
     const int half = m / 2;
 #pragma unroll
@@ -464,6 +603,14 @@ __global__ __launch_bounds__(64) void k_finalize(const ItemDesc* __restrict__ it
     }
     return;
   }
+  // rows of L, then rows of X^T = (L^{-1})^T (lane j's column of L^{-1}),
+  // read by every lane with broadcast loads; 1 / L_kk
+  constexpr int LD = (P + 1) & ~1;   // even: 16-byte aligned rows
+  __shared__ __align__(16) double Ls[P * LD];
+  __shared__ __align__(16) double XT[P * LD];
+  __shared__ double rdg[P];
+  const double isc = 1.0 / sc;
+  const double ih1 = 1.0 / (h - 1.0);
   double a[P];
   if (!from_start) {
     const int full = A.full[it];
@@ -481,11 +628,11 @@ __global__ __launch_bounds__(64) void k_finalize(const ItemDesc* __restrict__ it
     }
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-      const double dmj = lane_bcast(dm, j), scj = lane_bcast(sc, j);
+      const double dmj = lane_bcast(dm, j), iscj = lane_bcast(isc, j);
       if (in && j < p) {
         const double v = a[j] - h * (dm * dmj);
         lam[lane * PMAX + j] = v;
-        a[j] = v / (sc * scj) / (h - 1.0);
+        a[j] = v * (isc * iscj) * ih1;
       } else {
         a[j] = j == lane ? 1.0 : 0.0;
       }
@@ -493,7 +640,7 @@ __global__ __launch_bounds__(64) void k_finalize(const ItemDesc* __restrict__ it
     if (in) {
       const double mnew = mux[lane] + dm;
       mux[lane] = mnew;
-      muz[lane] = (mnew - D.loc[lane]) / sc;
+      muz[lane] = (mnew - D.loc[lane]) * isc;
     }
   } else {
 #pragma unroll
@@ -512,67 +659,99 @@ __global__ __launch_bounds__(64) void k_finalize(const ItemDesc* __restrict__ it
         n1 += fabs(a[j]);
       }
   }
-n1 = wave_max(n1);
-  // Cholesky: column k of L from row k (lane k) and each lane's own row
-  double diag = 1.0;   // L[lane][lane]
+  n1 = wave_max(n1);
+  // Cholesky, column by column: L_ik = (S_ik - sum_{j<k} L_ij L_kj) / L_kk,
+  // lane i holding row i; row k of L comes from LDS (its entries j < k were
+  // stored at the steps j); two partial sums shorten the chain
+  double diag = 1.0, rdiag = 1.0;   // L[lane][lane], its reciprocal
 #pragma unroll
   for (int k = 0; k < P; ++k) {
-    double sk = a[k];
+    const double* __restrict__ Lk = Ls + k * LD;
+    double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-    for (int j = 0; j < k; ++j) sk = fma(-a[j], lane_bcast(a[j], k), sk);
+    for (int j = 0; j + 1 < k; j += 2) {
+      const double2 l2 = *reinterpret_cast<const double2*>(Lk + j);
+      s0 = fma(a[j], l2.x, s0);
+      s1 = fma(a[j + 1], l2.y, s1);
+    }
+    if (k & 1) s0 = fma(a[k - 1], Lk[k - 1], s0);
+    const double sk = a[k] - (s0 + s1);
     const double d = lane_bcast(sk, k);
     if (!(d > 0.0) || !(d < 1e300)) {    // uniform
       if (lane == 0) A.status[it] = from_start ? ST_DROP_FIRST : ST_SINGULAR;
       return;
     }
     const double lkk = sqrt(d);
-    if (lane == k) diag = lkk;
-    a[k] = lane == k ? lkk : (lane > k ? sk / lkk : 0.0);
+    const double r = 1.0 / lkk;
+    if (lane == k) {
+      diag = lkk;
+      rdiag = r;
+      rdg[k] = r;
+    }
+    a[k] = lane == k ? lkk : (lane > k ? sk * r : 0.0);
+    if (lane >= k && lane < P) Ls[lane * LD + k] = a[k];
+    __syncthreads();   // one wave: orders the row stores before the next reads
   }
-  // inverse factor X = L^{-1}: column `lane`, rows in order
+  // inverse factor X = L^{-1}: column `lane`, rows in order, x_i =
+  // (delta_i - sum_{k<i} L_ik x_k) / L_ii with row i of L from LDS
   double x[P];
 #pragma unroll
   for (int i = 0; i < P; ++i) {
-    double si = lane == i ? 1.0 : 0.0;
+    const double* __restrict__ Li = Ls + i * LD;
+    double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-    for (int k = 0; k < i; ++k) si = fma(-lane_bcast(a[k], i), x[k], si);
-    x[i] = si / lane_bcast(diag, i);
+    for (int k = 0; k + 1 < i; k += 2) {
+      const double2 l2 = *reinterpret_cast<const double2*>(Li + k);
+      s0 = fma(l2.x, x[k], s0);
+      s1 = fma(l2.y, x[k + 1], s1);
+    }
+    if (i & 1) s0 = fma(Li[i - 1], x[i - 1], s0);
+    x[i] = ((lane == i ? 1.0 : 0.0) - (s0 + s1)) * rdg[i];
   }
-  // 1-norm of Sigma^{-1} = X^T X: column `lane`, entries b in order.  The
-  // single-swap mode keeps Lam^{-1} = D^{-1} Sigma^{-1} D^{-1} / (h-1); the
-  // distance switch takes the packed inverse P~ (data units) as the factor.
+  if (lane < P) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) XT[lane * LD + k] = x[k];
+  }
+  __syncthreads();
+  // 1-norm of Sigma^{-1} = X^T X: column `lane`, entry b = sum_k x_k X_kb
+  // with row b of X^T from LDS.  The single-swap mode keeps Lam^{-1} =
+  // D^{-1} Sigma^{-1} D^{-1} / (h-1); the distance switch takes the packed
+  // inverse P~ (data units) as the factor.
   const bool keep_inv = smw_mode || dist_form;
   double n2 = 0.0;
 #pragma unroll
   for (int b = 0; b < P; ++b) {
     if (b < p) {
-      double v = 0.0;
+      const double* __restrict__ Xb = XT + b * LD;
+      double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-      for (int k = b; k < P; ++k) v = fma(x[k], lane_bcast(x[k], b), v);
+      for (int k = 0; k + 1 < P; k += 2) {
+        const double2 x2 = *reinterpret_cast<const double2*>(Xb + k);
+        s0 = fma(x[k], x2.x, s0);
+        s1 = fma(x[k + 1], x2.y, s1);
+      }
+      if (P & 1) s0 = fma(x[P - 1], Xb[P - 1], s0);
+      const double v = s0 + s1;
       n2 += fabs(v);
       if (keep_inv) {
-        const double scb = lane_bcast(sc, b);
-        const double vx = v / (sc * scb);             // (Sigma^{-1} in data units)_{lane, b}
-        if (in && smw_mode) sinv[lane * PMAX + b] = vx / (h - 1.0);
+        const double vx = v * (isc * lane_bcast(isc, b));   // (Sigma^{-1} in data units)_{lane, b}
+        if (in && smw_mode) sinv[lane * PMAX + b] = vx * ih1;
         if (in && dist_form && b <= lane) mt[lane * PMAX + b] = (b < lane ? 2.0 : 1.0) * vx;
       }
     }
   }
   if (!in) n2 = 0.0;
-n2 = wave_max(n2);
+  n2 = wave_max(n2);
   double* __restrict__ linv = A.linv + (size_t)it * MSTRIDE;
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     if (i < p) {
-      if (!dist_form) mt[i * PMAX + lane] = lane <= i ? x[i] / sc : 0.0;
+      if (!dist_form) mt[i * PMAX + lane] = lane <= i ? x[i] * isc : 0.0;
       if (in) linv[i * PMAX + lane] = x[i];
     }
   }
-  const double lg = log(diag);
-  double ld = 0.0;
-#pragma unroll
-  for (int j = 0; j < P; ++j)
-    if (j < p) ld += lane_bcast(lg, j);
+  (void)rdiag;
+  const double ld = wave_sum(in ? log(diag) : 0.0);
   if (lane == 0) {
     A.form[it] = dist_form ? 1 : 0;
     A.logdet[it] = 2.0 * ld;

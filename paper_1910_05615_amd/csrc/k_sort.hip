@@ -1190,8 +1190,18 @@ __global__ __launch_bounds__(SS_NT) void k_seg_lds_slow(const K* __restrict__ ke
   int* flg = gs + 4 * 256 + 4;
   V* sv = reinterpret_cast<V*>(sk);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int sb = blockIdx.x; sb < nseg; sb += gridDim.x) {
-    if (out[sb].start != SEG_REDO) continue;   // uniform
+  // this block's segments sb = blockIdx.x + t gridDim.x (t < SS_NT: the
+  // grid is sized for that), all marks read at once into a bit set
+  __shared__ uint32_t redo_bits[SS_NT / 32];
+  if (tid < SS_NT / 32) redo_bits[tid] = 0u;
+  __syncthreads();
+  if (blockIdx.x + (int64_t)tid * gridDim.x < nseg &&
+      out[blockIdx.x + tid * gridDim.x].start == SEG_REDO)
+    atomicOr(&redo_bits[tid >> 5], 1u << (tid & 31));
+  __syncthreads();
+  for (int wd = 0; wd < SS_NT / 32; ++wd)
+  for (uint32_t bits = redo_bits[wd]; bits; bits &= bits - 1u) {   // uniform
+    const int sb = blockIdx.x + (wd * 32 + __ffs(bits) - 1) * gridDim.x;
     const int sg = seg_first + sb;
     const K* __restrict__ src = keys + seg_off[sg];
     const int L = (int)seg_len[sg];
@@ -1622,6 +1632,8 @@ hipError_t launch_seg_lds(const SortPlan& P, const double* seg_craw, double q1, 
   // crowd into few normalised keys, which k_seg_lds_slow then takes up
   // (a small grid that skips the rest)
   constexpr int SLOW_GRID = 256;
+  // at most SS_NT segments per block of the slow kernel
+  const int slow_grid = std::min(P.nseg, std::max(SLOW_GRID, (P.nseg + SS_NT - 1) / SS_NT));
   // keys per thread: the smallest of 4, 6, ..., 16 that holds the longest
   // segment (the passes work on every slot, padding included: 9,765-row
   // blocks take 10,240 slots, not 12,288)
@@ -1632,7 +1644,7 @@ hipError_t launch_seg_lds(const SortPlan& P, const double* seg_craw, double q1, 
   hipLaunchKernelGGL((k_seg_lds<K, KPT>), dim3(P.nseg), dim3(SS_NT), 0, s,                     \
                      static_cast<const K*>(P.keys), P.seg_off, P.seg_len, seg_craw, P.seg_first, \
                      q1, crew, mode, out);                                                     \
-  hipLaunchKernelGGL((k_seg_lds_slow<K, KPT>), dim3(std::min(P.nseg, SLOW_GRID)), dim3(SS_NT), \
+  hipLaunchKernelGGL((k_seg_lds_slow<K, KPT>), dim3(slow_grid), dim3(SS_NT),                  \
                      0, s, static_cast<const K*>(P.keys), P.seg_off, P.seg_len, seg_craw,       \
                      P.seg_first, P.nseg, q1, crew, mode, out)
 #define BY_KPT(K)                        \

@@ -74,7 +74,8 @@ def test_select_bit_exact(m, h):
     assert np.array_equal(got_mask.cpu().numpy(), mk)
 
 
-@pytest.mark.parametrize("case", ["ties", "all_equal", "zeros", "two_values", "nan", "tiny"])
+@pytest.mark.parametrize("case", ["ties", "all_equal", "zeros", "two_values", "nan", "tiny",
+                                  "heavy_tail", "crowded_threshold", "equal_block_at_threshold"])
 def test_select_ties_and_degenerate(case):
     P = _P()
     rng = np.random.default_rng(3)
@@ -90,6 +91,16 @@ def test_select_ties_and_degenerate(case):
     elif case == "nan":
         d2 = rng.random(m)
         d2[rng.choice(m, 50, replace=False)] = np.nan
+    elif case == "heavy_tail":      # keys over many binades
+        d2 = np.abs(rng.standard_cauchy(m)) ** 3
+    elif case == "crowded_threshold":   # ~400 distinct keys within 1e-12 of the h-th
+        d2 = rng.random(m) * 10.0
+        near = rng.choice(m, 400, replace=False)
+        d2[near] = 5.0 + rng.random(400) * 1e-12
+        d2[d2 < 5.0] = d2[d2 < 5.0] * 0.5   # the h-th smallest lands among them
+    elif case == "equal_block_at_threshold":   # 300 equal keys across rank h
+        d2 = rng.random(m) * 10.0
+        d2[rng.choice(m, 300, replace=False)] = float(np.sort(d2)[h])
     else:
         d2 = rng.random(m) * 1e-300
     got_idx, _ = P.select(torch.from_numpy(d2).to(_dev()), h)
