@@ -262,6 +262,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-p40-distance", action="store_true")
     ap.add_argument("--workload", default="chunked_p20",
                     choices=["chunked_p20", "batched_uneven", "large_p40"],
@@ -349,6 +350,22 @@ def main() -> int:
                  "identical_to_eager": bool(torch.equal(F.hsubset, Fg.hsubset) and
                                             torch.equal(F.outlier, Fg.outlier) and
                                             torch.equal(F.sigma, Fg.sigma))}
+    # the autotuned C-step loop (opts tune): the first warm-up fit times the
+    # candidate distance tilings and keeps the fastest; the timed fits take it
+    tuned = None
+    if not args.no_tune:
+        def same(Fa, Fb):
+            return bool(torch.equal(F.hsubset, Fa.hsubset) and torch.equal(F.outlier, Fa.outlier)
+                        and torch.equal(F.sigma, Fa.sigma) and torch.equal(F.dist, Fa.dist))
+        Ft, t_t, _ = timed(graph=False, tune=True)
+        tuned = {"value": N / t_t, "unit": "rows/s", "ms_per_step": t_t * 1e3,
+                 "identical_to_untuned": same(Ft, F),
+                 "plan": dict(zip(("p_bucket", "rows_per_distance_tile", "distance_passes",
+                                   "csteps_of_last_fit"), R.tuned_plans()[-1]))}
+        if not args.no_graph:
+            Ftg, t_tg, _ = timed(graph=True, tune=True)
+            tuned["graph"] = {"value": N / t_tg, "unit": "rows/s", "ms_per_step": t_tg * 1e3,
+                              "identical_to_untuned": same(Ftg, F)}
     reruns = R.sort_reruns() - reruns0
 
     # ---------------------------------------------------------------- plain fit
@@ -386,6 +403,7 @@ def main() -> int:
                    "n": N, "p": P, "blocks": q, "m": m, "h": h, "input_dtype": "f32",
                    "launch": "batched"},
         "batched_graph": graph,
+        "batched_tuned": tuned,
         "plain": plain,
         "roofline": roofline,
         "kernels": kernels,

@@ -97,6 +97,15 @@ typedef struct rtdetmcd_opts {
   int32_t graph;            /* 1: replay the C-step rounds from a captured hipGraph */
   int32_t rounds_per_sync;  /* C-steps enqueued between host checks of convergence (default 4) */
   int32_t distance;         /* RTDETMCD_DIST_* (default CHOLESKY) */
+  int32_t tune;             /* 1: autotune the batched C-step loop (default 0): on the first
+                             * fit of a shape (p bucket, item count, rows, longest block,
+                             * input type) the library times the distance pass of the
+                             * first C-step under each candidate tiling (rows per tile
+                             * 256..4096, one pass for both starts of a block or one per
+                             * start) and keeps the fastest; later fits of that shape take
+                             * the kept tiling, and their first convergence check comes
+                             * after as many C-steps as the previous fit took (at least
+                             * rounds_per_sync).  Results do not depend on it. */
 } rtdetmcd_opts;
 
 /* Output buffers of a fit.  Every field is a caller-allocated device buffer or
@@ -137,6 +146,15 @@ rtdetmcd_status rtdetmcd_destroy(rtdetmcd_handle h);
 rtdetmcd_status rtdetmcd_set_stream(rtdetmcd_handle h, void* hip_stream);
 /* Message of the last error on this handle (valid until the next call). */
 const char* rtdetmcd_last_error(rtdetmcd_handle h);
+
+/* The autotuned plans a handle holds (opts.tune), most recent last: up to
+ * `cap` rows of 4 int64 (p bucket, rows per distance tile, distance passes
+ * per block pair (1: one pass for both starts, 2: one per start), C-steps of
+ * the last fit) into `out` (host memory, may be NULL when cap = 0).  *count
+ * receives the number of plans held.  Errors: RTDETMCD_EINVAL for a null
+ * handle or count. */
+rtdetmcd_status rtdetmcd_tuned_plans(rtdetmcd_handle h, int64_t* out, int32_t cap,
+                                     int32_t* count);
 /* Paper defaults (Sec. 2.1, 3.3, 3.4, 5). */
 void rtdetmcd_default_opts(rtdetmcd_opts* o);
 

@@ -6,4 +6,4 @@ The compute path is the in-tree shared library ``librtdetmcd.so`` (C ABI in
 from .api import (Fit, RobustMCD, RTDetMCDError, backward, chi2_cdf, chi2_quantile,  # noqa: F401
                   consistency, cstep, distances, distances_into, fit, fit_batched, make_opts, plan, score,
                   random_partition, score_into, select, sort_reruns, START_WARM, profile,
-                  profile_read)
+                  profile_read, tuned_plans)

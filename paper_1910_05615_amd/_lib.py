@@ -16,7 +16,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESINGUL
 # exported symbols, in the header's order
 SYMBOLS = [
     "rtdetmcd_create", "rtdetmcd_destroy", "rtdetmcd_set_stream", "rtdetmcd_last_error",
-    "rtdetmcd_default_opts", "rtdetmcd_plan", "rtdetmcd_fit", "rtdetmcd_fit_batched",
+    "rtdetmcd_tuned_plans", "rtdetmcd_default_opts", "rtdetmcd_plan", "rtdetmcd_fit", "rtdetmcd_fit_batched",
     "rtdetmcd_chi2_quantile", "rtdetmcd_chi2_cdf", "rtdetmcd_consistency",
     "rtdetmcd_distances", "rtdetmcd_score", "rtdetmcd_select", "rtdetmcd_cstep",
     "rtdetmcd_cstep_noalloc", "rtdetmcd_profile", "rtdetmcd_profile_read",
@@ -29,7 +29,7 @@ class Opts(C.Structure):
                 ("cstep_mode", c_i32), ("max_csteps", c_i32), ("kappa_max", c_f64),
                 ("cutoff_q", c_f64), ("pool_mode", c_i32), ("rew_consistency", c_i32),
                 ("omega", c_i32), ("launch", c_i32), ("graph", c_i32),
-                ("rounds_per_sync", c_i32), ("distance", c_i32)]
+                ("rounds_per_sync", c_i32), ("distance", c_i32), ("tune", c_i32)]
 
 
 class Out(C.Structure):
@@ -62,6 +62,7 @@ def load() -> C.CDLL:
         "rtdetmcd_destroy": (c_i32, [c_vp]),
         "rtdetmcd_set_stream": (c_i32, [c_vp, c_vp]),
         "rtdetmcd_last_error": (C.c_char_p, [c_vp]),
+        "rtdetmcd_tuned_plans": (c_i32, [c_vp, P(c_i64), c_i32, P(c_i32)]),
         "rtdetmcd_default_opts": (None, [P(Opts)]),
         "rtdetmcd_plan": (c_i32, [c_i64, c_i32, c_i64, c_i32, P(Opts), P(c_i32), P(c_i64), P(c_i64)]),
         "rtdetmcd_fit": (c_i32, [c_vp, c_vp, c_i32, c_i64, c_i32, c_i64, c_i64, c_i32, P(Opts), P(Out)]),

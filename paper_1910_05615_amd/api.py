@@ -74,7 +74,7 @@ def make_opts(alpha: float = 0.75, standardize: str = "unimcd", cstep_mode: str 
               max_csteps: int = 100, kappa_max: float = 1000.0, cutoff_q: float = 0.975,
               pool: str = "printed", rew_consistency: bool = False, omega: int = 4096,
               launch: str = "batched", graph: bool = False, rounds_per_sync: int = 4,
-              distance: str = "cholesky") -> _lib.Opts:
+              distance: str = "cholesky", tune: bool = False) -> _lib.Opts:
     lib = _lib.load()
     o = _lib.Opts()
     lib.rtdetmcd_default_opts(C.byref(o))
@@ -91,6 +91,7 @@ def make_opts(alpha: float = 0.75, standardize: str = "unimcd", cstep_mode: str 
     o.graph = int(graph)
     o.rounds_per_sync = rounds_per_sync
     o.distance = DIST[distance]
+    o.tune = int(tune)
     return o
 
 
@@ -217,6 +218,20 @@ def profile_read(device=None) -> dict:
         out[name] = {"ms": ms.value, "launches": n.value, "bytes": b.value,
                      "flops_useful": fu.value, "flops_exec": fe.value}
     return out
+
+
+def tuned_plans(device=None) -> list:
+    """The autotuned C-step plans of this device's handle (opts tune=True),
+    most recent last: [(p bucket, rows per distance tile, distance passes per
+    start pair, C-steps of the last fit)] (rtdetmcd_tuned_plans)."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    lib, h = _handle(dev)
+    cnt = C.c_int32()
+    _check(lib, h, lib.rtdetmcd_tuned_plans(h, None, 0, C.byref(cnt)), "rtdetmcd_tuned_plans")
+    buf = (C.c_int64 * (4 * max(1, cnt.value)))()
+    _check(lib, h, lib.rtdetmcd_tuned_plans(h, buf, cnt.value, C.byref(cnt)),
+           "rtdetmcd_tuned_plans")
+    return [tuple(int(buf[4 * k + j]) for j in range(4)) for k in range(cnt.value)]
 
 
 def sort_reruns(device=None) -> int:

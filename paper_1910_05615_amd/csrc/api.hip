@@ -207,6 +207,90 @@ rtdetmcd_status graph_for(rtdetmcd_ctx* ctx, const std::vector<int64_t>& key, in
   return RTDETMCD_OK;
 }
 
+// Distance tiling of a batched C-step loop under opts.tune: the kept plan
+// of this shape, or a new one measured on the first C-step's distance pass
+// (every candidate timed twice with HIP events on the handle's stream, the
+// faster kept).  The distance pass only writes the distances, which the
+// loop's own first pass writes again, so the measurement leaves no trace.
+// *idx: the plan's index in ctx->tune.
+rtdetmcd_status tuned_dist_plan(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int bucket,
+                                int dtype, int first, int n, bool dense, bool pairs_ok,
+                                const int32_t* form, int* idx) {
+  int64_t rows = 0, max_m = 0;
+  for (int i = first; i < first + n; ++i) {
+    rows += S.items[i].m;
+    max_m = std::max(max_m, S.items[i].m);
+  }
+  const std::vector<int64_t> key = {bucket, dtype, n, rows, max_m, dense ? 1 : 0,
+                                    pairs_ok ? 1 : 0, form ? 1 : 0};
+  for (size_t k = 0; k < ctx->tune.size(); ++k)
+    if (ctx->tune[k].key == key) {
+      *idx = (int)k;
+      return RTDETMCD_OK;
+    }
+  auto table = [&](int T, int mode) {
+    std::vector<Tile> t;
+    for (int i = first; i < first + n; ++i) {
+      if (mode == 2 && S.pt_first[i] < 0) continue;   // one tile list per start pair
+      const int nd = (int)((S.items[i].m + T - 1) / T);
+      for (int k = 0; k < nd; ++k) t.push_back({i, k});
+    }
+    return t;
+  };
+  const int rows_c[] = {256, 512, 1024, 2048, 4096};
+  Tile* tmp = nullptr;
+  RTD_HIP(hipMalloc(&tmp, table(256, 1).size() * sizeof(Tile)));
+  hipEvent_t e[2] = {nullptr, nullptr};
+  RTD_HIP(hipEventCreate(&e[0]));
+  RTD_HIP(hipEventCreate(&e[1]));
+  int best_T = DIST_TILE, best_mode = 1;
+  float best = 1e30f;
+  hipError_t err = hipSuccess;
+  for (int mode = 1; mode <= (pairs_ok ? 2 : 1) && err == hipSuccess; ++mode)
+    for (const int T : rows_c) {
+      const std::vector<Tile> t = table(T, mode);
+      err = hipMemcpy(tmp, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice);
+      for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
+        err = hipEventRecord(e[0], ctx->stream);
+        if (err == hipSuccess)
+          err = launch_dist(bucket, dtype, dense, mode, D.items, tmp, (int)t.size(), T, D.A.mtri,
+                            D.A.mux, D.A.status, form, D.A.d2, ctx->stream);
+        if (err == hipSuccess) err = hipEventRecord(e[1], ctx->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(e[1]);
+        float ms = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e[0], e[1]);
+        if (err == hipSuccess && ms < best) {
+          best = ms;
+          best_T = T;
+          best_mode = mode;
+        }
+      }
+      if (err != hipSuccess) break;
+    }
+  (void)hipEventDestroy(e[0]);
+  (void)hipEventDestroy(e[1]);
+  (void)hipFree(tmp);
+  RTD_HIP(err);
+  rtdetmcd_ctx::TunePlan tp;
+  tp.key = key;
+  tp.bucket = bucket;
+  tp.tile_rows = best_T;
+  tp.mode = best_mode;
+  const std::vector<Tile> t = table(best_T, best_mode);
+  tp.ntiles = (int)t.size();
+  RTD_HIP(hipMalloc(&tp.tiles, t.size() * sizeof(Tile)));
+  RTD_HIP(hipMemcpy(tp.tiles, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice));
+  constexpr size_t kMaxPlans = 64;
+  if (ctx->tune.size() >= kMaxPlans) {   // the oldest plan goes (its graphs with it)
+    drop_graphs(ctx);
+    (void)hipFree(ctx->tune.front().tiles);
+    ctx->tune.erase(ctx->tune.begin());
+  }
+  ctx->tune.push_back(tp);
+  *idx = (int)ctx->tune.size() - 1;
+  return RTDETMCD_OK;
+}
+
 rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int bucket,
                            int dtype, int first, int n, const rtdetmcd_opts& o,
                            int32_t* pin_flag) {
@@ -229,16 +313,28 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
     const bool dense = S.rows_dense(first, first + n, bucket);
     RTD_HIP(launch_finalize(bucket, D.items, D.A, first, n, 1, maxs, o.kappa_max, o.cstep_mode,
                             o.distance, st));
-    const int R = std::max(1, o.rounds_per_sync);
+    int R = std::max(1, o.rounds_per_sync);
     // items may hold the explicit-inverse form only with the distance switch
     // or the single-swap mode
     const int32_t* form =
         (o.distance || o.cstep_mode == RTDETMCD_CSTEP_SMW) ? D.A.form : nullptr;
+    // distance tiling: the plan's tables, or the tuned ones
+    const Tile* dtab = dtl + dt0;
+    int dntab = dtn, dtile = DIST_TILE, dmode = pairs ? 2 : 1, tix = -1;
+    if (o.tune) {
+      RTD_TRY(tuned_dist_plan(ctx, S, D, bucket, dtype, first, n, dense, pairs, form, &tix));
+      const rtdetmcd_ctx::TunePlan& tp = ctx->tune[tix];
+      dtab = tp.tiles;
+      dntab = tp.ntiles;
+      dtile = tp.tile_rows;
+      dmode = tp.mode;
+      R = std::max(R, tp.iters);   // the first check after the previous fit's C-step count
+    }
     // one C-step of every active item
     // one C-step of every active item; the selection zeroes the active count
     auto step = [&](hipStream_t s) -> rtdetmcd_status {
-      RTD_HIP(launch_dist(bucket, dtype, dense, pairs ? 2 : 1, D.items, dtl + dt0, dtn, DIST_TILE,
-                          D.A.mtri, D.A.mux, D.A.status, form, D.A.d2, s));
+      RTD_HIP(launch_dist(bucket, dtype, dense, dmode, D.items, dtab, dntab, dtile, D.A.mtri,
+                          D.A.mux, D.A.status, form, D.A.d2, s));
       RTD_HIP(launch_select(D.items, D.A, first, n, max_m, o.cstep_mode, s, 1));
       RTD_HIP(launch_sscp(bucket, dtype, SSCP_CSTEP, D.items, D.A, D.stiles + st0, stn,
                           SSCP_TILE, nullptr, nullptr, s));
@@ -265,8 +361,8 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
       }
       {
         ProfMark pm(ctx, RTDETMCD_PROF_CSTEP_DIST, s, byt_d, fl_d, fl_d);
-        RTD_HIP(launch_dist(bucket, dtype, dense, pairs ? 2 : 1, D.items, dtl + dt0, dtn,
-                            DIST_TILE, D.A.mtri, D.A.mux, D.A.status, form, D.A.d2, s));
+        RTD_HIP(launch_dist(bucket, dtype, dense, dmode, D.items, dtab, dntab, dtile, D.A.mtri,
+                            D.A.mux, D.A.status, form, D.A.d2, s));
         pm.end(s);
       }
       {
@@ -310,7 +406,7 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
       // the item count and the total row count of the set), the grid sizes
       // and the options
       const ItemArrays& A = D.A;
-      const void* ptrs[] = {ctx->ws,   D.items,  dtl,      D.stiles, A.status, A.iter,
+      const void* ptrs[] = {ctx->ws,   D.items,  dtab,     D.stiles, A.status, A.iter,
                             A.kswap,   A.full,   A.logdet, A.mux,    A.lamx,   A.muz,
                             A.sigz,    A.linv,   A.mtri,   A.d2,     A.mask,   A.swap,
                             A.part,    A.nactive, A.form,  A.sinv};
@@ -318,8 +414,8 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
       for (const void* q : ptrs) key.push_back((int64_t)(uintptr_t)q);
       int64_t kbits;
       std::memcpy(&kbits, &o.kappa_max, 8);
-      const int64_t scal[] = {bucket, dtype, first, n, (pairs ? 2 : 1) + (dense ? 4 : 0),
-                              dt0, dtn, st0, stn, max_nt, max_m, (int64_t)S.items.size(),
+      const int64_t scal[] = {bucket, dtype, first, n, dmode + (dense ? 4 : 0),
+                              dntab, dtile, st0, stn, max_nt, max_m, (int64_t)S.items.size(),
                               S.rows, o.cstep_mode, maxs, R, kbits, o.distance};
       key.insert(key.end(), std::begin(scal), std::end(scal));
       hipGraphExec_t ge = nullptr;
@@ -335,7 +431,10 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
       }
       RTD_HIP(hipEventRecord(ctx->gev[1], ctx->gstream));
       RTD_HIP(hipStreamWaitEvent(st, ctx->gev[1], 0));
-      if (done) return RTDETMCD_OK;
+      if (done) {
+        if (tix >= 0) ctx->tune[tix].iters = t + R - 1;
+        return RTDETMCD_OK;
+      }
     }
     for (; t <= maxs; ++t) {
       RTD_TRY(step(st));
@@ -345,6 +444,7 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
         if (*pin_flag == 0) break;
       }
     }
+    if (tix >= 0) ctx->tune[tix].iters = std::min(t, maxs);
     return RTDETMCD_OK;
   }
   // plain: one item at a time, host-driven, one host check per step
@@ -387,7 +487,8 @@ rtdetmcd_status check_opts(rtdetmcd_ctx* ctx, const rtdetmcd_opts* in, rtdetmcd_
   if (!(o.alpha > 0.5 && o.alpha <= 1.0) || o.max_csteps < 1 || !(o.kappa_max > 1.0) ||
       !(o.cutoff_q > 0.0 && o.cutoff_q < 1.0) || o.omega < 1 || o.standardize < 0 ||
       o.standardize > 1 || o.cstep_mode < 0 || o.cstep_mode > 3 || o.pool_mode < 0 ||
-      o.pool_mode > 1 || o.launch < 0 || o.launch > 1 || o.distance < 0 || o.distance > 1) {
+      o.pool_mode > 1 || o.launch < 0 || o.launch > 1 || o.distance < 0 || o.distance > 1 ||
+      o.tune < 0 || o.tune > 1) {
     ctx->err = "invalid option value";
     return RTDETMCD_EINVAL;
   }
@@ -482,6 +583,7 @@ void rtdetmcd_default_opts(rtdetmcd_opts* o) {
   o->graph = 0;
   o->rounds_per_sync = 4;
   o->distance = RTDETMCD_DIST_CHOLESKY;
+  o->tune = 0;
 }
 
 rtdetmcd_status rtdetmcd_create(rtdetmcd_handle* out, int32_t device, void* hip_stream) {
@@ -522,7 +624,22 @@ rtdetmcd_status rtdetmcd_destroy(rtdetmcd_handle ctx) {
   if (ctx->flag) (void)hipHostFree(ctx->flag);
   if (ctx->stage) (void)hipFree(ctx->stage);
   for (hipEvent_t e : ctx->prof_events) (void)hipEventDestroy(e);
+  for (const auto& tp : ctx->tune) (void)hipFree(tp.tiles);
   delete ctx;
+  return RTDETMCD_OK;
+}
+
+rtdetmcd_status rtdetmcd_tuned_plans(rtdetmcd_handle ctx, int64_t* out, int32_t cap,
+                                     int32_t* count) {
+  if (!ctx || !count || cap < 0 || (cap > 0 && !out)) return RTDETMCD_EINVAL;
+  *count = (int32_t)ctx->tune.size();
+  for (int k = 0; k < (int)ctx->tune.size() && k < cap; ++k) {
+    const auto& tp = ctx->tune[k];
+    out[4 * k] = tp.bucket;
+    out[4 * k + 1] = tp.tile_rows;
+    out[4 * k + 2] = tp.mode;
+    out[4 * k + 3] = tp.iters;
+  }
   return RTDETMCD_OK;
 }
 

@@ -145,4 +145,13 @@ struct rtdetmcd_ctx {
   std::vector<ProfRec> prof;
   std::vector<hipEvent_t> prof_events;   // every event created for profiling (reused)
   size_t prof_next = 0;                  // next free event of prof_events
+  // autotuned C-step plans (opts.tune): shape key -> distance tiling (with
+  // its device tile table) and the C-step count of the last fit
+  struct TunePlan {
+    std::vector<int64_t> key;
+    int bucket = 0, tile_rows = 0, mode = 1, iters = 0;
+    rtd::Tile* tiles = nullptr;            // device table of the kept tiling
+    int ntiles = 0;
+  };
+  std::vector<TunePlan> tune;
 };

@@ -68,6 +68,7 @@ extern "C" rtdetmcd_status rtdetmcd_cstep_noalloc(
   rtdetmcd_opts o;
   RTD_TRY(check_opts(ctx, o_in, o));
   o.graph = 0;   // capturing a graph allocates
+  o.tune = 0;    // so does a tuned plan
   if (!X || !mu0 || !sigma0 || p < 1 || ld < p || !(h_sub > p && h_sub < m) ||
       (dtype != 0 && dtype != 1)) {
     ctx->err = "rtdetmcd_cstep_noalloc: bad argument (need p < h < m)";

@@ -57,3 +57,39 @@ def test_plan_rules_match_oracle():
         P.plan(10, 8, 0, 0)
     with pytest.raises(Exception):
         P.plan(1000, 65, 0, 0)
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of rtdetmcd_opts, rtdetmcd_out and rtdetmcd_dataset
+    have the header's size and field offsets (a C program compiled against
+    include/rtdetmcd.h prints them), and the library's defaults hold."""
+    import ctypes
+    import subprocess
+    from paper_1910_05615_amd import _lib
+    structs = {"rtdetmcd_opts": _lib.Opts, "rtdetmcd_out": _lib.Out,
+               "rtdetmcd_dataset": _lib.DatasetDesc}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "rtdetmcd.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True,
+                             text=True).stdout.splitlines():
+        s, f, v = ln.split()
+        got[(s, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+    lib = _lib.load()
+    o = _lib.Opts()
+    lib.rtdetmcd_default_opts(ctypes.byref(o))
+    assert o.struct_size == ctypes.sizeof(_lib.Opts)
+    assert (o.tune, o.graph, o.rounds_per_sync, o.distance) == (0, 0, 4, 0)

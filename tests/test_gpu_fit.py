@@ -143,6 +143,51 @@ def test_graph_replays_equal_eager(rounds):
     check_fit(ga, oracle.fit(a.X, n_chunks=4), "graph")
 
 
+def test_tuned_fits_equal_untuned_and_keep_their_plan():
+    # opts tune: the first fit of a shape times the candidate distance
+    # tilings and keeps the fastest; later fits take it (eager and graph),
+    # and every result equals the untuned fit's bit for bit (the tiling only
+    # changes which block computes a row's distance)
+    P = _P()
+    a = synthdata.workload_chunked_p20(n=120_000)
+    b = synthdata.small_gaussian(30_011, 7, seed=37, dtype=np.float32, rho=0.6, eps=0.15,
+                                 kind="point", gamma=6)
+    Xa = torch.from_numpy(a.X).to(_dev())
+    Xb = torch.from_numpy(b.X).to(_dev())
+    ref_a = P.fit(Xa, n_chunks=8)
+    ref_b = P.fit(Xb, n_chunks=3)
+    before = len(P.tuned_plans())
+    fits = [(P.fit(Xa, n_chunks=8, tune=True), ref_a), (P.fit(Xb, n_chunks=3, tune=True), ref_b)]
+    plans = P.tuned_plans()
+    assert len(plans) == before + 2
+    for bucket, rows, mode, iters in plans[-2:]:
+        assert bucket in (8, 20) and rows in (256, 512, 1024, 2048, 4096) and mode in (1, 2)
+    assert plans[-2][3] >= int(ref_a.block_iters.max().cpu())
+    assert plans[-1][3] >= int(ref_b.block_iters.max().cpu())
+    for _ in range(2):
+        fits.append((P.fit(Xa, n_chunks=8, tune=True), ref_a))
+        fits.append((P.fit(Xa, n_chunks=8, tune=True, graph=True), ref_a))
+        fits.append((P.fit(Xb, n_chunks=3, tune=True, graph=True), ref_b))
+        torch.cuda.synchronize()
+    assert len(P.tuned_plans()) == before + 2   # the kept plans are reused
+    for F, ref in fits:
+        for name in _ALL:
+            assert torch.equal(getattr(F, name), getattr(ref, name)), name
+    # batched uneven datasets in one call
+    sets = [synthdata.small_gaussian(n, p, seed=60 + i, dtype=np.float32, rho=0.5, eps=0.1,
+                                     kind="point", gamma=6)
+            for i, (n, p) in enumerate([(9_000, 5), (41_000, 10), (17_000, 20), (25_000, 40)])]
+    Xs = [torch.from_numpy(s.X).to(_dev()) for s in sets]
+    r0, st0 = P.fit_batched(Xs)
+    r1, st1 = P.fit_batched(Xs, tune=True)
+    r2, st2 = P.fit_batched(Xs, tune=True, graph=True)
+    assert st0 == st1 == st2 == [0] * 4
+    for F0, F1, F2 in zip(r0, r1, r2):
+        for name in _ALL:
+            assert torch.equal(getattr(F1, name), getattr(F0, name)), name
+            assert torch.equal(getattr(F2, name), getattr(F0, name)), name
+
+
 def test_graph_cache_tells_batches_of_other_total_rows_apart():
     # two batches that share the block count, p bucket, tile counts and the
     # longest block but not the total row count: the per-row state arrays sit
