@@ -36,116 +36,14 @@ __device__ inline int block_excl_scan(int v, int* wtot, int& total) {
 }
 
 // ---------------------------------------------------------------------------
-// h-subset selection (Sec. 2.1 C-step steps 2-3) by radix select on the
-// float64 bit patterns, digits 12/13/13/13/13 bits from the top, then one pass
-// in row order that resolves ties by index and records the swapped rows for
-// the update-based step (Sec. 3.5).
+// h-subset selection (Sec. 2.1 C-step steps 2-3): the h-th smallest key (the
+// float64 bit pattern of d2) from one histogram over the item's key range
+// and an exact ranking of the keys in the bin that holds rank h (radix select
+// when that bin is crowded), then one pass in row order that resolves ties
+// by index and records the swapped rows for the update-based step (Sec. 3.5).
 // ---------------------------------------------------------------------------
 constexpr int SEL_NT = 1024;
 
-__global__ __launch_bounds__(SEL_NT) void k_select(const ItemDesc* __restrict__ items,
-                                                   ItemArrays A, int first_item,
-                                                   int cstep_mode, int reset_nactive) {
-  if (reset_nactive && blockIdx.x == 0 && threadIdx.x == 0) *A.nactive = 0;
-  __shared__ unsigned hist[8192];
-  __shared__ int wtot[3][SEL_NT / 64];
-  __shared__ int s_bin, s_cnt;
-  __shared__ long long s_below;
-  const int it = first_item + blockIdx.x;
-  if (A.status[it] != ACTIVE) return;
-  const ItemDesc D = items[it];
-  const int64_t m = D.m, h = D.h;
-  const double* __restrict__ d2 = A.d2 + D.roff;
-  uint8_t* __restrict__ mask = A.mask + D.roff;
-  int32_t* __restrict__ swp = A.swap + D.roff;
-  const int tid = threadIdx.x;
-
-  const int shifts[5] = {52, 39, 26, 13, 0};
-  const int bitsv[5] = {12, 13, 13, 13, 13};
-  uint64_t prefix = 0, pmask = 0;
-  int64_t rank = h;   // 1-based rank of the threshold key among candidates
-  bool take_all = false;
-#pragma unroll
-  for (int ps = 0; ps < 5; ++ps) {
-    const int shift = shifts[ps], bits = bitsv[ps];
-    const int nbins = 1 << bits;
-    for (int b = tid; b < nbins; b += SEL_NT) hist[b] = 0u;
-    __syncthreads();
-    for (int64_t i = tid; i < m; i += SEL_NT) {
-      const uint64_t k = key_of(d2[i]);
-      if ((k & pmask) == prefix) atomicAdd(&hist[(k >> shift) & (uint64_t)(nbins - 1)], 1u);
-    }
-    __syncthreads();
-    // locate the bin that holds the rank-th candidate
-    const int per = nbins / SEL_NT;   // 4 or 8 bins per thread
-    int loc = 0;
-    for (int b = 0; b < per; ++b) loc += (int)hist[tid * per + b];
-    int tot;
-    const int before = block_excl_scan<SEL_NT>(loc, wtot[0], tot);
-    if ((int64_t)before < rank && rank <= (int64_t)(before + loc)) {
-      int64_t run = before;
-      for (int b = 0; b < per; ++b) {
-        const int c = (int)hist[tid * per + b];
-        if (rank <= run + c) { s_bin = tid * per + b; s_cnt = c; s_below = run; break; }
-        run += c;
-      }
-    }
-    __syncthreads();
-    prefix |= (uint64_t)s_bin << shift;
-    pmask |= (uint64_t)(nbins - 1) << shift;
-    rank -= s_below;
-    const int cnt = s_cnt;
-    __syncthreads();
-    if ((int64_t)cnt == rank) { take_all = true; break; }
-  }
-
-  // final pass in row order
-  const int it0 = A.iter[it];
-  const bool first = (it0 == 0);
-  int64_t tie_seen = 0, nin = 0, nout = 0;
-  const int64_t half = m / 2;
-  for (int64_t base = 0; base < m; base += SEL_NT) {
-    const int64_t i = base + tid;
-    const bool valid = i < m;
-    const uint64_t k = valid ? key_of(d2[i]) : ~0ull;
-    bool sel;
-    int eq = 0;
-    if (take_all) {
-      sel = valid && ((k & pmask) <= prefix);
-    } else {
-      eq = (valid && k == prefix) ? 1 : 0;
-      sel = valid && k < prefix;
-    }
-    int tot_eq;
-    const int eq_before = block_excl_scan<SEL_NT>(eq, wtot[0], tot_eq);
-    if (!take_all && eq && (tie_seen + eq_before) < rank) sel = true;
-    tie_seen += tot_eq;
-    const int old = valid ? (int)mask[i] : 0;
-    const int ent = (sel && !old) ? 1 : 0;
-    const int lft = (valid && !sel && old) ? 1 : 0;
-    int tot_in, tot_out;
-    const int pin = block_excl_scan<SEL_NT>(ent, wtot[1], tot_in);
-    const int pout = block_excl_scan<SEL_NT>(lft, wtot[2], tot_out);
-    if (!first) {
-      if (ent) swp[nin + pin] = (int32_t)i;
-      if (lft) swp[half + nout + pout] = (int32_t)i;
-    }
-    if (valid) mask[i] = sel ? 1 : 0;
-    nin += tot_in;
-    nout += tot_out;
-  }
-  if (tid == 0) {
-    const int itn = it0 + 1;
-    A.iter[it] = itn;
-    A.kswap[it] = first ? 0 : (int32_t)nin;
-    int full;
-    if (first || cstep_mode == 0) full = 1;
-    else if (cstep_mode == 1) full = 0;
-    else full = (8 * nin > h) ? 1 : 0;
-    A.full[it] = full;
-    if (!first && nin == 0) A.status[it] = ST_CONVERGED;
-  }
-}
 
 // Same selection for items of at most SEL_NT * SEL_KR rows, with the keys
 // held in registers (row i * SEL_NT + tid in slot i): the digit passes do not
@@ -453,6 +351,254 @@ __global__ __launch_bounds__(SEL_NT) void k_select_reg(const ItemDesc* __restric
     if (first || cstep_mode == 0) full = 1;
     else if (cstep_mode == 1) full = 0;
     else full = (8 * (int64_t)nin > h) ? 1 : 0;
+    A.full[it] = full;
+    if (!first && nin == 0) A.status[it] = ST_CONVERGED;
+  }
+}
+
+// h-subset selection of an item longer than SEL_NT * SEL_KR rows: the
+// threshold search and the membership of k_select_reg over chunks of
+// SEL_NT * SEL_KR rows (the keys read again for each of: bounds, histogram,
+// the threshold bin's keys, membership), swap lists in row order across the
+// chunks.
+__global__ __launch_bounds__(SEL_NT) void k_select(const ItemDesc* __restrict__ items,
+                                                   ItemArrays A, int first_item,
+                                                   int cstep_mode, int reset_nactive) {
+  if (reset_nactive && blockIdx.x == 0 && threadIdx.x == 0) *A.nactive = 0;
+  __shared__ __align__(16) unsigned hist[8192];
+  __shared__ int wtot[SEL_WV];
+  __shared__ int tab[3][SEL_KR * SEL_WV];
+  __shared__ int wsum[8];
+  __shared__ int s_bin, s_cnt, s_nc, s_all;
+  __shared__ long long s_below, s_rank;
+  __shared__ uint64_t s_prefix;
+  __shared__ uint64_t s_bound[2 * SEL_WV];
+  const int it = first_item + blockIdx.x;
+  if (A.status[it] != ACTIVE) return;
+  const ItemDesc D = items[it];
+  const int64_t m = D.m, h = D.h;
+  const double* __restrict__ d2 = A.d2 + D.roff;
+  uint8_t* __restrict__ mask = A.mask + D.roff;
+  int32_t* __restrict__ swp = A.swap + D.roff;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint64_t below = (1ull << lane) - 1ull;
+  constexpr int CH = SEL_NT * SEL_KR;
+  uint64_t key[SEL_KR];
+  auto load = [&](int64_t c0) {
+#pragma unroll
+    for (int i = 0; i < SEL_KR; ++i) {
+      const int64_t r = c0 + i * SEL_NT + tid;
+      key[i] = r < m ? key_of(d2[r]) : 0ull;
+    }
+  };
+  const int it0 = A.iter[it];
+  uint64_t prefix = 0, pmask = ~0ull;
+  int64_t rank = h;
+  bool take_all = false;
+  {
+    uint64_t kmn = ~0ull, kmx = 0ull;
+    for (int64_t c0 = 0; c0 < m; c0 += CH) {
+      load(c0);
+#pragma unroll
+      for (int i = 0; i < SEL_KR; ++i)
+        if (c0 + i * SEL_NT + tid < m) {
+          kmn = key[i] < kmn ? key[i] : kmn;
+          if (key[i] != ~0ull && key[i] > kmx) kmx = key[i];
+        }
+    }
+    kmn = wave_min_u64(kmn);
+    kmx = wave_max_u64(kmx);
+    if (lane == 0) {
+      s_bound[w] = kmn;
+      s_bound[SEL_WV + w] = kmx;
+    }
+    for (int b = tid; b < SEL_NB; b += SEL_NT) hist[b] = 0u;
+    if (tid == 0) s_nc = 0;
+    __syncthreads();
+    kmn = ~0ull;
+    kmx = 0ull;
+#pragma unroll
+    for (int q = 0; q < SEL_WV; ++q) {
+      kmn = s_bound[q] < kmn ? s_bound[q] : kmn;
+      kmx = s_bound[SEL_WV + q] > kmx ? s_bound[SEL_WV + q] : kmx;
+    }
+    const uint64_t span = kmx > kmn ? kmx - kmn : 0ull;
+    const int bl = span ? 64 - __clzll((long long)span) : 0;
+    const int sh = bl > SEL_NBB ? bl - SEL_NBB : 0;
+    auto bin_of = [&](uint64_t k) -> int {
+      if (k == ~0ull) return SEL_NB - 1;
+      const uint64_t b = (k - kmn) >> sh;
+      return b < (uint64_t)SEL_NB ? (int)b : SEL_NB - 1;
+    };
+    for (int64_t c0 = 0; c0 < m; c0 += CH) {
+      load(c0);
+#pragma unroll
+      for (int i = 0; i < SEL_KR; ++i)
+        if (c0 + i * SEL_NT + tid < m) atomicAdd(&hist[bin_of(key[i])], 1u);
+    }
+    __syncthreads();
+    constexpr int per = SEL_NB / SEL_NT;
+    int loc = 0;
+#pragma unroll
+    for (int b = 0; b < per; ++b) loc += (int)hist[tid * per + b];
+    int tot;
+    const int before = block_excl_scan<SEL_NT>(loc, wtot, tot);
+    if ((int64_t)before < rank && rank <= (int64_t)(before + loc)) {
+      int64_t run = before;
+      for (int b = 0; b < per; ++b) {
+        const int c = (int)hist[tid * per + b];
+        if (rank <= run + c) { s_bin = tid * per + b; s_cnt = c; s_below = run; break; }
+        run += c;
+      }
+    }
+    __syncthreads();
+    const int bstar = s_bin, cnt = s_cnt;
+    const int64_t k1 = rank - s_below;
+    if (cnt <= SEL_CMAX) {   // uniform
+      uint64_t* ck = reinterpret_cast<uint64_t*>(hist);
+      for (int64_t c0 = 0; c0 < m; c0 += CH) {
+        load(c0);
+#pragma unroll
+        for (int i = 0; i < SEL_KR; ++i)
+          if (c0 + i * SEL_NT + tid < m && bin_of(key[i]) == bstar)
+            ck[atomicAdd(&s_nc, 1)] = key[i];
+      }
+      __syncthreads();
+      if (tid < cnt) {
+        const uint64_t x = ck[tid];
+        int nless = 0, nleq = 0;
+        for (int j = 0; j < cnt; ++j) {
+          const uint64_t y = ck[j];
+          nless += y < x ? 1 : 0;
+          nleq += y <= x ? 1 : 0;
+        }
+        if (nless < k1 && k1 <= nleq) {
+          s_prefix = x;
+          s_rank = k1 - nless;
+          s_all = k1 == nleq ? 1 : 0;
+        }
+      }
+      __syncthreads();
+      prefix = s_prefix;
+      rank = s_rank;
+      take_all = s_all != 0;
+    } else {
+      // a crowded bin: radix select on the float64 bit patterns, digits
+      // 12/13/13/13/13 bits from the top
+      __syncthreads();
+      pmask = 0;
+      const int shifts[5] = {52, 39, 26, 13, 0};
+      const int bitsv[5] = {12, 13, 13, 13, 13};
+      for (int ps = 0; ps < 5; ++ps) {
+        const int shift = shifts[ps], bits = bitsv[ps];
+        const int nbins = 1 << bits;
+        for (int b = tid; b < nbins; b += SEL_NT) hist[b] = 0u;
+        __syncthreads();
+        for (int64_t i = tid; i < m; i += SEL_NT) {
+          const uint64_t k = key_of(d2[i]);
+          if ((k & pmask) == prefix) atomicAdd(&hist[(k >> shift) & (uint64_t)(nbins - 1)], 1u);
+        }
+        __syncthreads();
+        const int pb = nbins / SEL_NT;
+        int lc = 0;
+        for (int b = 0; b < pb; ++b) lc += (int)hist[tid * pb + b];
+        int tt;
+        const int bf = block_excl_scan<SEL_NT>(lc, wtot, tt);
+        if ((int64_t)bf < rank && rank <= (int64_t)(bf + lc)) {
+          int64_t run = bf;
+          for (int b = 0; b < pb; ++b) {
+            const int c = (int)hist[tid * pb + b];
+            if (rank <= run + c) { s_bin = tid * pb + b; s_cnt = c; s_below = run; break; }
+            run += c;
+          }
+        }
+        __syncthreads();
+        prefix |= (uint64_t)s_bin << shift;
+        pmask |= (uint64_t)(nbins - 1) << shift;
+        rank -= s_below;
+        const int c2 = s_cnt;
+        __syncthreads();
+        if ((int64_t)c2 == rank) { take_all = true; break; }
+      }
+    }
+  }
+  // membership chunk by chunk; ties at the threshold key go to the lowest
+  // row indices; swap lists in row order
+  const bool first = (it0 == 0);
+  const int64_t half = m / 2;
+  int64_t tie_seen = 0, nin = 0;
+  int64_t nout = 0;
+  for (int64_t c0 = 0; c0 < m; c0 += CH) {
+    load(c0);
+    uint32_t selb = 0, oldb = 0;
+#pragma unroll
+    for (int i = 0; i < SEL_KR; ++i) {
+      const int64_t r = c0 + i * SEL_NT + tid;
+      const bool valid = r < m;
+      if (valid && mask[r] != 0) oldb |= 1u << i;
+      const bool sel = take_all ? (valid && (key[i] & pmask) <= prefix) : (valid && key[i] < prefix);
+      if (sel) selb |= 1u << i;
+    }
+    if (!take_all) {   // uniform
+      uint32_t eqb = 0;
+#pragma unroll
+      for (int i = 0; i < SEL_KR; ++i) {
+        const bool eq = (c0 + i * SEL_NT + tid) < m && key[i] == prefix;
+        const uint64_t b = __ballot(eq);
+        if (eq) eqb |= 1u << i;
+        if (lane == 0) tab[0][i * SEL_WV + w] = __popcll(b);
+      }
+      __syncthreads();
+      const int neq = scan256_excl(tab[0], SEL_KR * SEL_WV, wsum);
+#pragma unroll
+      for (int i = 0; i < SEL_KR; ++i) {
+        const bool eq = (eqb >> i) & 1u;
+        const uint64_t b = __ballot(eq);
+        const int64_t er = tie_seen + tab[0][i * SEL_WV + w] + __popcll(b & below);
+        if (eq && er < rank) selb |= 1u << i;
+      }
+      tie_seen += neq;
+    }
+    uint32_t entb = 0, lftb = 0;
+#pragma unroll
+    for (int i = 0; i < SEL_KR; ++i) {
+      const int64_t r = c0 + i * SEL_NT + tid;
+      const bool valid = r < m;
+      const bool sel = (selb >> i) & 1u;
+      const bool old = (oldb >> i) & 1u;
+      const bool ent = sel && !old, lft = valid && !sel && old;
+      if (ent) entb |= 1u << i;
+      if (lft) lftb |= 1u << i;
+      const uint64_t be = __ballot(ent), bl = __ballot(lft);
+      if (lane == 0) {
+        tab[1][i * SEL_WV + w] = __popcll(be);
+        tab[2][i * SEL_WV + w] = __popcll(bl);
+      }
+      if (valid) mask[r] = sel ? 1 : 0;
+    }
+    __syncthreads();
+    const int2 nio = scan256_excl2(tab[1], tab[2], SEL_KR * SEL_WV, wsum);
+    if (!first) {
+#pragma unroll
+      for (int i = 0; i < SEL_KR; ++i) {
+        const int64_t r = c0 + i * SEL_NT + tid;
+        const bool ent = (entb >> i) & 1u, lft = (lftb >> i) & 1u;
+        const uint64_t be = __ballot(ent), bl = __ballot(lft);
+        if (ent) swp[nin + tab[1][i * SEL_WV + w] + __popcll(be & below)] = (int32_t)r;
+        if (lft) swp[half + nout + tab[2][i * SEL_WV + w] + __popcll(bl & below)] = (int32_t)r;
+      }
+    }
+    nin += nio.x;
+    nout += nio.y;
+    __syncthreads();   // tab is read by every thread before the next chunk writes it
+  }
+  if (tid == 0) {
+    A.iter[it] = it0 + 1;
+    A.kswap[it] = first ? 0 : (int32_t)nin;
+    int full;
+    if (first || cstep_mode == 0) full = 1;
+    else if (cstep_mode == 1) full = 0;
+    else full = (8 * nin > h) ? 1 : 0;
     A.full[it] = full;
     if (!first && nin == 0) A.status[it] = ST_CONVERGED;
   }

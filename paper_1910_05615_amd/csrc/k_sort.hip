@@ -128,7 +128,8 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K* __restrict__ kin,
                                                       const int64_t* __restrict__ seg_off,
                                                       const int64_t* __restrict__ seg_len,
                                                       int shift,
-                                                      const int32_t* __restrict__ offs) {
+                                                      const int32_t* __restrict__ offs,
+                                                      int32_t* __restrict__ zero_after) {
   __shared__ int wc[RS_WAVES][256];
   __shared__ int td[256];            // tile-local start of each digit
   __shared__ int go[256];            // global position of a tile slot: go[d] + slot
@@ -140,6 +141,7 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const K* __restrict__ kin,
   const int64_t end = so + seg_len[t.seg];
   const int nvalid = (int)min((int64_t)RS_TILE, end - base);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (zero_after != nullptr && blockIdx.x == 0 && tid == 0) *zero_after = 0;   // (no longer read)
   for (int d = tid; d < RS_WAVES * 256; d += RS_NT) (&wc[0][0])[d] = 0;
   __syncthreads();
   K kv[RS_ITEMS];
@@ -235,6 +237,80 @@ __global__ __launch_bounds__(RS_NT) void k_rs_check(const K* __restrict__ keys,
     if (k + 1 < end) bad = bad || keys[k] > keys[k + 1];
   }
   if (bad) *flag = 1;
+}
+
+// After passes on the high 48 bits of 64-bit keys (stable, so keys equal
+// there keep their order of arrival): runs of equal high bits that hold a
+// descent of the full key are listed, each from its first descent (the walks
+// only read: another run's fix-up never touches this run), as (start << 12
+// | length) in list[1..cap] with the count in list[0] (as int32, zero on
+// entry).  A run longer than FIXUP_RUN, or more runs than cap, sets *flag
+// (the fit is then run again with the full-width sort).
+constexpr int GRUN_MAX = 256;   // longest run fixed in place
+template <typename K>
+__global__ __launch_bounds__(RS_NT) void k_rs_runs(const K* __restrict__ keys,
+                                                   const SegTile* __restrict__ tiles,
+                                                   const int64_t* __restrict__ seg_off,
+                                                   const int64_t* __restrict__ seg_len,
+                                                   uint64_t* __restrict__ list, int cap,
+                                                   int32_t* __restrict__ flag) {
+  const SegTile t = tiles[blockIdx.x];
+  const int64_t so = seg_off[t.seg];
+  const int64_t base = so + (int64_t)t.tile * RS_TILE;
+  const int64_t end = so + seg_len[t.seg];
+  auto hi = [](K k) { return (uint64_t)(k >> 16); };
+#pragma unroll 4
+  for (int i = 0; i < RS_ITEMS; ++i) {
+    const int64_t q = base + i * RS_NT + threadIdx.x;
+    if (q + 1 >= end) continue;
+    const K a = keys[q], b = keys[q + 1];
+    if (!(hi(a) == hi(b) && a > b)) continue;
+    const uint64_t hq = hi(a);
+    int64_t s0 = q;
+    bool first = true, over = false;
+    K right = a;
+    while (s0 > so) {
+      if (q - s0 >= GRUN_MAX) { over = true; break; }
+      const K left = keys[s0 - 1];
+      if (hi(left) != hq) break;
+      if (left > right) { first = false; break; }   // an earlier descent takes the run
+      right = left;
+      --s0;
+    }
+    if (!first) continue;
+    int64_t e = q + 2;
+    while (!over && e < end && hi(keys[e]) == hq) {
+      if (e - s0 >= GRUN_MAX) over = true;
+      ++e;
+    }
+    if (over) {
+      *flag = 1;
+      continue;
+    }
+    const int slot = atomicAdd(reinterpret_cast<int32_t*>(list), 1);
+    if (slot < cap) list[1 + slot] = ((uint64_t)s0 << 12) | (uint64_t)(e - s0);
+    else *flag = 1;
+  }
+}
+
+// Insertion sort of each listed run, one thread per run.
+template <typename K>
+__global__ __launch_bounds__(256) void k_rs_fixup(K* __restrict__ keys,
+                                                  const uint64_t* __restrict__ list, int cap) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int n = min(*reinterpret_cast<const int32_t*>(list), cap);
+  if (r >= n) return;
+  const uint64_t e = list[1 + r];
+  const int64_t s0 = (int64_t)(e >> 12), len = (int64_t)(e & 0xFFF);
+  for (int64_t a = s0 + 1; a < s0 + len; ++a) {
+    const K x = keys[a];
+    int64_t b = a;
+    while (b > s0 && keys[b - 1] > x) {
+      keys[b] = keys[b - 1];
+      --b;
+    }
+    keys[b] = x;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1585,12 +1661,26 @@ template <typename K>
 hipError_t sort_segments_t(SortPlan& P, hipStream_t s) {
   K* a = static_cast<K*>(P.keys);
   K* b = static_cast<K*>(P.tmp);
-  for (int ps = 0; ps < (int)sizeof(K); ++ps) {
+  // 64-bit keys (of doubles): the passes order the high 48 bits (sign,
+  // exponent and 36 mantissa bits: values that agree there are equal in
+  // practice), and the runs of equal high bits that are out of order on the
+  // full key are then put in order in place; the full-width sort (eight
+  // passes) only with ballot ranking
+  const bool hi_only = sizeof(K) == 8 && !P.safe;
+  const int ps0 = hi_only ? 2 : 0;
+  // the run list of the fix-up lives in the tile counts, free after the
+  // last scan: its count (list[0]) is cleared by the last scatter
+  // (32 runs per tile of 4096 keys: continuous data hold a few; more fall
+  // back to the full-width sort)
+  uint64_t* list = reinterpret_cast<uint64_t*>(P.counts);
+  const int cap = (int)std::min<int64_t>((int64_t)P.ntiles * 32, INT32_MAX / 2);
+  for (int ps = ps0; ps < (int)sizeof(K); ++ps) {
     const int shift = 8 * ps;
+    const bool last = ps == (int)sizeof(K) - 1;
     // the top byte of a double's key (sign and the high 7 of 11 exponent
     // bits) takes one or two values in practice: peel it; a float's (high 7
     // of 8 exponent bits) spreads enough for atomics
-    const bool top = sizeof(K) == 8 && ps == (int)sizeof(K) - 1;
+    const bool top = sizeof(K) == 8 && last;
     if (top)
       hipLaunchKernelGGL((k_rs_count<K, true>), dim3(P.ntiles), dim3(RS_NT), 0, s, a, P.tiles,
                          P.seg_off, P.seg_len, shift, P.counts);
@@ -1599,21 +1689,29 @@ hipError_t sort_segments_t(SortPlan& P, hipStream_t s) {
                          P.seg_off, P.seg_len, shift, P.counts);
     hipLaunchKernelGGL(k_rs_scan, dim3(P.nseg), dim3(SCAN_NT), 0, s, P.counts, P.seg_tile0,
                        P.tile_first, P.offs);
+    int32_t* zero = (hi_only && last) ? P.counts : nullptr;
     if (P.safe)
       hipLaunchKernelGGL((k_rs_scatter<K, true, false>), dim3(P.ntiles), dim3(RS_NT), 0, s, a,
-                         b, P.tiles, P.seg_off, P.seg_len, shift, P.offs);
+                         b, P.tiles, P.seg_off, P.seg_len, shift, P.offs, zero);
     else if (top)
       hipLaunchKernelGGL((k_rs_scatter<K, false, true>), dim3(P.ntiles), dim3(RS_NT), 0, s, a,
-                         b, P.tiles, P.seg_off, P.seg_len, shift, P.offs);
+                         b, P.tiles, P.seg_off, P.seg_len, shift, P.offs, zero);
     else
       hipLaunchKernelGGL((k_rs_scatter<K, false, false>), dim3(P.ntiles), dim3(RS_NT), 0, s, a,
-                         b, P.tiles, P.seg_off, P.seg_len, shift, P.offs);
+                         b, P.tiles, P.seg_off, P.seg_len, shift, P.offs, zero);
     K* t = a;
     a = b;
     b = t;
   }
-  // an even number of passes leaves the result in P.keys; the atomic ranks
-  // are checked through the order of the result
+  // an even number of passes leaves the result in P.keys
+  if (hi_only) {
+    hipLaunchKernelGGL((k_rs_runs<K>), dim3(P.ntiles), dim3(RS_NT), 0, s, a, P.tiles, P.seg_off,
+                       P.seg_len, list, cap, P.flag);
+    // one thread per listed run: a grid for the capacity, threads beyond
+    // the count return at once
+    hipLaunchKernelGGL((k_rs_fixup<K>), dim3((cap + 255) / 256), dim3(256), 0, s, a, list, cap);
+  }
+  // the atomic ranks and the fix-up are checked through the order of the result
   if (!P.safe)
     hipLaunchKernelGGL((k_rs_check<K>), dim3(P.ntiles), dim3(RS_NT), 0, s, a, P.tiles, P.seg_off,
                        P.seg_len, P.flag);

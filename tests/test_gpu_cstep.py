@@ -76,10 +76,10 @@ def test_select_bit_exact(m, h):
 
 @pytest.mark.parametrize("case", ["ties", "all_equal", "zeros", "two_values", "nan", "tiny",
                                   "heavy_tail", "crowded_threshold", "equal_block_at_threshold"])
-def test_select_ties_and_degenerate(case):
+@pytest.mark.parametrize("m,h", [(4099, 2050), (40_003, 30_001)])   # one chunk / several
+def test_select_ties_and_degenerate(case, m, h):
     P = _P()
     rng = np.random.default_rng(3)
-    m, h = 4099, 2050
     if case == "ties":
         d2 = rng.integers(0, 20, m).astype(np.float64)
     elif case == "all_equal":
