@@ -30,10 +30,19 @@ struct SortHost {
   std::vector<int32_t> tile0;     // nseg + 1, absolute
   std::vector<SegTile> tiles;
   std::vector<double> craw;
+  std::vector<int32_t> bk0;       // nseg + 1: buckets of the sample sort, absolute
+  std::vector<SegTile> bktab;     // (segment, rank within it) of every bucket
   int64_t keys = 0;               // total keys
+  int64_t maxlen = 0;
+  bool buckets = false;           // the sample sort may take the long segments
   void add(int64_t L, double cr) {
     const int T = sort_tile_keys();
     if (tile0.empty()) tile0.push_back(0);
+    if (bk0.empty()) bk0.push_back(0);
+    const int64_t nb = bucket_count(L);
+    for (int64_t b = 0; b < nb; ++b) bktab.push_back({(int)off.size(), (int)b});
+    bk0.push_back((int32_t)bktab.size());
+    maxlen = std::max(maxlen, L);
     off.push_back(keys);
     len.push_back(L);
     craw.push_back(cr);
@@ -43,13 +52,21 @@ struct SortHost {
     keys += L;
   }
   int nseg() const { return (int)off.size(); }
+  // Staging keys of the sample sort (zero where it cannot be used): a
+  // plan with a segment too long for one LDS segment, none too long for
+  // the buckets, 64-bit keys.
+  int64_t bucket_keys() const {
+    if (!buckets || key_bytes != 8 || maxlen <= lds_sort_capacity() || maxlen > bucket_max_len())
+      return 0;
+    return (int64_t)bktab.size() * bucket_capacity();
+  }
 };
 
 struct SortDev {
   SortPlan plan;
   SegStat* st = nullptr;
   double* craw = nullptr;
-  size_t o_off = 0, o_len = 0, o_t0 = 0, o_tiles = 0, o_st = 0, o_craw = 0;
+  size_t o_off = 0, o_len = 0, o_t0 = 0, o_tiles = 0, o_st = 0, o_craw = 0, o_bk0 = 0, o_bkt = 0;
 };
 
 void layout_sort(Layout& L, const SortHost& H, SortDev& D) {
@@ -59,6 +76,8 @@ void layout_sort(Layout& L, const SortHost& H, SortDev& D) {
   D.o_tiles = L.add(H.tiles.size() * sizeof(SegTile));
   D.o_st = L.add(H.off.size() * sizeof(SegStat));
   D.o_craw = L.add(H.craw.size() * 8);
+  D.o_bk0 = L.add(H.bk0.size() * 4);
+  D.o_bkt = L.add(H.bktab.size() * sizeof(SegTile));
 }
 
 void bind_sort(char* base, const SortHost& H, SortDev& D, void* keys, void* tmp, int32_t* counts,
@@ -76,6 +95,10 @@ void bind_sort(char* base, const SortHost& H, SortDev& D, void* keys, void* tmp,
   P.counts = counts;
   P.offs = offs;
   P.tile_first = 0;
+  P.bk0 = reinterpret_cast<int32_t*>(base + D.o_bk0);
+  P.bk_tab = reinterpret_cast<SegTile*>(base + D.o_bkt);
+  P.bk_first = 0;
+  P.nbk = (int)H.bktab.size();
   D.st = reinterpret_cast<SegStat*>(base + D.o_st);
   D.craw = reinterpret_cast<double*>(base + D.o_craw);
 }
@@ -86,13 +109,15 @@ void upload_sort(Uploader& up, const SortHost& H, SortDev& D) {
   up.add(const_cast<int32_t*>(D.plan.seg_tile0), H.tile0.data(), H.tile0.size());
   up.add(const_cast<SegTile*>(D.plan.tiles), H.tiles.data(), H.tiles.size());
   up.add(D.craw, H.craw.data(), H.craw.size());
+  up.add(const_cast<int32_t*>(D.plan.bk0), H.bk0.data(), H.bk0.size());
+  up.add(const_cast<SegTile*>(D.plan.bk_tab), H.bktab.data(), H.bktab.size());
 }
 
 // Sort + estimator over the segments [a, b) of a plan.
 rtdetmcd_status sort_stats(rtdetmcd_ctx* ctx, const SortHost& H, SortDev& D, int a, int b,
                            int mode, double q1, double crew1) {
   if (b <= a) return RTDETMCD_OK;
-  SortPlan P = D.plan.sub(a, b, H.tile0.data());
+  SortPlan P = D.plan.sub(a, b, H.tile0.data(), H.bk0.data());
   const int64_t maxlen = *std::max_element(H.len.begin() + a, H.len.begin() + b);
   if (maxlen <= lds_sort_capacity()) {
     double keys = 0.0;
@@ -103,7 +128,10 @@ rtdetmcd_status sort_stats(rtdetmcd_ctx* ctx, const SortHost& H, SortDev& D, int
     pm.end(ctx->stream);
     return RTDETMCD_OK;
   }
-  RTD_HIP(sort_segments(P, ctx->stream));
+  if (H.bucket_keys() > 0 && !ctx->sort_safe)
+    RTD_HIP(sort_buckets(P, ctx->stream));
+  else
+    RTD_HIP(sort_segments(P, ctx->stream));
   if (mode == SEGSTAT_UNIMCD)
     RTD_HIP(launch_unimcd_multiblock(P, D.craw + a, q1, crew1, D.st + a, ctx->stream));
   else
@@ -218,6 +246,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   S64.key_bytes = 8;
   SN.key_bytes = 8;
   SR.key_bytes = 8;
+  SN.buckets = SR.buckets = true;
   std::vector<int32_t> std_seg0(ND);
   std::vector<int> std_in64(ND);
   for (int k = 0; k < ND; ++k) {
@@ -280,9 +309,11 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   layout_sort(L, SN, DN);
   layout_sort(L, SR, DR);
   const int64_t kbytes = std::max({S32.keys * 4 + S64.keys * 8, SN.keys * 8, SR.keys * 8});
+  // the staging slots of the sample sort live in the ping-pong buffer
+  const int64_t tbytes = std::max({kbytes, SN.bucket_keys() * 8, SR.bucket_keys() * 8});
   const size_t maxtiles = std::max({S32.tiles.size() + S64.tiles.size(), SN.tiles.size(),
                                     SR.tiles.size()});
-  const size_t o_keys = L.add((size_t)kbytes), o_tmp = L.add((size_t)kbytes);
+  const size_t o_keys = L.add((size_t)kbytes), o_tmp = L.add((size_t)tbytes);
   const size_t o_counts = L.add(maxtiles * 256 * 4), o_offs = L.add(maxtiles * 256 * 4);
   const size_t maxseg = std::max({(size_t)S32.nseg() + S64.nseg(), (size_t)SN.nseg(),
                                   (size_t)SR.nseg()});

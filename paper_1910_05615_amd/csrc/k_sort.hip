@@ -1322,6 +1322,347 @@ __global__ __launch_bounds__(SS_NT) void k_seg_lds_slow(const K* __restrict__ ke
 }
 
 // ---------------------------------------------------------------------------
+// Sample sort of long segments.  Splitters are taken from a sorted strided
+// sample of each segment; one pass sends every key to its class: the open
+// range between two neighbouring splitters, or the value of a splitter.
+// Each range (a bucket of at most BK_CAP keys) is then sorted in LDS by one
+// block, with the passes and check of k_seg_lds, and written to its final
+// place, followed by its upper splitter's value as often as that value
+// occurs.  Classes of a segment with nb buckets, in key order:
+// range 0, value 0, range 1, ..., value nb-2, range nb-1 (class 2i is range
+// i, class 2i + 1 the value of splitter i).
+// ---------------------------------------------------------------------------
+constexpr int BK_NT = 256;           // threads of the sample kernel
+constexpr int BK_SAMPLE = 2048;      // sample size per segment
+constexpr int BK_KPT = 16;
+constexpr int BK_CAP = SS_NT * BK_KPT;   // keys per bucket (one LDS segment)
+constexpr int BK_EXP = 10240;        // expected keys per bucket (capacity / 1.6)
+constexpr int BK_NBMAX = 64;         // buckets per segment
+static_assert(2 * BK_NBMAX <= RS_NT, "one thread per class in k_bk_scatter");
+
+// Order key of a value: the inverse of val_of.
+__device__ inline uint64_t key_of_val(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ inline uint32_t key_of_val(float x) {
+  const uint32_t b = __float_as_uint(x);
+  return (b >> 31) ? ~b : (b | 0x80000000u);
+}
+
+// Class of key k among the nsp sorted splitters sp: 2 i + (k == sp[i]),
+// i = the number of splitters below k.
+template <typename K>
+__device__ inline int bk_class(K k, const K* sp, int nsp) {
+  int i = 0;
+#pragma unroll
+  for (int st = BK_NBMAX / 2; st > 0; st >>= 1)
+    if (i + st <= nsp && sp[i + st - 1] < k) i += st;
+  return 2 * i + ((i < nsp && sp[i] == k) ? 1 : 0);
+}
+
+// One block per segment: clears its class counters and, for nb >= 2,
+// writes the nb - 1 splitters: order statistics i BK_SAMPLE / nb of the
+// sample of keys (2 s + 1) L / (2 BK_SAMPLE), s < BK_SAMPLE, sorted by a
+// bitonic network.
+template <typename K>
+__global__ __launch_bounds__(BK_NT) void k_bk_sample(const K* __restrict__ keys,
+                                                     const int64_t* __restrict__ seg_off,
+                                                     const int64_t* __restrict__ seg_len,
+                                                     const int32_t* __restrict__ bk0,
+                                                     int seg_first, int bk_first,
+                                                     K* __restrict__ split,
+                                                     int32_t* __restrict__ cnt) {
+  __shared__ K smp[BK_SAMPLE];
+  const int sg = seg_first + blockIdx.x;
+  const int j0 = bk0[sg] - bk_first, nb = bk0[sg + 1] - bk0[sg];
+  const int tid = threadIdx.x;
+  for (int c = tid; c < 2 * nb; c += BK_NT) cnt[2 * j0 + c] = 0;
+  if (nb < 2) return;   // uniform
+  const int64_t L = seg_len[sg];
+  const K* __restrict__ src = keys + seg_off[sg];
+  for (int i = tid; i < BK_SAMPLE; i += BK_NT)
+    smp[i] = src[((2 * (int64_t)i + 1) * L) / (2 * BK_SAMPLE)];
+  __syncthreads();
+  for (int k = 2; k <= BK_SAMPLE; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < BK_SAMPLE / 2; i += BK_NT) {
+        const int lo = 2 * i - (i & (j - 1)), hi = lo + j;   // lo: bit log2(j) clear
+        const K a = smp[lo], b = smp[hi];
+        if ((a > b) == ((lo & k) == 0)) {
+          smp[lo] = b;
+          smp[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = tid + 1; i < nb; i += BK_NT) split[j0 + i - 1] = smp[(i * BK_SAMPLE) / nb];
+}
+
+// One block per radix tile (RS_TILE keys of one segment): the class of
+// every key, one atomic per class for the tile's place in its bucket, then
+// the range keys, grouped by class in LDS, written to their buckets'
+// staging slots (stg[j BK_CAP ...] for bucket j of the plan).  Value
+// classes are only counted.  A bucket filled beyond BK_CAP sets *flag.
+template <typename K>
+__global__ __launch_bounds__(RS_NT) void k_bk_scatter(const K* __restrict__ keys,
+                                                      K* __restrict__ stg,
+                                                      const SegTile* __restrict__ tiles,
+                                                      const int64_t* __restrict__ seg_off,
+                                                      const int64_t* __restrict__ seg_len,
+                                                      const int32_t* __restrict__ bk0,
+                                                      int bk_first, const K* __restrict__ split,
+                                                      int32_t* __restrict__ cnt,
+                                                      int32_t* __restrict__ flag) {
+  constexpr int NC = 2 * BK_NBMAX;
+  __shared__ K sp[BK_NBMAX];
+  __shared__ int lc[NC], lb[NC], gb[NC];
+  __shared__ int w0tot;
+  __shared__ K sl[RS_TILE];
+  __shared__ uint8_t cl[RS_TILE];
+  const SegTile t = tiles[blockIdx.x];
+  const int sg = t.seg;
+  const int64_t so = seg_off[sg];
+  const int64_t base = so + (int64_t)t.tile * RS_TILE;
+  const int nvalid = (int)min((int64_t)RS_TILE, so + seg_len[sg] - base);
+  const int j0 = bk0[sg] - bk_first, nb = bk0[sg + 1] - bk0[sg], nsp = nb - 1;
+  const int tid = threadIdx.x, w = tid >> 6;
+  if (tid < nsp) sp[tid] = split[j0 + tid];
+  if (tid < NC) lc[tid] = 0;
+  __syncthreads();
+  K kv[RS_ITEMS];
+  int cr[RS_ITEMS];   // class << 16 | rank within the tile's class
+#pragma unroll
+  for (int i = 0; i < RS_ITEMS; ++i) {
+    const int q = i * RS_NT + tid;
+    cr[i] = -1;
+    kv[i] = 0;
+    if (q < nvalid) {
+      kv[i] = keys[base + q];
+      const int c = bk_class(kv[i], sp, nsp);
+      cr[i] = (c << 16) | atomicAdd(&lc[c], 1);
+    }
+  }
+  __syncthreads();
+  int stored = 0, x = 0;
+  if (tid < NC) {   // waves 0 and 1: one class each
+    const int n = lc[tid];
+    gb[tid] = n ? atomicAdd(&cnt[2 * j0 + tid], n) : 0;   // n = 0 beyond class 2 nb - 2
+    stored = (tid & 1) ? 0 : n;
+    x = wave_incl_sum(stored);
+    if (tid == 63) w0tot = x;
+  }
+  __syncthreads();
+  if (tid < NC) lb[tid] = x - stored + (w == 1 ? w0tot : 0);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < RS_ITEMS; ++i) {
+    const int c = cr[i] >> 16;
+    if (cr[i] >= 0 && !(c & 1)) {
+      const int p = lb[c] + (cr[i] & 0xFFFF);
+      sl[p] = kv[i];
+      cl[p] = (uint8_t)c;
+    }
+  }
+  __syncthreads();
+  const int nst = lb[NC - 1];   // class NC - 1 is a value class: the total
+  for (int q = tid; q < nst; q += RS_NT) {
+    const int c = cl[q];
+    const int pos = gb[c] + q - lb[c];
+    if (pos < BK_CAP) stg[(int64_t)(j0 + (c >> 1)) * BK_CAP + pos] = sl[q];
+    else *flag = 1;
+  }
+}
+
+// Where bucket jl of the plan goes: its segment's first key, and the keys
+// of the classes before it (every wave reads the counts; no barrier).
+struct BkPlace {
+  int64_t out;   // first output position of the bucket's keys
+  int L;         // keys of the bucket (capped at BK_CAP)
+  int sg, b, j0, nb;
+};
+__device__ inline BkPlace bk_place(int jl, const SegTile* __restrict__ bk_tab,
+                                   const int64_t* __restrict__ seg_off,
+                                   const int32_t* __restrict__ bk0, int bk_first,
+                                   const int32_t* __restrict__ cnt) {
+  BkPlace r;
+  const SegTile e = bk_tab[bk_first + jl];
+  r.sg = e.seg;
+  r.b = e.tile;
+  r.j0 = bk0[r.sg] - bk_first;
+  r.nb = bk0[r.sg + 1] - bk0[r.sg];
+  const int32_t* __restrict__ c = cnt + 2 * r.j0;
+  const int lane = threadIdx.x & 63;
+  int s = 0;
+  for (int k = lane; k < 2 * r.b; k += 64) s += c[k];
+  s = __builtin_amdgcn_readlane(wave_incl_sum(s), 63);
+  r.out = seg_off[r.sg] + s;
+  r.L = min(c[2 * r.b], BK_CAP);
+  return r;
+}
+
+// The bucket's upper splitter value, repeated as often as it occurs.
+template <typename K>
+__device__ inline void bk_fill_value(const BkPlace& pl, K* __restrict__ keys,
+                                     const K* __restrict__ split,
+                                     const int32_t* __restrict__ cnt) {
+  if (pl.b >= pl.nb - 1) return;
+  const int ne = cnt[2 * pl.j0 + 2 * pl.b + 1];
+  const int64_t o = pl.out + cnt[2 * pl.j0 + 2 * pl.b];   // after every key of the range
+  const K v = split[pl.j0 + pl.b];
+  for (int i = threadIdx.x; i < ne; i += SS_NT) keys[o + i] = v;
+}
+
+template <typename K, typename V>
+__device__ inline void bk_write(const BkPlace& pl, const V* __restrict__ sv, K* __restrict__ keys) {
+  for (int i = threadIdx.x; i < pl.L; i += SS_NT) keys[pl.out + i] = (K)key_of_val(sv[i]);
+}
+
+// One block per bucket: the normalised-key passes of k_seg_lds and its
+// check; a bucket whose keys crowd into few normalised keys is marked
+// (mark[jl] = 1) and left to k_bk_sort_slow.
+template <typename K>
+__global__ __launch_bounds__(SS_NT) void k_bk_sort(const K* __restrict__ stg, K* __restrict__ keys,
+                                                   const SegTile* __restrict__ bk_tab,
+                                                   const int64_t* __restrict__ seg_off,
+                                                   const int32_t* __restrict__ bk0, int bk_first,
+                                                   const K* __restrict__ split,
+                                                   const int32_t* __restrict__ cnt,
+                                                   int32_t* __restrict__ mark) {
+  using V = typename std::conditional<sizeof(K) == 8, double, float>::type;
+  constexpr int KPT = BK_KPT;
+  constexpr int CAP = BK_CAP;
+  constexpr int RN = KPT + 1;
+  __shared__ K sk[CAP + RN + 1];
+  __shared__ double scratch[3 * SS_NT];
+  int* wc = reinterpret_cast<int*>(scratch);
+  int* runs = reinterpret_cast<int*>(scratch);
+  __shared__ int gs[4 * 256 + 8];
+  int* wt = gs + 4 * 256;
+  int* flg = gs + 4 * 256 + 4;
+  V* sv = reinterpret_cast<V*>(sk);
+  const int jl = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const BkPlace pl = bk_place(jl, bk_tab, seg_off, bk0, bk_first, cnt);
+  bk_fill_value(pl, keys, split, cnt);
+  const int L = pl.L;
+  if (L == 0) {   // uniform
+    if (tid == 0) mark[jl] = 0;
+    return;
+  }
+  const K* __restrict__ src = stg + (int64_t)jl * BK_CAP;
+  K kv[KPT];
+#pragma unroll
+  for (int i = 0; i < KPT; ++i) {
+    const int pos = w * KPT * 64 + i * 64 + lane;
+    kv[i] = pos < L ? src[pos] : ~(K)0;
+  }
+  const int S = ((L + SS_NT - 1) / SS_NT) | 1;
+  const int a0 = min(tid * S, L), a1 = min(a0 + S, L);
+  const int n = a1 - a0;
+  DigitNorm dn;
+  {
+    uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+#pragma unroll
+    for (int i = 0; i < KPT; ++i) {
+      const uint32_t hk = (uint32_t)(kv[i] >> (8 * sizeof(K) - 32));
+      mn = min(mn, hk);
+      if (w * KPT * 64 + i * 64 + lane < L) mx = max(mx, hk);
+    }
+    mn = wave_min_u32(mn);
+    mx = wave_max_u32(mx);
+    uint32_t* rr = reinterpret_cast<uint32_t*>(scratch + 2 * SS_NT);
+    if (lane == 0) {
+      rr[w] = mn;
+      rr[SS_WV + w] = mx;
+    }
+    if (tid < 3) flg[tid] = 0;
+  }
+  lds_radix_pass<K, RK_ATOM, DigitNorm, KPT, false, true>(
+      kv, 0, dn, sk, wc, gs, wt, reinterpret_cast<const uint32_t*>(scratch + 2 * SS_NT));
+  lds_radix_pass<K, RK_ATOM, DigitNorm, KPT>(kv, 8, dn, sk, wc, gs, wt);
+  lds_radix_pass<K, RK_ATOM, DigitNorm, KPT, true>(kv, 16, dn, sk, wc, gs, wt);
+  V x[RN];
+  if (check_fix<V, RN>(sv, L, a0, n, x, KeyNormV{dn}, NORM_MAX_DESC, flg, runs)) {
+    if (tid == 0) mark[jl] = 1;
+    return;
+  }
+  if (tid == 0) mark[jl] = 0;
+  bk_write(pl, sv, keys);
+}
+
+// The buckets k_bk_sort marked, each by one block of a small grid (at most
+// SS_NT buckets per block): the order-key passes and the full-width sort
+// of k_seg_lds_slow.
+template <typename K>
+__global__ __launch_bounds__(SS_NT) void k_bk_sort_slow(const K* __restrict__ stg,
+                                                        K* __restrict__ keys,
+                                                        const SegTile* __restrict__ bk_tab,
+                                                        const int64_t* __restrict__ seg_off,
+                                                        const int32_t* __restrict__ bk0,
+                                                        int bk_first, int nbk,
+                                                        const int32_t* __restrict__ cnt,
+                                                        const int32_t* __restrict__ mark) {
+  using V = typename std::conditional<sizeof(K) == 8, double, float>::type;
+  constexpr int KPT = BK_KPT;
+  constexpr int CAP = BK_CAP;
+  constexpr int RN = KPT + 1;
+  __shared__ K sk[CAP + RN + 1];
+  __shared__ double scratch[3 * SS_NT];
+  int* wc = reinterpret_cast<int*>(scratch);
+  int* runs = reinterpret_cast<int*>(scratch);
+  __shared__ int gs[4 * 256 + 8];
+  int* wt = gs + 4 * 256;
+  int* flg = gs + 4 * 256 + 4;
+  V* sv = reinterpret_cast<V*>(sk);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  __shared__ uint32_t redo_bits[SS_NT / 32];
+  if (tid < SS_NT / 32) redo_bits[tid] = 0u;
+  __syncthreads();
+  if (blockIdx.x + (int64_t)tid * gridDim.x < nbk && mark[blockIdx.x + tid * gridDim.x])
+    atomicOr(&redo_bits[tid >> 5], 1u << (tid & 31));
+  __syncthreads();
+  for (int wd = 0; wd < SS_NT / 32; ++wd)
+  for (uint32_t bits = redo_bits[wd]; bits; bits &= bits - 1u) {   // uniform
+    const int jl = blockIdx.x + (wd * 32 + __ffs(bits) - 1) * gridDim.x;
+    const BkPlace pl = bk_place(jl, bk_tab, seg_off, bk0, bk_first, cnt);
+    const int L = pl.L;
+    const K* __restrict__ src = stg + (int64_t)jl * BK_CAP;
+    K kv[KPT];
+    auto load = [&]() {
+#pragma unroll
+      for (int i = 0; i < KPT; ++i) {
+        const int pos = w * KPT * 64 + i * 64 + lane;
+        kv[i] = pos < L ? src[pos] : ~(K)0;
+      }
+    };
+    const int S = ((L + SS_NT - 1) / SS_NT) | 1;
+    const int a0 = min(tid * S, L), a1 = min(a0 + S, L), n = a1 - a0;
+    __syncthreads();   // the previous bucket is done with the shared arrays
+    if (tid < 3) flg[tid] = 0;
+    load();
+    DigitKey32 d32;
+    lds_radix_pass<K, RK_ATOM, DigitKey32, KPT>(kv, 0, d32, sk, wc, gs, wt);
+    lds_radix_pass<K, RK_ATOM, DigitKey32, KPT>(kv, 8, d32, sk, wc, gs, wt);
+    lds_radix_pass<K, RK_ATOM, DigitKey32, KPT>(kv, 16, d32, sk, wc, gs, wt);
+    lds_radix_pass<K, RK_PEEL, DigitKey32, KPT, true>(kv, 24, d32, sk, wc, gs, wt);
+    V x[RN];
+    if (check_fix<V, RN>(sv, L, a0, n, x, Key32{}, CAP, flg, runs)) {
+      __syncthreads();
+      load();
+      DigitFull df;
+#pragma unroll 1
+      for (int shift = 0; shift < 8 * (int)sizeof(K) - 8; shift += 8)
+        lds_radix_pass<K, RK_BALLOT, DigitFull, KPT>(kv, shift, df, sk, wc, gs, wt);
+      lds_radix_pass<K, RK_BALLOT, DigitFull, KPT, true>(kv, 8 * (int)sizeof(K) - 8, df, sk, wc,
+                                                         gs, wt);
+    }
+    bk_write(pl, sv, keys);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Univariate MCD over long sorted segments, spread over many blocks (the
 // radix tiles, RS_TILE keys each): block sums -> per-segment prefix -> window
 // minima per block -> per-segment choice of the window -> kept-row sums ->
@@ -1332,16 +1673,26 @@ constexpr int MB_NT = RS_NT;                  // 256 threads, RS_ITEMS keys each
 
 constexpr int MB_WV = MB_NT / 64;
 
-// Centred partial sums of v[a, b) by the whole block: lane-strided (coalesced)
-// loads, a fixed order per thread, then block sums.
+// Centred partial sums of v[a, b), b - a <= RS_TILE, by the whole block:
+// lane-strided (coalesced) loads, all issued before the first sum, a fixed
+// order per thread, then block sums.
 template <typename K>
 __device__ inline void blk_range_sums(const K* __restrict__ v, int64_t a, int64_t b, double c,
                                       double* red, double& s1, double& s2) {
   double l[2] = {0.0, 0.0};
-  for (int64_t k = a + threadIdx.x; k < b; k += MB_NT) {
-    const double d = val_of<K>(v[k]) - c;
-    l[0] += d;
-    l[1] = fma(d, d, l[1]);
+  K kv[RS_ITEMS];
+#pragma unroll
+  for (int i = 0; i < RS_ITEMS; ++i) {
+    const int64_t k = a + i * MB_NT + threadIdx.x;
+    kv[i] = k < b ? v[k] : (K)0;
+  }
+#pragma unroll
+  for (int i = 0; i < RS_ITEMS; ++i) {
+    if (a + i * MB_NT + threadIdx.x < b) {
+      const double d = val_of<K>(kv[i]) - c;
+      l[0] += d;
+      l[1] = fma(d, d, l[1]);
+    }
   }
   block_sums<2, MB_WV>(l, red);
   s1 = l[0];
@@ -1453,11 +1804,20 @@ __global__ __launch_bounds__(MB_NT) void k_mb_window(const K* __restrict__ keys,
   double best = INFINITY;
   int64_t bj = -1;
   if (a < nw) {   // uniform over the block
-    for (int q = tid; q < RS_TILE; q += MB_NT) {
-      const int qs = q + q / RS_ITEMS;
-      const int64_t pl = a + q, ph = a + hh + q;
-      sl[qs] = pl < L ? v[pl] : v[L - 1];
-      sh[qs] = ph < L ? v[ph] : v[L - 1];
+    {
+      K lo[RS_ITEMS], hi[RS_ITEMS];   // every load issued before the first store
+#pragma unroll
+      for (int i = 0; i < RS_ITEMS; ++i) {
+        const int64_t pl = a + i * MB_NT + tid, ph = pl + hh;
+        lo[i] = v[pl < L ? pl : L - 1];
+        hi[i] = v[ph < L ? ph : L - 1];
+      }
+#pragma unroll
+      for (int i = 0; i < RS_ITEMS; ++i) {
+        const int q = i * MB_NT + tid;
+        sl[q + q / RS_ITEMS] = lo[i];
+        sh[q + q / RS_ITEMS] = hi[i];
+      }
     }
     __syncthreads();
     double x1, x2;   // P at a + hh (block-wide, ends with a barrier)
@@ -1608,8 +1968,16 @@ __global__ __launch_bounds__(MB_NT) void k_mb_kept(const K* __restrict__ keys,
   const double c = P[0], mu = P[1], lim = P[3];
   const int64_t a = (int64_t)t.tile * RS_TILE, b = min(a + (int64_t)RS_TILE, L);
   double cs[3] = {0.0, 0.0, 0.0};
-  for (int64_t k = a + threadIdx.x; k < b; k += MB_NT) {
-    const double x = val_of<K>(v[k]);
+  K kv[RS_ITEMS];   // every load issued before the first sum
+#pragma unroll
+  for (int i = 0; i < RS_ITEMS; ++i) {
+    const int64_t k = a + i * MB_NT + threadIdx.x;
+    kv[i] = k < b ? v[k] : (K)0;
+  }
+#pragma unroll
+  for (int i = 0; i < RS_ITEMS; ++i) {
+    if (a + i * MB_NT + threadIdx.x >= b) continue;
+    const double x = val_of<K>(kv[i]);
     const double e = x - mu;
     if (e * e <= lim) {
       const double d = x - c;
@@ -1766,6 +2134,36 @@ hipError_t launch_seg_lds(const SortPlan& P, const double* seg_craw, double q1, 
 }
 
 int lds_sort_capacity() { return LDS_KEYS; }
+
+int64_t bucket_count(int64_t L) { return L <= BK_CAP ? 1 : (L + BK_EXP - 1) / BK_EXP; }
+int bucket_capacity() { return BK_CAP; }
+int64_t bucket_max_len() { return (int64_t)BK_NBMAX * BK_EXP; }
+
+template <typename K>
+hipError_t sort_buckets_t(SortPlan& P, hipStream_t s) {
+  K* keys = static_cast<K*>(P.keys);
+  K* stg = static_cast<K*>(P.tmp);
+  // class counters [2 nbk], splitters [nbk], marks [nbk] in the tile counts
+  int32_t* cnt = P.counts;
+  K* split = reinterpret_cast<K*>(P.counts + 2 * (size_t)P.nbk);
+  int32_t* mark = P.counts + 2 * (size_t)P.nbk + (size_t)P.nbk * sizeof(K) / 4;
+  hipLaunchKernelGGL((k_bk_sample<K>), dim3(P.nseg), dim3(BK_NT), 0, s, keys, P.seg_off,
+                     P.seg_len, P.bk0, P.seg_first, P.bk_first, split, cnt);
+  hipLaunchKernelGGL((k_bk_scatter<K>), dim3(P.ntiles), dim3(RS_NT), 0, s, keys, stg, P.tiles,
+                     P.seg_off, P.seg_len, P.bk0, P.bk_first, split, cnt, P.flag);
+  hipLaunchKernelGGL((k_bk_sort<K>), dim3(P.nbk), dim3(SS_NT), 0, s, stg, keys, P.bk_tab,
+                     P.seg_off, P.bk0, P.bk_first, split, cnt, mark);
+  // at most SS_NT buckets per block of the slow kernel
+  const int slow_grid = std::min(P.nbk, std::max(256, (P.nbk + SS_NT - 1) / SS_NT));
+  hipLaunchKernelGGL((k_bk_sort_slow<K>), dim3(slow_grid), dim3(SS_NT), 0, s, stg, keys,
+                     P.bk_tab, P.seg_off, P.bk0, P.bk_first, P.nbk, cnt, mark);
+  return hipGetLastError();
+}
+
+hipError_t sort_buckets(SortPlan& P, hipStream_t s) {
+  if (P.nseg <= 0 || P.nbk <= 0) return hipSuccess;
+  return P.key_bytes == 4 ? sort_buckets_t<uint32_t>(P, s) : sort_buckets_t<uint64_t>(P, s);
+}
 
 template <typename K>
 hipError_t unimcd_multiblock_t(const SortPlan& P, const double* seg_craw, double q1, double crew,

@@ -38,9 +38,17 @@ struct SortPlan {
   int safe = 0;                 // 1: rank equal digits with ballots, not LDS atomics
   int32_t* flag = nullptr;      // set to 1 when a sorted segment is found out of order
   int seg_first = 0;            // absolute index of the first segment of the plan
-  // The plan restricted to segments [a, b): pointers offset, tile counts
-  // given by the host copy of the absolute seg_tile0 table.
-  SortPlan sub(int a, int b, const int32_t* host_seg_tile0) const {
+  // Buckets of the sample sort (sort_buckets): segment s owns the buckets
+  // [bk0[s], bk0[s + 1]) (absolute), bucket j is (bk_tab[j].seg, bk_tab[j].tile =
+  // its rank within the segment).  Of a plan, buckets [bk_first, + nbk).
+  const int32_t* bk0 = nullptr;     // [nseg + 1]
+  const SegTile* bk_tab = nullptr;
+  int bk_first = 0;
+  int nbk = 0;
+  // The plan restricted to segments [a, b): pointers offset, tile and
+  // bucket counts given by the host copies of the absolute seg_tile0 and
+  // bk0 tables.
+  SortPlan sub(int a, int b, const int32_t* host_seg_tile0, const int32_t* host_bk0) const {
     SortPlan r = *this;
     const int ta = host_seg_tile0[a], tb = host_seg_tile0[b];
     r.nseg = b - a;
@@ -53,6 +61,8 @@ struct SortPlan {
     r.counts = counts + (size_t)ta * 256;
     r.offs = offs + (size_t)ta * 256;
     r.tile_first = ta;
+    r.bk_first = host_bk0[a];
+    r.nbk = host_bk0[b] - host_bk0[a];
     return r;
   }
 };
@@ -78,5 +88,15 @@ hipError_t launch_unimcd_multiblock(const SortPlan& P, const double* seg_craw, d
                                     double crew, SegStat* out, hipStream_t s);
 hipError_t launch_seg_lds(const SortPlan& P, const double* seg_craw, double q1, double crew,
                           int mode, SegStat* out, int64_t max_len, hipStream_t s);
+
+// Sample sort of segments of 64-bit keys, each at most bucket_max_len() long
+// (P.keys sorted in place): bucket_count(L) buckets per segment of L keys,
+// each sorted in LDS, with P.tmp holding nbk * bucket_capacity() keys and
+// P.counts at least 5 nbk ints.  A bucket that outgrows its capacity sets
+// *P.flag (the caller then sorts again with the radix passes).
+int64_t bucket_count(int64_t L);
+int bucket_capacity();
+int64_t bucket_max_len();
+hipError_t sort_buckets(SortPlan& P, hipStream_t s);
 
 }  // namespace rtd
