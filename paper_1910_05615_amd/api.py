@@ -96,8 +96,10 @@ def make_opts(alpha: float = 0.75, standardize: str = "unimcd", cstep_mode: str 
 
 
 def plan(n: int, p: int, h_sub: int = 0, n_chunks: int = 0, **opts):
-    lib = _lib.load()
-    o = make_opts(**opts)
+    return _plan_o(_lib.load(), n, p, h_sub, n_chunks, make_opts(**opts))
+
+
+def _plan_o(lib, n: int, p: int, h_sub: int, n_chunks: int, o):
     q, m, h = C.c_int32(), C.c_int64(), C.c_int64()
     st = lib.rtdetmcd_plan(n, p, h_sub, n_chunks, C.byref(o), C.byref(q), C.byref(m), C.byref(h))
     if st != 0:
@@ -295,6 +297,54 @@ def _alloc_fit(X: torch.Tensor, q: int, m: int, h: int):
     return F, out
 
 
+def _alloc_fits(Xs, plans):
+    """The outputs of many fits: one device allocation per element type for
+    the whole batch (every Fit's tensors are views of it), split in one
+    call per type; the pointers handed to the library are computed from the
+    offsets."""
+    dev = Xs[0].device
+    fsz, isz, usz = [], [], []
+    for X, (q, m, h) in zip(Xs, plans):
+        n, p = X.shape
+        fsz.append(4 * p + 2 * p * p + 2 + n)
+        isz.append(q * h + 3 * q)
+        usz.append(2 * n)
+    k = len(Xs)
+    f_all = torch.empty(sum(fsz), dtype=torch.float64, device=dev)
+    i_all = torch.empty(sum(isz), dtype=torch.int32, device=dev)
+    u_all = torch.empty(sum(usz), dtype=torch.uint8, device=dev)
+    w_all = torch.empty(k, dtype=torch.int64, device=dev)
+    fb, ib, ub, wb = f_all.data_ptr(), i_all.data_ptr(), u_all.data_ptr(), w_all.data_ptr()
+    fparts, iparts, uparts = f_all.split(fsz), i_all.split(isz), u_all.split(usz)
+    wparts = w_all.split(1)
+    fits, outs = [], []
+    fo = io = uo = 0
+    for j, (X, (q, m, h)) in enumerate(zip(Xs, plans)):
+        n, p = X.shape
+        pp = p * p
+        mu, sg, mr, sr, ld, loc, sc, dist = fparts[j].split([p, pp, p, pp, 2, p, p, n])
+        hs, bst, bsa, bit = iparts[j].split([q * h, q, q, q])
+        out_u, rew = uparts[j].split([n, n])
+        F = Fit(mu=mu, sigma=sg.view(p, p), mu_raw=mr, sigma_raw=sr.view(p, p), logdet=ld,
+                loc=loc, scale=sc, dist=dist, hsubset=hs.view(q, h), block_status=bst,
+                block_start=bsa, block_iters=bit, outlier=out_u, rew_mask=rew, n_w=wparts[j],
+                q=q, m=m, h=h)
+        f0, i0, u0 = fb + 8 * fo, ib + 4 * io, ub + uo
+        outs.append(_lib.Out(mu=f0, sigma=f0 + 8 * p, mu_raw=f0 + 8 * (p + pp),
+                             sigma_raw=f0 + 8 * (2 * p + pp), logdet=f0 + 8 * (2 * p + 2 * pp),
+                             loc=f0 + 8 * (2 * p + 2 * pp + 2),
+                             scale=f0 + 8 * (3 * p + 2 * pp + 2),
+                             dist=f0 + 8 * (4 * p + 2 * pp + 2), hsubset=i0,
+                             block_status=i0 + 4 * q * h, block_start=i0 + 4 * (q * h + q),
+                             block_iters=i0 + 4 * (q * h + 2 * q), outlier=u0, rew_mask=u0 + n,
+                             n_w=wb + 8 * j))
+        fits.append(F)
+        fo += fsz[j]
+        io += isz[j]
+        uo += usz[j]
+    return fits, outs
+
+
 def random_partition(n: int, seed: int, device=None) -> torch.Tensor:
     """A random permutation of the n rows (int32, on `device`) for the random
     partition of Sec. 4: block l of a fit given ``perm`` is rows
@@ -398,15 +448,17 @@ def fit_batched(Xs: Sequence[torch.Tensor], h_subs: Optional[Sequence[int]] = No
     perms = list(perms) if perms is not None else [None] * k
     warms = list(warms) if warms is not None else [None] * k
     arr = (_lib.DatasetDesc * k)()
-    fits = []
     keep = []   # warm-start tensors stay alive until the call returns
+    plans = []
     for i, X in enumerate(Xs):
         _check_X(X)
         n, p = X.shape
-        q, m, h = plan(n, p, h_subs[i], n_chunks[i], **opts)
-        F, out = _alloc_fit(X, q, m, h)
+        plans.append(_plan_o(lib, n, p, h_subs[i], n_chunks[i], o))
+    fits, outs = _alloc_fits(Xs, plans) if k else ([], [])
+    for i, X in enumerate(Xs):
+        n, p = X.shape
+        F, out = fits[i], outs[i]
         F.c_rew = lib.rtdetmcd_consistency(o.cutoff_q, p) if o.rew_consistency else 1.0
-        fits.append(F)
         pm = perms[i]
         if pm is not None:
             if (pm.dtype != torch.int32 or pm.device != X.device or pm.dim() != 1

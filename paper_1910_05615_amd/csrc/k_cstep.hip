@@ -383,7 +383,26 @@ __global__ __launch_bounds__(SEL_NT) void k_select(const ItemDesc* __restrict__ 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint64_t below = (1ull << lane) - 1ull;
   constexpr int CH = SEL_NT * SEL_KR;
+  // the threshold passes walk the chunks with the next chunk's loads in
+  // flight while the current one is worked on: prime(), then next(c0) at
+  // the top of the chunk at c0; the membership pass (more live state) loads
+  // each chunk when it reaches it, load(c0).  Keys of rows beyond m are 0.
   uint64_t key[SEL_KR];
+  double nraw[SEL_KR];
+  auto fetch = [&](int64_t c0) {
+#pragma unroll
+    for (int i = 0; i < SEL_KR; ++i) {
+      const int64_t r = c0 + i * SEL_NT + tid;
+      nraw[i] = r < m ? d2[r] : 0.0;
+    }
+  };
+  auto prime = [&]() { fetch(0); };
+  auto next = [&](int64_t c0) {
+#pragma unroll
+    for (int i = 0; i < SEL_KR; ++i)
+      key[i] = c0 + i * SEL_NT + tid < m ? key_of(nraw[i]) : 0ull;
+    if (c0 + CH < m) fetch(c0 + CH);
+  };
   auto load = [&](int64_t c0) {
 #pragma unroll
     for (int i = 0; i < SEL_KR; ++i) {
@@ -397,8 +416,9 @@ __global__ __launch_bounds__(SEL_NT) void k_select(const ItemDesc* __restrict__ 
   bool take_all = false;
   {
     uint64_t kmn = ~0ull, kmx = 0ull;
+    prime();
     for (int64_t c0 = 0; c0 < m; c0 += CH) {
-      load(c0);
+      next(c0);
 #pragma unroll
       for (int i = 0; i < SEL_KR; ++i)
         if (c0 + i * SEL_NT + tid < m) {
@@ -430,8 +450,9 @@ __global__ __launch_bounds__(SEL_NT) void k_select(const ItemDesc* __restrict__ 
       const uint64_t b = (k - kmn) >> sh;
       return b < (uint64_t)SEL_NB ? (int)b : SEL_NB - 1;
     };
+    prime();
     for (int64_t c0 = 0; c0 < m; c0 += CH) {
-      load(c0);
+      next(c0);
 #pragma unroll
       for (int i = 0; i < SEL_KR; ++i)
         if (c0 + i * SEL_NT + tid < m) atomicAdd(&hist[bin_of(key[i])], 1u);
@@ -456,8 +477,9 @@ __global__ __launch_bounds__(SEL_NT) void k_select(const ItemDesc* __restrict__ 
     const int64_t k1 = rank - s_below;
     if (cnt <= SEL_CMAX) {   // uniform
       uint64_t* ck = reinterpret_cast<uint64_t*>(hist);
+      prime();
       for (int64_t c0 = 0; c0 < m; c0 += CH) {
-        load(c0);
+        next(c0);
 #pragma unroll
         for (int i = 0; i < SEL_KR; ++i)
           if (c0 + i * SEL_NT + tid < m && bin_of(key[i]) == bstar)
