@@ -1519,6 +1519,19 @@ __device__ inline void bk_write(const BkPlace& pl, const V* __restrict__ sv, K* 
   for (int i = threadIdx.x; i < pl.L; i += SS_NT) keys[pl.out + i] = (K)key_of_val(sv[i]);
 }
 
+// The bucket kernels instantiate the shared passes and checks with types of
+// their own: sharing the instantiations of k_seg_lds made the compiler
+// spill 62 registers in k_seg_lds<uint64_t, 16> (none with separate ones).
+struct BkNorm : DigitNorm {};
+struct BkKey32Digit : DigitKey32 {};
+struct BkFullDigit : DigitFull {};
+struct BkKeyNorm {
+  BkNorm dn;
+  __device__ uint32_t of_val(double x) const { return dn.of_val(x); }
+  __device__ uint32_t of_val(float x) const { return dn.of_val((double)x); }
+};
+struct BkKey32 : Key32 {};
+
 // One block per bucket: the normalised-key passes of k_seg_lds and its
 // check; a bucket whose keys crowd into few normalised keys is marked
 // (mark[jl] = 1) and left to k_bk_sort_slow.
@@ -1561,7 +1574,7 @@ __global__ __launch_bounds__(SS_NT) void k_bk_sort(const K* __restrict__ stg, K*
   const int S = ((L + SS_NT - 1) / SS_NT) | 1;
   const int a0 = min(tid * S, L), a1 = min(a0 + S, L);
   const int n = a1 - a0;
-  DigitNorm dn;
+  BkNorm dn;
   {
     uint32_t mn = 0xFFFFFFFFu, mx = 0u;
 #pragma unroll
@@ -1579,12 +1592,12 @@ __global__ __launch_bounds__(SS_NT) void k_bk_sort(const K* __restrict__ stg, K*
     }
     if (tid < 3) flg[tid] = 0;
   }
-  lds_radix_pass<K, RK_ATOM, DigitNorm, KPT, false, true>(
+  lds_radix_pass<K, RK_ATOM, BkNorm, KPT, false, true>(
       kv, 0, dn, sk, wc, gs, wt, reinterpret_cast<const uint32_t*>(scratch + 2 * SS_NT));
-  lds_radix_pass<K, RK_ATOM, DigitNorm, KPT>(kv, 8, dn, sk, wc, gs, wt);
-  lds_radix_pass<K, RK_ATOM, DigitNorm, KPT, true>(kv, 16, dn, sk, wc, gs, wt);
+  lds_radix_pass<K, RK_ATOM, BkNorm, KPT>(kv, 8, dn, sk, wc, gs, wt);
+  lds_radix_pass<K, RK_ATOM, BkNorm, KPT, true>(kv, 16, dn, sk, wc, gs, wt);
   V x[RN];
-  if (check_fix<V, RN>(sv, L, a0, n, x, KeyNormV{dn}, NORM_MAX_DESC, flg, runs)) {
+  if (check_fix<V, RN>(sv, L, a0, n, x, BkKeyNorm{dn}, NORM_MAX_DESC, flg, runs)) {
     if (tid == 0) mark[jl] = 1;
     return;
   }
@@ -1642,20 +1655,20 @@ __global__ __launch_bounds__(SS_NT) void k_bk_sort_slow(const K* __restrict__ st
     __syncthreads();   // the previous bucket is done with the shared arrays
     if (tid < 3) flg[tid] = 0;
     load();
-    DigitKey32 d32;
-    lds_radix_pass<K, RK_ATOM, DigitKey32, KPT>(kv, 0, d32, sk, wc, gs, wt);
-    lds_radix_pass<K, RK_ATOM, DigitKey32, KPT>(kv, 8, d32, sk, wc, gs, wt);
-    lds_radix_pass<K, RK_ATOM, DigitKey32, KPT>(kv, 16, d32, sk, wc, gs, wt);
-    lds_radix_pass<K, RK_PEEL, DigitKey32, KPT, true>(kv, 24, d32, sk, wc, gs, wt);
+    BkKey32Digit d32;
+    lds_radix_pass<K, RK_ATOM, BkKey32Digit, KPT>(kv, 0, d32, sk, wc, gs, wt);
+    lds_radix_pass<K, RK_ATOM, BkKey32Digit, KPT>(kv, 8, d32, sk, wc, gs, wt);
+    lds_radix_pass<K, RK_ATOM, BkKey32Digit, KPT>(kv, 16, d32, sk, wc, gs, wt);
+    lds_radix_pass<K, RK_PEEL, BkKey32Digit, KPT, true>(kv, 24, d32, sk, wc, gs, wt);
     V x[RN];
-    if (check_fix<V, RN>(sv, L, a0, n, x, Key32{}, CAP, flg, runs)) {
+    if (check_fix<V, RN>(sv, L, a0, n, x, BkKey32{}, CAP, flg, runs)) {
       __syncthreads();
       load();
-      DigitFull df;
+      BkFullDigit df;
 #pragma unroll 1
       for (int shift = 0; shift < 8 * (int)sizeof(K) - 8; shift += 8)
-        lds_radix_pass<K, RK_BALLOT, DigitFull, KPT>(kv, shift, df, sk, wc, gs, wt);
-      lds_radix_pass<K, RK_BALLOT, DigitFull, KPT, true>(kv, 8 * (int)sizeof(K) - 8, df, sk, wc,
+        lds_radix_pass<K, RK_BALLOT, BkFullDigit, KPT>(kv, shift, df, sk, wc, gs, wt);
+      lds_radix_pass<K, RK_BALLOT, BkFullDigit, KPT, true>(kv, 8 * (int)sizeof(K) - 8, df, sk, wc,
                                                          gs, wt);
     }
     bk_write(pl, sv, keys);
