@@ -383,10 +383,11 @@ __global__ __launch_bounds__(SEL_NT) void k_select(const ItemDesc* __restrict__ 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint64_t below = (1ull << lane) - 1ull;
   constexpr int CH = SEL_NT * SEL_KR;
-  // the threshold passes walk the chunks with the next chunk's loads in
-  // flight while the current one is worked on: prime(), then next(c0) at
-  // the top of the chunk at c0; the membership pass (more live state) loads
-  // each chunk when it reaches it, load(c0).  Keys of rows beyond m are 0.
+  // the bounds and histogram passes walk the chunks with the next chunk's
+  // loads in flight while the current one is worked on: prime(), then
+  // next(c0) at the top of the chunk at c0; the candidate and membership
+  // passes (more live state: prefetching there spills) load each chunk when
+  // they reach it, load(c0).  Keys of rows beyond m are 0.
   uint64_t key[SEL_KR];
   double nraw[SEL_KR];
   auto fetch = [&](int64_t c0) {
@@ -477,9 +478,8 @@ __global__ __launch_bounds__(SEL_NT) void k_select(const ItemDesc* __restrict__ 
     const int64_t k1 = rank - s_below;
     if (cnt <= SEL_CMAX) {   // uniform
       uint64_t* ck = reinterpret_cast<uint64_t*>(hist);
-      prime();
       for (int64_t c0 = 0; c0 < m; c0 += CH) {
-        next(c0);
+        load(c0);
 #pragma unroll
         for (int i = 0; i < SEL_KR; ++i)
           if (c0 + i * SEL_NT + tid < m && bin_of(key[i]) == bstar)
