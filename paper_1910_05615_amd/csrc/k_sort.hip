@@ -689,13 +689,23 @@ struct DigitKey32 {   // the high 32 bits of the key (all of a float key)
     return (int)(((uint32_t)(k >> (8 * sizeof(K) - 32)) >> shift) & 0xFFu);
   }
 };
-// The segment-normalised 24-bit key floor((x - lo) 2^24 / (hi - lo)) of the
-// item's value x, clamped to [0, 2^24 - 1] (padding: 2^24 - 1).  Each step
-// (fma with a positive scale, clamps, truncation) is monotone in x, so its
-// order never contradicts the order of the values; unlike the high bits of
-// the order key, all three digits spread over the segment's values.
+// Padding of a block's key slots beyond the segment: slot q holds the order
+// key ~0 - q (a NaN pattern, above every real key), so padded slots spread
+// over the digits instead of all ranking on one counter.
+template <typename K>
+__device__ inline K pad_key(int q) { return ~(K)0 - (K)q; }
+template <typename K>
+__device__ inline bool is_pad(K k) { return k > ~(K)0 - (K)65536; }
+constexpr uint32_t NORM_TOP = 16777216u - 4096u;   // real keys below, padding from here
+
+// The segment-normalised 24-bit key floor((x - lo) T / (hi - lo)) of the
+// item's value x, T = 2^24 - 2^12, clamped to [0, T - 1]; padding slot q
+// takes T + (q mod 2^12).  Each step (fma with a positive scale, clamps,
+// truncation) is monotone in x, so its order never contradicts the order of
+// the values; unlike the high bits of the order key, all three digits
+// spread over the segment's values.
 struct DigitNorm {
-  double sc, off;   // 2^24 / (hi - lo), -lo sc
+  double sc, off;   // T / (hi - lo), -lo sc
   // From per-wave bounds of the high 32 bits of the order keys, rr[0..16)
   // (minima) and rr[16..32) (maxima), read after a barrier: 16 lanes of
   // every wave reduce them, so every lane gets the same values, kept in
@@ -725,17 +735,17 @@ struct DigitNorm {
       lo = val_of<K>((K)mn);
       hi = val_of<K>((K)mx);
     }
-    const double s = 16777216.0 / (hi - lo);
+    const double s = (double)NORM_TOP / (hi - lo);
     sc = uniform_d((hi > lo && s < 1e300) ? s : 0.0);
     off = uniform_d(-lo * sc);
   }
   __device__ uint32_t of_val(double x) const {
-    const double t = fmin(fmax(fma(x, sc, off), 0.0), 16777215.0);
+    const double t = fmin(fmax(fma(x, sc, off), 0.0), (double)(NORM_TOP - 1u));
     return (uint32_t)t;
   }
   template <typename K>
   __device__ uint32_t of_key(K k) const {
-    return k == ~(K)0 ? 16777215u : of_val(val_of<K>(k));
+    return is_pad<K>(k) ? NORM_TOP + ((uint32_t)~k & 4095u) : of_val(val_of<K>(k));
   }
   template <typename K>
   __device__ int operator()(K k, int shift) const { return (int)((of_key<K>(k) >> shift) & 0xFFu); }
@@ -1176,13 +1186,12 @@ __global__ __launch_bounds__(SS_NT) void k_seg_lds(const K* __restrict__ keys,
     if (tid == 0) out[sb] = SegStat{};
     return;
   }
-  const K pad = ~(K)0;
   K kv[KPT];
   auto load = [&]() {
 #pragma unroll
     for (int i = 0; i < KPT; ++i) {
       const int pos = w * KPT * 64 + i * 64 + lane;
-      kv[i] = pos < L ? src[pos] : pad;
+      kv[i] = pos < L ? src[pos] : pad_key<K>(pos);
     }
   };
   // this thread's contiguous range of sorted positions: S (odd) from t S
@@ -1286,7 +1295,7 @@ __global__ __launch_bounds__(SS_NT) void k_seg_lds_slow(const K* __restrict__ ke
 #pragma unroll
       for (int i = 0; i < KPT; ++i) {
         const int pos = w * KPT * 64 + i * 64 + lane;
-        kv[i] = pos < L ? src[pos] : ~(K)0;
+        kv[i] = pos < L ? src[pos] : pad_key<K>(pos);
       }
     };
     const int S = ((L + SS_NT - 1) / SS_NT) | 1;
@@ -1569,7 +1578,7 @@ __global__ __launch_bounds__(SS_NT) void k_bk_sort(const K* __restrict__ stg, K*
 #pragma unroll
   for (int i = 0; i < KPT; ++i) {
     const int pos = w * KPT * 64 + i * 64 + lane;
-    kv[i] = pos < L ? src[pos] : ~(K)0;
+    kv[i] = pos < L ? src[pos] : pad_key<K>(pos);
   }
   const int S = ((L + SS_NT - 1) / SS_NT) | 1;
   const int a0 = min(tid * S, L), a1 = min(a0 + S, L);
@@ -1647,7 +1656,7 @@ __global__ __launch_bounds__(SS_NT) void k_bk_sort_slow(const K* __restrict__ st
 #pragma unroll
       for (int i = 0; i < KPT; ++i) {
         const int pos = w * KPT * 64 + i * 64 + lane;
-        kv[i] = pos < L ? src[pos] : ~(K)0;
+        kv[i] = pos < L ? src[pos] : pad_key<K>(pos);
       }
     };
     const int S = ((L + SS_NT - 1) / SS_NT) | 1;
