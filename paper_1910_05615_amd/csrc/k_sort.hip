@@ -1410,10 +1410,12 @@ __global__ __launch_bounds__(BK_NT) void k_bk_sample(const K* __restrict__ keys,
 }
 
 // One block per radix tile (RS_TILE keys of one segment): the class of
-// every key, one atomic per class for the tile's place in its bucket, then
-// the range keys, grouped by class in LDS, written to their buckets'
-// staging slots (stg[j BK_CAP ...] for bucket j of the plan).  Value
-// classes are only counted.  A bucket filled beyond BK_CAP sets *flag.
+// every key and its rank within the tile's keys of that class (LDS
+// atomics), one global atomic per class for the tile's place in its
+// bucket, then each range key written straight to its bucket's staging
+// slots (stg[j BK_CAP ...] for bucket j of the plan): a tile's keys of one
+// class land in one contiguous run.  Value classes are only counted.  A
+// bucket filled beyond BK_CAP sets *flag.
 template <typename K>
 __global__ __launch_bounds__(RS_NT) void k_bk_scatter(const K* __restrict__ keys,
                                                       K* __restrict__ stg,
@@ -1426,17 +1428,14 @@ __global__ __launch_bounds__(RS_NT) void k_bk_scatter(const K* __restrict__ keys
                                                       int32_t* __restrict__ flag) {
   constexpr int NC = 2 * BK_NBMAX;
   __shared__ K sp[BK_NBMAX];
-  __shared__ int lc[NC], lb[NC], gb[NC];
-  __shared__ int w0tot;
-  __shared__ K sl[RS_TILE];
-  __shared__ uint8_t cl[RS_TILE];
+  __shared__ int lc[NC], gb[NC];
   const SegTile t = tiles[blockIdx.x];
   const int sg = t.seg;
   const int64_t so = seg_off[sg];
   const int64_t base = so + (int64_t)t.tile * RS_TILE;
   const int nvalid = (int)min((int64_t)RS_TILE, so + seg_len[sg] - base);
   const int j0 = bk0[sg] - bk_first, nb = bk0[sg + 1] - bk0[sg], nsp = nb - 1;
-  const int tid = threadIdx.x, w = tid >> 6;
+  const int tid = threadIdx.x;
   if (tid < nsp) sp[tid] = split[j0 + tid];
   if (tid < NC) lc[tid] = 0;
   __syncthreads();
@@ -1445,42 +1444,30 @@ __global__ __launch_bounds__(RS_NT) void k_bk_scatter(const K* __restrict__ keys
 #pragma unroll
   for (int i = 0; i < RS_ITEMS; ++i) {
     const int q = i * RS_NT + tid;
+    kv[i] = q < nvalid ? keys[base + q] : (K)0;
+  }
+#pragma unroll
+  for (int i = 0; i < RS_ITEMS; ++i) {
     cr[i] = -1;
-    kv[i] = 0;
-    if (q < nvalid) {
-      kv[i] = keys[base + q];
+    if (i * RS_NT + tid < nvalid) {
       const int c = bk_class(kv[i], sp, nsp);
       cr[i] = (c << 16) | atomicAdd(&lc[c], 1);
     }
   }
   __syncthreads();
-  int stored = 0, x = 0;
-  if (tid < NC) {   // waves 0 and 1: one class each
+  if (tid < NC) {
     const int n = lc[tid];
     gb[tid] = n ? atomicAdd(&cnt[2 * j0 + tid], n) : 0;   // n = 0 beyond class 2 nb - 2
-    stored = (tid & 1) ? 0 : n;
-    x = wave_incl_sum(stored);
-    if (tid == 63) w0tot = x;
   }
-  __syncthreads();
-  if (tid < NC) lb[tid] = x - stored + (w == 1 ? w0tot : 0);
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < RS_ITEMS; ++i) {
     const int c = cr[i] >> 16;
     if (cr[i] >= 0 && !(c & 1)) {
-      const int p = lb[c] + (cr[i] & 0xFFFF);
-      sl[p] = kv[i];
-      cl[p] = (uint8_t)c;
+      const int pos = gb[c] + (cr[i] & 0xFFFF);
+      if (pos < BK_CAP) stg[(int64_t)(j0 + (c >> 1)) * BK_CAP + pos] = kv[i];
+      else *flag = 1;
     }
-  }
-  __syncthreads();
-  const int nst = lb[NC - 1];   // class NC - 1 is a value class: the total
-  for (int q = tid; q < nst; q += RS_NT) {
-    const int c = cl[q];
-    const int pos = gb[c] + q - lb[c];
-    if (pos < BK_CAP) stg[(int64_t)(j0 + (c >> 1)) * BK_CAP + pos] = sl[q];
-    else *flag = 1;
   }
 }
 
