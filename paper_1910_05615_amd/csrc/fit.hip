@@ -53,11 +53,10 @@ struct SortHost {
   }
   int nseg() const { return (int)off.size(); }
   // Staging keys of the sample sort (zero where it cannot be used): a
-  // plan with a segment too long for one LDS segment, none too long for
-  // the buckets, 64-bit keys.
+  // plan with a segment too long for one LDS segment and none too long for
+  // the buckets.
   int64_t bucket_keys() const {
-    if (!buckets || key_bytes != 8 || maxlen <= lds_sort_capacity() || maxlen > bucket_max_len())
-      return 0;
+    if (!buckets || maxlen <= lds_sort_capacity() || maxlen > bucket_max_len()) return 0;
     return (int64_t)bktab.size() * bucket_capacity();
   }
 };
@@ -246,7 +245,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   S64.key_bytes = 8;
   SN.key_bytes = 8;
   SR.key_bytes = 8;
-  SN.buckets = SR.buckets = true;
+  S32.buckets = S64.buckets = SN.buckets = SR.buckets = true;
   std::vector<int32_t> std_seg0(ND);
   std::vector<int> std_in64(ND);
   for (int k = 0; k < ND; ++k) {
@@ -309,8 +308,11 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   layout_sort(L, SN, DN);
   layout_sort(L, SR, DR);
   const int64_t kbytes = std::max({S32.keys * 4 + S64.keys * 8, SN.keys * 8, SR.keys * 8});
-  // the staging slots of the sample sort live in the ping-pong buffer
-  const int64_t tbytes = std::max({kbytes, SN.bucket_keys() * 8, SR.bucket_keys() * 8});
+  // the staging slots of the sample sort live in the ping-pong buffer (the
+  // 64-bit standardisation plan's part of it starts after the 32-bit keys)
+  const int64_t tbytes = std::max({kbytes, S32.bucket_keys() * 4,
+                                   S32.keys * 4 + S64.bucket_keys() * 8, SN.bucket_keys() * 8,
+                                   SR.bucket_keys() * 8});
   const size_t maxtiles = std::max({S32.tiles.size() + S64.tiles.size(), SN.tiles.size(),
                                     SR.tiles.size()});
   const size_t o_keys = L.add((size_t)kbytes), o_tmp = L.add((size_t)tbytes);

@@ -89,8 +89,8 @@ hipError_t launch_unimcd_multiblock(const SortPlan& P, const double* seg_craw, d
 hipError_t launch_seg_lds(const SortPlan& P, const double* seg_craw, double q1, double crew,
                           int mode, SegStat* out, int64_t max_len, hipStream_t s);
 
-// Sample sort of segments of 64-bit keys, each at most bucket_max_len() long
-// (P.keys sorted in place): bucket_count(L) buckets per segment of L keys,
+// Sample sort of segments of at most bucket_max_len() keys (P.keys sorted
+// in place): bucket_count(L) buckets per segment of L keys,
 // each sorted in LDS, with P.tmp holding nbk * bucket_capacity() keys and
 // P.counts at least 5 nbk ints.  A bucket that outgrows its capacity sets
 // *P.flag (the caller then sorts again with the radix passes).
