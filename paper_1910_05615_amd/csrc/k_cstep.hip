@@ -642,9 +642,11 @@ __global__ __launch_bounds__(SEL_NT) void k_select(const ItemDesc* __restrict__ 
 // Sigma, then of L, in registers (rows and columns p..P-1 are the identity,
 // so the factor and its inverse carry an identity block that is never
 // written); the inverse is formed one column per lane.  Every loop is
-// unrolled over P and entries of other lanes are read with readlane, so no
-// step waits on shared memory.  The operations and their order are those of
-// a right-looking Cholesky and of column-wise forward substitution.
+// unrolled over P.  Each finished row of L, and each column of the inverse,
+// is published to LDS and read back by all lanes with broadcast loads
+// (single values of other lanes with readlane); the dot products of the
+// Cholesky and of the forward substitution run as two interleaved partial
+// sums, and the divisions are multiplications by the reciprocal diagonal.
 // ---------------------------------------------------------------------------
 __device__ inline double lane_bcast(double v, int l) {
   const long long b = __double_as_longlong(v);
