@@ -130,6 +130,19 @@ typedef struct rtdetmcd_out {
   uint8_t* rew_mask;      /* [n]   1 for the rows kept by the reweighting (Sec. 4 step 8:
                            *       fitted rows whose squared distance under the raw fit
                            *       does not exceed chi2_{p,cutoff_q}), 0 otherwise */
+  /* Diagnostics of rtdetmcd_fit / rtdetmcd_fit_batched (other calls ignore
+   * them), computed only when non-NULL: */
+  double*  ldtrace;       /* [q*max_csteps] per block, log det of the chosen start's scatter
+                           *       (standardised units) at each evaluated C-step, in order:
+                           *       non-increasing for full steps (Sec. 2.1, the C-step
+                           *       theorem); NaN from block_iters on */
+  double*  hmargin;       /* [q]   per block, d2_(h+1) - d2_(h) of the chosen start's last
+                           *       evaluated squared distances (Sec. 2.1 eq. cstep3): the gap
+                           *       at the h-subset threshold, 0 for a tie; NaN for an invalid
+                           *       block */
+  double*  cmargin;       /* [1]   smallest |dist^2 - chi2_{p,cutoff_q}| over the final
+                           *       distances (Sec. 4 step 10): the margin of the outlier
+                           *       flags; needs `dist`, NaN without it */
 } rtdetmcd_out;
 
 typedef struct rtdetmcd_ctx* rtdetmcd_handle;

@@ -267,6 +267,17 @@ def select_h(d2: np.ndarray, h: int) -> np.ndarray:
     return np.sort(order[:h])
 
 
+def h_gap(d2: np.ndarray, h: int) -> float:
+    """Near-tie margin of a selection: d2_(h+1) - d2_(h), the gap between the
+    largest distance kept and the smallest left out (0 for a tie across the
+    threshold; the diagnostics of the h-subset decision).  NaN when every
+    distance is kept."""
+    if h >= len(d2):
+        return math.nan
+    s = np.sort(np.asarray(d2, dtype=np.float64))
+    return float(s[h] - s[h - 1])
+
+
 def subset_stats(X: np.ndarray, H: np.ndarray):
     """Mean and covariance (divisor h-1) of the rows in H (eq. cstep4a, cstep4b)."""
     Xh = X[H]
@@ -335,6 +346,12 @@ class CStepResult:
     iters: int
     logdets: List[float]             # logdet of Sigma_old at each evaluated step
     smw_steps: int = 0               # steps taken by the single-swap update (mode "smw")
+    hgap: float = math.nan           # h_gap of the last evaluated distances
+
+
+def _with_gap(r: "CStepResult", gap: float) -> "CStepResult":
+    r.hgap = gap
+    return r
 
 
 def csteps(X: np.ndarray, h: int, mu0: np.ndarray, sigma0: np.ndarray,
@@ -371,6 +388,7 @@ def csteps(X: np.ndarray, h: int, mu0: np.ndarray, sigma0: np.ndarray,
     mu, S = np.asarray(mu0, float), np.asarray(sigma0, float)
     H_prev = None
     logdets: List[float] = []
+    gap = math.nan        # h_gap of the last evaluated distances
     smw = None            # (Sigma^{-1}, log det Sigma) after a single-swap update
     nsmw = 0
     for t in range(1, max_steps + 1):
@@ -379,8 +397,8 @@ def csteps(X: np.ndarray, h: int, mu0: np.ndarray, sigma0: np.ndarray,
             if L is None:
                 # Sigma_old is not positive definite: no step can be taken and the
                 # subset (if any) has a singular covariance, so the start is dropped.
-                return CStepResult(ST_DROP_FIRST if H_prev is None else ST_SINGULAR,
-                                   None, None, None, math.nan, t - 1, logdets, nsmw)
+                return _with_gap(CStepResult(ST_DROP_FIRST if H_prev is None else ST_SINGULAR,
+                                   None, None, None, math.nan, t - 1, logdets, nsmw), gap)
             Sk, Lk = S, L
             if kappa_scale is not None:
                 Sk = S / np.outer(kappa_scale, kappa_scale)
@@ -397,9 +415,9 @@ def csteps(X: np.ndarray, h: int, mu0: np.ndarray, sigma0: np.ndarray,
                         np.max(np.sum(np.abs(Ski), axis=0)))
         if not (kap < kappa_max):
             if H_prev is None:
-                return CStepResult(ST_DROP_FIRST, None, None, None, math.nan, t - 1, logdets,
-                                   nsmw)
-            return CStepResult(ST_ILLCOND, H_prev, mu, S, ld, t - 1, logdets, nsmw)
+                return _with_gap(CStepResult(ST_DROP_FIRST, None, None, None, math.nan, t - 1, logdets,
+                                   nsmw), gap)
+            return _with_gap(CStepResult(ST_ILLCOND, H_prev, mu, S, ld, t - 1, logdets, nsmw), gap)
         logdets.append(ld)
         if smw is not None:
             d2 = mahalanobis2_inverse(X, mu, smw[0])
@@ -408,8 +426,9 @@ def csteps(X: np.ndarray, h: int, mu0: np.ndarray, sigma0: np.ndarray,
         else:
             d2 = mahalanobis2(X, mu, L)
         H = select_h(d2, h)
+        gap = h_gap(d2, h)
         if H_prev is not None and np.array_equal(H, H_prev):
-            return CStepResult(ST_CONVERGED, H, mu, S, ld, t, logdets, nsmw)
+            return _with_gap(CStepResult(ST_CONVERGED, H, mu, S, ld, t, logdets, nsmw), gap)
         smw_next = None
         if mode == "smw" and H_prev is not None:
             out_ = np.setdiff1d(H_prev, H)
@@ -427,8 +446,8 @@ def csteps(X: np.ndarray, h: int, mu0: np.ndarray, sigma0: np.ndarray,
                     if st is None:
                         break
                 if st is None:
-                    return CStepResult(ST_SINGULAR, None, None, None, math.nan, t, logdets,
-                                       nsmw)
+                    return _with_gap(CStepResult(ST_SINGULAR, None, None, None, math.nan, t, logdets,
+                                       nsmw), gap)
                 _, mu, Lam, Lam_inv, ldl = st
                 S = 0.5 * (Lam + Lam.T) / (h - 1)
                 smw_next = ((h - 1) * Lam_inv, ldl - p * math.log(h - 1))
@@ -438,12 +457,12 @@ def csteps(X: np.ndarray, h: int, mu0: np.ndarray, sigma0: np.ndarray,
         smw = smw_next
         H_prev = H
     if smw is not None:
-        return CStepResult(ST_NOTCONV, H_prev, mu, S, smw[1], max_steps, logdets, nsmw)
+        return _with_gap(CStepResult(ST_NOTCONV, H_prev, mu, S, smw[1], max_steps, logdets, nsmw), gap)
     L = chol_or_none(S)
     if L is None:
-        return CStepResult(ST_SINGULAR, None, None, None, math.nan, max_steps, logdets, nsmw)
-    return CStepResult(ST_NOTCONV, H_prev, mu, S, 2.0 * float(np.sum(np.log(np.diag(L)))),
-                       max_steps, logdets, nsmw)
+        return _with_gap(CStepResult(ST_SINGULAR, None, None, None, math.nan, max_steps, logdets, nsmw), gap)
+    return _with_gap(CStepResult(ST_NOTCONV, H_prev, mu, S, 2.0 * float(np.sum(np.log(np.diag(L)))),
+                       max_steps, logdets, nsmw), gap)
 
 
 # --------------------------------------------------------------------------
@@ -617,6 +636,10 @@ def fit(X: np.ndarray, alpha: float = 0.75, h_sub: int = 0, n_chunks: int = 0,
     chunk_iters = np.zeros(q, np.int32)
     hsub = np.full((q, h), -1, np.int64)
     starts_diag = []
+    # O12 diagnostics of the chosen start of each block: log det of Sigma_old
+    # at each evaluated C-step, and the selection gap of its last distances
+    block_logdets = np.full((q, max_csteps), np.nan)
+    block_hgap = np.full(q, np.nan)
     if warm is not None:
         mu_w = (np.asarray(warm[0], float) - loc) / scale
         S_w = np.asarray(warm[1], float) / np.outer(scale, scale)
@@ -650,6 +673,8 @@ def fit(X: np.ndarray, alpha: float = 0.75, h_sub: int = 0, n_chunks: int = 0,
         chunk_status[l] = r.status
         chunk_start[l] = START_WARM if warm is not None else best
         chunk_iters[l] = r.iters
+        block_logdets[l, :len(r.logdets)] = r.logdets
+        block_hgap[l] = r.hgap
         hsub[l] = rows[r.H]
         fits_mu.append(r.mu)
         fits_sig.append(c_alpha * r.sigma)
@@ -694,4 +719,6 @@ def fit(X: np.ndarray, alpha: float = 0.75, h_sub: int = 0, n_chunks: int = 0,
         diag=dict(starts=starts_diag, kl_keys=keys, keep=np.asarray(valid)[keep],
                   d2_final=d2all, d2_reweight=d2, valid=np.asarray(valid),
                   mu_raw_z=mu_raw, sigma_raw_z=sig_raw, mu_rew_z=mu_rew,
-                  sigma_rew_z=sig_rew, c_alpha=c_alpha, chi2=chi2))
+                  sigma_rew_z=sig_rew, c_alpha=c_alpha, chi2=chi2,
+                  block_logdets=block_logdets, block_hgap=block_hgap,
+                  cmargin=float(np.min(np.abs(d2all - chi2)))))

@@ -36,7 +36,8 @@ class Out(C.Structure):
     _fields_ = [("mu", c_vp), ("sigma", c_vp), ("mu_raw", c_vp), ("sigma_raw", c_vp),
                 ("logdet", c_vp), ("dist", c_vp), ("outlier", c_vp), ("hsubset", c_vp),
                 ("block_status", c_vp), ("block_start", c_vp), ("block_iters", c_vp),
-                ("loc", c_vp), ("scale", c_vp), ("n_w", c_vp), ("rew_mask", c_vp)]
+                ("loc", c_vp), ("scale", c_vp), ("n_w", c_vp), ("rew_mask", c_vp),
+                ("ldtrace", c_vp), ("hmargin", c_vp), ("cmargin", c_vp)]
 
 
 class DatasetDesc(C.Structure):

@@ -267,6 +267,13 @@ class Fit:
     m: int
     h: int
     c_rew: float = 1.0            # factor of the reweighted scatter
+    # diagnostics (fit(..., diagnostics=True)): log det of each block's chosen
+    # start at each evaluated C-step (q x max_csteps, NaN beyond block_iters),
+    # the gap d2_(h+1) - d2_(h) of its last distances (q), and the smallest
+    # |dist^2 - chi2| of the final distances (1)
+    ldtrace: Optional[torch.Tensor] = None
+    hmargin: Optional[torch.Tensor] = None
+    cmargin: Optional[torch.Tensor] = None
 
 
 def _alloc_fit(X: torch.Tensor, q: int, m: int, h: int):
@@ -295,6 +302,22 @@ def _alloc_fit(X: torch.Tensor, q: int, m: int, h: int):
                    loc=F.loc.data_ptr(), scale=F.scale.data_ptr(), n_w=F.n_w.data_ptr(),
                    rew_mask=F.rew_mask.data_ptr())
     return F, out
+
+
+def _alloc_diag(fits, outs, maxs: int):
+    """The diagnostics outputs of fits (one float64 allocation for all)."""
+    sz = [F.q * maxs + F.q + 1 for F in fits]
+    d_all = torch.empty(sum(sz), dtype=torch.float64, device=fits[0].mu.device)
+    base = d_all.data_ptr()
+    off = 0
+    for F, out, part in zip(fits, outs, d_all.split(sz)):
+        q = F.q
+        tr, hm, cm = part.split([q * maxs, q, 1])
+        F.ldtrace, F.hmargin, F.cmargin = tr.view(q, maxs), hm, cm
+        out.ldtrace = base + 8 * off
+        out.hmargin = base + 8 * (off + q * maxs)
+        out.cmargin = base + 8 * (off + q * maxs + q)
+        off += q * maxs + q + 1
 
 
 def _alloc_fits(Xs, plans):
@@ -355,16 +378,19 @@ def random_partition(n: int, seed: int, device=None) -> torch.Tensor:
 
 
 def fit(X: torch.Tensor, h_sub: int = 0, n_chunks: int = 0,
-        perm: Optional[torch.Tensor] = None, warm=None, **opts) -> Fit:
+        perm: Optional[torch.Tensor] = None, warm=None, diagnostics: bool = False,
+        **opts) -> Fit:
     """RT-DetMCD fit of X (n x p) on the GPU; all outputs stay on the device.
 
     perm: optional int32 device tensor of n row indices, the random partition
     of Sec. 4 (see random_partition); None gives contiguous blocks.
     warm: optional (mu, sigma) of a previous fit (units of X), the warm start
-    of the last paragraph of Sec. 4."""
+    of the last paragraph of Sec. 4.
+    diagnostics: also return the log det trace, selection gaps and flag
+    margin (Fit.ldtrace, hmargin, cmargin)."""
     if perm is not None or warm is not None:
         fits, status = fit_batched([X], h_subs=[h_sub], n_chunks=[n_chunks], perms=[perm],
-                                   warms=[warm], **opts)
+                                   warms=[warm], diagnostics=diagnostics, **opts)
         if status[0] != 0:
             lib, hd = _handle(X.device)
             _check(lib, hd, status[0], "rtdetmcd_fit_batched")
@@ -375,6 +401,8 @@ def fit(X: torch.Tensor, h_sub: int = 0, n_chunks: int = 0,
     lib, hd = _handle(X.device)
     o = make_opts(**opts)
     F, out = _alloc_fit(X, q, m, h)
+    if diagnostics:
+        _alloc_diag([F], [out], o.max_csteps)
     F.c_rew = lib.rtdetmcd_consistency(o.cutoff_q, p) if o.rew_consistency else 1.0
     st = lib.rtdetmcd_fit(hd, _ptr(X), _dtype_code(X), n, p, X.stride(0), h_sub, n_chunks,
                           C.byref(o), C.byref(out))
@@ -433,13 +461,13 @@ class RobustMCD(torch.autograd.Function):
 def fit_batched(Xs: Sequence[torch.Tensor], h_subs: Optional[Sequence[int]] = None,
                 n_chunks: Optional[Sequence[int]] = None,
                 perms: Optional[Sequence[Optional[torch.Tensor]]] = None,
-                warms: Optional[Sequence] = None, **opts):
+                warms: Optional[Sequence] = None, diagnostics: bool = False, **opts):
     """Fit many independent datasets in the same launches.
 
     perms: optional per-dataset random partitions (int32 device tensors of n
     row indices, or None).  warms: optional per-dataset warm starts ((mu,
-    sigma) in the units of X, or None).  Returns (list of Fit, list of
-    per-dataset status codes)."""
+    sigma) in the units of X, or None).  diagnostics: as in fit.  Returns
+    (list of Fit, list of per-dataset status codes)."""
     lib, hd = _handle(Xs[0].device)
     o = make_opts(**opts)
     k = len(Xs)
@@ -455,6 +483,8 @@ def fit_batched(Xs: Sequence[torch.Tensor], h_subs: Optional[Sequence[int]] = No
         n, p = X.shape
         plans.append(_plan_o(lib, n, p, h_subs[i], n_chunks[i], o))
     fits, outs = _alloc_fits(Xs, plans) if k else ([], [])
+    if diagnostics and k:
+        _alloc_diag(fits, outs, o.max_csteps)
     for i, X in enumerate(Xs):
         n, p = X.shape
         F, out = fits[i], outs[i]

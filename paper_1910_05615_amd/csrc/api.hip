@@ -133,6 +133,7 @@ void layout_items(Layout& L, const ItemSet& S, size_t off[NOFF]) {
   off[19] = L.add(S.ptiles.size() * sizeof(Tile));
   off[20] = L.add(I * 4);             // form
   off[21] = L.add(I * MSTRIDE * 8);   // sinv
+  off[22] = L.add(I * (size_t)S.ldtr_n * 8);   // log det trace
 }
 
 void bind_items(char* base, const ItemSet& S, const size_t off[NOFF], ItemDev& D) {
@@ -159,7 +160,8 @@ void bind_items(char* base, const ItemSet& S, const size_t off[NOFF], ItemDev& D
   D.ptiles = reinterpret_cast<Tile*>(base + off[19]);
   A.form = reinterpret_cast<int32_t*>(base + off[20]);
   A.sinv = reinterpret_cast<double*>(base + off[21]);
-  (void)S;
+  A.ldtr = S.ldtr_n > 0 ? reinterpret_cast<double*>(base + off[22]) : nullptr;
+  A.ldtr_n = S.ldtr_n;
 }
 
 // The executable graph of R C-steps for `key`: from the cache, or captured
@@ -409,7 +411,7 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
       const void* ptrs[] = {ctx->ws,   D.items,  dtab,     D.stiles, A.status, A.iter,
                             A.kswap,   A.full,   A.logdet, A.mux,    A.lamx,   A.muz,
                             A.sigz,    A.linv,   A.mtri,   A.d2,     A.mask,   A.swap,
-                            A.part,    A.nactive, A.form,  A.sinv};
+                            A.part,    A.nactive, A.form,  A.sinv,   A.ldtr};
       std::vector<int64_t> key;
       for (const void* q : ptrs) key.push_back((int64_t)(uintptr_t)q);
       int64_t kbits;

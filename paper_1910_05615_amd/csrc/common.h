@@ -59,6 +59,8 @@ struct ItemArrays {
   int32_t* nactive;  // [1] items still active after the last finalize
   int32_t* form;     // [I] 0: mtri holds L^{-1} D^{-1}; 1: the packed explicit inverse P~
   double* sinv;      // [I*MSTRIDE] inverse of lamx (data units), kept by the single-swap mode
+  double* ldtr;      // [I*ldtr_n] log det of the scatter at each evaluated C-step, or null
+  int32_t ldtr_n;    // entries per item (the C-step limit)
 };
 
 constexpr int PSTRIDE = 1 + PMAX + TRI;  // count, sum, packed sscp

@@ -65,6 +65,7 @@ struct ItemSet {
   std::vector<int> dt_first, dt_count;   // per item, into dtiles
   std::vector<int> pt_first, pt_count;   // per item, into ptiles (pair leaders only)
   int64_t rows = 0;                      // sum of m
+  int32_t ldtr_n = 0;                    // log det trace entries per item (0: none kept)
   void add(const ItemDesc& d) {
     ItemDesc e = d;
     e.roff = rows;
@@ -113,7 +114,7 @@ struct ItemDev {
   ItemArrays A{};
 };
 
-constexpr int NOFF = 22;   // workspace offsets of one item set
+constexpr int NOFF = 23;   // workspace offsets of one item set
 void layout_items(Layout& L, const ItemSet& S, size_t off[NOFF]);
 void bind_items(char* base, const ItemSet& S, const size_t off[NOFF], ItemDev& D);
 

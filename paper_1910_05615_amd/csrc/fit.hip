@@ -276,6 +276,15 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   // ---------------------------------------------------------------- workspace
   Layout L;
   size_t offC[NOFF], offB[NOFF], offG[NOFF];
+  // diagnostics: the C-step items keep their log det trace when a dataset
+  // asks for it
+  bool want_trace = false, want_diag = false;
+  for (int k = 0; k < nd; ++k) {
+    const rtdetmcd_out& ok = sets[k].out;
+    want_trace = want_trace || ok.ldtrace != nullptr;
+    want_diag = want_diag || ok.ldtrace || ok.hmargin || ok.cmargin;
+  }
+  C.ldtr_n = want_trace ? o.max_csteps : 0;
   layout_items(L, C, offC);
   layout_items(L, B, offB);
   layout_items(L, G, offG);
@@ -630,6 +639,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   }
   RTD_HIP(launch_hsub(CD.items, CD.A, F, dds, douts, 0, NB, st));
   RTD_HIP(launch_outputs(dds, GD.A, F, douts, 0, ND, st));
+  if (want_diag) RTD_HIP(launch_diag(CD.items, CD.A, F, dds, douts, NB, ND, o.max_csteps, st));
   pm_fit.end(st);
   // ---------------------------------------------------------------- status
   RTD_HIP(hipMemcpyAsync(dinfo.data(), dds, ND * sizeof(DsInfo), hipMemcpyDeviceToHost, st));

@@ -114,5 +114,10 @@ hipError_t launch_hsub(const ItemDesc* citems, ItemArrays A, FitArrays F, const 
                        const struct rtdetmcd_out* outs, int first, int n, hipStream_t s);
 hipError_t launch_outputs(const DsInfo* ds, ItemArrays G, FitArrays F,
                           const struct rtdetmcd_out* outs, int first_ds, int nds, hipStream_t s);
+// The requested diagnostics of every block and dataset of a fit (the log
+// det trace, the selection gap, the flag margin of rtdetmcd_out).
+hipError_t launch_diag(const ItemDesc* citems, ItemArrays A, FitArrays F, const DsInfo* ds,
+                       const struct rtdetmcd_out* outs, int nb, int nds, int maxs,
+                       hipStream_t s);
 
 }  // namespace rtd

@@ -770,6 +770,8 @@ __global__ __launch_bounds__(64) void k_finalize(const ItemDesc* __restrict__ it
       else if (!(kap < kappa_max)) st = ST_ILLCOND;
       A.status[it] = st;
       if (st == ACTIVE && A.nactive) atomicAdd(A.nactive, 1);
+      if (st == ACTIVE && A.ldtr && A.iter[it] < A.ldtr_n)   // the step will be evaluated
+        A.ldtr[(size_t)it * A.ldtr_n + A.iter[it]] = A.logdet[it];
     }
     return;
   }
@@ -936,6 +938,8 @@ __global__ __launch_bounds__(64) void k_finalize(const ItemDesc* __restrict__ it
     }
     A.status[it] = st;
     if (st == ACTIVE && A.nactive) atomicAdd(A.nactive, 1);
+    if (st == ACTIVE && A.ldtr && A.iter[it] < A.ldtr_n)   // the step will be evaluated
+      A.ldtr[(size_t)it * A.ldtr_n + A.iter[it]] = 2.0 * ld;
   }
 }
 

@@ -851,6 +851,84 @@ __global__ __launch_bounds__(256) void k_outputs(const DsInfo* __restrict__ ds, 
   }
 }
 
+// Diagnostics of a fit, written only where the caller asked for them.
+// Blocks [0, nb): per fitted block, the log det of the chosen start's scatter
+// at each of its evaluated C-steps (NaN from block_iters on) and the gap
+// d2_(h+1) - d2_(h) of its last evaluated distances (smallest distance left
+// out minus largest kept).  Blocks [nb, nb + nds): per dataset, the smallest
+// |dist^2 - chi2_{p,q}| over the final distances.
+__global__ __launch_bounds__(256) void k_diag(const ItemDesc* __restrict__ citems, ItemArrays A,
+                                              FitArrays F, const DsInfo* __restrict__ ds,
+                                              const rtdetmcd_out* __restrict__ outs, int nb,
+                                              int maxs) {
+  __shared__ double red[2][4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double a = -INFINITY, b = INFINITY;   // largest kept, smallest left out (or smallest margin)
+  bool want = false;
+  double* dst = nullptr;
+  if ((int)blockIdx.x < nb) {
+    const int bk = blockIdx.x;
+    const int dd = F.bds[bk];
+    const DsInfo d = ds[dd];
+    const rtdetmcd_out o = outs[dd];
+    const int lb = bk - d.blk0;
+    const int ch = F.bitem[bk];
+    if (o.ldtrace) {
+      const int iters = ch >= 0 ? F.biters[bk] : 0;
+      for (int t = tid; t < maxs; t += blockDim.x)
+        o.ldtrace[(size_t)lb * maxs + t] =
+            (ch >= 0 && A.ldtr && t < iters && t < A.ldtr_n) ? A.ldtr[(size_t)ch * A.ldtr_n + t]
+                                                             : NAN;
+    }
+    if (o.hmargin && ch >= 0) {   // uniform
+      const ItemDesc C = citems[ch];
+      const double* __restrict__ d2 = A.d2 + C.roff;
+      const uint8_t* __restrict__ mk = A.mask + C.roff;
+      for (int64_t i = tid; i < C.m; i += blockDim.x) {
+        const double v = d2[i];
+        if (mk[i]) a = fmax(a, v);
+        else b = fmin(b, v);
+      }
+      want = true;
+      dst = o.hmargin + lb;
+    } else if (o.hmargin && tid == 0) {
+      o.hmargin[lb] = NAN;
+    }
+  } else {
+    const int dd = blockIdx.x - nb;
+    const DsInfo d = ds[dd];
+    const rtdetmcd_out o = outs[dd];
+    if (o.cmargin) {   // uniform
+      if (o.dist && d.err == 0) {
+        for (int64_t i = tid; i < d.n; i += blockDim.x) {
+          const double v = o.dist[i];
+          b = fmin(b, fabs(v * v - d.chi2p));
+        }
+        want = true;
+        dst = o.cmargin;
+      } else if (tid == 0) {
+        *o.cmargin = NAN;
+      }
+    }
+  }
+  if (!want) return;   // uniform
+  a = wave_max(a);
+  b = -wave_max(-b);
+  if (lane == 0) {
+    red[0][w] = a;
+    red[1][w] = b;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int k = 1; k < 4; ++k) {
+      a = fmax(a, red[0][k]);
+      b = fmin(b, red[1][k]);
+    }
+    const bool cm = (int)blockIdx.x >= nb;
+    *dst = cm ? b : ((a > -INFINITY && b < INFINITY) ? b - a : NAN);
+  }
+}
+
 // MODE 0 for p >= 16 on the float64 matrix cores: the scores of 16 rows at a
 // time, D = W_tile (16 output columns x 4) x Z^T (4 x 16 rows) over the k
 // steps (16x16x4 MFMA).  Each wave stages chunks of its rows in its own LDS
@@ -1121,6 +1199,13 @@ hipError_t launch_outputs(const DsInfo* ds, ItemArrays G, FitArrays F, const rtd
                           int first_ds, int nds, hipStream_t s) {
   if (nds <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_outputs, dim3(nds), dim3(256), 0, s, ds, G, F, outs, first_ds);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag(const ItemDesc* citems, ItemArrays A, FitArrays F, const DsInfo* ds,
+                       const rtdetmcd_out* outs, int nb, int nds, int maxs, hipStream_t s) {
+  if (nb + nds <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_diag, dim3(nb + nds), dim3(256), 0, s, citems, A, F, ds, outs, nb, maxs);
   return hipGetLastError();
 }
 

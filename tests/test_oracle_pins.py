@@ -781,3 +781,54 @@ def test_warm_start_on_new_data_lowers_no_determinant():
         ld = st[0].logdets
         assert all(b <= a + 1e-9 for a, b in zip(ld[1:], ld[2:]))
     assert np.all(f1.chunk_start == oracle.START_WARM)
+
+
+# ---------------------------------------------------------------- O12 diagnostics
+
+from oracle import rtdetmcd as R   # noqa: E402
+
+def test_h_gap_hand_case_and_ties():
+    # sorted (1, 2, 3, 5): keeping 2 leaves 3 as the smallest left out
+    assert R.h_gap(np.array([3.0, 1.0, 2.0, 5.0]), 2) == 1.0
+    # a tie across the threshold
+    assert R.h_gap(np.array([2.0, 1.0, 2.0, 7.0]), 2) == 0.0
+    assert math.isnan(R.h_gap(np.array([1.0, 2.0]), 2))
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_h_gap_is_the_gap_between_kept_and_left_out(seed):
+    # against the selected subset itself: smallest distance outside H minus
+    # the largest inside (ties by row index do not change the values)
+    rng = np.random.default_rng(seed)
+    d2 = np.round(rng.exponential(size=40), 1)   # rounded: ties occur
+    for h in (5, 20, 39):
+        H = R.select_h(d2, h)
+        out = np.setdiff1d(np.arange(40), H)
+        assert R.h_gap(d2, h) == d2[out].min() - d2[H].max()
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_logdet_trace_follows_the_cstep_theorem(seed):
+    # Sec. 2.1: a C-step never increases det(Sigma); the trace holds one entry
+    # per evaluated step of the chosen start, its last entry that start's
+    # final log det (converged blocks), NaN after
+    ds = synthdata.small_gaussian(1200, 4, seed=seed, eps=0.1)
+    F = R.fit(ds.X, n_chunks=2)
+    tr = F.diag["block_logdets"]
+    for l in range(F.q):
+        it = int(F.chunk_iters[l])
+        assert np.all(np.isfinite(tr[l, :it])) and np.all(np.isnan(tr[l, it:]))
+        assert np.all(np.diff(tr[l, :it]) <= 1e-12)
+        best = F.diag["starts"][l][int(F.chunk_start[l])]
+        assert best.logdets == list(tr[l, :it])
+        if F.chunk_status[l] == R.ST_CONVERGED:
+            assert tr[l, it - 1] == best.logdet
+
+
+def test_flag_margin_is_the_closest_final_distance_to_the_cutoff():
+    ds = synthdata.small_gaussian(1500, 3, seed=4, eps=0.1)
+    F = R.fit(ds.X, n_chunks=1)
+    chi2 = F.diag["chi2"]
+    brute = min(abs(float(d) ** 2 - chi2) for d in F.dist)
+    assert math.isclose(F.diag["cmargin"], brute, rel_tol=1e-9, abs_tol=1e-12)
+    assert F.diag["cmargin"] <= min(abs(F.diag["d2_final"] - chi2)) + 1e-15
