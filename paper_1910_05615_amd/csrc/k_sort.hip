@@ -1342,12 +1342,13 @@ __global__ __launch_bounds__(SS_NT) void k_seg_lds_slow(const K* __restrict__ ke
 // i, class 2i + 1 the value of splitter i).
 // ---------------------------------------------------------------------------
 constexpr int BK_NT = 256;           // threads of the sample kernel
-constexpr int BK_SAMPLE = 2048;      // sample size per segment
+constexpr int BK_SAMPLE = 2048;      // largest sample per segment (128 keys per bucket)
 constexpr int BK_KPT = 16;
 constexpr int BK_CAP = SS_NT * BK_KPT;   // keys per bucket (one LDS segment)
 constexpr int BK_EXP = 10240;        // expected keys per bucket (capacity / 1.6)
 constexpr int BK_NBMAX = 64;         // buckets per segment
 static_assert(2 * BK_NBMAX <= RS_NT, "one thread per class in k_bk_scatter");
+static_assert(BK_SAMPLE <= BK_CAP, "a sampled segment holds more keys than the sample");
 
 // Order key of a value: the inverse of val_of.
 __device__ inline uint64_t key_of_val(double x) {
@@ -1371,9 +1372,9 @@ __device__ inline int bk_class(K k, const K* sp, int nsp) {
 }
 
 // One block per segment: clears its class counters and, for nb >= 2,
-// writes the nb - 1 splitters: order statistics i BK_SAMPLE / nb of the
-// sample of keys (2 s + 1) L / (2 BK_SAMPLE), s < BK_SAMPLE, sorted by a
-// bitonic network.
+// writes the nb - 1 splitters: order statistics i S / nb of the sample of
+// keys (2 s + 1) L / (2 S), s < S, sorted by a bitonic network; S is the
+// smallest power of two from 256 to BK_SAMPLE holding 128 keys per bucket.
 template <typename K>
 __global__ __launch_bounds__(BK_NT) void k_bk_sample(const K* __restrict__ keys,
                                                      const int64_t* __restrict__ seg_off,
@@ -1388,14 +1389,15 @@ __global__ __launch_bounds__(BK_NT) void k_bk_sample(const K* __restrict__ keys,
   const int tid = threadIdx.x;
   for (int c = tid; c < 2 * nb; c += BK_NT) cnt[2 * j0 + c] = 0;
   if (nb < 2) return;   // uniform
-  const int64_t L = seg_len[sg];
+  const int64_t L = seg_len[sg];   // > BK_CAP >= BK_SAMPLE: distinct sampled positions
   const K* __restrict__ src = keys + seg_off[sg];
-  for (int i = tid; i < BK_SAMPLE; i += BK_NT)
-    smp[i] = src[((2 * (int64_t)i + 1) * L) / (2 * BK_SAMPLE)];
+  int S = 256;
+  while (S < 128 * nb && S < BK_SAMPLE) S <<= 1;
+  for (int i = tid; i < S; i += BK_NT) smp[i] = src[((2 * (int64_t)i + 1) * L) / (2 * S)];
   __syncthreads();
-  for (int k = 2; k <= BK_SAMPLE; k <<= 1) {
+  for (int k = 2; k <= S; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = tid; i < BK_SAMPLE / 2; i += BK_NT) {
+      for (int i = tid; i < S / 2; i += BK_NT) {
         const int lo = 2 * i - (i & (j - 1)), hi = lo + j;   // lo: bit log2(j) clear
         const K a = smp[lo], b = smp[hi];
         if ((a > b) == ((lo & k) == 0)) {
@@ -1406,7 +1408,7 @@ __global__ __launch_bounds__(BK_NT) void k_bk_sample(const K* __restrict__ keys,
       __syncthreads();
     }
   }
-  for (int i = tid + 1; i < nb; i += BK_NT) split[j0 + i - 1] = smp[(i * BK_SAMPLE) / nb];
+  for (int i = tid + 1; i < nb; i += BK_NT) split[j0 + i - 1] = smp[(i * S) / nb];
 }
 
 // One block per radix tile (RS_TILE keys of one segment): the class of
