@@ -149,11 +149,13 @@ typedef struct rtdetmcd_ctx* rtdetmcd_handle;
 
 /* Create a handle on `device` that enqueues on `hip_stream` (a hipStream_t;
  * NULL = the null stream).  The handle owns a device workspace that grows on
- * demand and is freed by rtdetmcd_destroy.  Sorts of columns longer than one
- * LDS segment rank equal radix digits with LDS atomics and check the order
- * of the result; a fit that finds a segment out of order is run again with
- * ballot ranking.  RTDETMCD_SAFE_SORT=1 in the environment at creation makes
- * the handle rank with ballots from the start. */
+ * demand and is freed by rtdetmcd_destroy.  Columns longer than one LDS
+ * segment are sorted by buckets (a sample sort) or by global radix passes,
+ * both ranking with LDS atomics and checked; a fit whose check fails, or
+ * whose bucket overflows, is run again with the full-width radix sort and
+ * ballot ranking only (counted by rtdetmcd_sort_reruns).
+ * RTDETMCD_SAFE_SORT=1 in the environment at creation selects that sort
+ * from the start. */
 rtdetmcd_status rtdetmcd_create(rtdetmcd_handle* out, int32_t device, void* hip_stream);
 rtdetmcd_status rtdetmcd_destroy(rtdetmcd_handle h);
 rtdetmcd_status rtdetmcd_set_stream(rtdetmcd_handle h, void* hip_stream);
@@ -334,8 +336,9 @@ rtdetmcd_status rtdetmcd_profile_read(rtdetmcd_handle h, int32_t kind, double* m
                                       int64_t* launches, double* bytes, double* flops_useful,
                                       double* flops_exec);
 
-/* Number of fits on this handle that were run a second time with ballot
- * ranking because a global sort's order check failed (see rtdetmcd_create).
+/* Number of fits on this handle that were run a second time on the
+ * full-width, ballot-ranked sort because a long-column sort's check failed or
+ * a bucket of the sample sort overflowed (see rtdetmcd_create).
  * Such a fit takes about twice its usual time; its results are those of the
  * ballot-ranked run.  Host-only; -1 for a null handle. */
 int64_t rtdetmcd_sort_reruns(rtdetmcd_handle h);
