@@ -98,6 +98,8 @@ void bind_sort(char* base, const SortHost& H, SortDev& D, void* keys, void* tmp,
   P.bk_tab = reinterpret_cast<SegTile*>(base + D.o_bkt);
   P.bk_first = 0;
   P.nbk = (int)H.bktab.size();
+  P.bk_max = 0;
+  for (size_t k = 0; k + 1 < H.bk0.size(); ++k) P.bk_max = std::max(P.bk_max, H.bk0[k + 1] - H.bk0[k]);
   D.st = reinterpret_cast<SegStat*>(base + D.o_st);
   D.craw = reinterpret_cast<double*>(base + D.o_craw);
 }

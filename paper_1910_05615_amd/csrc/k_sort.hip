@@ -1342,13 +1342,15 @@ __global__ __launch_bounds__(SS_NT) void k_seg_lds_slow(const K* __restrict__ ke
 // i, class 2i + 1 the value of splitter i).
 // ---------------------------------------------------------------------------
 constexpr int BK_NT = 256;           // threads of the sample kernel
-constexpr int BK_SAMPLE = 2048;      // largest sample per segment (128 keys per bucket)
+constexpr int BK_SAMPLE = 2048;      // sample of up to 16 buckets (128 keys per bucket)
+constexpr int BK_SAMPLE_BIG = 8192;  // sample of up to BK_NBMAX buckets
 constexpr int BK_KPT = 16;
 constexpr int BK_CAP = SS_NT * BK_KPT;   // keys per bucket (one LDS segment)
 constexpr int BK_EXP = 10240;        // expected keys per bucket (capacity / 1.6)
 constexpr int BK_NBMAX = 64;         // buckets per segment
 static_assert(2 * BK_NBMAX <= RS_NT, "one thread per class in k_bk_scatter");
-static_assert(BK_SAMPLE <= BK_CAP, "a sampled segment holds more keys than the sample");
+static_assert(BK_SAMPLE_BIG <= BK_CAP, "a sampled segment holds more keys than the sample");
+static_assert(BK_SAMPLE_BIG >= 128 * BK_NBMAX, "128 sampled keys per bucket");
 
 // Order key of a value: the inverse of val_of.
 __device__ inline uint64_t key_of_val(double x) {
@@ -1374,8 +1376,8 @@ __device__ inline int bk_class(K k, const K* sp, int nsp) {
 // One block per segment: clears its class counters and, for nb >= 2,
 // writes the nb - 1 splitters: order statistics i S / nb of the sample of
 // keys (2 s + 1) L / (2 S), s < S, sorted by a bitonic network; S is the
-// smallest power of two from 256 to BK_SAMPLE holding 128 keys per bucket.
-template <typename K>
+// smallest power of two from 256 to SMAX holding 128 keys per bucket.
+template <typename K, int SMAX>
 __global__ __launch_bounds__(BK_NT) void k_bk_sample(const K* __restrict__ keys,
                                                      const int64_t* __restrict__ seg_off,
                                                      const int64_t* __restrict__ seg_len,
@@ -1383,16 +1385,16 @@ __global__ __launch_bounds__(BK_NT) void k_bk_sample(const K* __restrict__ keys,
                                                      int seg_first, int bk_first,
                                                      K* __restrict__ split,
                                                      int32_t* __restrict__ cnt) {
-  __shared__ K smp[BK_SAMPLE];
+  __shared__ K smp[SMAX];
   const int sg = seg_first + blockIdx.x;
   const int j0 = bk0[sg] - bk_first, nb = bk0[sg + 1] - bk0[sg];
   const int tid = threadIdx.x;
   for (int c = tid; c < 2 * nb; c += BK_NT) cnt[2 * j0 + c] = 0;
   if (nb < 2) return;   // uniform
-  const int64_t L = seg_len[sg];   // > BK_CAP >= BK_SAMPLE: distinct sampled positions
+  const int64_t L = seg_len[sg];   // > BK_CAP >= SMAX: distinct sampled positions
   const K* __restrict__ src = keys + seg_off[sg];
   int S = 256;
-  while (S < 128 * nb && S < BK_SAMPLE) S <<= 1;
+  while (S < 128 * nb && S < SMAX) S <<= 1;
   for (int i = tid; i < S; i += BK_NT) smp[i] = src[((2 * (int64_t)i + 1) * L) / (2 * S)];
   __syncthreads();
   for (int k = 2; k <= S; k <<= 1) {
@@ -2158,8 +2160,13 @@ hipError_t sort_buckets_t(SortPlan& P, hipStream_t s) {
   int32_t* cnt = P.counts;
   K* split = reinterpret_cast<K*>(P.counts + 2 * (size_t)P.nbk);
   int32_t* mark = P.counts + 2 * (size_t)P.nbk + (size_t)P.nbk * sizeof(K) / 4;
-  hipLaunchKernelGGL((k_bk_sample<K>), dim3(P.nseg), dim3(BK_NT), 0, s, keys, P.seg_off,
-                     P.seg_len, P.bk0, P.seg_first, P.bk_first, split, cnt);
+  // (a block's LDS holds the largest sample any of its segments takes)
+  if (P.bk_max * 128 > BK_SAMPLE)
+    hipLaunchKernelGGL((k_bk_sample<K, BK_SAMPLE_BIG>), dim3(P.nseg), dim3(BK_NT), 0, s, keys,
+                       P.seg_off, P.seg_len, P.bk0, P.seg_first, P.bk_first, split, cnt);
+  else
+    hipLaunchKernelGGL((k_bk_sample<K, BK_SAMPLE>), dim3(P.nseg), dim3(BK_NT), 0, s, keys,
+                       P.seg_off, P.seg_len, P.bk0, P.seg_first, P.bk_first, split, cnt);
   hipLaunchKernelGGL((k_bk_scatter<K>), dim3(P.ntiles), dim3(RS_NT), 0, s, keys, stg, P.tiles,
                      P.seg_off, P.seg_len, P.bk0, P.bk_first, split, cnt, P.flag);
   hipLaunchKernelGGL((k_bk_sort<K>), dim3(P.nbk), dim3(SS_NT), 0, s, stg, keys, P.bk_tab,

@@ -1,6 +1,8 @@
 // Segmented sort and order-statistic estimators (declarations).
 #pragma once
 
+#include <algorithm>
+
 #include "common.h"
 
 namespace rtd {
@@ -45,6 +47,7 @@ struct SortPlan {
   const SegTile* bk_tab = nullptr;
   int bk_first = 0;
   int nbk = 0;
+  int bk_max = 0;                   // most buckets of one segment
   // The plan restricted to segments [a, b): pointers offset, tile and
   // bucket counts given by the host copies of the absolute seg_tile0 and
   // bk0 tables.
@@ -63,6 +66,8 @@ struct SortPlan {
     r.tile_first = ta;
     r.bk_first = host_bk0[a];
     r.nbk = host_bk0[b] - host_bk0[a];
+    r.bk_max = 0;
+    for (int k = a; k < b; ++k) r.bk_max = std::max(r.bk_max, host_bk0[k + 1] - host_bk0[k]);
     return r;
   }
 };

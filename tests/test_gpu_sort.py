@@ -87,3 +87,24 @@ def test_atomic_and_ballot_ranking_agree(monkeypatch, dtype, n, p, q, kind):
     # two summation orders pick windows a few places apart
     if n * p <= 2_000_000 and kind not in ("heavy", "rounded"):
         check_fit(Fa, oracle.fit(Xh, n_chunks=q), f"{dtype.__name__} n={n}")
+
+
+@pytest.mark.parametrize("n,p", [(16_384, 3),    # one LDS segment exactly
+                                 (16_385, 3),    # the smallest sample sort: two buckets
+                                 (655_360, 2),   # the largest sample sort: 64 buckets
+                                 (655_361, 2)])  # beyond it: the global radix passes
+def test_sort_paths_at_their_limits(monkeypatch, n, p):
+    # single blocks of n rows, so the standardisation columns and the
+    # refinement columns are all n keys long
+    import paper_1910_05615_amd as P
+    ds = synthdata.small_gaussian(n, p, seed=61, dtype=np.float32, rho=0.5, eps=0.1)
+    X = torch.from_numpy(ds.X).to("cuda:0")
+    monkeypatch.delenv("RTDETMCD_SAFE_SORT", raising=False)
+    Fa = _fit_with_fresh_handle(P, X, n_chunks=1)
+    from paper_1910_05615_amd import api
+    assert api._last_fresh_reruns == 0
+    monkeypatch.setenv("RTDETMCD_SAFE_SORT", "1")
+    Fb = _fit_with_fresh_handle(P, X, n_chunks=1)
+    for name in _ALL:
+        assert torch.equal(getattr(Fa, name), getattr(Fb, name)), name
+    check_fit(Fa, oracle.fit(ds.X, n_chunks=1), f"n={n}")
