@@ -130,10 +130,9 @@ void layout_items(Layout& L, const ItemSet& S, size_t off[NOFF]) {
   off[16] = L.add((size_t)S.rows * 4);   // swap
   off[17] = L.add(S.stiles.size() * PSTRIDE * 8);  // partials
   off[18] = L.add(64);                   // nactive
-  off[19] = L.add(S.ptiles.size() * sizeof(Tile));
-  off[20] = L.add(I * 4);             // form
-  off[21] = L.add(I * MSTRIDE * 8);   // sinv
-  off[22] = L.add(I * (size_t)S.ldtr_n * 8);   // log det trace
+  off[19] = L.add(I * 4);             // form
+  off[20] = L.add(I * MSTRIDE * 8);   // sinv
+  off[21] = L.add(I * (size_t)S.ldtr_n * 8);   // log det trace
 }
 
 void bind_items(char* base, const ItemSet& S, const size_t off[NOFF], ItemDev& D) {
@@ -157,10 +156,9 @@ void bind_items(char* base, const ItemSet& S, const size_t off[NOFF], ItemDev& D
   A.swap = reinterpret_cast<int32_t*>(base + off[16]);
   A.part = reinterpret_cast<double*>(base + off[17]);
   A.nactive = reinterpret_cast<int32_t*>(base + off[18]);
-  D.ptiles = reinterpret_cast<Tile*>(base + off[19]);
-  A.form = reinterpret_cast<int32_t*>(base + off[20]);
-  A.sinv = reinterpret_cast<double*>(base + off[21]);
-  A.ldtr = S.ldtr_n > 0 ? reinterpret_cast<double*>(base + off[22]) : nullptr;
+  A.form = reinterpret_cast<int32_t*>(base + off[19]);
+  A.sinv = reinterpret_cast<double*>(base + off[20]);
+  A.ldtr = S.ldtr_n > 0 ? reinterpret_cast<double*>(base + off[21]) : nullptr;
   A.ldtr_n = S.ldtr_n;
 }
 
@@ -216,24 +214,22 @@ rtdetmcd_status graph_for(rtdetmcd_ctx* ctx, const std::vector<int64_t>& key, in
 // loop's own first pass writes again, so the measurement leaves no trace.
 // *idx: the plan's index in ctx->tune.
 rtdetmcd_status tuned_dist_plan(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int bucket,
-                                int dtype, int first, int n, bool dense, bool pairs_ok,
+                                int dtype, int first, int n, bool dense,
                                 const int32_t* form, int* idx) {
   int64_t rows = 0, max_m = 0;
   for (int i = first; i < first + n; ++i) {
     rows += S.items[i].m;
     max_m = std::max(max_m, S.items[i].m);
   }
-  const std::vector<int64_t> key = {bucket, dtype, n, rows, max_m, dense ? 1 : 0,
-                                    pairs_ok ? 1 : 0, form ? 1 : 0};
+  const std::vector<int64_t> key = {bucket, dtype, n, rows, max_m, dense ? 1 : 0, form ? 1 : 0};
   for (size_t k = 0; k < ctx->tune.size(); ++k)
     if (ctx->tune[k].key == key) {
       *idx = (int)k;
       return RTDETMCD_OK;
     }
-  auto table = [&](int T, int mode) {
+  auto table = [&](int T) {
     std::vector<Tile> t;
     for (int i = first; i < first + n; ++i) {
-      if (mode == 2 && S.pt_first[i] < 0) continue;   // one tile list per start pair
       const int nd = (int)((S.items[i].m + T - 1) / T);
       for (int k = 0; k < nd; ++k) t.push_back({i, k});
     }
@@ -241,34 +237,32 @@ rtdetmcd_status tuned_dist_plan(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D,
   };
   const int rows_c[] = {256, 512, 1024, 2048, 4096};
   Tile* tmp = nullptr;
-  RTD_HIP(hipMalloc(&tmp, table(256, 1).size() * sizeof(Tile)));
+  RTD_HIP(hipMalloc(&tmp, table(256).size() * sizeof(Tile)));
   hipEvent_t e[2] = {nullptr, nullptr};
   RTD_HIP(hipEventCreate(&e[0]));
   RTD_HIP(hipEventCreate(&e[1]));
-  int best_T = DIST_TILE, best_mode = 1;
+  int best_T = DIST_TILE;
   float best = 1e30f;
   hipError_t err = hipSuccess;
-  for (int mode = 1; mode <= (pairs_ok ? 2 : 1) && err == hipSuccess; ++mode)
-    for (const int T : rows_c) {
-      const std::vector<Tile> t = table(T, mode);
-      err = hipMemcpy(tmp, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice);
-      for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
-        err = hipEventRecord(e[0], ctx->stream);
-        if (err == hipSuccess)
-          err = launch_dist(bucket, dtype, dense, mode, D.items, tmp, (int)t.size(), T, D.A.mtri,
-                            D.A.mux, D.A.status, form, D.A.d2, ctx->stream);
-        if (err == hipSuccess) err = hipEventRecord(e[1], ctx->stream);
-        if (err == hipSuccess) err = hipEventSynchronize(e[1]);
-        float ms = 0.0f;
-        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e[0], e[1]);
-        if (err == hipSuccess && ms < best) {
-          best = ms;
-          best_T = T;
-          best_mode = mode;
-        }
+  for (const int T : rows_c) {
+    const std::vector<Tile> t = table(T);
+    err = hipMemcpy(tmp, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice);
+    for (int rep = 0; rep < 2 && err == hipSuccess; ++rep) {
+      err = hipEventRecord(e[0], ctx->stream);
+      if (err == hipSuccess)
+        err = launch_dist(bucket, dtype, dense, D.items, tmp, (int)t.size(), T, D.A.mtri,
+                          D.A.mux, D.A.status, form, D.A.d2, ctx->stream);
+      if (err == hipSuccess) err = hipEventRecord(e[1], ctx->stream);
+      if (err == hipSuccess) err = hipEventSynchronize(e[1]);
+      float ms = 0.0f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e[0], e[1]);
+      if (err == hipSuccess && ms < best) {
+        best = ms;
+        best_T = T;
       }
-      if (err != hipSuccess) break;
     }
+    if (err != hipSuccess) break;
+  }
   (void)hipEventDestroy(e[0]);
   (void)hipEventDestroy(e[1]);
   (void)hipFree(tmp);
@@ -277,8 +271,8 @@ rtdetmcd_status tuned_dist_plan(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D,
   tp.key = key;
   tp.bucket = bucket;
   tp.tile_rows = best_T;
-  tp.mode = best_mode;
-  const std::vector<Tile> t = table(best_T, best_mode);
+  tp.mode = 1;   // one factor per pass
+  const std::vector<Tile> t = table(best_T);
   tp.ntiles = (int)t.size();
   RTD_HIP(hipMalloc(&tp.tiles, t.size() * sizeof(Tile)));
   RTD_HIP(hipMemcpy(tp.tiles, t.data(), t.size() * sizeof(Tile), hipMemcpyHostToDevice));
@@ -299,14 +293,9 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
   hipStream_t st = ctx->stream;
   const int maxs = o.max_csteps;
   if (o.launch == RTDETMCD_LAUNCH_BATCHED) {
-    // tiles of the items [first, first+n) are contiguous in all tables; when
-    // the range is made of whole start pairs, one distance pass serves both
-    const bool pairs = dist_pairs_pay(bucket) && (n % 2 == 0) && S.pt_first[first] >= 0 &&
-                       S.pt_first[first + n - 2] >= 0;
-    const Tile* dtl = pairs ? D.ptiles : D.dtiles;
-    const int dt0 = pairs ? S.pt_first[first] : S.dt_first[first];
-    const int dtn = pairs ? S.pt_first[first + n - 2] + S.pt_count[first + n - 2] - dt0
-                          : S.dt_first[first + n - 1] + S.dt_count[first + n - 1] - dt0;
+    // tiles of the items [first, first+n) are contiguous in all tables
+    const int dt0 = S.dt_first[first];
+    const int dtn = S.dt_first[first + n - 1] + S.dt_count[first + n - 1] - dt0;
     const int st0 = S.items[first].tile0;
     const int stn = S.items[first + n - 1].tile0 + S.items[first + n - 1].ntiles - st0;
     int64_t max_m = 0;
@@ -321,21 +310,20 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
     const int32_t* form =
         (o.distance || o.cstep_mode == RTDETMCD_CSTEP_SMW) ? D.A.form : nullptr;
     // distance tiling: the plan's tables, or the tuned ones
-    const Tile* dtab = dtl + dt0;
-    int dntab = dtn, dtile = DIST_TILE, dmode = pairs ? 2 : 1, tix = -1;
+    const Tile* dtab = D.dtiles + dt0;
+    int dntab = dtn, dtile = DIST_TILE, tix = -1;
     if (o.tune) {
-      RTD_TRY(tuned_dist_plan(ctx, S, D, bucket, dtype, first, n, dense, pairs, form, &tix));
+      RTD_TRY(tuned_dist_plan(ctx, S, D, bucket, dtype, first, n, dense, form, &tix));
       const rtdetmcd_ctx::TunePlan& tp = ctx->tune[tix];
       dtab = tp.tiles;
       dntab = tp.ntiles;
       dtile = tp.tile_rows;
-      dmode = tp.mode;
       R = std::max(R, tp.iters);   // the first check after the previous fit's C-step count
     }
     // one C-step of every active item
     // one C-step of every active item; the selection zeroes the active count
     auto step = [&](hipStream_t s) -> rtdetmcd_status {
-      RTD_HIP(launch_dist(bucket, dtype, dense, dmode, D.items, dtab, dntab, dtile, D.A.mtri,
+      RTD_HIP(launch_dist(bucket, dtype, dense, D.items, dtab, dntab, dtile, D.A.mtri,
                           D.A.mux, D.A.status, form, D.A.d2, s));
       RTD_HIP(launch_select(D.items, D.A, first, n, max_m, o.cstep_mode, s, 1));
       RTD_HIP(launch_sscp(bucket, dtype, SSCP_CSTEP, D.items, D.A, D.stiles + st0, stn,
@@ -363,7 +351,7 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
       }
       {
         ProfMark pm(ctx, RTDETMCD_PROF_CSTEP_DIST, s, byt_d, fl_d, fl_d);
-        RTD_HIP(launch_dist(bucket, dtype, dense, dmode, D.items, dtab, dntab, dtile, D.A.mtri,
+        RTD_HIP(launch_dist(bucket, dtype, dense, D.items, dtab, dntab, dtile, D.A.mtri,
                             D.A.mux, D.A.status, form, D.A.d2, s));
         pm.end(s);
       }
@@ -416,7 +404,7 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
       for (const void* q : ptrs) key.push_back((int64_t)(uintptr_t)q);
       int64_t kbits;
       std::memcpy(&kbits, &o.kappa_max, 8);
-      const int64_t scal[] = {bucket, dtype, first, n, dmode + (dense ? 4 : 0),
+      const int64_t scal[] = {bucket, dtype, first, n, dense ? 1 : 0,
                               dntab, dtile, st0, stn, max_nt, max_m, (int64_t)S.items.size(),
                               S.rows, o.cstep_mode, maxs, R, kbits, o.distance};
       key.insert(key.end(), std::begin(scal), std::end(scal));
@@ -458,7 +446,7 @@ rtdetmcd_status run_csteps(rtdetmcd_ctx* ctx, const ItemSet& S, ItemDev& D, int 
     RTD_HIP(hipStreamSynchronize(st));
     if (*pin_flag != ACTIVE) continue;
     for (int t = 1; t <= maxs; ++t) {
-      RTD_HIP(launch_dist(bucket, dtype, S.rows_dense(i, i + 1, bucket), 1, D.items,
+      RTD_HIP(launch_dist(bucket, dtype, S.rows_dense(i, i + 1, bucket), D.items,
                           D.dtiles + S.dt_first[i], S.dt_count[i],
                           DIST_TILE, D.A.mtri, D.A.mux, D.A.status,
                           (o.distance || o.cstep_mode == RTDETMCD_CSTEP_SMW) ? D.A.form : nullptr,
@@ -716,7 +704,7 @@ rtdetmcd_status rtdetmcd_distances(rtdetmcd_handle ctx, const void* X, int32_t d
   const double es = dtype == 0 ? 4.0 : 8.0;
   ProfMark pm(ctx, RTDETMCD_PROF_DISTANCES, ctx->stream, (double)n * (es * p + 8.0),
               (double)n * (p * (p + 1.0) + 3.0 * p));
-  RTD_HIP(launch_dist(bucket_of(p), dtype, S.rows_dense(0, (int)S.items.size(), bucket_of(p)), 1,
+  RTD_HIP(launch_dist(bucket_of(p), dtype, S.rows_dense(0, (int)S.items.size(), bucket_of(p)),
                       D.items, D.dtiles, (int)S.dtiles.size(), DIST_TILE,
                       D.A.mtri, D.A.mux, nullptr, nullptr, d2, ctx->stream));
   pm.end(ctx->stream);

@@ -94,8 +94,6 @@ inline int bucket_of(int p) {
 }
 
 // Launch helpers implemented in the .hip files (all enqueue on `s`).
-// ipt = 2: every tile names the first of two items (the two starts of a
-// block) that share their rows; ipt = 1: one item per tile.
 // Largest power-of-two load (16, 8 or the element size) that divides a row of
 // `bucket` elements: the distance kernels read whole rows with it.
 inline int dist_row_align(int bucket, int dtype) {
@@ -107,19 +105,15 @@ inline bool rows_dense_at(const void* X, int64_t ld, int p, int dtype, int bucke
   return p == bucket && ld == p &&
          reinterpret_cast<uintptr_t>(X) % (uintptr_t)dist_row_align(bucket, dtype) == 0;
 }
-// Whether the C-step distance pass should evaluate both starts of a block
-// from one read of each row (pair tiles).  Up to p = 40 one row per thread
-// with one factor, run over both starts' items, is faster even though it
-// reads the rows twice (10^6 x 20: 35 against 37 us; x 40: 130 against 154).
-inline bool dist_pairs_pay(int bucket) { return bucket > 40; }
 // dense: every item of the launch satisfies rows_dense_at (the kernels then
-// skip the per-element path for narrower or strided rows).  ipt: 1, or 2 for
-// pair tiles (both starts of a block per tile), valid only where
-// dist_pairs_pay(bucket); otherwise hipErrorInvalidValue.
+// skip the per-element path for narrower or strided rows).  One item per
+// tile: the C-step pass runs over both starts' items of a block, reading
+// each row twice (10^6 x 20: 35 against 37 us for one read feeding both
+// factors; x 40: 130 against 154).
 // form: per-item distance form (ItemArrays::form), or null when every item
 // holds L^{-1} D^{-1} (the launch then takes the kernels without the
 // explicit-inverse evaluation).
-hipError_t launch_dist(int bucket, int dtype, int dense, int ipt, const ItemDesc* items,
+hipError_t launch_dist(int bucket, int dtype, int dense, const ItemDesc* items,
                        const Tile* tiles,
                        int ntiles, int tile_rows, const double* mtri, const double* mux,
                        const int32_t* status, const int32_t* form, double* d2, hipStream_t s);

@@ -61,9 +61,8 @@ struct Uploader {
 // per-item launches).
 struct ItemSet {
   std::vector<ItemDesc> items;
-  std::vector<Tile> dtiles, stiles, ptiles;
+  std::vector<Tile> dtiles, stiles;
   std::vector<int> dt_first, dt_count;   // per item, into dtiles
-  std::vector<int> pt_first, pt_count;   // per item, into ptiles (pair leaders only)
   int64_t rows = 0;                      // sum of m
   int32_t ldtr_n = 0;                    // log det trace entries per item (0: none kept)
   void add(const ItemDesc& d) {
@@ -77,16 +76,6 @@ struct ItemSet {
     const int nd = (int)((e.m + DIST_TILE - 1) / DIST_TILE);
     for (int t = 0; t < nd; ++t) dtiles.push_back({(int)items.size(), t});
     dt_count.push_back(nd);
-    pt_first.push_back(-1);
-    pt_count.push_back(0);
-    // the two starts of a block share their rows: one distance tile serves both
-    if (e.start == 1 && !items.empty() && items.back().start == 0 && items.back().ds == e.ds &&
-        items.back().blk == e.blk) {
-      const int lead = (int)items.size() - 1;
-      pt_first[lead] = (int)ptiles.size();
-      pt_count[lead] = nd;
-      for (int t = 0; t < nd; ++t) ptiles.push_back({lead, t});
-    }
     rows += e.m;
     items.push_back(e);
   }
@@ -110,11 +99,10 @@ struct ItemDev {
   ItemDesc* items = nullptr;
   Tile* dtiles = nullptr;
   Tile* stiles = nullptr;
-  Tile* ptiles = nullptr;
   ItemArrays A{};
 };
 
-constexpr int NOFF = 23;   // workspace offsets of one item set
+constexpr int NOFF = 22;   // workspace offsets of one item set
 void layout_items(Layout& L, const ItemSet& S, size_t off[NOFF]);
 void bind_items(char* base, const ItemSet& S, const size_t off[NOFF], ItemDev& D);
 

@@ -470,7 +470,6 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
   up.add(CD.items, C.items.data(), C.items.size());
   up.add(CD.dtiles, C.dtiles.data(), C.dtiles.size());
   up.add(CD.stiles, C.stiles.data(), C.stiles.size());
-  up.add(CD.ptiles, C.ptiles.data(), C.ptiles.size());
   up.add(BD.items, B.items.data(), B.items.size());
   up.add(BD.dtiles, B.dtiles.data(), B.dtiles.size());
   up.add(BD.stiles, B.stiles.data(), B.stiles.size());
@@ -612,7 +611,7 @@ rtdetmcd_status fit_many(rtdetmcd_ctx* ctx, int nd, const rtdetmcd_dataset* sets
     const int a = g.ds0, b = g.ds1;
     const int dt0 = G.dt_first[a], dtn = G.dt_first[b - 1] + G.dt_count[b - 1] - dt0;
     const int st0 = G.items[a].tile0, stn = G.items[b - 1].tile0 + G.items[b - 1].ntiles - st0;
-    RTD_HIP(launch_dist(g.bucket, g.dtype, G.rows_dense(a, b, g.bucket), 1, GD.items,
+    RTD_HIP(launch_dist(g.bucket, g.dtype, G.rows_dense(a, b, g.bucket), GD.items,
                         GD.dtiles + dt0, dtn, DIST_TILE, GD.A.mtri, GD.A.mux, nullptr,
                         o.distance ? GD.A.form : nullptr, GD.A.d2, st));
     RTD_HIP(launch_sscp(g.bucket, g.dtype, SSCP_D2CUT, GD.items, GD.A, GD.stiles + st0, stn,

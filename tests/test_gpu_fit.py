@@ -271,9 +271,9 @@ def test_random_partition_rejects_bad_permutations():
 
 
 @pytest.mark.parametrize("p", [48, 64])
-def test_fit_wide_p_pair_tiles(p):
-    """p = 48, 64: the C-step distances take the staged kernel with both
-    starts of a block from one read of each row (pair tiles)."""
+def test_fit_wide_p(p):
+    """p = 48, 64: the distance kernels form the outputs 16 at a time (the
+    register-blocked path of the direct kernel)."""
     ds = synthdata.small_gaussian(7001, p, seed=p, dtype=np.float32, rho=0.4, eps=0.1,
                                   kind="shift", gamma=8)
     ref = oracle.fit(ds.X, n_chunks=2)

@@ -97,7 +97,7 @@ def test_fit_variants_match_oracle(kw):
 
 @pytest.mark.parametrize("launch", ["batched", "plain"])
 def test_fit_inverse_distances_wide_rows(launch):
-    # p = 48: the staged distance kernels
+    # p = 48: the register-blocked distance kernels
     ds = synthdata.small_gaussian(30_007, 48, seed=48, dtype=np.float32, rho=0.5, eps=0.1,
                                   kind="shift", gamma=8)
     ref = oracle.fit(ds.X, n_chunks=2, distance="inverse", cstep_mode="smw")
