@@ -360,7 +360,7 @@ def main() -> int:
         Ft, t_t, _ = timed(graph=False, tune=True)
         tuned = {"value": N / t_t, "unit": "rows/s", "ms_per_step": t_t * 1e3,
                  "identical_to_untuned": same(Ft, F),
-                 "plan": dict(zip(("p_bucket", "rows_per_distance_tile", "distance_passes",
+                 "plan": dict(zip(("p_bucket", "rows_per_distance_tile", "items_per_distance_tile",
                                    "csteps_of_last_fit"), R.tuned_plans()[-1]))}
         if not args.no_graph:
             Ftg, t_tg, _ = timed(graph=True, tune=True)

@@ -101,8 +101,7 @@ typedef struct rtdetmcd_opts {
                              * fit of a shape (p bucket, item count, rows, longest block,
                              * input type) the library times the distance pass of the
                              * first C-step under each candidate tiling (rows per tile
-                             * 256..4096, one pass for both starts of a block or one per
-                             * start) and keeps the fastest; later fits of that shape take
+                             * 256..4096) and keeps the fastest; later fits of that shape take
                              * the kept tiling, and their first convergence check comes
                              * after as many C-steps as the previous fit took (at least
                              * rounds_per_sync).  Results do not depend on it. */
@@ -163,9 +162,9 @@ rtdetmcd_status rtdetmcd_set_stream(rtdetmcd_handle h, void* hip_stream);
 const char* rtdetmcd_last_error(rtdetmcd_handle h);
 
 /* The autotuned plans a handle holds (opts.tune), most recent last: up to
- * `cap` rows of 4 int64 (p bucket, rows per distance tile, distance passes
- * per block pair (1: one pass for both starts, 2: one per start), C-steps of
- * the last fit) into `out` (host memory, may be NULL when cap = 0).  *count
+ * `cap` rows of 4 int64 (p bucket, rows per distance tile, items per
+ * distance tile (1), C-steps of the last fit) into `out` (host memory, may
+ * be NULL when cap = 0).  *count
  * receives the number of plans held.  Errors: RTDETMCD_EINVAL for a null
  * handle or count. */
 rtdetmcd_status rtdetmcd_tuned_plans(rtdetmcd_handle h, int64_t* out, int32_t cap,
