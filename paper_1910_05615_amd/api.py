@@ -224,8 +224,8 @@ def profile_read(device=None) -> dict:
 
 def tuned_plans(device=None) -> list:
     """The autotuned C-step plans of this device's handle (opts tune=True),
-    most recent last: [(p bucket, rows per distance tile, distance passes per
-    start pair, C-steps of the last fit)] (rtdetmcd_tuned_plans)."""
+    most recent last: [(p bucket, rows per distance tile, items per distance
+    tile, C-steps of the last fit)] (rtdetmcd_tuned_plans)."""
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
     lib, h = _handle(dev)
     cnt = C.c_int32()
