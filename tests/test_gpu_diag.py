@@ -55,3 +55,16 @@ def test_batched_diagnostics_match_oracle():
     assert status == [0, 0, 0]
     for s, F in zip(sets, fits):
         _check_diag(F, oracle.fit(s.X), f"batched n={s.X.shape[0]}")
+
+
+def test_plain_launch_diagnostics_equal_batched():
+    # the per-block launches keep the same trace, gaps and margin
+    import paper_1910_05615_amd as P
+    ds = synthdata.small_gaussian(24_000, 6, seed=43, dtype=np.float32, eps=0.1)
+    X = torch.from_numpy(ds.X).to("cuda:0")
+    Fb = P.fit(X, n_chunks=3, diagnostics=True)
+    Fp = P.fit(X, n_chunks=3, diagnostics=True, launch="plain")
+    assert torch.equal(Fb.ldtrace.isnan(), Fp.ldtrace.isnan())
+    assert torch.equal(torch.nan_to_num(Fb.ldtrace), torch.nan_to_num(Fp.ldtrace))
+    assert torch.equal(Fb.hmargin, Fp.hmargin)
+    assert torch.equal(Fb.cmargin, Fp.cmargin)
