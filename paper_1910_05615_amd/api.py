@@ -322,36 +322,35 @@ def _alloc_diag(fits, outs, maxs: int):
 
 def _alloc_fits(Xs, plans):
     """The outputs of many fits: one device allocation per element type for
-    the whole batch (every Fit's tensors are views of it), split in one
-    call per type; the pointers handed to the library are computed from the
-    offsets."""
+    the whole batch, cut into every fit's outputs by one split per type (the
+    views are the Fit tensors); the pointers handed to the library are
+    computed from the offsets."""
     dev = Xs[0].device
     fsz, isz, usz = [], [], []
     for X, (q, m, h) in zip(Xs, plans):
         n, p = X.shape
-        fsz.append(4 * p + 2 * p * p + 2 + n)
-        isz.append(q * h + 3 * q)
-        usz.append(2 * n)
+        pp = p * p
+        fsz += [p, pp, p, pp, 2, p, p, n]
+        isz += [q * h, q, q, q]
+        usz += [n, n]
     k = len(Xs)
     f_all = torch.empty(sum(fsz), dtype=torch.float64, device=dev)
     i_all = torch.empty(sum(isz), dtype=torch.int32, device=dev)
     u_all = torch.empty(sum(usz), dtype=torch.uint8, device=dev)
     w_all = torch.empty(k, dtype=torch.int64, device=dev)
     fb, ib, ub, wb = f_all.data_ptr(), i_all.data_ptr(), u_all.data_ptr(), w_all.data_ptr()
-    fparts, iparts, uparts = f_all.split(fsz), i_all.split(isz), u_all.split(usz)
-    wparts = w_all.split(1)
+    fv, iv, uv, wv = f_all.split(fsz), i_all.split(isz), u_all.split(usz), w_all.split(1)
     fits, outs = [], []
     fo = io = uo = 0
     for j, (X, (q, m, h)) in enumerate(zip(Xs, plans)):
         n, p = X.shape
         pp = p * p
-        mu, sg, mr, sr, ld, loc, sc, dist = fparts[j].split([p, pp, p, pp, 2, p, p, n])
-        hs, bst, bsa, bit = iparts[j].split([q * h, q, q, q])
-        out_u, rew = uparts[j].split([n, n])
+        mu, sg, mr, sr, ld, loc, sc, dist = fv[8 * j:8 * j + 8]
+        hs, bst, bsa, bit = iv[4 * j:4 * j + 4]
         F = Fit(mu=mu, sigma=sg.view(p, p), mu_raw=mr, sigma_raw=sr.view(p, p), logdet=ld,
                 loc=loc, scale=sc, dist=dist, hsubset=hs.view(q, h), block_status=bst,
-                block_start=bsa, block_iters=bit, outlier=out_u, rew_mask=rew, n_w=wparts[j],
-                q=q, m=m, h=h)
+                block_start=bsa, block_iters=bit, outlier=uv[2 * j], rew_mask=uv[2 * j + 1],
+                n_w=wv[j], q=q, m=m, h=h)
         f0, i0, u0 = fb + 8 * fo, ib + 4 * io, ub + uo
         outs.append(_lib.Out(mu=f0, sigma=f0 + 8 * p, mu_raw=f0 + 8 * (p + pp),
                              sigma_raw=f0 + 8 * (2 * p + pp), logdet=f0 + 8 * (2 * p + 2 * pp),
@@ -362,9 +361,9 @@ def _alloc_fits(Xs, plans):
                              block_iters=i0 + 4 * (q * h + 2 * q), outlier=u0, rew_mask=u0 + n,
                              n_w=wb + 8 * j))
         fits.append(F)
-        fo += fsz[j]
-        io += isz[j]
-        uo += usz[j]
+        fo += 4 * p + 2 * pp + 2 + n
+        io += q * h + 3 * q
+        uo += 2 * n
     return fits, outs
 
 
