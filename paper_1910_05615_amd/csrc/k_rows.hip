@@ -70,11 +70,15 @@ __global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items
   using S = SscpShape<T, P>;
   constexpr int NG = S::NG, NBL = S::NBL, CR = S::CR;
   __shared__ T xs_all[4][S::XS];          // per-wave row staging
-  __shared__ double red[NBL][4][64];      // block accumulators, summed wave by wave
+  // the wrap mode takes U four-row steps at a time (one tanh pass for all)
+  constexpr int U = MODE == SSCP_WRAP ? 2 : 1;
+  // block accumulators, summed wave by wave after the rows; during the rows
+  // the same LDS holds each wave's tanh arguments (wrap mode)
+  constexpr int TW = MODE == SSCP_WRAP ? 64 * NG * U : 0;
+  constexpr int NRED = NBL * 4 * 64 > 4 * TW ? NBL * 4 * 64 : 4 * TW;
+  __shared__ double red_tw[NRED];
+  double(*red)[4][64] = reinterpret_cast<double(*)[4][64]>(red_tw);
   __shared__ int64_t rows_all[4][CR];     // gathered row indices (update steps)
-  // tanh arguments of the wrapped values of one step, gathered per wave
-  constexpr int TW = MODE == SSCP_WRAP ? 64 * NG : 1;
-  __shared__ double tw_all[4][TW];
 
   const Tile tl = tiles[blockIdx.x];
   const int it = tl.item;
@@ -202,84 +206,98 @@ __global__ __launch_bounds__(256) void k_sscp(const ItemDesc* __restrict__ items
         if (lane + 64 * k < nv) nx[k] = src[lane + 64 * k];
     }
     __syncwarp();   // staged rows visible to the whole wave
-    for (int st = 0; st < n; st += 4) {
-      const int r = st + kr;
-      const bool on = r < n && ((selm >> r) & 1ull);
-      double w = on ? (((negm >> r) & 1ull) ? -1.0 : 1.0) : 0.0;
-      double v[NG];
-      double r2 = 0.0;
+    for (int st = 0; st < n; st += 4 * U) {
+      double v[U][NG], wu[U];
 #pragma unroll
-      for (int g = 0; g < NG; ++g) {
-        const int col = 16 * g + cc;
-        double z = 0.0;
-        if (col < p) {
-          const double x = r < n ? (double)xs[r * P + col] : 0.0;
-          if (MODE == SSCP_CSTEP || MODE == SSCP_D2CUT || MODE == SSCP_ADJ) z = x - cen[g];
-          else z = (x - cen[g]) / isc[g];
-          if (MODE == SSCP_GSSCM) r2 = fma(z, z, r2);
-        } else if (col == p) {
-          z = 1.0;
-        }
-        v[g] = z;
-      }
-      if (MODE == SSCP_WRAP) {
-        // g of every value of the step; the tanh branch (a minority of the
-        // values) is evaluated once for all of the wave's values that take
-        // it, gathered in LDS, instead of once per column group
-        double* __restrict__ tw = tw_all[wv];
-        const uint64_t below = (1ull << lane) - 1ull;
-        int cnt = 0, slot[NG];
+      for (int u = 0; u < U; ++u) {
+        const int r = st + 4 * u + kr;
+        const bool on = r < n && ((selm >> r) & 1ull);
+        double w = on ? (((negm >> r) & 1ull) ? -1.0 : 1.0) : 0.0;
+        double r2 = 0.0;
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
-          const double a = fabs(v[g]);
-          const bool mid = !(a <= WRAP_B) && a <= WRAP_C;
-          const uint64_t m = __ballot(mid);
-          slot[g] = mid ? cnt + __popcll(m & below) : -1;
-          if (mid) tw[slot[g]] = WRAP_Q2 * (WRAP_C - a);
-          cnt += __popcll(m);
+          const int col = 16 * g + cc;
+          double z = 0.0;
+          if (col < p) {
+            const double x = r < n ? (double)xs[r * P + col] : 0.0;
+            if (MODE == SSCP_CSTEP || MODE == SSCP_D2CUT || MODE == SSCP_ADJ) z = x - cen[g];
+            else z = (x - cen[g]) / isc[g];
+            if (MODE == SSCP_GSSCM) r2 = fma(z, z, r2);
+          } else if (col == p) {
+            z = 1.0;
+          }
+          v[u][g] = z;
         }
+        if (MODE == SSCP_ADJ) {
+          const double wr = __shfl(wcur, r < n ? r : 0, 64);
+          w = on ? wr : 0.0;
+        }
+        if (MODE == SSCP_GSSCM) {
+          // weight xi^2(||z||) of eq. (LR); the 16 lanes of a row add their parts
+          r2 = row16_sum(r2);
+          const double rr = sqrt(r2);
+          double xi;
+          if (gB <= gA) xi = (rr <= gA) ? 1.0 : 0.0;
+          else xi = (rr <= gA) ? 1.0 : ((rr <= gB) ? (gB - rr) / (gB - gA) : 0.0);
+          w = on ? xi * xi : 0.0;
+        }
+        wu[u] = w;
+      }
+      if (MODE == SSCP_WRAP) {
+        // g of every value of the U steps; the tanh branch (a minority of
+        // the values) is evaluated once for all of the wave's values that
+        // take it, gathered in LDS, instead of once per column group and step
+        double* __restrict__ tw = red_tw + wv * TW;
+        const uint64_t below = (1ull << lane) - 1ull;
+        int cnt = 0, slot[U][NG];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int g = 0; g < NG; ++g) {
+            const double a = fabs(v[u][g]);
+            const bool mid = !(a <= WRAP_B) && a <= WRAP_C;
+            const uint64_t m = __ballot(mid);
+            slot[u][g] = mid ? cnt + __popcll(m & below) : -1;
+            if (mid) tw[slot[u][g]] = WRAP_Q2 * (WRAP_C - a);
+            cnt += __popcll(m);
+          }
         __syncwarp();
         for (int b0 = 0; b0 < cnt; b0 += 64)
           if (b0 + lane < cnt) tw[b0 + lane] = tanh(tw[b0 + lane]);
         __syncwarp();
 #pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int g = 0; g < NG; ++g) {
+            const double a = fabs(v[u][g]);
+            if (slot[u][g] >= 0) v[u][g] = copysign(WRAP_Q1 * tw[slot[u][g]], v[u][g]);
+            else if (!(a <= WRAP_C)) v[u][g] = 0.0;
+          }
+        __syncwarp();   // tw is free for the next steps
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (st + 4 * u >= n) break;   // uniform: no rows left in the chunk
+        const double w = wu[u];
+        double av[NG], bv[NG];
+#pragma unroll
         for (int g = 0; g < NG; ++g) {
-          const double a = fabs(v[g]);
-          if (slot[g] >= 0) v[g] = copysign(WRAP_Q1 * tw[slot[g]], v[g]);
-          else if (!(a <= WRAP_C)) v[g] = 0.0;
+          bv[g] = w == 0.0 ? 0.0 : v[u][g];
+          av[g] = w * bv[g];
         }
-        __syncwarp();   // tw is free for the next step
-      }
-      if (MODE == SSCP_ADJ) {
-        const double wr = __shfl(wcur, r < n ? r : 0, 64);
-        w = on ? wr : 0.0;
-      }
-      if (MODE == SSCP_GSSCM) {
-        // weight xi^2(||z||) of eq. (LR); the 16 lanes of a row add their parts
-        r2 = row16_sum(r2);
-        const double rr = sqrt(r2);
-        double xi;
-        if (gB <= gA) xi = (rr <= gA) ? 1.0 : 0.0;
-        else xi = (rr <= gA) ? 1.0 : ((rr <= gB) ? (gB - rr) / (gB - gA) : 0.0);
-        w = on ? xi * xi : 0.0;
-      }
-      double av[NG];
+        int q = 0;
 #pragma unroll
-      for (int g = 0; g < NG; ++g) {
-        if (w == 0.0) v[g] = 0.0;
-        av[g] = w * v[g];
+        for (int gi = 0; gi < NG; ++gi)
+#pragma unroll
+          for (int gj = 0; gj <= gi; ++gj, ++q)
+            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[gi], bv[gj], acc[q], 0, 0, 0);
       }
-      int q = 0;
-#pragma unroll
-      for (int gi = 0; gi < NG; ++gi)
-#pragma unroll
-        for (int gj = 0; gj <= gi; ++gj, ++q)
-          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[gi], v[gj], acc[q], 0, 0, 0);
     }
     n = nn;
   }
 
   // fixed-order sum over the four waves (wave 0 first) and the tile partial
+  if (MODE == SSCP_WRAP) __syncthreads();   // every wave is done with its tanh arguments
   for (int k = 0; k < 4; ++k) {
     if (wv == k) {
 #pragma unroll
